@@ -1,0 +1,219 @@
+/*
+ * cpi.h -- C ABI of the MI355X (gfx950) correlation plenoptic imaging library.
+ *
+ * The library computes the two steps of correlation plenoptic imaging (CPI):
+ *
+ *  1. the 4-D correlation function of Eq. (1) (Section "CPI algorithm",
+ *     item 1):  Gamma(rho_a, rho_b) = <A(rho_a) B(rho_b)> - <A(rho_a)><B(rho_b)>
+ *     over N frame pairs, both averages normalised by N.  It is evaluated
+ *     exactly: numer = N * S_ab - S_a * S_b in int64 (S_ab the sum of
+ *     products, S_a and S_b the per-pixel sums, S_ab contracted on int8 matrix
+ *     cores with int32 partial sums), then gamma = fl64(fl64(numer) / fl64(N*N));
+ *
+ *  2. refocusing (Section "CPI algorithm", item 2; refocusing optimisation in
+ *     Section 4.1): for each plane parameter alpha and output pixel (x_r, y_r)
+ *       u_x = alpha*(x_r - ca_x) + ca_x + (1 - alpha)*mag_x*(x_b - cb_x)
+ *       u_y = alpha*(y_r - ca_y) + ca_y + (1 - alpha)*mag_y*(y_b - cb_y)
+ *       I_alpha(x_r, y_r) = sum over detector-B pixels (x_b, y_b) of the
+ *         bilinear sample of the view Gamma(., rho_b) at (u_x, u_y),
+ *     corners outside the Ha x Wa view contributing zero.  Interpolation
+ *     coordinates are built on the device from FP64 per-plane tables; samples
+ *     are weighted and summed in FP32.
+ *
+ * Conventions shared by every entry point
+ *  - Pixel index rho = y * W + x (0-based) on both detectors.
+ *  - Frames are frame-major: frame i occupies bytes [i*FB, (i+1)*FB) with
+ *      FB = P          for CPI_FRAMES_U8   (one byte per pixel), or
+ *      FB = ceil(P/8)  for CPI_FRAMES_BIT1 (pixel 8j+k in bit k of byte j,
+ *                                           padding bits of the last byte ignored).
+ *  - Gamma storage: CPI_GAMMA_VIEW_MAJOR  -> element (rho_a, rho_b) at rho_b*Pa + rho_a
+ *                   CPI_GAMMA_PIXEL_MAJOR -> element (rho_a, rho_b) at rho_a*Pb + rho_b
+ *  - Ownership: frame, Gamma, output and workspace pointers are DEVICE
+ *    pointers owned by the caller; the library never allocates or frees device
+ *    memory.  Geometry and alpha pointers are HOST pointers, read before the
+ *    call returns.  Device pointers must be 16-byte aligned.
+ *  - Asynchrony: after validation every call only enqueues work on `stream`
+ *    (a hipStream_t, NULL = the null stream); results are valid once the
+ *    stream has reached that point.  Calls on distinct streams with distinct
+ *    workspaces may run concurrently.  cpi_autotune_refocus and the stream
+ *    save/load calls synchronise the stream.
+ *  - Errors: every entry point returns a cpi_status and never aborts.  Invalid
+ *    arguments are rejected before anything is enqueued; cpi_last_error()
+ *    returns this thread's text for the last failure.
+ */
+#ifndef CPI_H
+#define CPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CPI_OK = 0,
+  CPI_ERR_INVALID_ARG = 1,  /* null/misaligned pointer, bad size, bad enum, non-finite alpha */
+  CPI_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement */
+  CPI_ERR_OVERFLOW = 3,     /* N^2 * max|a| * max|b| >= 2^63 or N^2 >= 2^53 */
+  CPI_ERR_WORKSPACE = 4,    /* workspace smaller than the *_workspace_size figure */
+  CPI_ERR_DEVICE = 5,       /* HIP runtime or launch failure (text in cpi_last_error) */
+  CPI_ERR_NOT_READY = 6     /* stream handle has no frames yet */
+} cpi_status;
+
+typedef enum { CPI_FRAMES_U8 = 0, CPI_FRAMES_BIT1 = 1 } cpi_frame_format;
+
+typedef enum { CPI_GAMMA_VIEW_MAJOR = 0, CPI_GAMMA_PIXEL_MAJOR = 1 } cpi_gamma_layout;
+
+/* Refocus geometry.  wa x ha: detector A (spatial, Da); wb x hb: detector B
+ * (lens plane, Db); mag_*: magnification from Db to Da pixel units; ca_*,
+ * cb_*: optical-axis centres on Da and Db in pixels; out_w x out_h: output
+ * grid, whose pixel (x_r, y_r) sits at Da coordinates (x_r, y_r). */
+typedef struct {
+  int32_t wa, ha, wb, hb;
+  double mag_x, mag_y;
+  double ca_x, ca_y, cb_x, cb_y;
+  int32_t out_w, out_h;
+} cpi_geometry;
+
+/* Library version string (static storage). */
+const char* cpi_version(void);
+/* Name of a status code (static storage). */
+const char* cpi_status_string(cpi_status s);
+/* Detail text of the last failed call on this thread ("" if none). */
+const char* cpi_last_error(void);
+
+/* Default geometry: mag = wa/wb and ha/hb, centres (w-1)/2 and (h-1)/2,
+ * output grid = the Da grid.  `out` is a host pointer. */
+cpi_status cpi_geometry_default(int32_t wa, int32_t ha, int32_t wb, int32_t hb,
+                                cpi_geometry* out);
+
+/* ---------------------------------------------------------------------------
+ * Correlation function, Eq. (1), exact.
+ *
+ * cpi_correlate_workspace_size: bytes of device workspace cpi_correlate needs
+ *   for these sizes (written to *bytes, a host pointer).
+ *
+ * cpi_correlate: Gamma for n frame pairs.
+ *   frames_a  n frames of pa pixels (detector A), format `fmt`
+ *   frames_b  n frames of pb pixels (detector B), format `fmt`
+ *   gamma     nullable, pa*pb doubles in `layout`: fl64(numer)/fl64(n*n)
+ *   gamma_f32 nullable, pa*pb floats in `layout`:  fl32(gamma)
+ *   numer     nullable, pa*pb int64 in `layout`:   n*S_ab - S_a*S_b
+ *   sum_a     nullable, pa int64: S_a;  sum_b nullable, pb int64: S_b
+ *   At least one of gamma, gamma_f32, numer must be non-null.
+ *   Binary data (every byte 0 or 1, or CPI_FRAMES_BIT1) is contracted from
+ *   packed bits; other uint8 data from bytes (offset by -128 when a value
+ *   exceeds 127, which leaves numer unchanged); int32 partial sums are folded
+ *   into int64 whenever the next block of frames could overflow them.
+ *   Errors: CPI_ERR_INVALID_ARG (null frames/workspace, n, pa or pb <= 0,
+ *   bad enum, misalignment, all outputs null), CPI_ERR_OVERFLOW (n*n*255*255
+ *   >= 2^63 for U8, n*n >= 2^53 for either format), CPI_ERR_WORKSPACE,
+ *   CPI_ERR_DEVICE.
+ * ------------------------------------------------------------------------- */
+cpi_status cpi_correlate_workspace_size(int64_t n, int64_t pa, int64_t pb,
+                                        cpi_frame_format fmt, size_t* bytes);
+cpi_status cpi_correlate(const void* frames_a, const void* frames_b, int64_t n,
+                         int64_t pa, int64_t pb, cpi_frame_format fmt,
+                         cpi_gamma_layout layout, double* gamma, float* gamma_f32,
+                         int64_t* numer, int64_t* sum_a, int64_t* sum_b,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Plain FP32 correlator, the comparison path for the int8 one: frames are
+ * unpacked to FP32, S_ab, S_a and S_b are FP32 sums (FMA), and
+ *   gamma_f32 = fl32(S_ab/n) - fl32(fl32(S_a/n) * fl32(S_b/n))   (FP32 ops).
+ * Same inputs, layout and errors as cpi_correlate; gamma_f32 must be non-null. */
+cpi_status cpi_correlate_f32_plain_workspace_size(int64_t n, int64_t pa, int64_t pb,
+                                                  cpi_frame_format fmt, size_t* bytes);
+cpi_status cpi_correlate_f32_plain(const void* frames_a, const void* frames_b,
+                                   int64_t n, int64_t pa, int64_t pb,
+                                   cpi_frame_format fmt, cpi_gamma_layout layout,
+                                   float* gamma_f32, void* workspace,
+                                   size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Refocusing (shift-and-sum of perspective views).
+ *
+ * gamma    Gamma as FP32 in CPI_GAMMA_VIEW_MAJOR storage: Pb = wb*hb views of
+ *          ha x wa pixels (device)
+ * g        geometry (host)
+ * alphas   n_alpha plane parameters (host, finite), 1 <= n_alpha <= 4096
+ * out      n_alpha * out_h * out_w floats, plane-major then row-major (device)
+ *
+ * cpi_refocus runs the batched kernel (many planes per launch) with the tile
+ * configuration cached by cpi_autotune_refocus for this shape, or a default.
+ * cpi_refocus_plain runs one plane per launch with direct gathers.
+ * cpi_autotune_refocus times the candidate configurations on these inputs,
+ * caches the fastest (in memory and, if CPI_AUTOTUNE_CACHE names a file, on
+ * disk), synchronises `stream`, and leaves the refocused stack in `out`.
+ * Errors: CPI_ERR_INVALID_ARG (null pointers, non-positive sizes, non-finite
+ * geometry or alpha, n_alpha out of range), CPI_ERR_WORKSPACE, CPI_ERR_DEVICE.
+ * ------------------------------------------------------------------------- */
+cpi_status cpi_refocus_workspace_size(const cpi_geometry* g, int32_t n_alpha,
+                                      size_t* bytes);
+cpi_status cpi_refocus(const float* gamma, const cpi_geometry* g,
+                       const double* alphas, int32_t n_alpha, float* out,
+                       void* workspace, size_t workspace_bytes, void* stream);
+cpi_status cpi_refocus_plain(const float* gamma, const cpi_geometry* g,
+                             const double* alphas, int32_t n_alpha, float* out,
+                             void* workspace, size_t workspace_bytes, void* stream);
+cpi_status cpi_autotune_refocus(const float* gamma, const cpi_geometry* g,
+                                const double* alphas, int32_t n_alpha, float* out,
+                                void* workspace, size_t workspace_bytes,
+                                void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Streaming: frame chunks folded into device-resident sums as rank-k updates
+ * (the sums of Eq. (1) are additive over frames), so Gamma for all frames so
+ * far is available after every chunk.
+ *
+ * cpi_stream_workspace_size: device bytes a stream needs for pa, pb, fmt and
+ *   chunks of at most max_chunk frames.
+ * cpi_stream_create: builds a handle over caller workspace (device) on `stream`;
+ *   the handle owns host-side state only.  Sums start at zero.
+ * cpi_stream_push: folds k <= max_chunk frame pairs (device pointers, format
+ *   fmt) into S_ab, S_a, S_b and refreshes the handle's FP32 Gamma.
+ * cpi_stream_push_host: the same for host chunks (pinned memory gives an
+ *   asynchronous copy; pageable memory is copied synchronously).
+ * cpi_stream_frames: frames folded so far (host pointer).
+ * cpi_stream_gamma: writes Gamma for all frames so far (each output nullable).
+ * cpi_stream_gamma_f32_ptr: device address of the handle's FP32 view-major
+ *   Gamma, refreshed by every push.
+ * cpi_stream_refocus: refocuses the current Gamma (as cpi_refocus).
+ * cpi_stream_state_size / save / load: checkpoint of (N, S_a, S_b, S_ab) in a
+ *   host buffer; both synchronise the stream.  A checkpoint loads only into a
+ *   stream of the same pa, pb and fmt.
+ * cpi_stream_destroy: frees the handle (not the workspace).
+ * Errors: CPI_ERR_INVALID_ARG, CPI_ERR_OVERFLOW (N would break the bounds of
+ *   cpi_correlate), CPI_ERR_NOT_READY (gamma requested before any frame),
+ *   CPI_ERR_WORKSPACE, CPI_ERR_DEVICE.
+ * ------------------------------------------------------------------------- */
+typedef struct cpi_stream_s* cpi_stream_t;
+
+cpi_status cpi_stream_workspace_size(int64_t pa, int64_t pb, cpi_frame_format fmt,
+                                     int64_t max_chunk, size_t* bytes);
+cpi_status cpi_stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt,
+                             int64_t max_chunk, void* workspace, size_t bytes,
+                             void* stream, cpi_stream_t* out);
+cpi_status cpi_stream_push(cpi_stream_t s, const void* chunk_a, const void* chunk_b,
+                           int64_t k);
+cpi_status cpi_stream_push_host(cpi_stream_t s, const void* chunk_a,
+                                const void* chunk_b, int64_t k);
+cpi_status cpi_stream_frames(cpi_stream_t s, int64_t* n);
+cpi_status cpi_stream_gamma(cpi_stream_t s, cpi_gamma_layout layout, double* gamma,
+                            float* gamma_f32, int64_t* numer, int64_t* sum_a,
+                            int64_t* sum_b);
+cpi_status cpi_stream_gamma_f32_ptr(cpi_stream_t s, const float** gamma_f32);
+cpi_status cpi_stream_refocus(cpi_stream_t s, const cpi_geometry* g,
+                              const double* alphas, int32_t n_alpha, float* out,
+                              void* workspace, size_t workspace_bytes);
+cpi_status cpi_stream_state_size(cpi_stream_t s, size_t* bytes);
+cpi_status cpi_stream_save(cpi_stream_t s, void* host_buf, size_t bytes);
+cpi_status cpi_stream_load(cpi_stream_t s, const void* host_buf, size_t bytes);
+cpi_status cpi_stream_destroy(cpi_stream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPI_H */

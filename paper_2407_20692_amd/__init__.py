@@ -1,0 +1,33 @@
+"""MI355X (gfx950) correlation plenoptic imaging: exact correlation function
+and batched refocusing behind the C ABI of ``include/cpi.h``.
+
+Importing the package loads ``libcpi.so``; it raises ImportError when the
+library has not been built (``python -m paper_2407_20692_amd.build``).
+"""
+from .binding import (  # noqa: F401
+    CpiError,
+    EXPORTED,
+    FRAMES_BIT1,
+    FRAMES_U8,
+    GAMMA_PIXEL_MAJOR,
+    GAMMA_VIEW_MAJOR,
+    Geometry,
+    LIB_PATH,
+    Stream,
+    alloc_workspace,
+    autotune_refocus,
+    correlate,
+    correlate_f32_plain,
+    correlate_f32_plain_workspace_size,
+    correlate_workspace_size,
+    frame_bytes,
+    geometry_default,
+    last_error,
+    lib,
+    make_geometry,
+    refocus,
+    refocus_plain,
+    refocus_workspace_size,
+    stream_workspace_size,
+    version,
+)

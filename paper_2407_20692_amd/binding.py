@@ -1,0 +1,394 @@
+"""ctypes binding of ``libcpi.so`` (the C ABI in ``include/cpi.h``).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the computation runs in the library's kernels.  The
+binding checks dtype, device, contiguity and size of every buffer before a
+call, because the C ABI takes bare pointers.  If the library has not been
+built, importing this module raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpi.so")
+
+# status codes
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_UNSUPPORTED = 2
+ERR_OVERFLOW = 3
+ERR_WORKSPACE = 4
+ERR_DEVICE = 5
+ERR_NOT_READY = 6
+
+FRAMES_U8 = 0
+FRAMES_BIT1 = 1
+GAMMA_VIEW_MAJOR = 0
+GAMMA_PIXEL_MAJOR = 1
+
+
+class CpiError(RuntimeError):
+    def __init__(self, status: int, name: str, detail: str):
+        super().__init__(f"{name}: {detail}")
+        self.status = status
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("wa", c_int32), ("ha", c_int32), ("wb", c_int32), ("hb", c_int32),
+        ("mag_x", c_double), ("mag_y", c_double),
+        ("ca_x", c_double), ("ca_y", c_double), ("cb_x", c_double), ("cb_y", c_double),
+        ("out_w", c_int32), ("out_h", c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGS = {
+    "cpi_version": (c_char_p, []),
+    "cpi_status_string": (c_char_p, [c_int]),
+    "cpi_last_error": (c_char_p, []),
+    "cpi_geometry_default": (c_int, [c_int32, c_int32, c_int32, c_int32, POINTER(Geometry)]),
+    "cpi_correlate_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
+    "cpi_correlate": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int, c_int,
+                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_size_t, c_void_p]),
+    "cpi_correlate_f32_plain_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int,
+                                                       POINTER(c_size_t)]),
+    "cpi_correlate_f32_plain": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int,
+                                        c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "cpi_refocus_workspace_size": (c_int, [POINTER(Geometry), c_int32, POINTER(c_size_t)]),
+    "cpi_refocus": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32, c_void_p,
+                            c_void_p, c_size_t, c_void_p]),
+    "cpi_refocus_plain": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
+                                  c_void_p, c_void_p, c_size_t, c_void_p]),
+    "cpi_autotune_refocus": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
+                                     c_void_p, c_void_p, c_size_t, c_void_p]),
+    "cpi_stream_workspace_size": (c_int, [c_int64, c_int64, c_int, c_int64, POINTER(c_size_t)]),
+    "cpi_stream_create": (c_int, [c_int64, c_int64, c_int, c_int64, c_void_p, c_size_t, c_void_p,
+                                  POINTER(c_void_p)]),
+    "cpi_stream_push": (c_int, [c_void_p, c_void_p, c_void_p, c_int64]),
+    "cpi_stream_push_host": (c_int, [c_void_p, c_void_p, c_void_p, c_int64]),
+    "cpi_stream_frames": (c_int, [c_void_p, POINTER(c_int64)]),
+    "cpi_stream_gamma": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p]),
+    "cpi_stream_gamma_f32_ptr": (c_int, [c_void_p, POINTER(c_void_p)]),
+    "cpi_stream_refocus": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
+                                   c_void_p, c_void_p, c_size_t]),
+    "cpi_stream_state_size": (c_int, [c_void_p, POINTER(c_size_t)]),
+    "cpi_stream_save": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "cpi_stream_load": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "cpi_stream_destroy": (c_int, [c_void_p]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_2407_20692_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def version() -> str:
+    return lib.cpi_version().decode()
+
+
+def last_error() -> str:
+    return lib.cpi_last_error().decode()
+
+
+def _check(status: int):
+    if status != OK:
+        name = lib.cpi_status_string(status).decode()
+        raise CpiError(status, name, last_error())
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch  # local: the CPU-only tests load the library without torch work
+    return torch
+
+
+def _dev_ptr(t, what: str, dtype=None, numel: int | None = None, nbytes: int | None = None):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, needs {numel}")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, needs {nbytes}")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return c_void_p(_torch().cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return c_void_p(stream)
+    return c_void_p(stream.cuda_stream)
+
+
+def frame_bytes(npix: int, fmt: int) -> int:
+    return npix if fmt == FRAMES_U8 else (npix + 7) // 8
+
+
+def _alphas(alphas):
+    a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).reshape(-1))
+    return a, a.ctypes.data_as(POINTER(c_double)), int(a.size)
+
+
+def alloc_workspace(nbytes: int, device=None):
+    """Device workspace as a uint8 tensor (at least 256 bytes)."""
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8,
+                       device=device if device is not None else "cuda")
+
+
+# ---------------------------------------------------------------------------
+# correlation
+# ---------------------------------------------------------------------------
+
+def correlate_workspace_size(n: int, pa: int, pb: int, fmt: int) -> int:
+    out = c_size_t(0)
+    _check(lib.cpi_correlate_workspace_size(n, pa, pb, fmt, ctypes.byref(out)))
+    return out.value
+
+
+def correlate(frames_a, frames_b, n: int, pa: int, pb: int, fmt: int,
+              layout: int = GAMMA_VIEW_MAJOR, gamma=None, gamma_f32=None, numer=None,
+              sum_a=None, sum_b=None, workspace=None, stream=None):
+    """Exact Gamma of Eq. (1) into the given device tensors (see cpi_correlate)."""
+    torch = _torch()
+    need = correlate_workspace_size(n, pa, pb, fmt)
+    if workspace is None:
+        workspace = alloc_workspace(need, frames_a.device)
+    _check(lib.cpi_correlate(
+        _dev_ptr(frames_a, "frames_a", torch.uint8, nbytes=n * frame_bytes(pa, fmt)),
+        _dev_ptr(frames_b, "frames_b", torch.uint8, nbytes=n * frame_bytes(pb, fmt)),
+        n, pa, pb, fmt, layout,
+        _dev_ptr(gamma, "gamma", torch.float64, numel=pa * pb),
+        _dev_ptr(gamma_f32, "gamma_f32", torch.float32, numel=pa * pb),
+        _dev_ptr(numer, "numer", torch.int64, numel=pa * pb),
+        _dev_ptr(sum_a, "sum_a", torch.int64, numel=pa),
+        _dev_ptr(sum_b, "sum_b", torch.int64, numel=pb),
+        _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need, _stream(stream)))
+    return workspace
+
+
+def correlate_f32_plain_workspace_size(n: int, pa: int, pb: int, fmt: int) -> int:
+    out = c_size_t(0)
+    _check(lib.cpi_correlate_f32_plain_workspace_size(n, pa, pb, fmt, ctypes.byref(out)))
+    return out.value
+
+
+def correlate_f32_plain(frames_a, frames_b, n: int, pa: int, pb: int, fmt: int, gamma_f32,
+                        layout: int = GAMMA_VIEW_MAJOR, workspace=None, stream=None):
+    """Plain FP32 Gamma (see cpi_correlate_f32_plain)."""
+    torch = _torch()
+    need = correlate_f32_plain_workspace_size(n, pa, pb, fmt)
+    if workspace is None:
+        workspace = alloc_workspace(need, frames_a.device)
+    _check(lib.cpi_correlate_f32_plain(
+        _dev_ptr(frames_a, "frames_a", torch.uint8, nbytes=n * frame_bytes(pa, fmt)),
+        _dev_ptr(frames_b, "frames_b", torch.uint8, nbytes=n * frame_bytes(pb, fmt)),
+        n, pa, pb, fmt, layout,
+        _dev_ptr(gamma_f32, "gamma_f32", torch.float32, numel=pa * pb),
+        _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need, _stream(stream)))
+    return workspace
+
+
+# ---------------------------------------------------------------------------
+# refocus
+# ---------------------------------------------------------------------------
+
+def geometry_default(wa: int, ha: int, wb: int, hb: int) -> Geometry:
+    g = Geometry()
+    _check(lib.cpi_geometry_default(wa, ha, wb, hb, ctypes.byref(g)))
+    return g
+
+
+def make_geometry(**kw) -> Geometry:
+    g = Geometry()
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+def refocus_workspace_size(g: Geometry, n_alpha: int) -> int:
+    out = c_size_t(0)
+    _check(lib.cpi_refocus_workspace_size(ctypes.byref(g), n_alpha, ctypes.byref(out)))
+    return out.value
+
+
+def _refocus_call(fn, gamma, g: Geometry, alphas, out, workspace, stream):
+    torch = _torch()
+    a, ap, na = _alphas(alphas)
+    need = refocus_workspace_size(g, na)
+    if workspace is None:
+        workspace = alloc_workspace(need, gamma.device)
+    pa = g.wa * g.ha
+    pb = g.wb * g.hb
+    _check(fn(_dev_ptr(gamma, "gamma", torch.float32, numel=pa * pb), ctypes.byref(g), ap, na,
+              _dev_ptr(out, "out", torch.float32, numel=na * g.out_w * g.out_h),
+              _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need, _stream(stream)))
+    del a
+    return workspace
+
+
+def refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
+    """Batched refocus of view-major FP32 Gamma into out (n_alpha, out_h, out_w)."""
+    return _refocus_call(lib.cpi_refocus, gamma, g, alphas, out, workspace, stream)
+
+
+def refocus_plain(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
+    """One-plane-per-launch refocus (the comparison path)."""
+    return _refocus_call(lib.cpi_refocus_plain, gamma, g, alphas, out, workspace, stream)
+
+
+def autotune_refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
+    """Times the refocus configurations, caches the best, leaves the result in out."""
+    return _refocus_call(lib.cpi_autotune_refocus, gamma, g, alphas, out, workspace, stream)
+
+
+# ---------------------------------------------------------------------------
+# streaming
+# ---------------------------------------------------------------------------
+
+def stream_workspace_size(pa: int, pb: int, fmt: int, max_chunk: int) -> int:
+    out = c_size_t(0)
+    _check(lib.cpi_stream_workspace_size(pa, pb, fmt, max_chunk, ctypes.byref(out)))
+    return out.value
+
+
+class Stream:
+    """Device-resident running sums of Eq. (1), updated chunk by chunk."""
+
+    def __init__(self, pa: int, pb: int, fmt: int, max_chunk: int, device=None, stream=None):
+        torch = _torch()
+        self.pa, self.pb, self.fmt, self.max_chunk = pa, pb, fmt, max_chunk
+        need = stream_workspace_size(pa, pb, fmt, max_chunk)
+        self.workspace = alloc_workspace(need, device)
+        self._stream = stream
+        h = c_void_p()
+        _check(lib.cpi_stream_create(pa, pb, fmt, max_chunk,
+                                     _dev_ptr(self.workspace, "workspace", torch.uint8, nbytes=need),
+                                     need, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib.cpi_stream_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, chunk_a, chunk_b, k: int):
+        torch = _torch()
+        _check(lib.cpi_stream_push(
+            self.handle,
+            _dev_ptr(chunk_a, "chunk_a", torch.uint8, nbytes=k * frame_bytes(self.pa, self.fmt)),
+            _dev_ptr(chunk_b, "chunk_b", torch.uint8, nbytes=k * frame_bytes(self.pb, self.fmt)),
+            k))
+
+    def push_host(self, chunk_a, chunk_b, k: int):
+        """Host chunks: numpy arrays or CPU tensors (pinned ones copy asynchronously)."""
+        keep = []
+
+        def host_ptr(x, nb, what):
+            if hasattr(x, "data_ptr"):
+                if x.is_cuda or not x.is_contiguous() or x.numel() * x.element_size() < nb:
+                    raise ValueError(f"{what} must be a contiguous host buffer of {nb} bytes")
+                return c_void_p(x.data_ptr())
+            arr = np.ascontiguousarray(x, dtype=np.uint8)
+            if arr.nbytes < nb:
+                raise ValueError(f"{what} must hold {nb} bytes")
+            keep.append(arr)
+            return c_void_p(arr.ctypes.data)
+
+        _check(lib.cpi_stream_push_host(
+            self.handle,
+            host_ptr(chunk_a, k * frame_bytes(self.pa, self.fmt), "chunk_a"),
+            host_ptr(chunk_b, k * frame_bytes(self.pb, self.fmt), "chunk_b"), k))
+        if keep:
+            # pageable memory: the copy is complete before the call returned
+            del keep
+
+    @property
+    def frames(self) -> int:
+        n = c_int64(0)
+        _check(lib.cpi_stream_frames(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def gamma(self, layout: int = GAMMA_VIEW_MAJOR, gamma=None, gamma_f32=None, numer=None,
+              sum_a=None, sum_b=None):
+        torch = _torch()
+        n = self.pa * self.pb
+        _check(lib.cpi_stream_gamma(
+            self.handle, layout,
+            _dev_ptr(gamma, "gamma", torch.float64, numel=n),
+            _dev_ptr(gamma_f32, "gamma_f32", torch.float32, numel=n),
+            _dev_ptr(numer, "numer", torch.int64, numel=n),
+            _dev_ptr(sum_a, "sum_a", torch.int64, numel=self.pa),
+            _dev_ptr(sum_b, "sum_b", torch.int64, numel=self.pb)))
+
+    def gamma_f32_ptr(self) -> int:
+        p = c_void_p()
+        _check(lib.cpi_stream_gamma_f32_ptr(self.handle, ctypes.byref(p)))
+        return p.value
+
+    def refocus(self, g: Geometry, alphas, out, workspace=None):
+        torch = _torch()
+        a, ap, na = _alphas(alphas)
+        need = refocus_workspace_size(g, na)
+        if workspace is None:
+            workspace = alloc_workspace(need, self.workspace.device)
+        _check(lib.cpi_stream_refocus(
+            self.handle, ctypes.byref(g), ap, na,
+            _dev_ptr(out, "out", torch.float32, numel=na * g.out_w * g.out_h),
+            _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need))
+        del a
+        return workspace
+
+    def state_size(self) -> int:
+        out = c_size_t(0)
+        _check(lib.cpi_stream_state_size(self.handle, ctypes.byref(out)))
+        return out.value
+
+    def save(self) -> bytes:
+        buf = ctypes.create_string_buffer(self.state_size())
+        _check(lib.cpi_stream_save(self.handle, buf, len(buf)))
+        return buf.raw
+
+    def load(self, state: bytes):
+        buf = ctypes.create_string_buffer(state, len(state))
+        _check(lib.cpi_stream_load(self.handle, buf, len(state)))

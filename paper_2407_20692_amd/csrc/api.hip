@@ -1,0 +1,728 @@
+// C ABI of the CPI library (declared in include/cpi.h).
+//
+// Every entry point validates its arguments on the host, then only enqueues
+// kernels on the caller's stream.  No entry point allocates device memory:
+// all scratch lives in the caller's workspace, laid out by plan.cpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <exception>
+#include <string>
+
+#include "autotune.h"
+#include "cpi.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cpi_status set_error(cpi_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+cpi_status device_error(hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return set_error(CPI_ERR_DEVICE, m);
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+template <typename F>
+cpi_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::exception& e) {
+    return set_error(CPI_ERR_DEVICE, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return set_error(CPI_ERR_DEVICE, "internal error");
+  }
+}
+
+#define CPI_HIP(call, what)                      \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return device_error(e_, what); \
+  } while (0)
+
+cpi::RefGeom ref_geom(const cpi_geometry* g) {
+  cpi::RefGeom r;
+  r.wa = g->wa;
+  r.ha = g->ha;
+  r.wb = g->wb;
+  r.hb = g->hb;
+  r.out_w = g->out_w;
+  r.out_h = g->out_h;
+  r.mag_x = g->mag_x;
+  r.mag_y = g->mag_y;
+  r.ca_x = g->ca_x;
+  r.ca_y = g->ca_y;
+  r.cb_x = g->cb_x;
+  r.cb_y = g->cb_y;
+  return r;
+}
+
+// Enqueue the whole exact correlation for one set of frames.
+//   sums_ws: int64 sums in the workspace (raw values, pa_pad / pb_pad long)
+cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const uint8_t* fb,
+                             uint8_t* ws, int layout, double* gamma, float* gamma_f32,
+                             int64_t* numer, hipStream_t st) {
+  int64_t* sum_a = reinterpret_cast<int64_t*>(ws + pl.off_sum_a);
+  int64_t* sum_b = reinterpret_cast<int64_t*>(ws + pl.off_sum_b);
+  uint32_t* stats = reinterpret_cast<uint32_t*>(ws + pl.off_stats);
+  uint8_t* op_a = ws + pl.off_op_a;
+  uint8_t* op_b = ws + pl.off_op_b;
+  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum_a), pl.pa_pad, 0, st), "fill");
+  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum_b), pl.pb_pad, 0, st), "fill");
+  CPI_HIP(cpi::fill_u32(stats, 64, 0, st), "fill");
+
+  cpi::GemmArgs g;
+  g.opm = op_b;
+  g.opn = op_a;
+  g.m_pad = pl.pb_pad;
+  g.n_pad = pl.pa_pad;
+  g.layout = layout;
+  g.pa = pl.pa;
+  g.pb = pl.pb;
+  g.n = pl.n;
+  g.sum_a = sum_a;
+  g.sum_b = sum_b;
+  g.stats = stats;
+  g.gamma = gamma;
+  g.gamma_f32 = gamma_f32;
+  g.numer = numer;
+
+  if (pl.fmt == CPI_FRAMES_BIT1) {
+    CPI_HIP(cpi::ingest_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, st), "ingest");
+    CPI_HIP(cpi::ingest_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, st), "ingest");
+    g.row_bytes = pl.row_bytes_bits;
+    g.kblocks = pl.kpad_bits / cpi::kBitBlock;
+    g.mode = cpi::EPI_FINAL;
+    CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
+    return CPI_OK;
+  }
+
+  // Byte frames: the maximum decides between bit rows (binary data) and
+  // int8 rows; both branches are enqueued and the device skips the other.
+  CPI_HIP(cpi::u8_stats(fa, pl.n, pl.pa, sum_a, stats, st), "stats");
+  CPI_HIP(cpi::u8_stats(fb, pl.n, pl.pb, sum_b, stats, st), "stats");
+  CPI_HIP(cpi::u8_to_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, stats, st), "ingest");
+  CPI_HIP(cpi::u8_to_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, stats, st), "ingest");
+  CPI_HIP(cpi::u8_to_bytes(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bytes, stats, st), "ingest");
+  CPI_HIP(cpi::u8_to_bytes(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bytes, stats, st), "ingest");
+
+  cpi::GemmArgs gb = g;
+  gb.row_bytes = pl.row_bytes_bits;
+  gb.kblocks = pl.kpad_bits / cpi::kBitBlock;
+  gb.mode = cpi::EPI_FINAL;
+  gb.cond = 1;
+  CPI_HIP(cpi::gemm_correlate(gb, true, st), "gemm");
+
+  cpi::GemmArgs gy = g;
+  gy.row_bytes = pl.row_bytes_bytes;
+  gy.cond = 2;
+  gy.offset_from_stats = 1;
+  gy.acc64 = reinterpret_cast<int64_t*>(ws + pl.off_acc64);
+  for (int pass = 0; pass < pl.passes; ++pass) {
+    const int64_t k0 = int64_t(pass) * cpi::kByteChunk;
+    int64_t k1 = k0 + cpi::kByteChunk;
+    if (k1 > pl.kpad_bytes) k1 = pl.kpad_bytes;
+    gy.k_byte_off = k0;
+    gy.kblocks = (k1 - k0) / cpi::kByteBlock;
+    if (pl.passes == 1)
+      gy.mode = cpi::EPI_FINAL;
+    else if (pass == 0)
+      gy.mode = cpi::EPI_STORE64;
+    else if (pass + 1 < pl.passes)
+      gy.mode = cpi::EPI_ADD64;
+    else
+      gy.mode = cpi::EPI_FINAL_ACC64;
+    CPI_HIP(cpi::gemm_correlate(gy, false, st), "gemm");
+  }
+  return CPI_OK;
+}
+
+cpi_status check_frames(const void* a, const void* b) {
+  if (!a || !b) return set_error(CPI_ERR_INVALID_ARG, "frame pointers must not be null");
+  if (!aligned16(a) || !aligned16(b))
+    return set_error(CPI_ERR_INVALID_ARG, "frame pointers must be 16-byte aligned");
+  return CPI_OK;
+}
+
+cpi_status check_refocus_args(const float* gamma, const cpi_geometry* g, const double* alphas,
+                              int32_t n_alpha, float* out, void* ws, size_t ws_bytes,
+                              cpi::RefocusPlan* pl) {
+  std::string why;
+  cpi_status s = cpi::plan_refocus(g, n_alpha, pl, &why);
+  if (s != CPI_OK) return set_error(s, why);
+  s = cpi::validate_alphas(g, alphas, n_alpha, &why);
+  if (s != CPI_OK) return set_error(s, why);
+  if (!gamma || !out || !ws) return set_error(CPI_ERR_INVALID_ARG, "null device pointer");
+  if (!aligned16(gamma) || !aligned16(out) || !aligned16(ws))
+    return set_error(CPI_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
+  if (ws_bytes < pl->total)
+    return set_error(CPI_ERR_WORKSPACE, "refocus workspace too small: need " +
+                                            std::to_string(pl->total) + " bytes");
+  return CPI_OK;
+}
+
+cpi_status enqueue_tables(const cpi_geometry* g, const double* alphas, int32_t n_alpha,
+                          const cpi::RefocusPlan& pl, uint8_t* ws, hipStream_t st) {
+  const cpi::RefGeom rg = ref_geom(g);
+  int32_t* itab = reinterpret_cast<int32_t*>(ws + pl.off_itab);
+  float* ftab = reinterpret_cast<float*>(ws + pl.off_ftab);
+  for (int first = 0; first < n_alpha; first += cpi::kAlphaPerLaunch) {
+    const int cnt = (n_alpha - first) < cpi::kAlphaPerLaunch ? n_alpha - first : cpi::kAlphaPerLaunch;
+    CPI_HIP(cpi::refocus_tables(rg, alphas, first, cnt, pl.table_stride, itab, ftab, st),
+            "refocus tables");
+  }
+  return CPI_OK;
+}
+
+}  // namespace
+
+namespace cpi {
+
+// Shared by the public refocus entry points and the autotuner.
+cpi_status refocus_enqueue(const float* gamma, const cpi_geometry* g, const double* alphas,
+                           int32_t n_alpha, float* out, void* workspace, size_t ws_bytes,
+                           hipStream_t st, const RefocusConfig* forced, bool plain) {
+  RefocusPlan pl;
+  cpi_status s = check_refocus_args(gamma, g, alphas, n_alpha, out, workspace, ws_bytes, &pl);
+  if (s != CPI_OK) return s;
+  uint8_t* ws = static_cast<uint8_t*>(workspace);
+  s = enqueue_tables(g, alphas, n_alpha, pl, ws, st);
+  if (s != CPI_OK) return s;
+  const RefGeom rg = ref_geom(g);
+  const int32_t* itab = reinterpret_cast<const int32_t*>(ws + pl.off_itab);
+  const float* ftab = reinterpret_cast<const float*>(ws + pl.off_ftab);
+  if (plain || g->wa < 2 || g->ha < 2) {
+    for (int k = 0; k < n_alpha; ++k)
+      CPI_HIP(refocus_plain(gamma, rg, itab, ftab, pl.table_stride, k, out, st), "refocus");
+    return CPI_OK;
+  }
+  RefocusConfig c = forced ? *forced : refocus_config_for(g, n_alpha);
+  float* partial = reinterpret_cast<float*>(ws + pl.off_partial);
+  CPI_HIP(refocus_batched(gamma, rg, itab, ftab, pl.table_stride, n_alpha, c, partial, out, st),
+          "refocus");
+  return CPI_OK;
+}
+
+}  // namespace cpi
+
+extern "C" {
+
+const char* cpi_version(void) { return "cpi-mi355x 0.1.0 (gfx950)"; }
+
+const char* cpi_status_string(cpi_status s) {
+  switch (s) {
+    case CPI_OK: return "CPI_OK";
+    case CPI_ERR_INVALID_ARG: return "CPI_ERR_INVALID_ARG";
+    case CPI_ERR_UNSUPPORTED: return "CPI_ERR_UNSUPPORTED";
+    case CPI_ERR_OVERFLOW: return "CPI_ERR_OVERFLOW";
+    case CPI_ERR_WORKSPACE: return "CPI_ERR_WORKSPACE";
+    case CPI_ERR_DEVICE: return "CPI_ERR_DEVICE";
+    case CPI_ERR_NOT_READY: return "CPI_ERR_NOT_READY";
+  }
+  return "CPI_ERR_UNKNOWN";
+}
+
+const char* cpi_last_error(void) { return g_last_error.c_str(); }
+
+cpi_status cpi_geometry_default(int32_t wa, int32_t ha, int32_t wb, int32_t hb, cpi_geometry* out) {
+  return guarded([&]() -> cpi_status {
+    if (!out) return set_error(CPI_ERR_INVALID_ARG, "out is null");
+    if (wa <= 0 || ha <= 0 || wb <= 0 || hb <= 0)
+      return set_error(CPI_ERR_INVALID_ARG, "sizes must be positive");
+    cpi_geometry g;
+    g.wa = wa;
+    g.ha = ha;
+    g.wb = wb;
+    g.hb = hb;
+    g.mag_x = double(wa) / double(wb);
+    g.mag_y = double(ha) / double(hb);
+    g.ca_x = (wa - 1) / 2.0;
+    g.ca_y = (ha - 1) / 2.0;
+    g.cb_x = (wb - 1) / 2.0;
+    g.cb_y = (hb - 1) / 2.0;
+    g.out_w = wa;
+    g.out_h = ha;
+    *out = g;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_correlate_workspace_size(int64_t n, int64_t pa, int64_t pb, cpi_frame_format fmt,
+                                        size_t* bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");
+    cpi::CorrPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_correlate(n, pa, pb, int(fmt), &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    *bytes = pl.total;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_correlate(const void* frames_a, const void* frames_b, int64_t n, int64_t pa,
+                         int64_t pb, cpi_frame_format fmt, cpi_gamma_layout layout,
+                         double* gamma, float* gamma_f32, int64_t* numer, int64_t* sum_a,
+                         int64_t* sum_b, void* workspace, size_t workspace_bytes,
+                         void* stream) {
+  return guarded([&]() -> cpi_status {
+    cpi::CorrPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_correlate(n, pa, pb, int(fmt), &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    s = check_frames(frames_a, frames_b);
+    if (s != CPI_OK) return s;
+    if (layout != CPI_GAMMA_VIEW_MAJOR && layout != CPI_GAMMA_PIXEL_MAJOR)
+      return set_error(CPI_ERR_INVALID_ARG, "unknown Gamma layout");
+    if (!gamma && !gamma_f32 && !numer)
+      return set_error(CPI_ERR_INVALID_ARG, "at least one of gamma, gamma_f32, numer is required");
+    const void* outs[5] = {gamma, gamma_f32, numer, sum_a, sum_b};
+    for (const void* o : outs)
+      if (o && !aligned16(o)) return set_error(CPI_ERR_INVALID_ARG, "outputs must be 16-byte aligned");
+    if (!workspace || !aligned16(workspace))
+      return set_error(CPI_ERR_INVALID_ARG, "workspace must be a 16-byte aligned device pointer");
+    if (workspace_bytes < pl.total)
+      return set_error(CPI_ERR_WORKSPACE,
+                       "correlate workspace too small: need " + std::to_string(pl.total) + " bytes");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    s = enqueue_correlate(pl, static_cast<const uint8_t*>(frames_a),
+                          static_cast<const uint8_t*>(frames_b), ws, int(layout), gamma,
+                          gamma_f32, numer, st);
+    if (s != CPI_OK) return s;
+    if (sum_a)
+      CPI_HIP(hipMemcpyAsync(sum_a, ws + pl.off_sum_a, size_t(pa) * 8, hipMemcpyDeviceToDevice, st),
+              "copy sums");
+    if (sum_b)
+      CPI_HIP(hipMemcpyAsync(sum_b, ws + pl.off_sum_b, size_t(pb) * 8, hipMemcpyDeviceToDevice, st),
+              "copy sums");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_correlate_f32_plain_workspace_size(int64_t n, int64_t pa, int64_t pb,
+                                                  cpi_frame_format fmt, size_t* bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");
+    cpi::PlainPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_correlate_plain(n, pa, pb, int(fmt), &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    *bytes = pl.total;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_correlate_f32_plain(const void* frames_a, const void* frames_b, int64_t n,
+                                   int64_t pa, int64_t pb, cpi_frame_format fmt,
+                                   cpi_gamma_layout layout, float* gamma_f32, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+  return guarded([&]() -> cpi_status {
+    cpi::PlainPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_correlate_plain(n, pa, pb, int(fmt), &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    s = check_frames(frames_a, frames_b);
+    if (s != CPI_OK) return s;
+    if (layout != CPI_GAMMA_VIEW_MAJOR && layout != CPI_GAMMA_PIXEL_MAJOR)
+      return set_error(CPI_ERR_INVALID_ARG, "unknown Gamma layout");
+    if (!gamma_f32 || !aligned16(gamma_f32))
+      return set_error(CPI_ERR_INVALID_ARG, "gamma_f32 must be a 16-byte aligned device pointer");
+    if (!workspace || !aligned16(workspace))
+      return set_error(CPI_ERR_INVALID_ARG, "workspace must be a 16-byte aligned device pointer");
+    if (workspace_bytes < pl.total)
+      return set_error(CPI_ERR_WORKSPACE,
+                       "plain workspace too small: need " + std::to_string(pl.total) + " bytes");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    float* fa = reinterpret_cast<float*>(ws + pl.off_fa);
+    float* fb = reinterpret_cast<float*>(ws + pl.off_fb);
+    float* sa = reinterpret_cast<float*>(ws + pl.off_sa);
+    float* sb = reinterpret_cast<float*>(ws + pl.off_sb);
+    CPI_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(sa), pl.pa_pad, 0, st), "fill");
+    CPI_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(sb), pl.pb_pad, 0, st), "fill");
+    CPI_HIP(cpi::unpack_f32(static_cast<const uint8_t*>(frames_a), int(fmt), n, pa, pl.kpad,
+                            pl.pa_pad, fa, sa, st),
+            "unpack");
+    CPI_HIP(cpi::unpack_f32(static_cast<const uint8_t*>(frames_b), int(fmt), n, pb, pl.kpad,
+                            pl.pb_pad, fb, sb, st),
+            "unpack");
+    CPI_HIP(cpi::sgemm_gamma(fb, fa, pl.kpad, pl.pb_pad, pl.pa_pad, pa, pb, n, sa, sb,
+                             int(layout), gamma_f32, st),
+            "sgemm");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_refocus_workspace_size(const cpi_geometry* g, int32_t n_alpha, size_t* bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");
+    cpi::RefocusPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_refocus(g, n_alpha, &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    *bytes = pl.total;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_refocus(const float* gamma, const cpi_geometry* g, const double* alphas,
+                       int32_t n_alpha, float* out, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+  return guarded([&]() -> cpi_status {
+    return cpi::refocus_enqueue(gamma, g, alphas, n_alpha, out, workspace, workspace_bytes,
+                                static_cast<hipStream_t>(stream), nullptr, false);
+  });
+}
+
+cpi_status cpi_refocus_plain(const float* gamma, const cpi_geometry* g, const double* alphas,
+                             int32_t n_alpha, float* out, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+  return guarded([&]() -> cpi_status {
+    return cpi::refocus_enqueue(gamma, g, alphas, n_alpha, out, workspace, workspace_bytes,
+                                static_cast<hipStream_t>(stream), nullptr, true);
+  });
+}
+
+cpi_status cpi_autotune_refocus(const float* gamma, const cpi_geometry* g, const double* alphas,
+                                int32_t n_alpha, float* out, void* workspace,
+                                size_t workspace_bytes, void* stream) {
+  return guarded([&]() -> cpi_status {
+    cpi::RefocusPlan pl;
+    cpi_status s = check_refocus_args(gamma, g, alphas, n_alpha, out, workspace, workspace_bytes, &pl);
+    if (s != CPI_OK) return s;
+    std::string why;
+    s = cpi::autotune_refocus(gamma, g, alphas, n_alpha, out, workspace, workspace_bytes,
+                              static_cast<hipStream_t>(stream), &why);
+    if (s != CPI_OK) return set_error(s, why);
+    return CPI_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Streaming
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct cpi_stream_s {
+  cpi::StreamPlan plan;
+  int64_t pa = 0, pb = 0;
+  int fmt = 0;
+  uint8_t* ws = nullptr;
+  hipStream_t st = nullptr;
+  int64_t n_total = 0;
+};
+
+namespace {
+
+constexpr uint64_t kStateMagic = 0x31415453495043ull;   // "CPISTA1"
+
+struct StateHeader {
+  uint64_t magic;
+  int64_t pa, pb, fmt, n_total;
+};
+
+size_t state_bytes(const cpi_stream_s* s) {
+  return sizeof(StateHeader) + size_t(s->pa) * 8 + size_t(s->pb) * 8 +
+         size_t(s->pa) * size_t(s->pb) * (s->plan.state64 ? 8 : 4);
+}
+
+cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t* fb, int64_t k) {
+  if (k <= 0 || k > h->plan.max_chunk)
+    return set_error(CPI_ERR_INVALID_ARG, "chunk size must be in [1, max_chunk]");
+  const int64_t n_new = h->n_total + k;
+  if (!cpi::overflow_ok(n_new, h->fmt))
+    return set_error(CPI_ERR_OVERFLOW, "total frame count would break the exact bounds");
+  if (h->fmt == CPI_FRAMES_BIT1 && n_new >= (int64_t(1) << 31))
+    return set_error(CPI_ERR_OVERFLOW, "int32 stream state limited to 2^31 - 1 frames");
+  cpi::CorrPlan cp;
+  std::string why;
+  cpi_status s = cpi::plan_correlate(k, h->pa, h->pb, h->fmt, &cp, &why);
+  if (s != CPI_OK) return set_error(s, why);
+  // The chunk plan uses this chunk's padding; offsets come from the
+  // max-chunk plan, whose regions are at least as large.
+  const cpi::CorrPlan& mp = h->plan.chunk;
+  uint8_t* cws = h->ws + h->plan.off_chunk_ws;
+  int64_t* csum_a = reinterpret_cast<int64_t*>(cws + mp.off_sum_a);
+  int64_t* csum_b = reinterpret_cast<int64_t*>(cws + mp.off_sum_b);
+  uint32_t* stats = reinterpret_cast<uint32_t*>(cws + mp.off_stats);
+  uint8_t* op_a = cws + mp.off_op_a;
+  uint8_t* op_b = cws + mp.off_op_b;
+  int64_t* tot_a = reinterpret_cast<int64_t*>(h->ws + h->plan.off_sum_a);
+  int64_t* tot_b = reinterpret_cast<int64_t*>(h->ws + h->plan.off_sum_b);
+  hipStream_t st = h->st;
+  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum_a), cp.pa_pad, 0, st), "fill");
+  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum_b), cp.pb_pad, 0, st), "fill");
+  CPI_HIP(cpi::fill_u32(stats, 64, 0, st), "fill");
+
+  cpi::GemmArgs g;
+  g.opm = op_b;
+  g.opn = op_a;
+  g.m_pad = cp.pb_pad;
+  g.n_pad = cp.pa_pad;
+  g.layout = CPI_GAMMA_VIEW_MAJOR;
+  g.pa = h->pa;
+  g.pb = h->pb;
+  g.n = n_new;
+  g.kchunk = k;
+  g.sum_a = tot_a;
+  g.sum_b = tot_b;
+  g.csum_a = csum_a;
+  g.csum_b = csum_b;
+  g.stats = stats;
+  g.gamma_f32 = reinterpret_cast<float*>(h->ws + h->plan.off_gamma32);
+
+  if (h->fmt == CPI_FRAMES_BIT1) {
+    CPI_HIP(cpi::ingest_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, st), "ingest");
+    CPI_HIP(cpi::ingest_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, st), "ingest");
+    CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
+    CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
+    g.row_bytes = cp.row_bytes_bits;
+    g.kblocks = cp.kpad_bits / cpi::kBitBlock;
+    g.mode = cpi::EPI_STREAM32;
+    g.acc32 = reinterpret_cast<int32_t*>(h->ws + h->plan.off_sab);
+    CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
+  } else {
+    CPI_HIP(cpi::u8_stats(fa, k, h->pa, csum_a, stats, st), "stats");
+    CPI_HIP(cpi::u8_stats(fb, k, h->pb, csum_b, stats, st), "stats");
+    CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
+    CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
+    CPI_HIP(cpi::u8_to_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, stats, st), "ingest");
+    CPI_HIP(cpi::u8_to_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, stats, st), "ingest");
+    CPI_HIP(cpi::u8_to_bytes(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bytes, stats, st), "ingest");
+    CPI_HIP(cpi::u8_to_bytes(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bytes, stats, st), "ingest");
+    g.mode = cpi::EPI_STREAM64;
+    g.acc64 = reinterpret_cast<int64_t*>(h->ws + h->plan.off_sab);
+    cpi::GemmArgs gb = g;
+    gb.row_bytes = cp.row_bytes_bits;
+    gb.kblocks = cp.kpad_bits / cpi::kBitBlock;
+    gb.cond = 1;
+    CPI_HIP(cpi::gemm_correlate(gb, true, st), "gemm");
+    cpi::GemmArgs gy = g;
+    gy.row_bytes = cp.row_bytes_bytes;
+    gy.kblocks = cp.kpad_bytes / cpi::kByteBlock;
+    gy.cond = 2;
+    gy.offset_from_stats = 1;
+    CPI_HIP(cpi::gemm_correlate(gy, false, st), "gemm");
+  }
+  h->n_total = n_new;
+  return CPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpi_status cpi_stream_workspace_size(int64_t pa, int64_t pb, cpi_frame_format fmt,
+                                     int64_t max_chunk, size_t* bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");
+    cpi::StreamPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_stream(pa, pb, int(fmt), max_chunk, &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    *bytes = pl.total;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t max_chunk,
+                             void* workspace, size_t bytes, void* stream, cpi_stream_t* out) {
+  return guarded([&]() -> cpi_status {
+    if (!out) return set_error(CPI_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    cpi::StreamPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_stream(pa, pb, int(fmt), max_chunk, &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    if (!workspace || !aligned16(workspace))
+      return set_error(CPI_ERR_INVALID_ARG, "workspace must be a 16-byte aligned device pointer");
+    if (bytes < pl.total)
+      return set_error(CPI_ERR_WORKSPACE,
+                       "stream workspace too small: need " + std::to_string(pl.total) + " bytes");
+    cpi_stream_s* h = new cpi_stream_s();
+    h->plan = pl;
+    h->pa = pa;
+    h->pb = pb;
+    h->fmt = int(fmt);
+    h->ws = static_cast<uint8_t*>(workspace);
+    h->st = static_cast<hipStream_t>(stream);
+    const int64_t sab_words = pa * pb * (pl.state64 ? 2 : 1);
+    hipError_t e = cpi::fill_u32(reinterpret_cast<uint32_t*>(h->ws + pl.off_sab), sab_words, 0, h->st);
+    if (e == hipSuccess)
+      e = cpi::fill_u64(reinterpret_cast<uint64_t*>(h->ws + pl.off_sum_a), pl.chunk.pa_pad, 0, h->st);
+    if (e == hipSuccess)
+      e = cpi::fill_u64(reinterpret_cast<uint64_t*>(h->ws + pl.off_sum_b), pl.chunk.pb_pad, 0, h->st);
+    if (e != hipSuccess) {
+      delete h;
+      return device_error(e, "stream init");
+    }
+    *out = h;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_stream_push(cpi_stream_t s, const void* chunk_a, const void* chunk_b, int64_t k) {
+  return guarded([&]() -> cpi_status {
+    if (!s) return set_error(CPI_ERR_INVALID_ARG, "stream handle is null");
+    cpi_status c = check_frames(chunk_a, chunk_b);
+    if (c != CPI_OK) return c;
+    return stream_push_device(s, static_cast<const uint8_t*>(chunk_a),
+                              static_cast<const uint8_t*>(chunk_b), k);
+  });
+}
+
+cpi_status cpi_stream_push_host(cpi_stream_t s, const void* chunk_a, const void* chunk_b,
+                                int64_t k) {
+  return guarded([&]() -> cpi_status {
+    if (!s) return set_error(CPI_ERR_INVALID_ARG, "stream handle is null");
+    if (!chunk_a || !chunk_b) return set_error(CPI_ERR_INVALID_ARG, "chunk pointers must not be null");
+    if (k <= 0 || k > s->plan.max_chunk)
+      return set_error(CPI_ERR_INVALID_ARG, "chunk size must be in [1, max_chunk]");
+    uint8_t* da = s->ws + s->plan.off_stage_a;
+    uint8_t* db = s->ws + s->plan.off_stage_b;
+    const size_t ba = size_t(k) * size_t(cpi::frame_bytes(s->pa, s->fmt));
+    const size_t bb = size_t(k) * size_t(cpi::frame_bytes(s->pb, s->fmt));
+    CPI_HIP(hipMemcpyAsync(da, chunk_a, ba, hipMemcpyHostToDevice, s->st), "copy chunk");
+    CPI_HIP(hipMemcpyAsync(db, chunk_b, bb, hipMemcpyHostToDevice, s->st), "copy chunk");
+    return stream_push_device(s, da, db, k);
+  });
+}
+
+cpi_status cpi_stream_frames(cpi_stream_t s, int64_t* n) {
+  return guarded([&]() -> cpi_status {
+    if (!s || !n) return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    *n = s->n_total;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_stream_gamma(cpi_stream_t s, cpi_gamma_layout layout, double* gamma,
+                            float* gamma_f32, int64_t* numer, int64_t* sum_a, int64_t* sum_b) {
+  return guarded([&]() -> cpi_status {
+    if (!s) return set_error(CPI_ERR_INVALID_ARG, "stream handle is null");
+    if (layout != CPI_GAMMA_VIEW_MAJOR && layout != CPI_GAMMA_PIXEL_MAJOR)
+      return set_error(CPI_ERR_INVALID_ARG, "unknown Gamma layout");
+    const void* outs[5] = {gamma, gamma_f32, numer, sum_a, sum_b};
+    for (const void* o : outs)
+      if (o && !aligned16(o)) return set_error(CPI_ERR_INVALID_ARG, "outputs must be 16-byte aligned");
+    if (s->n_total == 0) return set_error(CPI_ERR_NOT_READY, "no frames pushed yet");
+    const int64_t* ta = reinterpret_cast<const int64_t*>(s->ws + s->plan.off_sum_a);
+    const int64_t* tb = reinterpret_cast<const int64_t*>(s->ws + s->plan.off_sum_b);
+    if (gamma || gamma_f32 || numer)
+      CPI_HIP(cpi::state_gamma(s->ws + s->plan.off_sab, s->plan.state64, ta, tb, s->n_total, s->pa,
+                               s->pb, int(layout), gamma, gamma_f32, numer, s->st),
+              "stream gamma");
+    if (sum_a)
+      CPI_HIP(hipMemcpyAsync(sum_a, ta, size_t(s->pa) * 8, hipMemcpyDeviceToDevice, s->st), "copy sums");
+    if (sum_b)
+      CPI_HIP(hipMemcpyAsync(sum_b, tb, size_t(s->pb) * 8, hipMemcpyDeviceToDevice, s->st), "copy sums");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_stream_gamma_f32_ptr(cpi_stream_t s, const float** gamma_f32) {
+  return guarded([&]() -> cpi_status {
+    if (!s || !gamma_f32) return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    *gamma_f32 = reinterpret_cast<const float*>(s->ws + s->plan.off_gamma32);
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_stream_refocus(cpi_stream_t s, const cpi_geometry* g, const double* alphas,
+                              int32_t n_alpha, float* out, void* workspace,
+                              size_t workspace_bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!s) return set_error(CPI_ERR_INVALID_ARG, "stream handle is null");
+    if (s->n_total == 0) return set_error(CPI_ERR_NOT_READY, "no frames pushed yet");
+    if (g && (int64_t(g->wa) * g->ha != s->pa || int64_t(g->wb) * g->hb != s->pb))
+      return set_error(CPI_ERR_INVALID_ARG, "geometry does not match the stream's detectors");
+    return cpi::refocus_enqueue(reinterpret_cast<const float*>(s->ws + s->plan.off_gamma32), g,
+                                alphas, n_alpha, out, workspace, workspace_bytes, s->st, nullptr,
+                                false);
+  });
+}
+
+cpi_status cpi_stream_state_size(cpi_stream_t s, size_t* bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!s || !bytes) return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    *bytes = state_bytes(s);
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_stream_save(cpi_stream_t s, void* host_buf, size_t bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!s || !host_buf) return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    if (bytes < state_bytes(s)) return set_error(CPI_ERR_INVALID_ARG, "state buffer too small");
+    uint8_t* dst = static_cast<uint8_t*>(host_buf);
+    StateHeader hd{kStateMagic, s->pa, s->pb, s->fmt, s->n_total};
+    std::memcpy(dst, &hd, sizeof(hd));
+    size_t off = sizeof(hd);
+    CPI_HIP(hipMemcpyAsync(dst + off, s->ws + s->plan.off_sum_a, size_t(s->pa) * 8,
+                           hipMemcpyDeviceToHost, s->st), "save");
+    off += size_t(s->pa) * 8;
+    CPI_HIP(hipMemcpyAsync(dst + off, s->ws + s->plan.off_sum_b, size_t(s->pb) * 8,
+                           hipMemcpyDeviceToHost, s->st), "save");
+    off += size_t(s->pb) * 8;
+    CPI_HIP(hipMemcpyAsync(dst + off, s->ws + s->plan.off_sab,
+                           size_t(s->pa) * size_t(s->pb) * (s->plan.state64 ? 8 : 4),
+                           hipMemcpyDeviceToHost, s->st), "save");
+    CPI_HIP(hipStreamSynchronize(s->st), "save");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_stream_load(cpi_stream_t s, const void* host_buf, size_t bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!s || !host_buf) return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    if (bytes < state_bytes(s)) return set_error(CPI_ERR_INVALID_ARG, "state buffer too small");
+    const uint8_t* src = static_cast<const uint8_t*>(host_buf);
+    StateHeader hd;
+    std::memcpy(&hd, src, sizeof(hd));
+    if (hd.magic != kStateMagic || hd.pa != s->pa || hd.pb != s->pb || hd.fmt != s->fmt ||
+        hd.n_total < 0 || (hd.n_total > 0 && !cpi::overflow_ok(hd.n_total, s->fmt)))
+      return set_error(CPI_ERR_INVALID_ARG, "checkpoint does not match this stream");
+    size_t off = sizeof(hd);
+    CPI_HIP(hipMemcpyAsync(s->ws + s->plan.off_sum_a, src + off, size_t(s->pa) * 8,
+                           hipMemcpyHostToDevice, s->st), "load");
+    off += size_t(s->pa) * 8;
+    CPI_HIP(hipMemcpyAsync(s->ws + s->plan.off_sum_b, src + off, size_t(s->pb) * 8,
+                           hipMemcpyHostToDevice, s->st), "load");
+    off += size_t(s->pb) * 8;
+    CPI_HIP(hipMemcpyAsync(s->ws + s->plan.off_sab, src + off,
+                           size_t(s->pa) * size_t(s->pb) * (s->plan.state64 ? 8 : 4),
+                           hipMemcpyHostToDevice, s->st), "load");
+    s->n_total = hd.n_total;
+    if (s->n_total > 0) {
+      const int64_t* ta = reinterpret_cast<const int64_t*>(s->ws + s->plan.off_sum_a);
+      const int64_t* tb = reinterpret_cast<const int64_t*>(s->ws + s->plan.off_sum_b);
+      CPI_HIP(cpi::state_gamma(s->ws + s->plan.off_sab, s->plan.state64, ta, tb, s->n_total, s->pa,
+                               s->pb, CPI_GAMMA_VIEW_MAJOR, nullptr,
+                               reinterpret_cast<float*>(s->ws + s->plan.off_gamma32), nullptr, s->st),
+              "load");
+    }
+    CPI_HIP(hipStreamSynchronize(s->st), "load");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_stream_destroy(cpi_stream_t s) {
+  return guarded([&]() -> cpi_status {
+    delete s;
+    return CPI_OK;
+  });
+}
+
+}  // extern "C"

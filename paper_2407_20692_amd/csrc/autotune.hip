@@ -1,0 +1,183 @@
+// Refocus autotuner.  The paper sizes its refocusing blocks from the device
+// memory available (Section 4.1); here the work decomposition of the batched
+// kernel (planes per work-group, output rows per wave, view-row splits) is
+// chosen by timing the candidates on the caller's inputs.  Results are kept
+// per (shape, device) in memory and, when CPI_AUTOTUNE_CACHE names a file, in
+// a text cache of lines "key kp rw splits microseconds".
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "autotune.h"
+#include "plan.h"
+
+namespace cpi {
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, RefocusConfig> g_cache;
+bool g_loaded = false;
+
+int log_level() {
+  const char* v = std::getenv("CPI_LOG_LEVEL");
+  return v ? std::atoi(v) : 0;
+}
+
+std::string device_tag() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "dev?";
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "dev?";
+  std::ostringstream os;
+  os << p.gcnArchName << "/cu" << p.multiProcessorCount;
+  std::string s = os.str();
+  for (char& c : s)
+    if (c == ' ' || c == ':') c = '_';
+  return s;
+}
+
+std::string shape_key(const cpi_geometry* g, int32_t n_alpha) {
+  std::ostringstream os;
+  os << "wa" << g->wa << "_ha" << g->ha << "_wb" << g->wb << "_hb" << g->hb << "_ow" << g->out_w
+     << "_oh" << g->out_h << "_na" << n_alpha << "@" << device_tag();
+  return os.str();
+}
+
+// Loads the cache file once; a malformed file is ignored as a whole.
+void load_cache_locked() {
+  if (g_loaded) return;
+  g_loaded = true;
+  const char* path = std::getenv("CPI_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  if (!f) return;
+  std::map<std::string, RefocusConfig> tmp;
+  std::string line;
+  while (std::getline(f, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream is(line);
+    std::string key;
+    RefocusConfig c;
+    double us = 0;
+    if (!(is >> key >> c.kp >> c.rw >> c.splits >> us) || !refocus_config_supported(c)) {
+      if (log_level() > 0)
+        std::fprintf(stderr, "cpi: ignoring malformed autotune cache %s\n", path);
+      return;
+    }
+    tmp[key] = c;
+  }
+  g_cache.insert(tmp.begin(), tmp.end());
+}
+
+void store_cache_locked(const std::string& key, const RefocusConfig& c, double us) {
+  g_cache[key] = c;
+  const char* path = std::getenv("CPI_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << ' ' << c.kp << ' ' << c.rw << ' ' << c.splits << ' ' << us << '\n';
+}
+
+int64_t workgroups(const cpi_geometry* g, int32_t n_alpha, const RefocusConfig& c) {
+  const int64_t tx = (g->out_w + 63) / 64;
+  const int64_t ty = (g->out_h + 4 * c.rw - 1) / (4 * c.rw);
+  const int64_t gr = (n_alpha + c.kp - 1) / c.kp;
+  return tx * ty * gr * c.splits;
+}
+
+}  // namespace
+
+RefocusConfig default_refocus_config(const cpi_geometry* g, int32_t n_alpha) {
+  RefocusConfig c;
+  c.kp = n_alpha >= 8 ? 8 : (n_alpha >= 4 ? 4 : (n_alpha >= 2 ? 2 : 1));
+  c.rw = g->out_h >= 16 ? 4 : (g->out_h >= 8 ? 2 : 1);
+  c.splits = 1;
+  const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
+  while (c.splits * 2 <= max_splits && workgroups(g, n_alpha, c) < 1024) c.splits *= 2;
+  return c;
+}
+
+RefocusConfig refocus_config_for(const cpi_geometry* g, int32_t n_alpha) {
+  const std::string key = shape_key(g, n_alpha);
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_cache_locked();
+  auto it = g_cache.find(key);
+  if (it != g_cache.end()) {
+    RefocusConfig c = it->second;
+    const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
+    if (c.splits > max_splits) c.splits = max_splits;
+    return c;
+  }
+  return default_refocus_config(g, n_alpha);
+}
+
+cpi_status autotune_refocus(const float* gamma, const cpi_geometry* g, const double* alphas,
+                            int32_t n_alpha, float* out, void* ws, size_t ws_bytes,
+                            hipStream_t st, std::string* why) {
+  std::vector<RefocusConfig> cands;
+  const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
+  for (int kp : {1, 2, 4, 8})
+    for (int rw : {1, 2, 4, 8})
+      for (int sp = 1; sp <= max_splits; sp *= 2) {
+        RefocusConfig c{kp, rw, sp};
+        if (!refocus_config_supported(c)) continue;
+        if (kp > 1 && kp / 2 >= n_alpha) continue;        // planes beyond n_alpha
+        if (rw > 1 && 4 * rw / 2 >= g->out_h) continue;   // rows beyond out_h
+        cands.push_back(c);
+      }
+  if (g->wa < 2 || g->ha < 2) cands.clear();
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (why) *why = "autotune: cannot create events";
+    return CPI_ERR_DEVICE;
+  }
+  RefocusConfig best = default_refocus_config(g, n_alpha);
+  double best_us = 1e300;
+  for (const RefocusConfig& c : cands) {
+    cpi_status s = refocus_enqueue(gamma, g, alphas, n_alpha, out, ws, ws_bytes, st, &c, false);
+    if (s != CPI_OK) continue;
+    const int reps = 3;
+    hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r)
+      refocus_enqueue(gamma, g, alphas, n_alpha, out, ws, ws_bytes, st, &c, false);
+    hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      if (why) *why = "autotune: device failure while timing";
+      return CPI_ERR_DEVICE;
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    const double us = 1000.0 * ms / reps;
+    if (log_level() > 1)
+      std::fprintf(stderr, "cpi: autotune kp=%d rw=%d splits=%d %.1f us\n", c.kp, c.rw, c.splits, us);
+    if (us < best_us) {
+      best_us = us;
+      best = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache_locked();
+    store_cache_locked(shape_key(g, n_alpha), best, best_us);
+  }
+  cpi_status s = refocus_enqueue(gamma, g, alphas, n_alpha, out, ws, ws_bytes, st, &best, false);
+  if (s != CPI_OK) return s;
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    if (why) *why = "autotune: device failure";
+    return CPI_ERR_DEVICE;
+  }
+  return CPI_OK;
+}
+
+}  // namespace cpi

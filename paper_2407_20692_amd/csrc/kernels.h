@@ -1,0 +1,111 @@
+// Device kernels of the CPI library and their host-side launchers.
+// Every launcher only enqueues work on `stream` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.h"
+
+namespace cpi {
+
+// ---- fills --------------------------------------------------------------
+hipError_t fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
+hipError_t fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
+hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t s);
+
+// ---- ingest: frame-major frames -> pixel-major operands ------------------
+// Packed-bit frames -> bit rows (row_bytes = kpad_bits/8), per-pixel popcounts
+// added into sums (int64).  Rows [npix, npix_pad) are written too.
+hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
+                       uint8_t* out, int64_t kpad_bits, int64_t* sums, hipStream_t s);
+// Byte frames: per-pixel sums (int64, added) and the maximum byte (atomic max
+// into stats[0]).
+hipError_t u8_stats(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
+                    uint32_t* stats, hipStream_t s);
+// Byte frames -> bit rows, enqueued unconditionally but executed only when
+// stats[0] <= 1 (binary data).
+hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
+                      uint8_t* out, int64_t kpad_bits, const uint32_t* stats, hipStream_t s);
+// Byte frames -> int8 rows (row_bytes = kpad_bytes), executed only when
+// stats[0] > 1; values are offset by -128 when stats[0] > 127; pads are 0.
+hipError_t u8_to_bytes(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
+                       uint8_t* out, int64_t kpad_bytes, const uint32_t* stats,
+                       hipStream_t s);
+
+// ---- int8 MFMA contraction with the exact epilogue -----------------------
+enum EpiMode : int {
+  EPI_FINAL = 0,        // Gamma from this pass's int32 sums
+  EPI_FINAL_ACC64 = 1,  // Gamma from acc64 + this pass
+  EPI_STORE64 = 2,      // acc64 = this pass
+  EPI_ADD64 = 3,        // acc64 += this pass
+  EPI_STREAM32 = 4,     // acc32 += this chunk; gamma_f32 from acc32
+  EPI_STREAM64 = 5      // acc64 += un-offset chunk sums; gamma_f32 from acc64
+};
+
+struct GemmArgs {
+  const uint8_t* opm = nullptr;     // M rows: detector-B pixels (views)
+  const uint8_t* opn = nullptr;     // N rows: detector-A pixels
+  int64_t row_bytes = 0;
+  int64_t k_byte_off = 0;           // first byte of this pass in every row
+  int64_t kblocks = 0;              // 64-byte row segments in this pass
+  int64_t m_pad = 0, n_pad = 0;     // padded operand rows
+  int mode = EPI_FINAL;
+  int layout = CPI_GAMMA_VIEW_MAJOR;
+  int cond = 0;                     // 0 always; 1 iff stats[0] <= 1; 2 iff stats[0] > 1
+  int offset_from_stats = 0;        // byte operands offset by -128 iff stats[0] > 127
+  int64_t pa = 0, pb = 0, n = 0;    // n: frames behind the result
+  int64_t kchunk = 0;               // frames of this chunk (EPI_STREAM64)
+  const int64_t* sum_a = nullptr;   // S_a, S_b of the result (raw, un-offset)
+  const int64_t* sum_b = nullptr;
+  const int64_t* csum_a = nullptr;  // chunk sums (EPI_STREAM64)
+  const int64_t* csum_b = nullptr;
+  const uint32_t* stats = nullptr;
+  double* gamma = nullptr;
+  float* gamma_f32 = nullptr;
+  int64_t* numer = nullptr;
+  int64_t* acc64 = nullptr;         // view-major Pb x Pa
+  int32_t* acc32 = nullptr;         // view-major Pb x Pa
+};
+
+// bits: operands are bit rows; otherwise int8 rows.
+hipError_t gemm_correlate(const GemmArgs& a, bool bits, hipStream_t s);
+
+// Gamma from a streaming state (view-major int32 or int64 S_ab, raw sums).
+hipError_t state_gamma(const void* sab, bool sab64, const int64_t* sum_a, const int64_t* sum_b,
+                       int64_t n, int64_t pa, int64_t pb, int layout, double* gamma,
+                       float* gamma_f32, int64_t* numer, hipStream_t s);
+
+// ---- plain FP32 path ------------------------------------------------------
+hipError_t unpack_f32(const uint8_t* frames, int fmt, int64_t n, int64_t npix, int64_t kpad,
+                      int64_t cols_pad, float* out, float* colsum, hipStream_t s);
+hipError_t sgemm_gamma(const float* fb, const float* fa, int64_t kpad, int64_t pb_pad,
+                       int64_t pa_pad, int64_t pa, int64_t pb, int64_t n, const float* sa,
+                       const float* sb, int layout, float* out, hipStream_t s);
+
+// ---- refocus -------------------------------------------------------------
+struct RefGeom {
+  int wa, ha, wb, hb, out_w, out_h;
+  double mag_x, mag_y, ca_x, ca_y, cb_x, cb_y;
+};
+
+// Per-plane coordinate tables for planes [first, first+count), count <= 64.
+hipError_t refocus_tables(const RefGeom& g, const double* alphas, int first, int count,
+                          int64_t stride, int32_t* itab, float* ftab, hipStream_t s);
+hipError_t refocus_plain(const float* gamma, const RefGeom& g, const int32_t* itab,
+                         const float* ftab, int64_t stride, int plane, float* out,
+                         hipStream_t s);
+
+struct RefocusConfig {
+  int kp = 8;        // planes per work-group
+  int rw = 4;        // output rows per wave
+  int splits = 1;    // view-row splits (partial sums reduced afterwards)
+};
+bool refocus_config_supported(const RefocusConfig& c);
+hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* itab,
+                           const float* ftab, int64_t stride, int n_alpha,
+                           const RefocusConfig& c, float* partial, float* out,
+                           hipStream_t s);
+
+}  // namespace cpi

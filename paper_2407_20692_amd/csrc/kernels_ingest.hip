@@ -1,0 +1,383 @@
+// Ingest: frame-major detector frames -> pixel-major contraction operands.
+//
+// The sums of Eq. (1) run over frames, so the contraction dimension of
+// S_ab = A^T B is the frame index.  Matrix-core operands want that dimension
+// contiguous per pixel, so every frame block is transposed once here:
+//   * binary frames become bit rows: bit j of 32-bit word w of row p is the
+//     value of pixel p in frame 32*w + j (the paper's bit packing, Section 4.1);
+//   * other byte frames become int8 rows, offset by -128 when a value exceeds
+//     127 (this leaves the numerator of Eq. (1) unchanged).
+// Per-pixel sums S_a, S_b are produced on the way.  Frames beyond n and
+// pixels beyond npix read as zero, so padded rows and columns contribute
+// nothing to any product.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "kernels.h"
+
+namespace cpi {
+
+namespace {
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t count, uint64_t v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_add_i64(int64_t* __restrict__ dst, const int64_t* __restrict__ src,
+                          int64_t count) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] += src[i];
+}
+
+// Lane-indexed insert of a wave-uniform value: lane L of `old` becomes v.
+template <int L>
+__device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t v) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(v), "i"(L));
+  return old;
+}
+
+// Bit of pixel J (0..127) in this lane's frame: 16 packed bytes or 128 bytes.
+template <int J>
+__device__ __forceinline__ uint32_t pixel_bit(const uint32_t (&d)[4]) {
+  return (d[J >> 5] >> (J & 31)) & 1u;
+}
+template <int J>
+__device__ __forceinline__ uint32_t pixel_bit(const uint32_t (&d)[32]) {
+  return (d[J >> 2] >> (8 * (J & 3))) & 0xffu;
+}
+
+// One ballot per pixel J: bit l of the result is pixel J in frame f0 + l.
+// Pixel J's 64 frame bits go to lane J % 64, words 2*SUB, 2*SUB+1 of half J/64.
+template <int SUB, int J, int ND>
+__device__ __forceinline__ void ballot_pixel(const uint32_t (&d)[ND], uint32_t (&w0)[16],
+                                             uint32_t (&w1)[16]) {
+  const unsigned long long m = __ballot(pixel_bit<J>(d));
+  const uint32_t lo = uint32_t(m), hi = uint32_t(m >> 32);
+  if constexpr (J < 64) {
+    w0[2 * SUB] = write_lane<J>(w0[2 * SUB], lo);
+    w0[2 * SUB + 1] = write_lane<J>(w0[2 * SUB + 1], hi);
+  } else {
+    w1[2 * SUB] = write_lane<J - 64>(w1[2 * SUB], lo);
+    w1[2 * SUB + 1] = write_lane<J - 64>(w1[2 * SUB + 1], hi);
+  }
+}
+
+template <int SUB, int ND, int... J>
+__device__ __forceinline__ void ballot_all(const uint32_t (&d)[ND], uint32_t (&w0)[16],
+                                           uint32_t (&w1)[16], std::integer_sequence<int, J...>) {
+  (ballot_pixel<SUB, J, ND>(d, w0, w1), ...);
+}
+
+// Loads the lane's frame data for sub-block SUB and transposes it.
+template <int SUB, int ND, typename Load>
+__device__ __forceinline__ void transpose_sub(Load&& load, uint32_t (&w0)[16],
+                                              uint32_t (&w1)[16]) {
+  uint32_t d[ND];
+  load(SUB, d);
+  ballot_all<SUB, ND>(d, w0, w1, std::make_integer_sequence<int, 128>{});
+}
+
+template <int ND, typename Load, int... S>
+__device__ __forceinline__ void transpose_block(Load&& load, uint32_t (&w0)[16],
+                                                uint32_t (&w1)[16],
+                                                std::integer_sequence<int, S...>) {
+  (transpose_sub<S, ND>(load, w0, w1), ...);
+}
+
+unsigned grid_for(int64_t count, int threads) {
+  int64_t g = (count + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return unsigned(g);
+}
+
+// Packed-bit frames -> bit rows.  One wave owns 128 pixels and a slice of
+// 512-frame blocks.  Lane l reads the 16 bytes (128 pixels) of frame
+// f0 + l; one wave ballot per pixel then yields that pixel's 64 frame bits,
+// which v_writelane drops into the register of the lane that owns the pixel
+// (pixel j -> lane j % 64, half j / 64).
+__global__ __launch_bounds__(64) void k_ingest_bits(
+    const uint8_t* __restrict__ frames, int64_t n, int64_t fbytes, uint32_t* __restrict__ out,
+    int64_t kw, int64_t nblocks, int64_t blocks_per_slice,
+    unsigned long long* __restrict__ sums) {
+  const int lane = threadIdx.x;
+  const int64_t p0 = int64_t(blockIdx.x) * 128;
+  const int64_t byte0 = p0 >> 3;
+  const int64_t kb0 = int64_t(blockIdx.y) * blocks_per_slice;
+  int64_t kb1 = kb0 + blocks_per_slice;
+  if (kb1 > nblocks) kb1 = nblocks;
+  const bool vec = ((fbytes & 15) == 0) && (byte0 + 16 <= fbytes);
+  unsigned long long s0 = 0, s1 = 0;
+  for (int64_t kb = kb0; kb < kb1; ++kb) {
+    uint32_t w0[16], w1[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      w0[i] = 0;
+      w1[i] = 0;
+    }
+    auto load = [&](int sub, uint32_t(&d)[4]) {
+      d[0] = d[1] = d[2] = d[3] = 0u;
+      const int64_t f = kb * 512 + sub * 64 + lane;
+      if (f < n) {
+        const uint8_t* src = frames + f * fbytes + byte0;
+        if (vec) {
+          const uint4 v = *reinterpret_cast<const uint4*>(src);
+          d[0] = v.x;
+          d[1] = v.y;
+          d[2] = v.z;
+          d[3] = v.w;
+        } else {
+          for (int b = 0; b < 16; ++b)
+            if (byte0 + b < fbytes) d[b >> 2] |= uint32_t(src[b]) << (8 * (b & 3));
+        }
+      }
+    };
+    transpose_block<4>(load, w0, w1, std::make_integer_sequence<int, 8>{});
+    uint4* o0 = reinterpret_cast<uint4*>(out + (p0 + lane) * kw + kb * 16);
+    uint4* o1 = reinterpret_cast<uint4*>(out + (p0 + 64 + lane) * kw + kb * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      o0[q] = make_uint4(w0[4 * q], w0[4 * q + 1], w0[4 * q + 2], w0[4 * q + 3]);
+      o1[q] = make_uint4(w1[4 * q], w1[4 * q + 1], w1[4 * q + 2], w1[4 * q + 3]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      s0 += __popc(w0[i]);
+      s1 += __popc(w1[i]);
+    }
+  }
+  atomicAdd(&sums[p0 + lane], s0);
+  atomicAdd(&sums[p0 + 64 + lane], s1);
+}
+
+// Byte frames -> bit rows (only when every byte is 0 or 1).  As k_ingest_bits,
+// with each lane reading 128 bytes of its frame.
+__global__ __launch_bounds__(64) void k_u8_to_bits(
+    const uint8_t* __restrict__ frames, int64_t n, int64_t npix, uint32_t* __restrict__ out,
+    int64_t kw, int64_t nblocks, int64_t blocks_per_slice, const uint32_t* __restrict__ stats) {
+  if (stats[0] > 1u) return;
+  const int lane = threadIdx.x;
+  const int64_t p0 = int64_t(blockIdx.x) * 128;
+  const int64_t kb0 = int64_t(blockIdx.y) * blocks_per_slice;
+  int64_t kb1 = kb0 + blocks_per_slice;
+  if (kb1 > nblocks) kb1 = nblocks;
+  const bool vec = ((npix & 15) == 0) && (p0 + 128 <= npix);
+  for (int64_t kb = kb0; kb < kb1; ++kb) {
+    uint32_t w0[16], w1[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      w0[i] = 0;
+      w1[i] = 0;
+    }
+    auto load = [&](int sub, uint32_t(&d)[32]) {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) d[i] = 0u;
+      const int64_t f = kb * 512 + sub * 64 + lane;
+      if (f < n) {
+        const uint8_t* src = frames + f * npix + p0;
+        if (vec) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const uint4 v = reinterpret_cast<const uint4*>(src)[q];
+            d[4 * q] = v.x;
+            d[4 * q + 1] = v.y;
+            d[4 * q + 2] = v.z;
+            d[4 * q + 3] = v.w;
+          }
+        } else {
+          for (int b = 0; b < 128; ++b)
+            if (p0 + b < npix) d[b >> 2] |= uint32_t(src[b]) << (8 * (b & 3));
+        }
+      }
+    };
+    transpose_block<32>(load, w0, w1, std::make_integer_sequence<int, 8>{});
+    uint4* o0 = reinterpret_cast<uint4*>(out + (p0 + lane) * kw + kb * 16);
+    uint4* o1 = reinterpret_cast<uint4*>(out + (p0 + 64 + lane) * kw + kb * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      o0[q] = make_uint4(w0[4 * q], w0[4 * q + 1], w0[4 * q + 2], w0[4 * q + 3]);
+      o1[q] = make_uint4(w1[4 * q], w1[4 * q + 1], w1[4 * q + 2], w1[4 * q + 3]);
+    }
+  }
+}
+
+// Per-pixel sums and the maximum byte.  A thread owns 16 consecutive pixels
+// and a slice of frames; its partial sums stay in uint32 (a slice holds at
+// most 2^24 frames of values <= 255).
+__global__ __launch_bounds__(256) void k_u8_stats(const uint8_t* __restrict__ frames, int64_t n,
+                                                  int64_t npix, int64_t frames_per_slice,
+                                                  unsigned long long* __restrict__ sums,
+                                                  uint32_t* __restrict__ stats) {
+  const int64_t px = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 16;
+  const int64_t f0 = int64_t(blockIdx.y) * frames_per_slice;
+  int64_t f1 = f0 + frames_per_slice;
+  if (f1 > n) f1 = n;
+  uint32_t s[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) s[b] = 0;
+  uint32_t mx = 0;
+  if (px < npix) {
+    const bool vec = ((npix & 15) == 0);
+    for (int64_t f = f0; f < f1; ++f) {
+      const uint8_t* src = frames + f * npix + px;
+      uint32_t d[4] = {0u, 0u, 0u, 0u};
+      if (vec) {
+        const uint4 v = *reinterpret_cast<const uint4*>(src);
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+      } else {
+        for (int b = 0; b < 16; ++b)
+          if (px + b < npix) d[b >> 2] |= uint32_t(src[b]) << (8 * (b & 3));
+      }
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const uint32_t v = (d[b >> 2] >> (8 * (b & 3))) & 0xffu;
+        s[b] += v;
+        mx = v > mx ? v : mx;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      if (px + b < npix && s[b]) atomicAdd(&sums[px + b], (unsigned long long)s[b]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(mx, off, 64);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0 && mx) atomicMax(stats, mx);
+}
+
+// Byte frames -> int8 rows through a 64 x 64 LDS tile (only when some byte
+// exceeds 1).  Pads (frames >= n, pixels >= npix) are written as 0, the
+// value of "no photon" in the offset domain.
+__global__ __launch_bounds__(256) void k_u8_to_bytes(const uint8_t* __restrict__ frames,
+                                                     int64_t n, int64_t npix,
+                                                     uint8_t* __restrict__ out, int64_t kpad,
+                                                     const uint32_t* __restrict__ stats) {
+  const uint32_t mx = stats[0];
+  if (mx <= 1u) return;
+  const uint32_t xo = mx > 127u ? 0x80u : 0u;
+  __shared__ uint8_t tile[64][64 + 4];
+  const int t = threadIdx.x;
+  const int64_t p0 = int64_t(blockIdx.x) * 64;
+  const int64_t f0 = int64_t(blockIdx.y) * 64;
+  {
+    const int fl = t >> 2, pc = (t & 3) * 16;
+    const int64_t f = f0 + fl;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const int64_t p = p0 + pc + b;
+      uint32_t v = 0;
+      if (f < n && p < npix) v = uint32_t(frames[f * npix + p]) ^ xo;
+      tile[fl][pc + b] = uint8_t(v);
+    }
+  }
+  __syncthreads();
+  {
+    const int pl = t >> 2, fc = (t & 3) * 16;
+    uint32_t d[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int b = 0; b < 16; ++b) d[b >> 2] |= uint32_t(tile[fc + b][pl]) << (8 * (b & 3));
+    *reinterpret_cast<uint4*>(out + (p0 + pl) * kpad + f0 + fc) = make_uint4(d[0], d[1], d[2], d[3]);
+  }
+}
+
+int64_t slices_for(int64_t groups, int64_t nblocks, int64_t target_waves) {
+  int64_t s = (target_waves + groups - 1) / groups;
+  if (s < 1) s = 1;
+  if (s > nblocks) s = nblocks;
+  if (s > 65535) s = 65535;
+  return s;
+}
+
+}  // namespace
+
+hipError_t fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_i64, dim3(grid_for(count, 256)), dim3(256), 0, s, dst, src, count);
+  return hipGetLastError();
+}
+
+hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
+                       uint8_t* out, int64_t kpad_bits, int64_t* sums, hipStream_t s) {
+  const int64_t groups = npix_pad / 128;
+  const int64_t nblocks = kpad_bits / 512;
+  const int64_t slices = slices_for(groups, nblocks, 8192);
+  const int64_t bps = (nblocks + slices - 1) / slices;
+  const int64_t used = (nblocks + bps - 1) / bps;
+  hipLaunchKernelGGL(k_ingest_bits, dim3(unsigned(groups), unsigned(used)), dim3(64), 0, s,
+                     frames, n, (npix + 7) / 8, reinterpret_cast<uint32_t*>(out), kpad_bits / 32,
+                     nblocks, bps, reinterpret_cast<unsigned long long*>(sums));
+  return hipGetLastError();
+}
+
+hipError_t u8_stats(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
+                    uint32_t* stats, hipStream_t s) {
+  const int64_t groups = (npix + 4095) / 4096;
+  int64_t slices = (2048 + groups - 1) / groups;
+  if (slices > n) slices = n;
+  int64_t fps = (n + slices - 1) / slices;
+  if (fps > (int64_t(1) << 24)) fps = int64_t(1) << 24;
+  slices = (n + fps - 1) / fps;
+  hipLaunchKernelGGL(k_u8_stats, dim3(unsigned(groups), unsigned(slices)), dim3(256), 0, s,
+                     frames, n, npix, fps, reinterpret_cast<unsigned long long*>(sums), stats);
+  return hipGetLastError();
+}
+
+hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
+                      uint8_t* out, int64_t kpad_bits, const uint32_t* stats, hipStream_t s) {
+  const int64_t groups = npix_pad / 128;
+  const int64_t nblocks = kpad_bits / 512;
+  const int64_t slices = slices_for(groups, nblocks, 8192);
+  const int64_t bps = (nblocks + slices - 1) / slices;
+  const int64_t used = (nblocks + bps - 1) / bps;
+  hipLaunchKernelGGL(k_u8_to_bits, dim3(unsigned(groups), unsigned(used)), dim3(64), 0, s,
+                     frames, n, npix, reinterpret_cast<uint32_t*>(out), kpad_bits / 32, nblocks,
+                     bps, stats);
+  return hipGetLastError();
+}
+
+hipError_t u8_to_bytes(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
+                       uint8_t* out, int64_t kpad_bytes, const uint32_t* stats,
+                       hipStream_t s) {
+  const int64_t gx = npix_pad / 64;
+  const int64_t gy = kpad_bytes / 64;
+  if (gy > 65535) {
+    // The frame axis of the grid is limited; cover it in several launches.
+    for (int64_t y0 = 0; y0 < gy; y0 += 65535) {
+      const int64_t cnt = (gy - y0) < 65535 ? (gy - y0) : 65535;
+      const int64_t fo = y0 * 64;
+      hipLaunchKernelGGL(k_u8_to_bytes, dim3(unsigned(gx), unsigned(cnt)), dim3(256), 0, s,
+                         frames + fo * npix, n - fo, npix, out + fo, kpad_bytes, stats);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipLaunchKernelGGL(k_u8_to_bytes, dim3(unsigned(gx), unsigned(gy)), dim3(256), 0, s, frames, n,
+                     npix, out, kpad_bytes, stats);
+  return hipGetLastError();
+}
+
+}  // namespace cpi

@@ -1,0 +1,170 @@
+"""GPU parity of refocusing (batched, plain and autotuned) against the FP64
+oracle.  Tolerance: per plane, max |I_gpu - I_oracle| / max |I_oracle|
+<= 1e-5, with I_oracle computed from the oracle's FP64 Gamma."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import WORKLOADS, alphas_for, generate_frames
+from tests.gpu_util import dev, log, plane_rel_err, to_dev
+from tests.phantoms import point_gamma
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def cpi():
+    import paper_2407_20692_amd as m
+    return m
+
+
+def _geom(cpi, g: oracle.Geometry):
+    return cpi.make_geometry(**g.__dict__)
+
+
+def _run(cpi, fn, gamma_vm_f32, g: oracle.Geometry, alphas):
+    import torch
+
+    out = torch.full((len(alphas) * g.out_h * g.out_w,), np.nan, dtype=torch.float32,
+                     device=dev())
+    fn(to_dev(np.asarray(gamma_vm_f32, dtype=np.float32)), _geom(cpi, g), alphas, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(len(alphas), g.out_h, g.out_w)
+
+
+@pytest.mark.parametrize("path", ["batched", "plain"])
+def test_hand_worked_1d(cpi, path):
+    with open(os.path.join(GOLDEN, "refocus_hand_1d.json")) as f:
+        fx = json.load(f)
+    g = oracle.Geometry(**fx["geometry"])
+    fn = cpi.refocus if path == "batched" else cpi.refocus_plain
+    log(f"case hand-worked 1d {path}")
+    got = _run(cpi, fn, np.array(fx["gamma_view_major"]), g, fx["alphas"])
+    assert np.array_equal(got, np.array(fx["expected"], dtype=np.float32))
+
+
+@pytest.fixture(scope="module")
+def tiny(cpi):
+    w = WORKLOADS["da32_db16_n1000_u8counts"]
+    a, b = generate_frames(w, workers=1)
+    ref = oracle.correlation(a, b, w.n_frames, w.pa, w.pb, oracle.FRAMES_U8)
+    gvm64 = oracle.to_layout(ref["gamma"], oracle.GAMMA_VIEW_MAJOR)
+    gvm32 = oracle.to_layout(ref["gamma_f32"], oracle.GAMMA_VIEW_MAJOR)
+    return w, gvm64, gvm32
+
+
+@pytest.mark.parametrize("path", ["batched", "plain"])
+def test_tiny_workload(cpi, tiny, path):
+    w, g64, g32 = tiny
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    al = alphas_for(w)
+    fn = cpi.refocus if path == "batched" else cpi.refocus_plain
+    log(f"case {w.name} refocus {path}")
+    got = _run(cpi, fn, g32, g, al)
+    want = oracle.refocus(g64, g, al)
+    assert plane_rel_err(got, want).max() <= TOL
+    again = _run(cpi, fn, g32, g, al)
+    assert np.array_equal(got, again)
+
+
+GEOMS = [
+    # non-default centres and magnification, output grid larger than Da
+    oracle.Geometry(24, 20, 6, 5, 1.7, 2.3, 10.2, 9.9, 2.4, 1.6, 70, 33),
+    # output smaller than Da, tiny lens grid
+    oracle.Geometry(40, 36, 3, 2, 3.0, 4.0, 19.5, 17.5, 1.0, 0.5, 17, 9),
+    # minimal views
+    oracle.Geometry(65, 2, 1, 1, 1.0, 1.0, 32.0, 0.5, 0.0, 0.0, 65, 2),
+]
+ALPHAS = [[1.0], [0.5, 0.75, 1.0, 1.25, 1.5], [-1.3, 0.0, 0.37, 2.9, 4.0, 1.0, 1.0 + 1e-9],
+          list(np.linspace(0.3, 1.7, 19))]
+
+
+@pytest.mark.parametrize("gi", range(len(GEOMS)))
+@pytest.mark.parametrize("ai", range(len(ALPHAS)))
+def test_geometries_and_alphas(cpi, gi, ai):
+    g = GEOMS[gi]
+    al = ALPHAS[ai]
+    rng = np.random.default_rng(gi * 10 + ai)
+    gam = rng.standard_normal((g.hb * g.wb, g.ha * g.wa))
+    gam32 = gam.astype(np.float32)
+    want = oracle.refocus(gam32.astype(np.float64), g, al)
+    for path, fn in [("batched", cpi.refocus), ("plain", cpi.refocus_plain)]:
+        log(f"case geometry {gi} alphas {ai} {path}")
+        got = _run(cpi, fn, gam32, g, al)
+        err = np.abs(got - want).max(axis=(1, 2))
+        scale = np.maximum(np.abs(want).max(axis=(1, 2)), np.abs(gam).sum() * 1e-3)
+        assert (err / scale).max() <= TOL, (path, err / scale)
+
+
+def test_alpha_one_row_sums(cpi, tiny):
+    w, g64, g32 = tiny
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    log("case alpha=1 row sums")
+    got = _run(cpi, cpi.refocus, g32, g, [1.0])[0]
+    want = g64.sum(axis=0).reshape(w.ha, w.wa)
+    assert plane_rel_err(got[None], want[None]).max() <= TOL
+
+
+@pytest.mark.parametrize("alpha_star", [0.6, 0.75, 1.25])
+def test_point_phantom(cpi, alpha_star):
+    g = oracle.default_geometry(32, 32, 16, 16)
+    gam, peak = point_gamma(g, alpha_star, 14, 17)
+    log(f"case point phantom {alpha_star}")
+    got = _run(cpi, cpi.refocus, gam, g, [alpha_star])[0]
+    assert abs(got[17, 14] - peak) <= 1e-5 * peak
+    assert np.unravel_index(np.argmax(got), got.shape) == (17, 14)
+
+
+def test_autotune_configs_deterministic_and_accurate(cpi, tiny):
+    """Every configuration the autotuner may pick meets the tolerance and is
+    bitwise reproducible; the tuned call leaves a valid stack in out."""
+    import torch
+
+    w, g64, g32 = tiny
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    al = np.linspace(0.5, 1.5, 13)
+    want = oracle.refocus(g64, g, al)
+    log("case autotune")
+    got = _run(cpi, cpi.autotune_refocus, g32, g, al)
+    assert plane_rel_err(got, want).max() <= TOL
+    after = _run(cpi, cpi.refocus, g32, g, al)   # uses the cached configuration
+    assert plane_rel_err(after, want).max() <= TOL
+    assert np.array_equal(after, _run(cpi, cpi.refocus, g32, g, al))
+    del torch
+
+
+def test_paper_like_full_size(cpi):
+    """Da 128x128, Db 64x64, 32 planes, Gamma from the oracle's exact
+    correlation of the 20000-frame workload; checked at 96 sampled pixels of
+    every plane (including each plane's largest-magnitude pixel)."""
+    w = WORKLOADS["da128_db64_n20000_u8bin"]
+    a, b = generate_frames(w)
+    log(f"case {w.name} refocus, oracle Gamma")
+    ref = oracle.correlation(a, b, w.n_frames, w.pa, w.pb, oracle.FRAMES_U8)
+    g64 = oracle.to_layout(ref["gamma"], oracle.GAMMA_VIEW_MAJOR)
+    g32 = oracle.to_layout(ref["gamma_f32"], oracle.GAMMA_VIEW_MAJOR)
+    del ref
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    al = alphas_for(w)
+    got = _run(cpi, cpi.refocus, g32, g, al)
+    rng = np.random.default_rng(3)
+    ys = list(rng.integers(0, w.ha, 64)) + [0, w.ha - 1, 0, w.ha - 1]
+    xs = list(rng.integers(0, w.wa, 64)) + [0, 0, w.wa - 1, w.wa - 1]
+    flat = np.abs(got.reshape(len(al), -1))
+    for k in range(len(al)):
+        yy, xx = np.unravel_index(np.argmax(flat[k]), (w.ha, w.wa))
+        ys.append(yy)
+        xs.append(xx)
+    ys, xs = np.array(ys), np.array(xs)
+    want = oracle.refocus_pixels(g64, g, al, ys, xs)
+    err = plane_rel_err(got[:, ys, xs], want)
+    log(f"per-plane relative error max {err.max():.3g}")
+    assert err.max() <= TOL
+    plain = _run(cpi, cpi.refocus_plain, g32, g, al)
+    assert plane_rel_err(plain[:, ys, xs], want).max() <= TOL

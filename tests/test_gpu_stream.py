@@ -1,0 +1,164 @@
+"""GPU parity of the streaming path: chunks folded into device-resident sums
+must give the single-shot oracle's Gamma bit for bit, after any chunking,
+through a checkpoint and across encodings."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import WORKLOADS, alphas_for, generate_frames, pack_bits_lsb
+from tests.gpu_util import assert_bit_exact, dev, log, oracle_in_layout, plane_rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cpi():
+    import paper_2407_20692_amd as m
+    return m
+
+
+def _gamma(cpi, s, layout=oracle.GAMMA_VIEW_MAJOR):
+    import torch
+
+    d = dev()
+    n = s.pa * s.pb
+    out = {
+        "gamma": torch.empty(n, dtype=torch.float64, device=d),
+        "gamma_f32": torch.empty(n, dtype=torch.float32, device=d),
+        "numer": torch.empty(n, dtype=torch.int64, device=d),
+        "sum_a": torch.empty(s.pa, dtype=torch.int64, device=d),
+        "sum_b": torch.empty(s.pb, dtype=torch.int64, device=d),
+    }
+    s.gamma(layout, **out)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _chunks(n, sizes):
+    lo = 0
+    for k in sizes:
+        if lo >= n:
+            break
+        yield lo, min(n, lo + k)
+        lo += k
+
+
+@pytest.mark.parametrize("fmt_name", ["bit1", "u8_binary", "u8_counts"])
+def test_chunked_equals_single_shot(cpi, fmt_name):
+    rng = np.random.default_rng(21)
+    n, pa, pb = 5000, 300, 70
+    if fmt_name == "u8_counts":
+        a = rng.integers(0, 256, size=(n, pa), dtype=np.uint8)
+        b = rng.integers(0, 256, size=(n, pb), dtype=np.uint8)
+        a[:2000] //= 128     # early chunks stay binary, later ones do not
+        b[:2000] //= 128
+    else:
+        a = (rng.random((n, pa)) < 0.2).astype(np.uint8)
+        b = (rng.random((n, pb)) < 0.2).astype(np.uint8)
+    fmt = cpi.FRAMES_BIT1 if fmt_name == "bit1" else cpi.FRAMES_U8
+    s = cpi.Stream(pa, pb, fmt, max_chunk=1200)
+    for lo, hi in _chunks(n, [1000, 1, 1200, 999, 64, 1136, 600]):
+        ca = pack_bits_lsb(a[lo:hi]) if fmt_name == "bit1" else a[lo:hi]
+        cb = pack_bits_lsb(b[lo:hi]) if fmt_name == "bit1" else b[lo:hi]
+        log(f"case stream {fmt_name} chunk [{lo},{hi})")
+        s.push(to_dev(ca), to_dev(cb), hi - lo)
+    assert s.frames == n
+    ref = oracle.correlation(a, b, n, pa, pb, oracle.FRAMES_U8)
+    for layout in (oracle.GAMMA_VIEW_MAJOR, oracle.GAMMA_PIXEL_MAJOR):
+        assert_bit_exact(_gamma(cpi, s, layout), oracle_in_layout(ref, layout))
+    s.close()
+
+
+def test_checkpoint_resume(cpi):
+    rng = np.random.default_rng(22)
+    n, pa, pb = 4000, 256, 64
+    a = (rng.random((n, pa)) < 0.1).astype(np.uint8)
+    b = (rng.random((n, pb)) < 0.1).astype(np.uint8)
+    pa_bits, pb_bits = pack_bits_lsb(a), pack_bits_lsb(b)
+    s1 = cpi.Stream(pa, pb, cpi.FRAMES_BIT1, max_chunk=1000)
+    for lo in range(0, 2000, 1000):
+        s1.push(to_dev(pa_bits[lo:lo + 1000]), to_dev(pb_bits[lo:lo + 1000]), 1000)
+    log("case checkpoint save/load")
+    state = s1.save()
+    s1.close()
+    s2 = cpi.Stream(pa, pb, cpi.FRAMES_BIT1, max_chunk=1000)
+    s2.load(state)
+    assert s2.frames == 2000
+    for lo in range(2000, n, 1000):
+        s2.push_host(pa_bits[lo:lo + 1000], pb_bits[lo:lo + 1000], 1000)
+    ref = oracle.correlation(a, b, n, pa, pb, oracle.FRAMES_U8)
+    assert_bit_exact(_gamma(cpi, s2), oracle_in_layout(ref, oracle.GAMMA_VIEW_MAJOR))
+    s2.close()
+
+
+def test_stream_gamma_f32_and_refocus_after_each_chunk(cpi):
+    import torch
+
+    w = WORKLOADS["da32_db16_n1000_u8counts"]
+    rng = np.random.default_rng(23)
+    n = 3000
+    a = (rng.random((n, w.pa)) < 0.15).astype(np.uint8)
+    b = (rng.random((n, w.pb)) < 0.15).astype(np.uint8)
+    s = cpi.Stream(w.pa, w.pb, cpi.FRAMES_BIT1, max_chunk=1000)
+    g = cpi.geometry_default(w.wa, w.ha, w.wb, w.hb)
+    og = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    al = alphas_for(w)
+    out = torch.empty(len(al) * w.pa, dtype=torch.float32, device=dev())
+    for lo in range(0, n, 1000):
+        s.push(to_dev(pack_bits_lsb(a[lo:lo + 1000])), to_dev(pack_bits_lsb(b[lo:lo + 1000])), 1000)
+        s.refocus(g, al, out)
+        torch.cuda.synchronize()
+        m = lo + 1000
+        log(f"case stream refocus after {m} frames")
+        ref = oracle.correlation(a[:m], b[:m], m, w.pa, w.pb, oracle.FRAMES_U8)
+        g32 = torch.empty(w.pa * w.pb, dtype=torch.float32, device=dev())
+        s.gamma(cpi.GAMMA_VIEW_MAJOR, gamma_f32=g32)
+        torch.cuda.synchronize()
+        want32 = oracle.to_layout(ref["gamma_f32"], oracle.GAMMA_VIEW_MAJOR).reshape(-1)
+        assert np.array_equal(g32.cpu().numpy(), want32)
+        want = oracle.refocus(oracle.to_layout(ref["gamma"], oracle.GAMMA_VIEW_MAJOR), og, al)
+        got = out.cpu().numpy().reshape(want.shape)
+        assert plane_rel_err(got, want).max() <= 1e-5
+    s.close()
+
+
+def test_stream_errors(cpi):
+    s = cpi.Stream(64, 16, cpi.FRAMES_BIT1, max_chunk=100)
+    import torch
+
+    with pytest.raises(cpi.CpiError) as e:
+        s.gamma(cpi.GAMMA_VIEW_MAJOR, gamma=torch.empty(64 * 16, dtype=torch.float64, device=dev()))
+    assert e.value.status == 6   # not ready
+    x = torch.zeros(200 * 8, dtype=torch.uint8, device=dev())
+    with pytest.raises(cpi.CpiError) as e:
+        s.push(x, x, 101)
+    assert e.value.status == 1
+    s.close()
+
+
+def test_streaming_workload_final_gamma(cpi):
+    """Da 128x128, Db 64x64, 1-bit frames in chunks of 1000 (first 40 chunks
+    of the streamed workload): final Gamma checked on 64 sampled views against
+    the single-shot oracle, plus exact row/column sums of the numerator."""
+    import torch
+
+    w = WORKLOADS["da128_db64_stream200x1000_bit1"]
+    n = 40000
+    a, b = generate_frames(w, count=n)
+    s = cpi.Stream(w.pa, w.pb, cpi.FRAMES_BIT1, max_chunk=w.chunk)
+    pa_bits, pb_bits = pack_bits_lsb(a), pack_bits_lsb(b)
+    for lo in range(0, n, w.chunk):
+        s.push(to_dev(pa_bits[lo:lo + w.chunk]), to_dev(pb_bits[lo:lo + w.chunk]), w.chunk)
+    log(f"case {w.name} first {n} frames")
+    got = _gamma(cpi, s)
+    num = got["numer"].reshape(w.pb, w.pa)
+    views = np.sort(np.random.default_rng(5).choice(w.pb, 64, replace=False))
+    ref = oracle.correlation(a, b, n, w.pa, w.pb, oracle.FRAMES_U8, cols_b=views)
+    assert np.array_equal(num[views], ref["numer"].T)
+    assert np.array_equal(got["gamma"].reshape(w.pb, w.pa)[views], ref["gamma"].T)
+    a64, b64 = a.astype(np.int64), b.astype(np.int64)
+    sa, sb = a64.sum(0), b64.sum(0)
+    rows_a = n * (a64 * b64.sum(1)[:, None]).sum(0) - sa * sb.sum()
+    assert np.array_equal(num.sum(axis=0), rows_a)
+    s.close()
+    del torch
