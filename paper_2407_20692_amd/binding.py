@@ -91,6 +91,11 @@ EXPORTED = tuple(_SIGS)
 
 
 def _load():
+    # torch ships its own HIP runtime and loads it under a different file name
+    # than the soname libcpi.so asks for; importing torch first makes libcpi.so
+    # bind to that same runtime instead of starting a second one in the process.
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "

@@ -40,10 +40,12 @@ __global__ void k_add_i64(int64_t* __restrict__ dst, const int64_t* __restrict__
 }
 
 // Lane-indexed insert of a wave-uniform value: lane L of `old` becomes v.
+// Written as a per-lane select so that the compiler sees an ordinary
+// lane-wise operation (a hand-placed v_writelane would be invisible to its
+// EXEC-masked register copies).
 template <int L>
 __device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t v) {
-  asm("v_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(v), "i"(L));
-  return old;
+  return (threadIdx.x & 63) == L ? v : old;
 }
 
 // Bit of pixel J (0..127) in this lane's frame: 16 packed bytes or 128 bytes.
@@ -104,7 +106,7 @@ unsigned grid_for(int64_t count, int threads) {
 // Packed-bit frames -> bit rows.  One wave owns 128 pixels and a slice of
 // 512-frame blocks.  Lane l reads the 16 bytes (128 pixels) of frame
 // f0 + l; one wave ballot per pixel then yields that pixel's 64 frame bits,
-// which v_writelane drops into the register of the lane that owns the pixel
+// which a lane select drops into the register of the lane that owns the pixel
 // (pixel j -> lane j % 64, half j / 64).
 __global__ __launch_bounds__(64) void k_ingest_bits(
     const uint8_t* __restrict__ frames, int64_t n, int64_t fbytes, uint32_t* __restrict__ out,
