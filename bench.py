@@ -1,0 +1,305 @@
+#!/usr/bin/env python3
+"""Benchmark of the correlation plenoptic imaging hot path on one MI355X.
+
+Workload: Da 128x128, Db 64x64, N = 20000 binary frames stored as bytes
+(SPAD-like occupancy ~0.1, seeded speckle through a 3-slit mask), 32 refocus
+planes alpha in [0.5, 1.5].  One step is one pass of the hot path with the
+inputs resident in HBM: ingest + int8 matrix-core contraction with the exact
+int64/FP64 epilogue (Gamma in FP64 and FP32) + batched refocus of 32 planes
+with the autotuned configuration (tuned once before timing).
+
+Printed as ONE JSON line:
+  value          Gamma pixel-pair*frames per second over the whole step
+                 (N * Pa * Pb per step / step time)
+  refocus        refocused planes per second of the batched kernel
+  fp32_plain     the plain FP32 path on the same inputs (correlator and
+                 one-plane-per-launch refocus) and the int8/FP32 ratios
+  streaming      chunk-to-stack latency p50/p99 and frames/s for 1000-frame
+                 1-bit chunks of the same geometry, each followed by a
+                 32-plane refocus
+  roofline       the contraction kernel (dominant) against the int8 peak,
+                 its duration measured with HIP events on its stream
+  cpu_baseline   the CPU oracle on a bounded sample of the same workload
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "da128_db64_n20000_u8bin"
+STREAM_WORKLOAD = "da128_db64_stream200x1000_bit1"
+INT8_PEAK = 5.0e15          # dense int8 matrix-core ops/s, MI355X
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemm_bits_da128_db64_n20000_pmc.txt")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_gemm.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per contraction launch from the committed counter summary,
+    if it was taken on the current kernel source; else None."""
+    fields = {}
+    try:
+        with open(PMC_SUMMARY) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256_16") != source_hash(GEMM_SOURCE):
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(a, b, w, alphas):
+    """The oracle, as it stands, on a bounded sample: Gamma for a quarter of
+    the detector-A pixels (all views, all frames) and one refocus plane."""
+    import numpy as np
+
+    import oracle
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    slab = np.arange(0, w.pa, 4)
+    t0 = time.perf_counter()
+    r = oracle.correlation(a, b, w.n_frames, w.pa, w.pb, oracle.FRAMES_U8, rows_a=slab)
+    t1 = time.perf_counter()
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    gam = np.zeros((w.pb, w.pa))
+    gam[:, slab] = r["gamma"].T
+    t2 = time.perf_counter()
+    oracle.refocus(gam, g, alphas[:1])
+    t3 = time.perf_counter()
+    corr_rate = w.n_frames * slab.size * w.pb / (t1 - t0)
+    return {
+        "value": corr_rate,
+        "unit": "pixel-pair*frames/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"Gamma of {slab.size} of {w.pa} detector-A pixels x {w.pb} views x "
+                   f"{w.n_frames} frames ({t1 - t0:.2f} s); refocus of 1 plane "
+                   f"({t3 - t2:.2f} s)"),
+        "refocus_planes_per_s": 1.0 / (t3 - t2),
+        "seconds": (t1 - t0) + (t3 - t2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--stream-chunks", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "copies": 5}))
+        return
+
+    import paper_2407_20692_amd as cpi
+    from synth import WORKLOADS, alphas_for, generate_frames, pack_bits_lsb
+
+    w = WORKLOADS[WORKLOAD]
+    log(f"bench: generating {w.name}")
+    a, b = generate_frames(w)
+    alphas = alphas_for(w)
+    n, pa, pb = w.n_frames, w.pa, w.pb
+    da = torch.from_numpy(a.reshape(-1)).to(dev)
+    db = torch.from_numpy(b.reshape(-1)).to(dev)
+    gamma = torch.empty(pa * pb, dtype=torch.float64, device=dev)
+    g32 = torch.empty(pa * pb, dtype=torch.float32, device=dev)
+    ws_c = cpi.alloc_workspace(cpi.correlate_workspace_size(n, pa, pb, cpi.FRAMES_U8), dev)
+    geo = cpi.geometry_default(w.wa, w.ha, w.wb, w.hb)
+    out = torch.empty(len(alphas) * w.pa, dtype=torch.float32, device=dev)
+    ws_r = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, len(alphas)), dev)
+
+    def step():
+        cpi.correlate(da, db, n, pa, pb, cpi.FRAMES_U8, cpi.GAMMA_VIEW_MAJOR,
+                      gamma=gamma, gamma_f32=g32, workspace=ws_c)
+        cpi.refocus(g32, geo, alphas, out, workspace=ws_r)
+
+    log("bench: autotuning the refocus kernel")
+    step()
+    cpi.autotune_refocus(g32, geo, alphas, out, workspace=ws_r)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    log(f"bench: timing {args.steps} steps")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    cpi.profile_begin()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    cpi.profile_end()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    groups = {}
+    for grp in ("ingest", "gemm", "refocus_tables", "refocus_batched"):
+        cnt, tot = cpi.profile_query(grp)
+        groups[grp] = tot / max(cnt, 1)
+    ms_corr = groups["ingest"] + groups["gemm"]
+    ms_ref = groups["refocus_tables"] + groups["refocus_batched"]
+
+    # plain FP32 comparison path on the same inputs
+    log("bench: plain FP32 path")
+    g32p = torch.empty(pa * pb, dtype=torch.float32, device=dev)
+    ws_p = cpi.alloc_workspace(cpi.correlate_f32_plain_workspace_size(n, pa, pb, cpi.FRAMES_U8), dev)
+    outp = torch.empty_like(out)
+    cpi.correlate_f32_plain(da, db, n, pa, pb, cpi.FRAMES_U8, g32p, workspace=ws_p)
+    cpi.refocus_plain(g32, geo, alphas, outp, workspace=ws_r)
+    torch.cuda.synchronize()
+    cpi.profile_begin()
+    for _ in range(args.plain_steps):
+        cpi.correlate_f32_plain(da, db, n, pa, pb, cpi.FRAMES_U8, g32p, workspace=ws_p)
+        cpi.refocus_plain(g32, geo, alphas, outp, workspace=ws_r)
+    torch.cuda.synchronize()
+    cpi.profile_end()
+    pg = {}
+    for grp in ("unpack_f32", "sgemm_f32", "refocus_tables", "refocus_plain"):
+        cnt, tot = cpi.profile_query(grp)
+        pg[grp] = tot / max(cnt, 1)
+    ms_corr_p = pg["unpack_f32"] + pg["sgemm_f32"]
+    ms_ref_p = pg["refocus_tables"] + pg["refocus_plain"]
+    del ws_p, g32p, outp
+
+    pairs = float(n) * pa * pb
+    line = {
+        "metric": "Gamma pixel-pair*frames/s and refocused planes/s: int8-MFMA vs plain FP32, 1 GPU",
+        "value": pairs / (ms_step * 1e-3),
+        "unit": "pixel-pair*frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_frames": n, "pa": pa, "pb": pb,
+                   "frames": "uint8 0/1, frame-major", "n_alpha": len(alphas),
+                   "alpha_range": [float(alphas[0]), float(alphas[-1])],
+                   "gamma_outputs": "FP64 + FP32, view-major"},
+        "correlate": {"ms": ms_corr, "ingest_ms": groups["ingest"], "gemm_ms": groups["gemm"],
+                      "pixel_pair_frames_per_s": pairs / (ms_corr * 1e-3)},
+        "refocus": {"ms": ms_ref, "planes_per_s": len(alphas) / (ms_ref * 1e-3)},
+        "fp32_plain": {
+            "correlate_ms": ms_corr_p, "unpack_ms": pg["unpack_f32"], "sgemm_ms": pg["sgemm_f32"],
+            "pixel_pair_frames_per_s": pairs / (ms_corr_p * 1e-3),
+            "sgemm_tflops": 2 * pairs / (pg["sgemm_f32"] * 1e-3) / 1e12,
+            "refocus_ms": ms_ref_p, "planes_per_s": len(alphas) / (ms_ref_p * 1e-3),
+            "int8_vs_fp32_correlate": ms_corr_p / ms_corr,
+            "batched_vs_plain_refocus": ms_ref_p / ms_ref,
+        },
+    }
+
+    gemm_ops = 2.0 * pairs
+    achieved = gemm_ops / (groups["gemm"] * 1e-3) / 1e12
+    line["roofline"] = {
+        "kernel": "k_gemm<bits> (int8 MFMA contraction + exact epilogue)",
+        "bound": "mfma",
+        "achieved": achieved,
+        "peak": INT8_PEAK / 1e12,
+        "unit": "TOP/s",
+        "frac": achieved * 1e12 / INT8_PEAK,
+        "traffic": measured_traffic(),
+        "algorithmic_ops_per_launch": gemm_ops,
+        "launch_ms": groups["gemm"],
+    }
+
+    if not args.no_stream:
+        ws = WORKLOADS[STREAM_WORKLOAD]
+        log(f"bench: streaming {args.stream_chunks} chunks of {ws.chunk}")
+        distinct = 20
+        sa_, sb_ = generate_frames(ws, count=distinct * ws.chunk)
+        ca = torch.from_numpy(pack_bits_lsb(sa_)).pin_memory()
+        cb = torch.from_numpy(pack_bits_lsb(sb_)).pin_memory()
+        fa_b, fb_b = cpi.frame_bytes(ws.pa, cpi.FRAMES_BIT1), cpi.frame_bytes(ws.pb, cpi.FRAMES_BIT1)
+        st = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev)
+        sgeo = cpi.geometry_default(ws.wa, ws.ha, ws.wb, ws.hb)
+        sal = alphas_for(ws)
+        sout = torch.empty(len(sal) * ws.pa, dtype=torch.float32, device=dev)
+        sws = cpi.alloc_workspace(cpi.refocus_workspace_size(sgeo, len(sal)), dev)
+        lat = []
+        dev_lat = []
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.stream_chunks):
+            j = k % distinct
+            cha = ca.view(-1, fa_b)[j * ws.chunk:(j + 1) * ws.chunk].reshape(-1)
+            chb = cb.view(-1, fb_b)[j * ws.chunk:(j + 1) * ws.chunk].reshape(-1)
+            t0 = time.perf_counter()
+            ev0.record()
+            st.push_host(cha, chb, ws.chunk)
+            st.refocus(sgeo, sal, sout, workspace=sws)
+            ev1.record()
+            ev1.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+            dev_lat.append(ev0.elapsed_time(ev1))
+        t_total = time.perf_counter() - t_start
+        line["streaming"] = {
+            "workload": ws.name,
+            "chunks": args.stream_chunks,
+            "chunk_frames": ws.chunk,
+            "frames": f"first {distinct} seeded chunks of the workload, cycled",
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "device_p50_ms": float(np.percentile(dev_lat, 50)),
+            "device_p99_ms": float(np.percentile(dev_lat, 99)),
+            "frames_per_s": args.stream_chunks * ws.chunk / t_total,
+            "n_alpha": len(sal),
+        }
+        st.close()
+
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(a, b, w, alphas)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -212,6 +212,23 @@ cpi_status cpi_stream_save(cpi_stream_t s, void* host_buf, size_t bytes);
 cpi_status cpi_stream_load(cpi_stream_t s, const void* host_buf, size_t bytes);
 cpi_status cpi_stream_destroy(cpi_stream_t s);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing (tracing).  While recording is on, every entry point brackets
+ * each group of kernels it enqueues with a pair of HIP events on the caller's
+ * stream.  Group names: "ingest" (sums and operand transposition), "gemm"
+ * (matrix-core contraction with its epilogue), "unpack_f32", "sgemm_f32",
+ * "refocus_tables", "refocus_batched" (including the reduction of split
+ * partial sums), "refocus_plain", "state_gamma".
+ * cpi_profile_begin clears earlier records and starts recording;
+ * cpi_profile_end stops it; cpi_profile_query waits for the recorded events
+ * and returns the number of launches and their summed duration for one group.
+ * Recording adds one event pair per group and call; it is meant for
+ * measurement runs.  Not thread-safe with concurrent calls on other threads.
+ * ------------------------------------------------------------------------- */
+cpi_status cpi_profile_begin(void);
+cpi_status cpi_profile_end(void);
+cpi_status cpi_profile_query(const char* group, int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,9 @@ from .binding import (  # noqa: F401
     last_error,
     lib,
     make_geometry,
+    profile_begin,
+    profile_end,
+    profile_query,
     refocus,
     refocus_plain,
     refocus_workspace_size,

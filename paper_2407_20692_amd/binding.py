@@ -85,6 +85,9 @@ _SIGS = {
     "cpi_stream_save": (c_int, [c_void_p, c_void_p, c_size_t]),
     "cpi_stream_load": (c_int, [c_void_p, c_void_p, c_size_t]),
     "cpi_stream_destroy": (c_int, [c_void_p]),
+    "cpi_profile_begin": (c_int, []),
+    "cpi_profile_end": (c_int, []),
+    "cpi_profile_query": (c_int, [c_char_p, POINTER(c_int64), POINTER(c_double)]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -279,6 +282,26 @@ def refocus_plain(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
 def autotune_refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
     """Times the refocus configurations, caches the best, leaves the result in out."""
     return _refocus_call(lib.cpi_autotune_refocus, gamma, g, alphas, out, workspace, stream)
+
+
+# ---------------------------------------------------------------------------
+# kernel timing
+# ---------------------------------------------------------------------------
+
+def profile_begin():
+    _check(lib.cpi_profile_begin())
+
+
+def profile_end():
+    _check(lib.cpi_profile_end())
+
+
+def profile_query(group: str):
+    """(launches, total milliseconds) recorded for one kernel group."""
+    n = c_int64(0)
+    ms = c_double(0.0)
+    _check(lib.cpi_profile_query(group.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 # ---------------------------------------------------------------------------

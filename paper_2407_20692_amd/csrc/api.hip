@@ -10,7 +10,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "autotune.h"
 #include "cpi.h"
@@ -20,6 +22,57 @@
 namespace {
 
 thread_local std::string g_last_error;
+
+// ---- kernel timing ---------------------------------------------------------
+struct ProfRec {
+  std::string group;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+void prof_clear_locked() {
+  for (ProfRec& r : g_prof) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+}
+
+// Brackets the kernels enqueued during its lifetime with two events.
+class ProfScope {
+ public:
+  ProfScope(const char* group, hipStream_t s) : s_(s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    ProfRec r;
+    r.group = group;
+    if (hipEventCreate(&r.a) != hipSuccess) return;
+    if (hipEventCreate(&r.b) != hipSuccess) {
+      hipEventDestroy(r.a);
+      return;
+    }
+    if (hipEventRecord(r.a, s_) != hipSuccess) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+      return;
+    }
+    idx_ = int64_t(g_prof.size());
+    g_prof.push_back(r);
+  }
+  ~ProfScope() {
+    if (idx_ < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (idx_ < int64_t(g_prof.size())) hipEventRecord(g_prof[size_t(idx_)].b, s_);
+  }
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  hipStream_t s_;
+  int64_t idx_ = -1;
+};
 
 cpi_status set_error(cpi_status s, const std::string& msg) {
   g_last_error = msg;
@@ -98,24 +151,32 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
   g.numer = numer;
 
   if (pl.fmt == CPI_FRAMES_BIT1) {
-    CPI_HIP(cpi::ingest_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, st), "ingest");
-    CPI_HIP(cpi::ingest_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, st), "ingest");
+    {
+      ProfScope ps("ingest", st);
+      CPI_HIP(cpi::ingest_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, st), "ingest");
+      CPI_HIP(cpi::ingest_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, st), "ingest");
+    }
     g.row_bytes = pl.row_bytes_bits;
     g.kblocks = pl.kpad_bits / cpi::kBitBlock;
     g.mode = cpi::EPI_FINAL;
+    ProfScope ps("gemm", st);
     CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
     return CPI_OK;
   }
 
   // Byte frames: the maximum decides between bit rows (binary data) and
   // int8 rows; both branches are enqueued and the device skips the other.
-  CPI_HIP(cpi::u8_stats(fa, pl.n, pl.pa, sum_a, stats, st), "stats");
-  CPI_HIP(cpi::u8_stats(fb, pl.n, pl.pb, sum_b, stats, st), "stats");
-  CPI_HIP(cpi::u8_to_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, stats, st), "ingest");
-  CPI_HIP(cpi::u8_to_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, stats, st), "ingest");
-  CPI_HIP(cpi::u8_to_bytes(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bytes, stats, st), "ingest");
-  CPI_HIP(cpi::u8_to_bytes(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bytes, stats, st), "ingest");
+  {
+    ProfScope ps("ingest", st);
+    CPI_HIP(cpi::u8_stats(fa, pl.n, pl.pa, sum_a, stats, st), "stats");
+    CPI_HIP(cpi::u8_stats(fb, pl.n, pl.pb, sum_b, stats, st), "stats");
+    CPI_HIP(cpi::u8_to_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, stats, st), "ingest");
+    CPI_HIP(cpi::u8_to_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, stats, st), "ingest");
+    CPI_HIP(cpi::u8_to_bytes(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bytes, stats, st), "ingest");
+    CPI_HIP(cpi::u8_to_bytes(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bytes, stats, st), "ingest");
+  }
 
+  ProfScope ps("gemm", st);
   cpi::GemmArgs gb = g;
   gb.row_bytes = pl.row_bytes_bits;
   gb.kblocks = pl.kpad_bits / cpi::kBitBlock;
@@ -176,6 +237,7 @@ cpi_status enqueue_tables(const cpi_geometry* g, const double* alphas, int32_t n
   const cpi::RefGeom rg = ref_geom(g);
   int32_t* itab = reinterpret_cast<int32_t*>(ws + pl.off_itab);
   float* ftab = reinterpret_cast<float*>(ws + pl.off_ftab);
+  ProfScope ps("refocus_tables", st);
   for (int first = 0; first < n_alpha; first += cpi::kAlphaPerLaunch) {
     const int cnt = (n_alpha - first) < cpi::kAlphaPerLaunch ? n_alpha - first : cpi::kAlphaPerLaunch;
     CPI_HIP(cpi::refocus_tables(rg, alphas, first, cnt, pl.table_stride, itab, ftab, st),
@@ -202,12 +264,14 @@ cpi_status refocus_enqueue(const float* gamma, const cpi_geometry* g, const doub
   const int32_t* itab = reinterpret_cast<const int32_t*>(ws + pl.off_itab);
   const float* ftab = reinterpret_cast<const float*>(ws + pl.off_ftab);
   if (plain || g->wa < 2 || g->ha < 2) {
+    ProfScope ps("refocus_plain", st);
     for (int k = 0; k < n_alpha; ++k)
       CPI_HIP(refocus_plain(gamma, rg, itab, ftab, pl.table_stride, k, out, st), "refocus");
     return CPI_OK;
   }
   RefocusConfig c = forced ? *forced : refocus_config_for(g, n_alpha);
   float* partial = reinterpret_cast<float*>(ws + pl.off_partial);
+  ProfScope ps("refocus_batched", st);
   CPI_HIP(refocus_batched(gamma, rg, itab, ftab, pl.table_stride, n_alpha, c, partial, out, st),
           "refocus");
   return CPI_OK;
@@ -349,14 +413,18 @@ cpi_status cpi_correlate_f32_plain(const void* frames_a, const void* frames_b, i
     float* fb = reinterpret_cast<float*>(ws + pl.off_fb);
     float* sa = reinterpret_cast<float*>(ws + pl.off_sa);
     float* sb = reinterpret_cast<float*>(ws + pl.off_sb);
-    CPI_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(sa), pl.pa_pad, 0, st), "fill");
-    CPI_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(sb), pl.pb_pad, 0, st), "fill");
-    CPI_HIP(cpi::unpack_f32(static_cast<const uint8_t*>(frames_a), int(fmt), n, pa, pl.kpad,
-                            pl.pa_pad, fa, sa, st),
-            "unpack");
-    CPI_HIP(cpi::unpack_f32(static_cast<const uint8_t*>(frames_b), int(fmt), n, pb, pl.kpad,
-                            pl.pb_pad, fb, sb, st),
-            "unpack");
+    {
+      ProfScope ps("unpack_f32", st);
+      CPI_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(sa), pl.pa_pad, 0, st), "fill");
+      CPI_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(sb), pl.pb_pad, 0, st), "fill");
+      CPI_HIP(cpi::unpack_f32(static_cast<const uint8_t*>(frames_a), int(fmt), n, pa, pl.kpad,
+                              pl.pa_pad, fa, sa, st),
+              "unpack");
+      CPI_HIP(cpi::unpack_f32(static_cast<const uint8_t*>(frames_b), int(fmt), n, pb, pl.kpad,
+                              pl.pb_pad, fb, sb, st),
+              "unpack");
+    }
+    ProfScope ps("sgemm_f32", st);
     CPI_HIP(cpi::sgemm_gamma(fb, fa, pl.kpad, pl.pb_pad, pl.pa_pad, pa, pb, n, sa, sb,
                              int(layout), gamma_f32, st),
             "sgemm");
@@ -484,24 +552,32 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
   g.gamma_f32 = reinterpret_cast<float*>(h->ws + h->plan.off_gamma32);
 
   if (h->fmt == CPI_FRAMES_BIT1) {
-    CPI_HIP(cpi::ingest_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, st), "ingest");
-    CPI_HIP(cpi::ingest_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, st), "ingest");
-    CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
-    CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
+    {
+      ProfScope ps("ingest", st);
+      CPI_HIP(cpi::ingest_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, st), "ingest");
+      CPI_HIP(cpi::ingest_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, st), "ingest");
+      CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
+      CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
+    }
+    ProfScope ps("gemm", st);
     g.row_bytes = cp.row_bytes_bits;
     g.kblocks = cp.kpad_bits / cpi::kBitBlock;
     g.mode = cpi::EPI_STREAM32;
     g.acc32 = reinterpret_cast<int32_t*>(h->ws + h->plan.off_sab);
     CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
   } else {
-    CPI_HIP(cpi::u8_stats(fa, k, h->pa, csum_a, stats, st), "stats");
-    CPI_HIP(cpi::u8_stats(fb, k, h->pb, csum_b, stats, st), "stats");
-    CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
-    CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
-    CPI_HIP(cpi::u8_to_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, stats, st), "ingest");
-    CPI_HIP(cpi::u8_to_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, stats, st), "ingest");
-    CPI_HIP(cpi::u8_to_bytes(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bytes, stats, st), "ingest");
-    CPI_HIP(cpi::u8_to_bytes(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bytes, stats, st), "ingest");
+    {
+      ProfScope ps("ingest", st);
+      CPI_HIP(cpi::u8_stats(fa, k, h->pa, csum_a, stats, st), "stats");
+      CPI_HIP(cpi::u8_stats(fb, k, h->pb, csum_b, stats, st), "stats");
+      CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
+      CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
+      CPI_HIP(cpi::u8_to_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, stats, st), "ingest");
+      CPI_HIP(cpi::u8_to_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, stats, st), "ingest");
+      CPI_HIP(cpi::u8_to_bytes(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bytes, stats, st), "ingest");
+      CPI_HIP(cpi::u8_to_bytes(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bytes, stats, st), "ingest");
+    }
+    ProfScope ps("gemm", st);
     g.mode = cpi::EPI_STREAM64;
     g.acc64 = reinterpret_cast<int64_t*>(h->ws + h->plan.off_sab);
     cpi::GemmArgs gb = g;
@@ -620,6 +696,7 @@ cpi_status cpi_stream_gamma(cpi_stream_t s, cpi_gamma_layout layout, double* gam
     if (s->n_total == 0) return set_error(CPI_ERR_NOT_READY, "no frames pushed yet");
     const int64_t* ta = reinterpret_cast<const int64_t*>(s->ws + s->plan.off_sum_a);
     const int64_t* tb = reinterpret_cast<const int64_t*>(s->ws + s->plan.off_sum_b);
+    ProfScope ps("state_gamma", s->st);
     if (gamma || gamma_f32 || numer)
       CPI_HIP(cpi::state_gamma(s->ws + s->plan.off_sab, s->plan.state64, ta, tb, s->n_total, s->pa,
                                s->pb, int(layout), gamma, gamma_f32, numer, s->st),
@@ -714,6 +791,43 @@ cpi_status cpi_stream_load(cpi_stream_t s, const void* host_buf, size_t bytes) {
               "load");
     }
     CPI_HIP(hipStreamSynchronize(s->st), "load");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_profile_begin(void) {
+  return guarded([&]() -> cpi_status {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear_locked();
+    g_prof_on = true;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_profile_end(void) {
+  return guarded([&]() -> cpi_status {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = false;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_profile_query(const char* group, int64_t* launches, double* total_ms) {
+  return guarded([&]() -> cpi_status {
+    if (!group || !launches || !total_ms) return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    int64_t cnt = 0;
+    double tot = 0.0;
+    for (ProfRec& r : g_prof) {
+      if (r.group != group) continue;
+      CPI_HIP(hipEventSynchronize(r.b), "profile");
+      float ms = 0.f;
+      CPI_HIP(hipEventElapsedTime(&ms, r.a, r.b), "profile");
+      ++cnt;
+      tot += ms;
+    }
+    *launches = cnt;
+    *total_ms = tot;
     return CPI_OK;
   });
 }
