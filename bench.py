@@ -224,7 +224,8 @@ def main():
                    "gamma_outputs": "FP64 + FP32, view-major"},
         "correlate": {"ms": ms_corr, "ingest_ms": groups["ingest"], "gemm_ms": groups["gemm"],
                       "pixel_pair_frames_per_s": pairs / (ms_corr * 1e-3)},
-        "refocus": {"ms": ms_ref, "planes_per_s": len(alphas) / (ms_ref * 1e-3)},
+        "refocus": {"ms": ms_ref, "planes_per_s": len(alphas) / (ms_ref * 1e-3),
+                    "config_kp_rw_splits": list(cpi.refocus_config(geo, len(alphas)))},
         "fp32_plain": {
             "correlate_ms": ms_corr_p, "unpack_ms": pg["unpack_f32"], "sgemm_ms": pg["sgemm_f32"],
             "pixel_pair_frames_per_s": pairs / (ms_corr_p * 1e-3),

@@ -161,6 +161,12 @@ cpi_status cpi_autotune_refocus(const float* gamma, const cpi_geometry* g,
                                 const double* alphas, int32_t n_alpha, float* out,
                                 void* workspace, size_t workspace_bytes,
                                 void* stream);
+/* The batched-kernel configuration cpi_refocus uses for this shape on the
+ * current device: planes per work-group, output rows per wave and view-row
+ * splits (host pointers). */
+cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha,
+                              int32_t* planes_per_group, int32_t* rows_per_wave,
+                              int32_t* view_splits);
 
 /* ---------------------------------------------------------------------------
  * Streaming: frame chunks folded into device-resident sums as rank-k updates

@@ -29,6 +29,7 @@ from .binding import (  # noqa: F401
     profile_end,
     profile_query,
     refocus,
+    refocus_config,
     refocus_plain,
     refocus_workspace_size,
     stream_workspace_size,

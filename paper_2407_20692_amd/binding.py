@@ -70,6 +70,8 @@ _SIGS = {
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
     "cpi_autotune_refocus": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
                                      c_void_p, c_void_p, c_size_t, c_void_p]),
+    "cpi_refocus_config": (c_int, [POINTER(Geometry), c_int32, POINTER(c_int32), POINTER(c_int32),
+                                   POINTER(c_int32)]),
     "cpi_stream_workspace_size": (c_int, [c_int64, c_int64, c_int, c_int64, POINTER(c_size_t)]),
     "cpi_stream_create": (c_int, [c_int64, c_int64, c_int, c_int64, c_void_p, c_size_t, c_void_p,
                                   POINTER(c_void_p)]),
@@ -277,6 +279,14 @@ def refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
 def refocus_plain(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
     """One-plane-per-launch refocus (the comparison path)."""
     return _refocus_call(lib.cpi_refocus_plain, gamma, g, alphas, out, workspace, stream)
+
+
+def refocus_config(g: Geometry, n_alpha: int):
+    """(planes per work-group, rows per wave, view splits) used by refocus()."""
+    kp, rw, sp = c_int32(0), c_int32(0), c_int32(0)
+    _check(lib.cpi_refocus_config(ctypes.byref(g), n_alpha, ctypes.byref(kp), ctypes.byref(rw),
+                                  ctypes.byref(sp)))
+    return kp.value, rw.value, sp.value
 
 
 def autotune_refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):

@@ -164,14 +164,20 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
     return CPI_OK;
   }
 
-  // Byte frames: the maximum decides between bit rows (binary data) and
-  // int8 rows; both branches are enqueued and the device skips the other.
+  // Byte frames: one pass builds bit rows, popcounts and the OR of all bytes.
+  // Binary data (OR <= 1) is then complete; otherwise the device also runs
+  // the byte-sum and int8-row passes and the byte contraction, and skips the
+  // bit contraction.  Both branches are enqueued; no host synchronisation.
+  int64_t* sum2_a = reinterpret_cast<int64_t*>(ws + pl.off_sum2_a);
+  int64_t* sum2_b = reinterpret_cast<int64_t*>(ws + pl.off_sum2_b);
   {
     ProfScope ps("ingest", st);
-    CPI_HIP(cpi::u8_stats(fa, pl.n, pl.pa, sum_a, stats, st), "stats");
-    CPI_HIP(cpi::u8_stats(fb, pl.n, pl.pb, sum_b, stats, st), "stats");
-    CPI_HIP(cpi::u8_to_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, stats, st), "ingest");
-    CPI_HIP(cpi::u8_to_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, stats, st), "ingest");
+    CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum2_a), pl.pa_pad, 0, st), "fill");
+    CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum2_b), pl.pb_pad, 0, st), "fill");
+    CPI_HIP(cpi::u8_to_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, stats, st), "ingest");
+    CPI_HIP(cpi::u8_to_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, stats, st), "ingest");
+    CPI_HIP(cpi::u8_sums(fa, pl.n, pl.pa, sum2_a, stats, st), "sums");
+    CPI_HIP(cpi::u8_sums(fb, pl.n, pl.pb, sum2_b, stats, st), "sums");
     CPI_HIP(cpi::u8_to_bytes(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bytes, stats, st), "ingest");
     CPI_HIP(cpi::u8_to_bytes(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bytes, stats, st), "ingest");
   }
@@ -188,6 +194,8 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
   gy.row_bytes = pl.row_bytes_bytes;
   gy.cond = 2;
   gy.offset_from_stats = 1;
+  gy.sum_a = sum2_a;
+  gy.sum_b = sum2_b;
   gy.acc64 = reinterpret_cast<int64_t*>(ws + pl.off_acc64);
   for (int pass = 0; pass < pl.passes; ++pass) {
     const int64_t k0 = int64_t(pass) * cpi::kByteChunk;
@@ -240,7 +248,8 @@ cpi_status enqueue_tables(const cpi_geometry* g, const double* alphas, int32_t n
   ProfScope ps("refocus_tables", st);
   for (int first = 0; first < n_alpha; first += cpi::kAlphaPerLaunch) {
     const int cnt = (n_alpha - first) < cpi::kAlphaPerLaunch ? n_alpha - first : cpi::kAlphaPerLaunch;
-    CPI_HIP(cpi::refocus_tables(rg, alphas, first, cnt, pl.table_stride, itab, ftab, st),
+    CPI_HIP(cpi::refocus_tables(rg, alphas, first, cnt, pl.table_stride, itab, ftab,
+                                ws + pl.off_ytab, st),
             "refocus tables");
   }
   return CPI_OK;
@@ -272,7 +281,8 @@ cpi_status refocus_enqueue(const float* gamma, const cpi_geometry* g, const doub
   RefocusConfig c = forced ? *forced : refocus_config_for(g, n_alpha);
   float* partial = reinterpret_cast<float*>(ws + pl.off_partial);
   ProfScope ps("refocus_batched", st);
-  CPI_HIP(refocus_batched(gamma, rg, itab, ftab, pl.table_stride, n_alpha, c, partial, out, st),
+  CPI_HIP(refocus_batched(gamma, rg, itab, ftab, ws + pl.off_ytab, ws + pl.off_bounds,
+                          pl.table_stride, n_alpha, c, partial, out, st),
           "refocus");
   return CPI_OK;
 }
@@ -364,12 +374,21 @@ cpi_status cpi_correlate(const void* frames_a, const void* frames_b, int64_t n, 
                           static_cast<const uint8_t*>(frames_b), ws, int(layout), gamma,
                           gamma_f32, numer, st);
     if (s != CPI_OK) return s;
-    if (sum_a)
-      CPI_HIP(hipMemcpyAsync(sum_a, ws + pl.off_sum_a, size_t(pa) * 8, hipMemcpyDeviceToDevice, st),
-              "copy sums");
-    if (sum_b)
-      CPI_HIP(hipMemcpyAsync(sum_b, ws + pl.off_sum_b, size_t(pb) * 8, hipMemcpyDeviceToDevice, st),
-              "copy sums");
+    // per-pixel sums: popcounts for bit rows, byte sums for non-binary bytes
+    const uint32_t* stats = reinterpret_cast<const uint32_t*>(ws + pl.off_stats);
+    const int64_t* s1a = reinterpret_cast<const int64_t*>(ws + pl.off_sum_a);
+    const int64_t* s1b = reinterpret_cast<const int64_t*>(ws + pl.off_sum_b);
+    const int64_t* s2a = reinterpret_cast<const int64_t*>(ws + pl.off_sum2_a);
+    const int64_t* s2b = reinterpret_cast<const int64_t*>(ws + pl.off_sum2_b);
+    if (fmt == CPI_FRAMES_BIT1) {
+      if (sum_a)
+        CPI_HIP(hipMemcpyAsync(sum_a, s1a, size_t(pa) * 8, hipMemcpyDeviceToDevice, st), "copy sums");
+      if (sum_b)
+        CPI_HIP(hipMemcpyAsync(sum_b, s1b, size_t(pb) * 8, hipMemcpyDeviceToDevice, st), "copy sums");
+    } else {
+      if (sum_a) CPI_HIP(cpi::select_i64(sum_a, s1a, s2a, pa, stats, st), "copy sums");
+      if (sum_b) CPI_HIP(cpi::select_i64(sum_b, s1b, s2b, pb, stats, st), "copy sums");
+    }
     return CPI_OK;
   });
 }
@@ -477,6 +496,23 @@ cpi_status cpi_autotune_refocus(const float* gamma, const cpi_geometry* g, const
   });
 }
 
+cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha, int32_t* planes_per_group,
+                              int32_t* rows_per_wave, int32_t* view_splits) {
+  return guarded([&]() -> cpi_status {
+    cpi::RefocusPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_refocus(g, n_alpha, &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    if (!planes_per_group || !rows_per_wave || !view_splits)
+      return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    const cpi::RefocusConfig c = cpi::refocus_config_for(g, n_alpha);
+    *planes_per_group = c.kp;
+    *rows_per_wave = c.rw;
+    *view_splits = c.splits;
+    return CPI_OK;
+  });
+}
+
 // ---------------------------------------------------------------------------
 // Streaming
 // ---------------------------------------------------------------------------
@@ -566,14 +602,18 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
     g.acc32 = reinterpret_cast<int32_t*>(h->ws + h->plan.off_sab);
     CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
   } else {
+    int64_t* csum2_a = reinterpret_cast<int64_t*>(cws + mp.off_sum2_a);
+    int64_t* csum2_b = reinterpret_cast<int64_t*>(cws + mp.off_sum2_b);
     {
       ProfScope ps("ingest", st);
-      CPI_HIP(cpi::u8_stats(fa, k, h->pa, csum_a, stats, st), "stats");
-      CPI_HIP(cpi::u8_stats(fb, k, h->pb, csum_b, stats, st), "stats");
-      CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
-      CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
-      CPI_HIP(cpi::u8_to_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, stats, st), "ingest");
-      CPI_HIP(cpi::u8_to_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, stats, st), "ingest");
+      CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum2_a), cp.pa_pad, 0, st), "fill");
+      CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum2_b), cp.pb_pad, 0, st), "fill");
+      CPI_HIP(cpi::u8_to_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, stats, st), "ingest");
+      CPI_HIP(cpi::u8_to_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, stats, st), "ingest");
+      CPI_HIP(cpi::u8_sums(fa, k, h->pa, csum2_a, stats, st), "sums");
+      CPI_HIP(cpi::u8_sums(fb, k, h->pb, csum2_b, stats, st), "sums");
+      CPI_HIP(cpi::add_select_i64(tot_a, csum_a, csum2_a, cp.pa_pad, stats, st), "sums");
+      CPI_HIP(cpi::add_select_i64(tot_b, csum_b, csum2_b, cp.pb_pad, stats, st), "sums");
       CPI_HIP(cpi::u8_to_bytes(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bytes, stats, st), "ingest");
       CPI_HIP(cpi::u8_to_bytes(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bytes, stats, st), "ingest");
     }
@@ -590,6 +630,8 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
     gy.kblocks = cp.kpad_bytes / cpi::kByteBlock;
     gy.cond = 2;
     gy.offset_from_stats = 1;
+    gy.csum_a = csum2_a;
+    gy.csum_b = csum2_b;
     CPI_HIP(cpi::gemm_correlate(gy, false, st), "gemm");
   }
   h->n_total = n_new;

@@ -87,7 +87,7 @@ void store_cache_locked(const std::string& key, const RefocusConfig& c, double u
 
 int64_t workgroups(const cpi_geometry* g, int32_t n_alpha, const RefocusConfig& c) {
   const int64_t tx = (g->out_w + 63) / 64;
-  const int64_t ty = (g->out_h + 4 * c.rw - 1) / (4 * c.rw);
+  const int64_t ty = (g->out_h + c.rw - 1) / c.rw;
   const int64_t gr = (n_alpha + c.kp - 1) / c.kp;
   return tx * ty * gr * c.splits;
 }
@@ -96,8 +96,8 @@ int64_t workgroups(const cpi_geometry* g, int32_t n_alpha, const RefocusConfig& 
 
 RefocusConfig default_refocus_config(const cpi_geometry* g, int32_t n_alpha) {
   RefocusConfig c;
-  c.kp = n_alpha >= 8 ? 8 : (n_alpha >= 4 ? 4 : (n_alpha >= 2 ? 2 : 1));
-  c.rw = g->out_h >= 16 ? 4 : (g->out_h >= 8 ? 2 : 1);
+  c.kp = n_alpha >= 8 ? 8 : 4;
+  c.rw = g->out_h >= 16 ? 16 : 8;
   c.splits = 1;
   const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
   while (c.splits * 2 <= max_splits && workgroups(g, n_alpha, c) < 1024) c.splits *= 2;
@@ -123,13 +123,13 @@ cpi_status autotune_refocus(const float* gamma, const cpi_geometry* g, const dou
                             hipStream_t st, std::string* why) {
   std::vector<RefocusConfig> cands;
   const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
-  for (int kp : {1, 2, 4, 8})
-    for (int rw : {1, 2, 4, 8})
+  for (int kp : {4, 8, 16})
+    for (int rw : {8, 16, 32})
       for (int sp = 1; sp <= max_splits; sp *= 2) {
         RefocusConfig c{kp, rw, sp};
         if (!refocus_config_supported(c)) continue;
-        if (kp > 1 && kp / 2 >= n_alpha) continue;        // planes beyond n_alpha
-        if (rw > 1 && 4 * rw / 2 >= g->out_h) continue;   // rows beyond out_h
+        if (kp > 4 && kp / 2 >= n_alpha) continue;        // planes beyond n_alpha
+        if (rw > 8 && rw / 2 >= g->out_h) continue;       // rows beyond out_h
         cands.push_back(c);
       }
   if (g->wa < 2 || g->ha < 2) cands.clear();

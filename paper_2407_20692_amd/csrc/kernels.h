@@ -20,14 +20,22 @@ hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t 
 // added into sums (int64).  Rows [npix, npix_pad) are written too.
 hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
                        uint8_t* out, int64_t kpad_bits, int64_t* sums, hipStream_t s);
-// Byte frames: per-pixel sums (int64, added) and the maximum byte (atomic max
-// into stats[0]).
-hipError_t u8_stats(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
-                    uint32_t* stats, hipStream_t s);
-// Byte frames -> bit rows, enqueued unconditionally but executed only when
-// stats[0] <= 1 (binary data).
+// Byte frames -> bit rows (bit = low bit of the byte) with per-pixel popcounts
+// added into sums, and the OR of every byte accumulated into stats[0].  The
+// rows and popcounts are the data exactly when stats[0] <= 1 (binary data);
+// stats[0] > 127 exactly when some byte exceeds 127.
 hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                      uint8_t* out, int64_t kpad_bits, const uint32_t* stats, hipStream_t s);
+                      uint8_t* out, int64_t kpad_bits, int64_t* sums, uint32_t* stats,
+                      hipStream_t s);
+// Per-pixel byte sums (int64, added into sums), executed only when
+// stats[0] > 1.
+hipError_t u8_sums(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
+                   const uint32_t* stats, hipStream_t s);
+// dst[i] = (stats[0] <= 1 ? from_bits : from_bytes)[i]; and dst[i] += the same.
+hipError_t select_i64(int64_t* dst, const int64_t* from_bits, const int64_t* from_bytes,
+                      int64_t count, const uint32_t* stats, hipStream_t s);
+hipError_t add_select_i64(int64_t* dst, const int64_t* from_bits, const int64_t* from_bytes,
+                          int64_t count, const uint32_t* stats, hipStream_t s);
 // Byte frames -> int8 rows (row_bytes = kpad_bytes), executed only when
 // stats[0] > 1; values are offset by -128 when stats[0] > 127; pads are 0.
 hipError_t u8_to_bytes(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
@@ -90,21 +98,27 @@ struct RefGeom {
   double mag_x, mag_y, ca_x, ca_y, cb_x, cb_y;
 };
 
-// Per-plane coordinate tables for planes [first, first+count), count <= 64.
+// Per-plane coordinate tables for planes [first, first+count), count <= 64:
+// integer parts and FP32 fractions of a_x, a_y, b_x, b_y; and, if ytab is
+// not null, the row table of the batched kernel (16 bytes per plane, y_b, y_r).
 hipError_t refocus_tables(const RefGeom& g, const double* alphas, int first, int count,
-                          int64_t stride, int32_t* itab, float* ftab, hipStream_t s);
+                          int64_t stride, int32_t* itab, float* ftab, void* ytab, hipStream_t s);
 hipError_t refocus_plain(const float* gamma, const RefGeom& g, const int32_t* itab,
                          const float* ftab, int64_t stride, int plane, float* out,
                          hipStream_t s);
 
 struct RefocusConfig {
-  int kp = 8;        // planes per work-group
-  int rw = 4;        // output rows per wave
+  int kp = 4;        // planes per work-group (one wave per plane)
+  int rw = 8;        // output rows per work-group tile
   int splits = 1;    // view-row splits (partial sums reduced afterwards)
 };
 bool refocus_config_supported(const RefocusConfig& c);
+// bounds: workspace for the window bounds per (plane group, tile column,
+// view column) and (plane group, tile row, view row), two ints each; sized
+// for plane groups of at least 4 planes and tiles of at least 64 x 8.
 hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* itab,
-                           const float* ftab, int64_t stride, int n_alpha,
+                           const float* ftab, const void* ytab, void* bounds, int64_t stride,
+                           int n_alpha,
                            const RefocusConfig& c, float* partial, float* out,
                            hipStream_t s);
 

@@ -20,6 +20,9 @@
 // frame, whatever order the hardware sums the K index in.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "kernels.h"
 
 namespace cpi {
@@ -97,7 +100,7 @@ __device__ __forceinline__ void store_result(const Epi& g, int64_t q, int64_t p,
   if (g.numer) g.numer[idx] = numer;
 }
 
-template <int FM, int FN, bool BITS, int MODE>
+template <int FM, int FN, bool BITS, int MODE, int SCHED, bool PF = true>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   if (g.cond) {
     const uint32_t mx = g.stats[0];
@@ -128,12 +131,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   for (int j = 0; j < FN; ++j) bn[j] = *reinterpret_cast<const v4i*>(pn + j * fstride);
 
   for (int64_t kb = 0; kb < g.kblocks; ++kb) {
+    // next block's operands: loaded now (PF) or at the end of the iteration
     const int64_t nx = (kb + 1 < g.kblocks ? kb + 1 : kb) * 64;
     v4i am2[FM], bn2[FN];
+    if constexpr (PF) {
 #pragma unroll
-    for (int i = 0; i < FM; ++i) am2[i] = *reinterpret_cast<const v4i*>(pm + i * fstride + nx);
+      for (int i = 0; i < FM; ++i) am2[i] = *reinterpret_cast<const v4i*>(pm + i * fstride + nx);
 #pragma unroll
-    for (int j = 0; j < FN; ++j) bn2[j] = *reinterpret_cast<const v4i*>(pn + j * fstride + nx);
+      for (int j = 0; j < FN; ++j) bn2[j] = *reinterpret_cast<const v4i*>(pn + j * fstride + nx);
+    }
 
     if constexpr (BITS) {
       const int mask = 0x01010101;
@@ -159,6 +165,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
             for (int j = 0; j < FN; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ea[i], eb[j], acc[i][j], 0, 0, 0);
+          if constexpr (SCHED > 0) {
+            // one matrix-core op, then SCHED vector ops (the next step's bit
+            // expansion), repeated over the step's FM*FN products
+#pragma unroll
+            for (int q = 0; q < FM * FN; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+              __builtin_amdgcn_sched_group_barrier(0x002, SCHED, 0);
+            }
+          }
         }
       }
     } else {
@@ -167,6 +182,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(am[i], bn[j], acc[i][j], 0, 0, 0);
+    }
+    if constexpr (!PF) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i) am2[i] = *reinterpret_cast<const v4i*>(pm + i * fstride + nx);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bn2[j] = *reinterpret_cast<const v4i*>(pn + j * fstride + nx);
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i) am[i] = am2[i];
@@ -215,35 +236,71 @@ __global__ __launch_bounds__(256) void k_state_gamma(const void* __restrict__ sa
   }
 }
 
-constexpr int kFM = 8, kFN = 4;   // wave tile 128 x 64, work-group tile 256 x 128
+struct TileChoice {
+  int fm, fn, sched, pf;
+};
+
+// Contraction tile of the bit-row kernel: wave tile 16*fm x 16*fn, the
+// interleave of bit expansion with matrix-core ops, register prefetch of the
+// next operand block.  CPI_GEMM_TILE="FMxFN[sS][pP]" overrides the default
+// (measurement runs).
+TileChoice tile_choice() {
+  static TileChoice t = [] {
+    TileChoice c{4, 4, 0, 1};
+    if (const char* v = std::getenv("CPI_GEMM_TILE")) {
+      int fm = 0, fn = 0, sc = 0, pf = 1;
+      if (std::sscanf(v, "%dx%ds%dp%d", &fm, &fn, &sc, &pf) >= 2) c = TileChoice{fm, fn, sc, pf};
+    }
+    return c;
+  }();
+  return t;
+}
+
+template <int FM, int FN, bool BITS, int MODE, int SCHED, bool PF = true>
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
+  const int64_t tiles_m = a.m_pad / (32 * FM);
+  const int64_t tiles_n = a.n_pad / (32 * FN);
+  if (tiles_m * (32 * FM) != a.m_pad || tiles_n * (32 * FN) != a.n_pad) return hipErrorInvalidValue;
+  const int64_t nwg = tiles_m * tiles_n;
+  if (nwg <= 0 || nwg > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gemm<FM, FN, BITS, MODE, SCHED, PF>), dim3(unsigned(nwg)), dim3(256), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_bits(const GemmArgs& a, hipStream_t s) {
+  const TileChoice t = tile_choice();
+  if (t.fm == 8 && t.fn == 4) return launch_gemm<8, 4, true, MODE, 0>(a, s);
+  if (t.fm == 4 && t.fn == 4 && t.sched == 0 && t.pf == 0)
+    return launch_gemm<4, 4, true, MODE, 0, false>(a, s);
+  if (t.fm == 4 && t.fn == 4 && t.sched == 2) return launch_gemm<4, 4, true, MODE, 2>(a, s);
+  if (t.fm == 2 && t.fn == 4) return launch_gemm<2, 4, true, MODE, 0>(a, s);
+  if (t.fm == 4 && t.fn == 2) return launch_gemm<4, 2, true, MODE, 0>(a, s);
+  return launch_gemm<4, 4, true, MODE, 0>(a, s);
+}
 
 }  // namespace
 
 hipError_t gemm_correlate(const GemmArgs& a, bool bits, hipStream_t s) {
-  const int64_t tiles_m = a.m_pad / (32 * kFM);
-  const int64_t tiles_n = a.n_pad / (32 * kFN);
-  if (tiles_m * (32 * kFM) != a.m_pad || tiles_n * (32 * kFN) != a.n_pad) return hipErrorInvalidValue;
-  const int64_t nwg = tiles_m * tiles_n;
-  if (nwg <= 0 || nwg > 0x7fffffff) return hipErrorInvalidValue;
-#define CPI_GEMM_CASE(M_)                                                                    \
-  case M_:                                                                                   \
-    if (bits)                                                                                \
-      hipLaunchKernelGGL((k_gemm<kFM, kFN, true, M_>), dim3(unsigned(nwg)), dim3(256), 0, s, a); \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_gemm<kFM, kFN, false, M_>), dim3(unsigned(nwg)), dim3(256), 0, s, a); \
-    break;
   switch (a.mode) {
-    CPI_GEMM_CASE(EPI_FINAL)
-    CPI_GEMM_CASE(EPI_FINAL_ACC64)
-    CPI_GEMM_CASE(EPI_STORE64)
-    CPI_GEMM_CASE(EPI_ADD64)
-    CPI_GEMM_CASE(EPI_STREAM32)
-    CPI_GEMM_CASE(EPI_STREAM64)
+    case EPI_FINAL:
+      return bits ? launch_bits<EPI_FINAL>(a, s) : launch_gemm<4, 4, false, EPI_FINAL, 0>(a, s);
+    case EPI_STREAM32:
+      return bits ? launch_bits<EPI_STREAM32>(a, s)
+                  : launch_gemm<4, 4, false, EPI_STREAM32, 0>(a, s);
+    case EPI_FINAL_ACC64:
+      return launch_gemm<4, 4, false, EPI_FINAL_ACC64, 0>(a, s);
+    case EPI_STORE64:
+      return launch_gemm<4, 4, false, EPI_STORE64, 0>(a, s);
+    case EPI_ADD64:
+      return launch_gemm<4, 4, false, EPI_ADD64, 0>(a, s);
+    case EPI_STREAM64:
+      return bits ? launch_gemm<4, 4, true, EPI_STREAM64, 0>(a, s)
+                  : launch_gemm<4, 4, false, EPI_STREAM64, 0>(a, s);
     default:
       return hipErrorInvalidValue;
   }
-#undef CPI_GEMM_CASE
-  return hipGetLastError();
 }
 
 hipError_t state_gamma(const void* sab, bool sab64, const int64_t* sum_a, const int64_t* sum_b,

@@ -55,7 +55,7 @@ __device__ __forceinline__ uint32_t pixel_bit(const uint32_t (&d)[4]) {
 }
 template <int J>
 __device__ __forceinline__ uint32_t pixel_bit(const uint32_t (&d)[32]) {
-  return (d[J >> 2] >> (8 * (J & 3))) & 0xffu;
+  return (d[J >> 2] >> (8 * (J & 3))) & 1u;
 }
 
 // One ballot per pixel J: bit l of the result is pixel J in frame f0 + l.
@@ -162,18 +162,22 @@ __global__ __launch_bounds__(64) void k_ingest_bits(
   atomicAdd(&sums[p0 + 64 + lane], s1);
 }
 
-// Byte frames -> bit rows (only when every byte is 0 or 1).  As k_ingest_bits,
-// with each lane reading 128 bytes of its frame.
+// Byte frames -> bit rows, as k_ingest_bits with each lane reading 128 bytes
+// of its frame.  The bit is the byte's low bit; the OR of all bytes goes to
+// stats[0], so the rows (and the popcount sums) are valid exactly when that
+// OR is at most 1.
 __global__ __launch_bounds__(64) void k_u8_to_bits(
     const uint8_t* __restrict__ frames, int64_t n, int64_t npix, uint32_t* __restrict__ out,
-    int64_t kw, int64_t nblocks, int64_t blocks_per_slice, const uint32_t* __restrict__ stats) {
-  if (stats[0] > 1u) return;
+    int64_t kw, int64_t nblocks, int64_t blocks_per_slice, unsigned long long* __restrict__ sums,
+    uint32_t* __restrict__ stats) {
   const int lane = threadIdx.x;
   const int64_t p0 = int64_t(blockIdx.x) * 128;
   const int64_t kb0 = int64_t(blockIdx.y) * blocks_per_slice;
   int64_t kb1 = kb0 + blocks_per_slice;
   if (kb1 > nblocks) kb1 = nblocks;
   const bool vec = ((npix & 15) == 0) && (p0 + 128 <= npix);
+  uint32_t any = 0;
+  unsigned long long s0 = 0, s1 = 0;
   for (int64_t kb = kb0; kb < kb1; ++kb) {
     uint32_t w0[16], w1[16];
 #pragma unroll
@@ -201,6 +205,8 @@ __global__ __launch_bounds__(64) void k_u8_to_bits(
             if (p0 + b < npix) d[b >> 2] |= uint32_t(src[b]) << (8 * (b & 3));
         }
       }
+#pragma unroll
+      for (int i = 0; i < 32; ++i) any |= d[i];
     };
     transpose_block<32>(load, w0, w1, std::make_integer_sequence<int, 8>{});
     uint4* o0 = reinterpret_cast<uint4*>(out + (p0 + lane) * kw + kb * 16);
@@ -210,27 +216,41 @@ __global__ __launch_bounds__(64) void k_u8_to_bits(
       o0[q] = make_uint4(w0[4 * q], w0[4 * q + 1], w0[4 * q + 2], w0[4 * q + 3]);
       o1[q] = make_uint4(w1[4 * q], w1[4 * q + 1], w1[4 * q + 2], w1[4 * q + 3]);
     }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      s0 += __popc(w0[i]);
+      s1 += __popc(w1[i]);
+    }
   }
+  atomicAdd(&sums[p0 + lane], s0);
+  atomicAdd(&sums[p0 + 64 + lane], s1);
+  any = (any | (any >> 8) | (any >> 16) | (any >> 24)) & 0xffu;
+  for (int off = 32; off > 0; off >>= 1) any |= __shfl_xor(any, off, 64);
+  if (lane == 0 && any) atomicOr(stats, any);
 }
 
-// Per-pixel sums and the maximum byte.  A thread owns 16 consecutive pixels
-// and a slice of frames; its partial sums stay in uint32 (a slice holds at
-// most 2^24 frames of values <= 255).
-__global__ __launch_bounds__(256) void k_u8_stats(const uint8_t* __restrict__ frames, int64_t n,
-                                                  int64_t npix, int64_t frames_per_slice,
-                                                  unsigned long long* __restrict__ sums,
-                                                  uint32_t* __restrict__ stats) {
-  const int64_t px = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 16;
+// Per-pixel byte sums (non-binary data only).  A work-group owns 256
+// consecutive pixels: 16 threads cover them 16 bytes each, and the 16 thread
+// rows walk interleaved frames of the group's frame slice.  Partial sums are
+// reduced in LDS, so each pixel receives one atomic per work-group.
+__global__ __launch_bounds__(256) void k_u8_sums(const uint8_t* __restrict__ frames, int64_t n,
+                                                 int64_t npix, int64_t frames_per_slice,
+                                                 unsigned long long* __restrict__ sums,
+                                                 const uint32_t* __restrict__ stats) {
+  if (stats[0] <= 1u) return;
+  __shared__ uint32_t red[16][256 + 1];
+  const int t = threadIdx.x;
+  const int col = t & 15, row = t >> 4;
+  const int64_t px = int64_t(blockIdx.x) * 256 + col * 16;
   const int64_t f0 = int64_t(blockIdx.y) * frames_per_slice;
   int64_t f1 = f0 + frames_per_slice;
   if (f1 > n) f1 = n;
   uint32_t s[16];
 #pragma unroll
   for (int b = 0; b < 16; ++b) s[b] = 0;
-  uint32_t mx = 0;
   if (px < npix) {
     const bool vec = ((npix & 15) == 0);
-    for (int64_t f = f0; f < f1; ++f) {
+    for (int64_t f = f0 + row; f < f1; f += 16) {
       const uint8_t* src = frames + f * npix + px;
       uint32_t d[4] = {0u, 0u, 0u, 0u};
       if (vec) {
@@ -244,21 +264,26 @@ __global__ __launch_bounds__(256) void k_u8_stats(const uint8_t* __restrict__ fr
           if (px + b < npix) d[b >> 2] |= uint32_t(src[b]) << (8 * (b & 3));
       }
 #pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        const uint32_t v = (d[b >> 2] >> (8 * (b & 3))) & 0xffu;
-        s[b] += v;
-        mx = v > mx ? v : mx;
-      }
+      for (int b = 0; b < 16; ++b) s[b] += (d[b >> 2] >> (8 * (b & 3))) & 0xffu;
     }
+  }
 #pragma unroll
-    for (int b = 0; b < 16; ++b)
-      if (px + b < npix && s[b]) atomicAdd(&sums[px + b], (unsigned long long)s[b]);
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t o = __shfl_xor(mx, off, 64);
-    mx = o > mx ? o : mx;
-  }
-  if ((threadIdx.x & 63) == 0 && mx) atomicMax(stats, mx);
+  for (int b = 0; b < 16; ++b) red[row][col * 16 + b] = s[b];
+  __syncthreads();
+  const int64_t p = int64_t(blockIdx.x) * 256 + t;
+  unsigned long long tot = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) tot += red[r][t];
+  if (p < npix && tot) atomicAdd(&sums[p], tot);
+}
+
+__global__ void k_select_i64(int64_t* __restrict__ dst, const int64_t* __restrict__ a,
+                             const int64_t* __restrict__ b, int64_t count,
+                             const uint32_t* __restrict__ stats, int add) {
+  const int64_t* src = stats[0] <= 1u ? a : b;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] = add ? dst[i] + src[i] : src[i];
 }
 
 // Byte frames -> int8 rows through a 64 x 64 LDS tile (only when some byte
@@ -334,21 +359,39 @@ hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t n
   return hipGetLastError();
 }
 
-hipError_t u8_stats(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
-                    uint32_t* stats, hipStream_t s) {
-  const int64_t groups = (npix + 4095) / 4096;
+hipError_t u8_sums(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
+                   const uint32_t* stats, hipStream_t s) {
+  const int64_t groups = (npix + 255) / 256;
   int64_t slices = (2048 + groups - 1) / groups;
-  if (slices > n) slices = n;
+  if (slices > (n + 15) / 16) slices = (n + 15) / 16;
+  if (slices < 1) slices = 1;
   int64_t fps = (n + slices - 1) / slices;
-  if (fps > (int64_t(1) << 24)) fps = int64_t(1) << 24;
+  // a thread row adds at most fps/16 bytes of <= 255 per pixel in uint32
+  if (fps > (int64_t(1) << 27)) fps = int64_t(1) << 27;
   slices = (n + fps - 1) / fps;
-  hipLaunchKernelGGL(k_u8_stats, dim3(unsigned(groups), unsigned(slices)), dim3(256), 0, s,
+  if (slices > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_u8_sums, dim3(unsigned(groups), unsigned(slices)), dim3(256), 0, s,
                      frames, n, npix, fps, reinterpret_cast<unsigned long long*>(sums), stats);
   return hipGetLastError();
 }
 
+hipError_t select_i64(int64_t* dst, const int64_t* from_bits, const int64_t* from_bytes,
+                      int64_t count, const uint32_t* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_i64, dim3(grid_for(count, 256)), dim3(256), 0, s, dst, from_bits,
+                     from_bytes, count, stats, 0);
+  return hipGetLastError();
+}
+
+hipError_t add_select_i64(int64_t* dst, const int64_t* from_bits, const int64_t* from_bytes,
+                          int64_t count, const uint32_t* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_i64, dim3(grid_for(count, 256)), dim3(256), 0, s, dst, from_bits,
+                     from_bytes, count, stats, 1);
+  return hipGetLastError();
+}
+
 hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                      uint8_t* out, int64_t kpad_bits, const uint32_t* stats, hipStream_t s) {
+                      uint8_t* out, int64_t kpad_bits, int64_t* sums, uint32_t* stats,
+                      hipStream_t s) {
   const int64_t groups = npix_pad / 128;
   const int64_t nblocks = kpad_bits / 512;
   const int64_t slices = slices_for(groups, nblocks, 8192);
@@ -356,7 +399,7 @@ hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t np
   const int64_t used = (nblocks + bps - 1) / bps;
   hipLaunchKernelGGL(k_u8_to_bits, dim3(unsigned(groups), unsigned(used)), dim3(64), 0, s,
                      frames, n, npix, reinterpret_cast<uint32_t*>(out), kpad_bits / 32, nblocks,
-                     bps, stats);
+                     bps, reinterpret_cast<unsigned long long*>(sums), stats);
   return hipGetLastError();
 }
 

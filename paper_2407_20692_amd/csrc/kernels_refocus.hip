@@ -133,124 +133,251 @@ __device__ __forceinline__ void clamp_cell(int i, float f, int size, int& c, flo
   w1 = (i == c) ? a1 : ((i == c + 1) ? a0 : 0.0f);
 }
 
-// Batched refocus: a work-group covers 64 output columns x (4*RW) rows for
-// KP planes and one slice of view rows; lane = column, each wave RW rows.
-template <int KP, int RW>
-__global__ __launch_bounds__(256) void k_ref_batched(
+// Row table of one plane: for output row y_r and lens-plane row y_b, the
+// clamped interpolation row and its two weights (the same arithmetic as the
+// column side below), laid out [plane][y_b][y_r] so that a wave's
+// consecutive output rows are one scalar load.
+struct YEntry {
+  int row;
+  float w0, w1;
+  int pad;
+};
+
+__global__ __launch_bounds__(256) void k_ref_ytab(GeomI g, const int32_t* __restrict__ itab,
+                                                  const float* __restrict__ ftab, int64_t stride,
+                                                  int first, int count, YEntry* __restrict__ ytab) {
+  const int k = blockIdx.x;
+  if (k >= count) return;
+  const int plane = first + k;
+  const int32_t* it = itab + int64_t(plane) * stride;
+  const float* ft = ftab + int64_t(plane) * stride;
+  const int e_by = g.out_w + g.out_h + g.wb;
+  const int64_t n = int64_t(g.hb) * g.out_h;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int yb = int(e / g.out_h), yr = int(e % g.out_h);
+    int y0 = it[g.out_w + yr] + it[e_by + yb];
+    float fy = ft[g.out_w + yr] + ft[e_by + yb];
+    if (fy >= 1.0f) {
+      y0 += 1;
+      fy -= 1.0f;
+    }
+    YEntry v;
+    clamp_cell(y0, fy, g.ha, v.row, v.w0, v.w1);
+    v.pad = 0;
+    ytab[int64_t(plane) * n + e] = v;
+  }
+}
+
+// Window bounds of the batched kernel.  For plane group gq (planes
+// gq*NW .. gq*NW+NW-1), tile column tx and lens-plane column x_b: the first and
+// last interpolation column any sample of the group's planes can start in,
+// clamped into [0, wa-2], the last one plus one for the right neighbour.
+// Likewise for rows.  Integer parts at the tile's extreme columns / rows bound
+// every sample because a_x and a_y are affine in the output coordinate.
+__global__ __launch_bounds__(256) void k_ref_bounds(GeomI g, const int32_t* __restrict__ itab,
+                                                    int64_t stride, int n_alpha, int nw, int rw,
+                                                    int groups, int tiles_x, int tiles_y,
+                                                    int2* __restrict__ bx, int2* __restrict__ by) {
+  const int e_bx = g.out_w + g.out_h, e_by = e_bx + g.wb;
+  const int64_t nxe = int64_t(groups) * tiles_x * g.wb;
+  const int64_t nye = int64_t(groups) * tiles_y * g.hb;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < nxe + nye;
+       e += int64_t(gridDim.x) * 256) {
+    const bool is_x = e < nxe;
+    const int64_t f = is_x ? e : e - nxe;
+    const int nb = is_x ? g.wb : g.hb;
+    const int nt = is_x ? tiles_x : tiles_y;
+    const int vb = int(f % nb);
+    const int t = int((f / nb) % nt);
+    const int gq = int(f / (int64_t(nb) * nt));
+    const int tsz = is_x ? 64 : rw;
+    const int lim = is_x ? g.out_w : g.out_h;
+    const int lo_o = t * tsz;
+    const int hi_o = (lo_o + tsz - 1) < lim ? lo_o + tsz - 1 : lim - 1;
+    const int ea = is_x ? 0 : g.out_w;
+    const int eb = (is_x ? e_bx : e_by) + vb;
+    int lo = 1 << 30, hi = -(1 << 30);
+    for (int k = 0; k < nw; ++k) {
+      const int pk = (gq * nw + k) < n_alpha ? gq * nw + k : n_alpha - 1;
+      const int32_t* it = itab + int64_t(pk) * stride;
+      const int a0 = it[ea + lo_o], a1 = it[ea + hi_o], ib = it[eb];
+      lo = min(lo, min(a0, a1) + ib);
+      hi = max(hi, max(a0, a1) + ib + 1);
+    }
+    const int size = is_x ? g.wa : g.ha;
+    lo = min(max(lo, 0), size - 2);
+    hi = min(max(hi, 0), size - 2) + 1;
+    if (is_x)
+      bx[f] = make_int2(lo, hi);
+    else
+      by[f] = make_int2(lo, hi);
+  }
+}
+
+// Batched refocus.  A work-group of NW waves covers one output tile of 64
+// columns x RW rows for NW consecutive planes (wave w = plane k0 + w) and one
+// slice of view rows; lane = column.
+//
+// For every view the union of the NW planes' sample footprints over the tile
+// is a small window of that view.  Windows are copied straight from global
+// memory into LDS (global_load_lds, no registers), double-buffered: the copy
+// of view v+1 is in flight while view v is interpolated, with one barrier per
+// view.  Rows have a fixed stride of kWinStride floats, so the two taps of a
+// row are adjacent and the next row is a constant offset away.  A view whose
+// window does not fit is read with direct paired gathers instead; both paths
+// give identical results.  Column coordinates are computed per lane for the
+// wave's own plane and reused for its RW rows; row coordinates come from the
+// row table as wave-uniform (scalar) values.
+constexpr int kWinStride = 128;           // LDS row stride (floats) = max window width
+constexpr int kWinRows = 64;              // max window height
+
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+
+struct Window {
+  int x0, y0, w, h;   // window origin and size in view pixels
+  bool fits;
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+template <int NW, int RW>
+__global__ __launch_bounds__(NW * 64) void k_ref_batched(
     const float* __restrict__ gamma, GeomI g, const int32_t* __restrict__ itab,
-    const float* __restrict__ ftab, int64_t stride, int n_alpha, int tiles_x, int groups,
-    int splits, int yb_per_split, float* __restrict__ dst, int64_t split_stride) {
+    const float* __restrict__ ftab, const YEntry* __restrict__ ytab,
+    const int2* __restrict__ bx, const int2* __restrict__ by, int64_t stride, int n_alpha,
+    int tiles_x, int tiles_y, int groups, int splits, int yb_per_split, float* __restrict__ dst,
+    int64_t split_stride) {
+  __shared__ float win0[kWinRows * kWinStride];
+  __shared__ float win1[kWinRows * kWinStride];
   int b = blockIdx.x;
   const int split = b % splits;
   b /= splits;
   const int grp = b % groups;
   b /= groups;
   const int tile_x = b % tiles_x, tile_y = b / tiles_x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int xr = tile_x * 64 + lane;
   const int xrc = xr < g.out_w ? xr : g.out_w - 1;
-  const int yr0 = tile_y * (4 * RW) + wave * RW;
-  const int k0 = grp * KP;
+  const int k0 = grp * NW;
+  const int plane = (k0 + wave) < n_alpha ? k0 + wave : n_alpha - 1;
   const int64_t pa = int64_t(g.wa) * g.ha;
   const int e_bx = g.out_w + g.out_h, e_by = e_bx + g.wb;
+  const int ty_lo = tile_y * RW;
 
-  int iax[KP];
-  float fax[KP];
-  int iay[KP][RW];
-  float fay[KP][RW];
-  const int32_t* itk[KP];
-  const float* ftk[KP];
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int plane = (k0 + k) < n_alpha ? k0 + k : n_alpha - 1;
-    itk[k] = itab + int64_t(plane) * stride;
-    ftk[k] = ftab + int64_t(plane) * stride;
-    iax[k] = itk[k][xrc];
-    fax[k] = ftk[k][xrc];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      const int yr = yr0 + r < g.out_h ? yr0 + r : g.out_h - 1;
-      iay[k][r] = itk[k][g.out_w + yr];
-      fay[k][r] = ftk[k][g.out_w + yr];
+  // column coordinates of this lane in this wave's plane
+  const int32_t* itw = itab + int64_t(plane) * stride;
+  const float* ftw = ftab + int64_t(plane) * stride;
+  const int iax = itw[xrc];
+  const float fax = ftw[xrc];
+  const YEntry* yw = ytab + int64_t(plane) * g.hb * g.out_h;
+  const int2* bxw = bx + (int64_t(grp) * tiles_x + tile_x) * g.wb;
+  const int2* byw = by + (int64_t(grp) * tiles_y + tile_y) * g.hb;
+
+  auto window = [&](int yb, int xb) {
+    const int2 cx = bxw[xb], cy = byw[yb];
+    Window w;
+    w.x0 = cx.x;
+    w.y0 = cy.x;
+    w.w = cx.y - cx.x + 1;
+    w.h = cy.y - cy.x + 1;
+    w.fits = w.w <= kWinStride && w.h <= kWinRows;
+    return w;
+  };
+  // Copy a window into LDS: wave w copies rows w, w+NW, ...; lane l columns l
+  // and l+64 (lanes beyond the window width stay idle).
+  auto copy_window = [&](const float* view, const Window& w, float* buf) {
+    for (int row = wave; row < w.h; row += NW) {
+      const float* src = view + int64_t(w.y0 + row) * g.wa + w.x0;
+      float* drow = buf + row * kWinStride;
+      if (lane < w.w)
+        __builtin_amdgcn_global_load_lds(src + lane, (lds_ptr_t)drow, 4, 0, 0);
+      if (64 + lane < w.w)
+        __builtin_amdgcn_global_load_lds(src + 64 + lane, (lds_ptr_t)(drow + 64), 4, 0, 0);
     }
-  }
+  };
 
-  float acc[KP][RW];
+  float acc[RW];
 #pragma unroll
-  for (int k = 0; k < KP; ++k)
-#pragma unroll
-    for (int r = 0; r < RW; ++r) acc[k][r] = 0.0f;
+  for (int r = 0; r < RW; ++r) acc[r] = 0.0f;
 
   const int yb0 = split * yb_per_split;
   const int yb1 = (yb0 + yb_per_split) < g.hb ? yb0 + yb_per_split : g.hb;
+  const int nview = (yb1 - yb0) * g.wb;
+  Window wn = window(yb0, 0);
+  if (wn.fits) copy_window(gamma + int64_t(yb0) * g.wb * pa, wn, win0);
+
   for (int yb = yb0; yb < yb1; ++yb) {
-    int yoff[KP][RW];
-    float wy0[KP][RW], wy1[KP][RW];
+    YEntry yq[RW];
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int iby = itk[k][e_by + yb];
-      const float fby = ftk[k][e_by + yb];
-#pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        int y0 = iay[k][r] + iby;
-        float fy = fay[k][r] + fby;
-        if (fy >= 1.0f) {
-          y0 += 1;
-          fy -= 1.0f;
-        }
-        int c;
-        clamp_cell(y0, fy, g.ha, c, wy0[k][r], wy1[k][r]);
-        yoff[k][r] = c * g.wa;
-      }
+    for (int r = 0; r < RW; ++r) {
+      const int yr = ty_lo + r < g.out_h ? ty_lo + r : g.out_h - 1;
+      yq[r] = yw[int64_t(yb) * g.out_h + yr];
     }
-    float racc[KP][RW];
+    float racc[RW];
 #pragma unroll
-    for (int k = 0; k < KP; ++k)
-#pragma unroll
-      for (int r = 0; r < RW; ++r) racc[k][r] = 0.0f;
+    for (int r = 0; r < RW; ++r) racc[r] = 0.0f;
     const float* vrow = gamma + int64_t(yb) * g.wb * pa;
     for (int xb = 0; xb < g.wb; ++xb) {
+      const Window wc = wn;
       const float* view = vrow + int64_t(xb) * pa;
+      const int vi = (yb - yb0) * g.wb + xb;
+      float* cur = (vi & 1) ? win1 : win0;
+      float* nxt = (vi & 1) ? win0 : win1;
+      // This view's copy is complete for every wave, and every wave is done
+      // with the previous view, whose buffer the next copy reuses.
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+      __syncthreads();
+      if (vi + 1 < nview) {
+        const int nyb = yb0 + (vi + 1) / g.wb, nxb = (vi + 1) % g.wb;
+        wn = window(nyb, nxb);
+        if (wn.fits) copy_window(gamma + (int64_t(nyb) * g.wb + nxb) * pa, wn, nxt);
+      }
+      int x0 = iax + itw[e_bx + xb];
+      float fx = fax + ftw[e_bx + xb];
+      if (fx >= 1.0f) {
+        x0 += 1;
+        fx -= 1.0f;
+      }
+      int xc;
+      float wx0, wx1;
+      clamp_cell(x0, fx, g.wa, xc, wx0, wx1);
+      if (wc.fits) {
+        const float* wl = cur + (xc - wc.x0);
 #pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        int x0 = iax[k] + itk[k][e_bx + xb];
-        float fx = fax[k] + ftk[k][e_bx + xb];
-        if (fx >= 1.0f) {
-          x0 += 1;
-          fx -= 1.0f;
+        for (int r = 0; r < RW; ++r) {
+          const float* p = wl + (yq[r].row - wc.y0) * kWinStride;
+          const float g00 = p[0], g01 = p[1], g10 = p[kWinStride], g11 = p[kWinStride + 1];
+          const float top = __builtin_fmaf(wx1, g01, wx0 * g00);
+          const float bot = __builtin_fmaf(wx1, g11, wx0 * g10);
+          racc[r] = __builtin_fmaf(yq[r].w0, top, racc[r]);
+          racc[r] = __builtin_fmaf(yq[r].w1, bot, racc[r]);
         }
-        int xc;
-        float wx0, wx1;
-        clamp_cell(x0, fx, g.wa, xc, wx0, wx1);
+      } else {
         const float* vx = view + xc;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
-          const float* p = vx + yoff[k][r];
-          const float g00 = p[0], g01 = p[1], g10 = p[g.wa], g11 = p[g.wa + 1];
-          const float top = __builtin_fmaf(wx1, g01, wx0 * g00);
-          const float bot = __builtin_fmaf(wx1, g11, wx0 * g10);
-          racc[k][r] = __builtin_fmaf(wy0[k][r], top, racc[k][r]);
-          racc[k][r] = __builtin_fmaf(wy1[k][r], bot, racc[k][r]);
+          const float* p = vx + int64_t(yq[r].row) * g.wa;
+          const f2u t0 = *reinterpret_cast<const f2u*>(p);
+          const f2u t1 = *reinterpret_cast<const f2u*>(p + g.wa);
+          const float top = __builtin_fmaf(wx1, t0.y, wx0 * t0.x);
+          const float bot = __builtin_fmaf(wx1, t1.y, wx0 * t1.x);
+          racc[r] = __builtin_fmaf(yq[r].w0, top, racc[r]);
+          racc[r] = __builtin_fmaf(yq[r].w1, bot, racc[r]);
         }
       }
     }
 #pragma unroll
-    for (int k = 0; k < KP; ++k)
-#pragma unroll
-      for (int r = 0; r < RW; ++r) acc[k][r] += racc[k][r];
+    for (int r = 0; r < RW; ++r) acc[r] += racc[r];
   }
 
   const int64_t opix = int64_t(g.out_w) * g.out_h;
   float* d = dst + int64_t(split) * split_stride;
-  if (xr < g.out_w) {
+  if (xr < g.out_w && k0 + wave < n_alpha) {
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      if (k0 + k >= n_alpha) break;
-#pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        const int yr = yr0 + r;
-        if (yr < g.out_h) d[int64_t(k0 + k) * opix + int64_t(yr) * g.out_w + xr] = acc[k][r];
-      }
+    for (int r = 0; r < RW; ++r) {
+      const int yr = ty_lo + r;
+      if (yr < g.out_h) d[int64_t(k0 + wave) * opix + int64_t(yr) * g.out_w + xr] = acc[r];
     }
   }
 }
@@ -267,13 +394,13 @@ __global__ __launch_bounds__(256) void k_sum_splits(const float* __restrict__ pa
   }
 }
 
-template <int KP, int RW>
+template <int NW, int RW>
 hipError_t launch_batched(const float* gamma, const GeomI& gi, const int32_t* itab,
-                          const float* ftab, int64_t stride, int n_alpha, int splits,
-                          float* partial, float* out, hipStream_t s) {
+                          const float* ftab, const YEntry* ytab, int2* bounds, int64_t stride,
+                          int n_alpha, int splits, float* partial, float* out, hipStream_t s) {
   const int tiles_x = (gi.out_w + 63) / 64;
-  const int tiles_y = (gi.out_h + 4 * RW - 1) / (4 * RW);
-  const int groups = (n_alpha + KP - 1) / KP;
+  const int tiles_y = (gi.out_h + RW - 1) / RW;
+  const int groups = (n_alpha + NW - 1) / NW;
   if (splits > gi.hb) splits = gi.hb;
   if (splits < 1) splits = 1;
   const int ybs = (gi.hb + splits - 1) / splits;
@@ -283,9 +410,19 @@ hipError_t launch_batched(const float* gamma, const GeomI& gi, const int32_t* it
   const int64_t opix = int64_t(gi.out_w) * gi.out_h;
   const int64_t count = opix * n_alpha;
   float* dst = splits > 1 ? partial : out;
-  hipLaunchKernelGGL((k_ref_batched<KP, RW>), dim3(unsigned(nwg)), dim3(256), 0, s, gamma, gi,
-                     itab, ftab, stride, n_alpha, tiles_x, groups, splits, ybs, dst, count);
+  int2* bx = bounds;
+  int2* by = bounds + int64_t(groups) * tiles_x * gi.wb;
+  const int64_t nb = int64_t(groups) * (int64_t(tiles_x) * gi.wb + int64_t(tiles_y) * gi.hb);
+  int64_t gb = (nb + 255) / 256;
+  if (gb > 4096) gb = 4096;
+  hipLaunchKernelGGL(k_ref_bounds, dim3(unsigned(gb)), dim3(256), 0, s, gi, itab, stride, n_alpha,
+                     NW, RW, groups, tiles_x, tiles_y, bx, by);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ref_batched<NW, RW>), dim3(unsigned(nwg)), dim3(NW * 64), 0, s, gamma,
+                     gi, itab, ftab, ytab, bx, by, stride, n_alpha, tiles_x, tiles_y, groups,
+                     splits, ybs, dst, count);
+  e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;
   int64_t gr = (count + 255) / 256;
   if (gr > 16384) gr = 16384;
@@ -297,12 +434,17 @@ hipError_t launch_batched(const float* gamma, const GeomI& gi, const int32_t* it
 }  // namespace
 
 hipError_t refocus_tables(const RefGeom& g, const double* alphas, int first, int count,
-                          int64_t stride, int32_t* itab, float* ftab, hipStream_t s) {
+                          int64_t stride, int32_t* itab, float* ftab, void* ytab, hipStream_t s) {
   if (count < 1 || count > kAlphaPerLaunch) return hipErrorInvalidValue;
   AlphaPack ap;
   for (int k = 0; k < kAlphaPerLaunch; ++k) ap.a[k] = k < count ? alphas[first + k] : 0.0;
   hipLaunchKernelGGL(k_ref_tables, dim3(unsigned(count)), dim3(256), 0, s, ap, count, first, g,
                      stride, itab, ftab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !ytab) return e;
+  const GeomI gi{g.wa, g.ha, g.wb, g.hb, g.out_w, g.out_h};
+  hipLaunchKernelGGL(k_ref_ytab, dim3(unsigned(count)), dim3(256), 0, s, gi, itab, ftab, stride,
+                     first, count, static_cast<YEntry*>(ytab));
   return hipGetLastError();
 }
 
@@ -317,35 +459,30 @@ hipError_t refocus_plain(const float* gamma, const RefGeom& g, const int32_t* it
 }
 
 bool refocus_config_supported(const RefocusConfig& c) {
-  const bool kp_ok = c.kp == 1 || c.kp == 2 || c.kp == 4 || c.kp == 8;
-  const bool rw_ok = c.rw == 1 || c.rw == 2 || c.rw == 4 || c.rw == 8;
-  return kp_ok && rw_ok && c.kp * c.rw <= 32 && c.splits >= 1 && c.splits <= kMaxViewSplits;
+  const bool pair_ok = (c.kp == 4 && (c.rw == 8 || c.rw == 16)) ||
+                       (c.kp == 8 && (c.rw == 8 || c.rw == 16 || c.rw == 32)) ||
+                       (c.kp == 16 && (c.rw == 8 || c.rw == 16));
+  return pair_ok && c.splits >= 1 && c.splits <= kMaxViewSplits;
 }
 
 hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* itab,
-                           const float* ftab, int64_t stride, int n_alpha,
-                           const RefocusConfig& c, float* partial, float* out,
+                           const float* ftab, const void* ytab, void* bounds, int64_t stride,
+                           int n_alpha, const RefocusConfig& c, float* partial, float* out,
                            hipStream_t s) {
   const GeomI gi{g.wa, g.ha, g.wb, g.hb, g.out_w, g.out_h};
-#define CPI_REF_CASE(KP_, RW_)                                                               \
-  if (c.kp == KP_ && c.rw == RW_)                                                            \
-    return launch_batched<KP_, RW_>(gamma, gi, itab, ftab, stride, n_alpha, c.splits, partial, \
-                                    out, s);
-  CPI_REF_CASE(1, 1)
-  CPI_REF_CASE(1, 2)
-  CPI_REF_CASE(1, 4)
-  CPI_REF_CASE(1, 8)
-  CPI_REF_CASE(2, 1)
-  CPI_REF_CASE(2, 2)
-  CPI_REF_CASE(2, 4)
-  CPI_REF_CASE(2, 8)
-  CPI_REF_CASE(4, 1)
-  CPI_REF_CASE(4, 2)
-  CPI_REF_CASE(4, 4)
+  const YEntry* yt = static_cast<const YEntry*>(ytab);
+  int2* bd = static_cast<int2*>(bounds);
+#define CPI_REF_CASE(NW_, RW_)                                                                \
+  if (c.kp == NW_ && c.rw == RW_)                                                             \
+    return launch_batched<NW_, RW_>(gamma, gi, itab, ftab, yt, bd, stride, n_alpha, c.splits, \
+                                    partial, out, s);
   CPI_REF_CASE(4, 8)
-  CPI_REF_CASE(8, 1)
-  CPI_REF_CASE(8, 2)
-  CPI_REF_CASE(8, 4)
+  CPI_REF_CASE(4, 16)
+  CPI_REF_CASE(8, 8)
+  CPI_REF_CASE(8, 16)
+  CPI_REF_CASE(8, 32)
+  CPI_REF_CASE(16, 8)
+  CPI_REF_CASE(16, 16)
 #undef CPI_REF_CASE
   return hipErrorInvalidValue;
 }

@@ -72,6 +72,10 @@ cpi_status plan_correlate(int64_t n, int64_t pa, int64_t pb, int fmt, CorrPlan* 
   off = align256(off + size_t(q.pa_pad) * 8);
   q.off_sum_b = off;
   off = align256(off + size_t(q.pb_pad) * 8);
+  q.off_sum2_a = off;
+  if (fmt == CPI_FRAMES_U8) off = align256(off + size_t(q.pa_pad) * 8);
+  q.off_sum2_b = off;
+  if (fmt == CPI_FRAMES_U8) off = align256(off + size_t(q.pb_pad) * 8);
   q.off_stats = off;
   off = align256(off + 256);
   q.off_op_a = off;
@@ -170,6 +174,14 @@ cpi_status plan_refocus(const cpi_geometry* g, int32_t n_alpha, RefocusPlan* p,
   off = align256(off + size_t(n_alpha) * size_t(q.table_stride) * 4);
   q.off_ftab = off;
   off = align256(off + size_t(n_alpha) * size_t(q.table_stride) * 4);
+  q.off_ytab = off;
+  off = align256(off + size_t(n_alpha) * size_t(g->hb) * size_t(g->out_h) * 16);
+  // window bounds of the batched kernel: at most n_alpha/4 plane groups,
+  // ceil(out_w/64) tile columns and ceil(out_h/8) tile rows
+  q.off_bounds = off;
+  const size_t groups = size_t((n_alpha + 3) / 4);
+  off = align256(off + groups * (size_t((g->out_w + 63) / 64) * size_t(g->wb) +
+                                 size_t((g->out_h + 7) / 8) * size_t(g->hb)) * 8);
   q.off_partial = off;
   const int64_t splits = std::min<int64_t>(kMaxViewSplits, g->hb);
   q.partial_bytes = size_t(splits) * size_t(n_alpha) * size_t(g->out_w) * size_t(g->out_h) * 4;

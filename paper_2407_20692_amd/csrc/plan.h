@@ -42,7 +42,8 @@ struct CorrPlan {
   int64_t row_bytes_bytes = 0;      // kpad_bytes (U8 only)
   int passes = 1;                   // int32 passes for byte operands
   // workspace layout (byte offsets)
-  size_t off_sum_a = 0, off_sum_b = 0, off_stats = 0;
+  // sums: popcounts of the bit rows; sum2: byte sums (U8 data that is not binary)
+  size_t off_sum_a = 0, off_sum_b = 0, off_sum2_a = 0, off_sum2_b = 0, off_stats = 0;
   size_t off_op_a = 0, off_op_b = 0, off_acc64 = 0;
   size_t total = 0;
 };
@@ -66,7 +67,7 @@ cpi_status plan_correlate_plain(int64_t n, int64_t pa, int64_t pb, int fmt,
 // batched kernel when the view loop is split over work-groups.
 struct RefocusPlan {
   int64_t table_stride = 0;         // entries per plane: out_w + out_h + wb + hb
-  size_t off_itab = 0, off_ftab = 0, off_partial = 0;
+  size_t off_itab = 0, off_ftab = 0, off_ytab = 0, off_bounds = 0, off_partial = 0;
   size_t partial_bytes = 0;         // capacity reserved for partial sums
   size_t total = 0;
 };
