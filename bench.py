@@ -33,6 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 WORKLOAD = "da128_db64_n20000_u8bin"
+LARGE_WORKLOAD = "da256_db128_n100000_bit1"
 STREAM_WORKLOAD = "da128_db64_stream200x1000_bit1"
 INT8_PEAK = 5.0e15          # dense int8 matrix-core ops/s, MI355X
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemm_bits_da128_db64_n20000_pmc.txt")
@@ -115,6 +116,9 @@ def main():
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--workload", choices=["paper_like", "large"], default="paper_like",
+                    help="paper_like: Da 128x128, Db 64x64, N=20000 bytes (default line); "
+                         "large: Da 256x256, Db 128x128, N=100000 packed bits, 128 planes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -137,22 +141,31 @@ def main():
     import paper_2407_20692_amd as cpi
     from synth import WORKLOADS, alphas_for, generate_frames, pack_bits_lsb
 
-    w = WORKLOADS[WORKLOAD]
+    large = args.workload == "large"
+    w = WORKLOADS[LARGE_WORKLOAD if large else WORKLOAD]
     log(f"bench: generating {w.name}")
-    a, b = generate_frames(w)
     alphas = alphas_for(w)
     n, pa, pb = w.n_frames, w.pa, w.pb
-    da = torch.from_numpy(a.reshape(-1)).to(dev)
-    db = torch.from_numpy(b.reshape(-1)).to(dev)
+    if large:
+        from synth.gpu_speckle import generate_binary_frames_gpu
+        fmt = cpi.FRAMES_BIT1
+        pa_bits, pb_bits = generate_binary_frames_gpu(w, device=dev)
+        da, db = pa_bits.reshape(-1), pb_bits.reshape(-1)
+        a = b = None
+    else:
+        fmt = cpi.FRAMES_U8
+        a, b = generate_frames(w)
+        da = torch.from_numpy(a.reshape(-1)).to(dev)
+        db = torch.from_numpy(b.reshape(-1)).to(dev)
     gamma = torch.empty(pa * pb, dtype=torch.float64, device=dev)
     g32 = torch.empty(pa * pb, dtype=torch.float32, device=dev)
-    ws_c = cpi.alloc_workspace(cpi.correlate_workspace_size(n, pa, pb, cpi.FRAMES_U8), dev)
+    ws_c = cpi.alloc_workspace(cpi.correlate_workspace_size(n, pa, pb, fmt), dev)
     geo = cpi.geometry_default(w.wa, w.ha, w.wb, w.hb)
     out = torch.empty(len(alphas) * w.pa, dtype=torch.float32, device=dev)
     ws_r = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, len(alphas)), dev)
 
     def step():
-        cpi.correlate(da, db, n, pa, pb, cpi.FRAMES_U8, cpi.GAMMA_VIEW_MAJOR,
+        cpi.correlate(da, db, n, pa, pb, fmt, cpi.GAMMA_VIEW_MAJOR,
                       gamma=gamma, gamma_f32=g32, workspace=ws_c)
         cpi.refocus(g32, geo, alphas, out, workspace=ws_r)
 
@@ -185,14 +198,14 @@ def main():
     # plain FP32 comparison path on the same inputs
     log("bench: plain FP32 path")
     g32p = torch.empty(pa * pb, dtype=torch.float32, device=dev)
-    ws_p = cpi.alloc_workspace(cpi.correlate_f32_plain_workspace_size(n, pa, pb, cpi.FRAMES_U8), dev)
+    ws_p = cpi.alloc_workspace(cpi.correlate_f32_plain_workspace_size(n, pa, pb, fmt), dev)
     outp = torch.empty_like(out)
-    cpi.correlate_f32_plain(da, db, n, pa, pb, cpi.FRAMES_U8, g32p, workspace=ws_p)
+    cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
     cpi.refocus_plain(g32, geo, alphas, outp, workspace=ws_r)
     torch.cuda.synchronize()
     cpi.profile_begin()
     for _ in range(args.plain_steps):
-        cpi.correlate_f32_plain(da, db, n, pa, pb, cpi.FRAMES_U8, g32p, workspace=ws_p)
+        cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
         cpi.refocus_plain(g32, geo, alphas, outp, workspace=ws_r)
     torch.cuda.synchronize()
     cpi.profile_end()
@@ -219,7 +232,8 @@ def main():
         "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": w.name, "n_frames": n, "pa": pa, "pb": pb,
-                   "frames": "uint8 0/1, frame-major", "n_alpha": len(alphas),
+                   "frames": ("1-bit packed, frame-major (generated on the device)" if large
+                              else "uint8 0/1, frame-major"), "n_alpha": len(alphas),
                    "alpha_range": [float(alphas[0]), float(alphas[-1])],
                    "gamma_outputs": "FP64 + FP32, view-major"},
         "correlate": {"ms": ms_corr, "ingest_ms": groups["ingest"], "gemm_ms": groups["gemm"],
@@ -250,7 +264,9 @@ def main():
         "launch_ms": groups["gemm"],
     }
 
-    if not args.no_stream:
+    if large:
+        line["roofline"]["traffic"] = None   # counters were taken on the paper-like workload
+    if not args.no_stream and not large:
         ws = WORKLOADS[STREAM_WORKLOAD]
         log(f"bench: streaming {args.stream_chunks} chunks of {ws.chunk}")
         distinct = 20
@@ -296,7 +312,7 @@ def main():
         }
         st.close()
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not large:
         log("bench: CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(a, b, w, alphas)
     print(json.dumps(line), flush=True)
