@@ -4,9 +4,11 @@
 Workload: Da 128x128, Db 64x64, N = 20000 binary frames stored as bytes
 (SPAD-like occupancy ~0.1, seeded speckle through a 3-slit mask), 32 refocus
 planes alpha in [0.5, 1.5].  One step is one pass of the hot path with the
-inputs resident in HBM: ingest + int8 matrix-core contraction with the exact
+inputs resident in HBM: ingest + matrix-core contraction with the exact
 int64/FP64 epilogue (Gamma in FP64 and FP32) + batched refocus of 32 planes
-with the autotuned configuration (tuned once before timing).
+with the autotuned configuration (tuned once before timing).  Binary frames
+are contracted as FP4 (E2M1) 0/1 operands with FP32 sums, exact below 2^24
+frames per pass; the int8 encoding of the same contraction is timed beside it.
 
 Printed as ONE JSON line:
   value          Gamma pixel-pair*frames per second over the whole step
@@ -17,8 +19,9 @@ Printed as ONE JSON line:
   streaming      chunk-to-stack latency p50/p99 and frames/s for 1000-frame
                  1-bit chunks of the same geometry, each followed by a
                  32-plane refocus
-  roofline       the contraction kernel (dominant) against the int8 peak,
+  roofline       the contraction kernel (dominant) against the FP4 peak,
                  its duration measured with HIP events on its stream
+  roofline_int8  the same contraction in the int8 encoding against the int8 peak
   cpu_baseline   the CPU oracle on a bounded sample of the same workload
 """
 import argparse
@@ -36,7 +39,8 @@ WORKLOAD = "da128_db64_n20000_u8bin"
 LARGE_WORKLOAD = "da256_db128_n100000_bit1"
 STREAM_WORKLOAD = "da128_db64_stream200x1000_bit1"
 INT8_PEAK = 5.0e15          # dense int8 matrix-core ops/s, MI355X
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemm_bits_da128_db64_n20000_pmc.txt")
+FP4_PEAK = 10.1e15          # dense FP4 (and FP6) matrix-core ops/s, MI355X
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemm_f4lds_da128_db64_n20000_pmc.txt")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_gemm.hip")
 
 
@@ -195,6 +199,24 @@ def main():
     ms_corr = groups["ingest"] + groups["gemm"]
     ms_ref = groups["refocus_tables"] + groups["refocus_batched"]
 
+    # the same contraction in the int8 encoding (bit-identical results)
+    log("bench: int8 encoding of the contraction")
+    cpi.set_mma_encoding(cpi.MMA_INT8)
+    try:
+        cpi.correlate(da, db, n, pa, pb, fmt, cpi.GAMMA_VIEW_MAJOR,
+                      gamma=gamma, gamma_f32=g32, workspace=ws_c)
+        torch.cuda.synchronize()
+        cpi.profile_begin()
+        for _ in range(max(3, args.steps // 4)):
+            cpi.correlate(da, db, n, pa, pb, fmt, cpi.GAMMA_VIEW_MAJOR,
+                          gamma=gamma, gamma_f32=g32, workspace=ws_c)
+        torch.cuda.synchronize()
+        cpi.profile_end()
+        cnt, tot = cpi.profile_query("gemm")
+        ms_gemm_int8 = tot / max(cnt, 1)
+    finally:
+        cpi.set_mma_encoding(cpi.MMA_AUTO)
+
     # plain FP32 comparison path on the same inputs
     log("bench: plain FP32 path")
     g32p = torch.empty(pa * pb, dtype=torch.float32, device=dev)
@@ -229,7 +251,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "fp4-e2m1 0/1 operands, fp32 sums (exact); int64/fp64 epilogue; fp32 refocus",
         "data": "synthetic",
         "config": {"workload": w.name, "n_frames": n, "pa": pa, "pb": pb,
                    "frames": ("1-bit packed, frame-major (generated on the device)" if large
@@ -245,7 +267,7 @@ def main():
             "pixel_pair_frames_per_s": pairs / (ms_corr_p * 1e-3),
             "sgemm_tflops": 2 * pairs / (pg["sgemm_f32"] * 1e-3) / 1e12,
             "refocus_ms": ms_ref_p, "planes_per_s": len(alphas) / (ms_ref_p * 1e-3),
-            "int8_vs_fp32_correlate": ms_corr_p / ms_corr,
+            "mfma_vs_fp32_correlate": ms_corr_p / ms_corr,
             "batched_vs_plain_refocus": ms_ref_p / ms_ref,
         },
     }
@@ -253,15 +275,25 @@ def main():
     gemm_ops = 2.0 * pairs
     achieved = gemm_ops / (groups["gemm"] * 1e-3) / 1e12
     line["roofline"] = {
-        "kernel": "k_gemm<bits> (int8 MFMA contraction + exact epilogue)",
+        "kernel": "k_gemm_f4lds (FP4 matrix-core contraction, LDS pipeline, exact epilogue)",
         "bound": "mfma",
         "achieved": achieved,
-        "peak": INT8_PEAK / 1e12,
+        "peak": FP4_PEAK / 1e12,
         "unit": "TOP/s",
-        "frac": achieved * 1e12 / INT8_PEAK,
+        "frac": achieved * 1e12 / FP4_PEAK,
         "traffic": measured_traffic(),
         "algorithmic_ops_per_launch": gemm_ops,
         "launch_ms": groups["gemm"],
+    }
+    achieved8 = gemm_ops / (ms_gemm_int8 * 1e-3) / 1e12
+    line["roofline_int8"] = {
+        "kernel": "k_gemm<bits> (int8 matrix-core contraction, exact epilogue)",
+        "bound": "mfma",
+        "achieved": achieved8,
+        "peak": INT8_PEAK / 1e12,
+        "unit": "TOP/s",
+        "frac": achieved8 * 1e12 / INT8_PEAK,
+        "launch_ms": ms_gemm_int8,
     }
 
     if large:

@@ -7,8 +7,10 @@
  *     item 1):  Gamma(rho_a, rho_b) = <A(rho_a) B(rho_b)> - <A(rho_a)><B(rho_b)>
  *     over N frame pairs, both averages normalised by N.  It is evaluated
  *     exactly: numer = N * S_ab - S_a * S_b in int64 (S_ab the sum of
- *     products, S_a and S_b the per-pixel sums, S_ab contracted on int8 matrix
- *     cores with int32 partial sums), then gamma = fl64(fl64(numer) / fl64(N*N));
+ *     products, S_a and S_b the per-pixel sums, S_ab contracted on matrix
+ *     cores: binary frames as FP4 (E2M1) 0/1 operands with FP32 sums, or as
+ *     int8 with int32 sums, byte frames as int8; every partial sum is an
+ *     exact integer), then gamma = fl64(fl64(numer) / fl64(N*N));
  *
  *  2. refocusing (Section "CPI algorithm", item 2; refocusing optimisation in
  *     Section 4.1): for each plane parameter alpha and output pixel (x_r, y_r)
@@ -167,6 +169,22 @@ cpi_status cpi_autotune_refocus(const float* gamma, const cpi_geometry* g,
 cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha,
                               int32_t* planes_per_group, int32_t* rows_per_wave,
                               int32_t* view_splits);
+
+/* Matrix-core encoding of binary frames (CPI_FRAMES_BIT1, and CPI_FRAMES_U8
+ * data whose bytes are all 0 or 1).
+ *   CPI_MMA_AUTO (default): FP4 (E2M1) operands with FP32 accumulation when
+ *     one contraction pass covers at most 2^24 frames (every partial sum is
+ *     then an integer below 2^24, exact in FP32), int8 operands with int32
+ *     sums otherwise;
+ *   CPI_MMA_INT8: int8 operands with int32 sums always.
+ * Both give identical, exact results.  The setting is process-wide and
+ * applies to calls enqueued after it returns (cpi_correlate, cpi_stream_push);
+ * the environment variable CPI_GEMM_ENC=int8 sets CPI_MMA_INT8 at load time.
+ * Errors: CPI_ERR_INVALID_ARG for an unknown value. */
+typedef enum { CPI_MMA_AUTO = 0, CPI_MMA_INT8 = 1 } cpi_mma_encoding;
+
+cpi_status cpi_set_mma_encoding(cpi_mma_encoding enc);
+cpi_mma_encoding cpi_get_mma_encoding(void);
 
 /* ---------------------------------------------------------------------------
  * Streaming: frame chunks folded into device-resident sums as rank-k updates

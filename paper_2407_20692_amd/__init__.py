@@ -2,7 +2,7 @@
 and batched refocusing behind the C ABI of ``include/cpi.h``.
 
 Importing the package loads ``libcpi.so``; it raises ImportError when the
-library has not been built (``python -m paper_2407_20692_amd.build``).
+library has not been built (``python paper_2407_20692_amd/build.py``).
 """
 from .binding import (  # noqa: F401
     CpiError,
@@ -13,6 +13,8 @@ from .binding import (  # noqa: F401
     GAMMA_VIEW_MAJOR,
     Geometry,
     LIB_PATH,
+    MMA_AUTO,
+    MMA_INT8,
     Stream,
     alloc_workspace,
     autotune_refocus,
@@ -22,6 +24,7 @@ from .binding import (  # noqa: F401
     correlate_workspace_size,
     frame_bytes,
     geometry_default,
+    get_mma_encoding,
     last_error,
     lib,
     make_geometry,
@@ -32,6 +35,7 @@ from .binding import (  # noqa: F401
     refocus_config,
     refocus_plain,
     refocus_workspace_size,
+    set_mma_encoding,
     stream_workspace_size,
     version,
 )

@@ -30,6 +30,8 @@ FRAMES_U8 = 0
 FRAMES_BIT1 = 1
 GAMMA_VIEW_MAJOR = 0
 GAMMA_PIXEL_MAJOR = 1
+MMA_AUTO = 0
+MMA_INT8 = 1
 
 
 class CpiError(RuntimeError):
@@ -90,6 +92,8 @@ _SIGS = {
     "cpi_profile_begin": (c_int, []),
     "cpi_profile_end": (c_int, []),
     "cpi_profile_query": (c_int, [c_char_p, POINTER(c_int64), POINTER(c_double)]),
+    "cpi_set_mma_encoding": (c_int, [c_int]),
+    "cpi_get_mma_encoding": (c_int, []),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -104,7 +108,7 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "
-            "(python -m paper_2407_20692_amd.build)")
+            "(python paper_2407_20692_amd/build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
@@ -292,6 +296,16 @@ def refocus_config(g: Geometry, n_alpha: int):
 def autotune_refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
     """Times the refocus configurations, caches the best, leaves the result in out."""
     return _refocus_call(lib.cpi_autotune_refocus, gamma, g, alphas, out, workspace, stream)
+
+
+def set_mma_encoding(enc: int):
+    """MMA_AUTO (FP4 operands for binary frames where exact) or MMA_INT8;
+    process-wide, for calls enqueued afterwards."""
+    _check(lib.cpi_set_mma_encoding(enc))
+
+
+def get_mma_encoding() -> int:
+    return lib.cpi_get_mma_encoding()
 
 
 # ---------------------------------------------------------------------------

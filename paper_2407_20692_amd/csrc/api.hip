@@ -513,6 +513,19 @@ cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha, int32_t* p
   });
 }
 
+cpi_status cpi_set_mma_encoding(cpi_mma_encoding enc) {
+  return guarded([&]() -> cpi_status {
+    if (enc != CPI_MMA_AUTO && enc != CPI_MMA_INT8)
+      return set_error(CPI_ERR_INVALID_ARG, "unknown matrix-core encoding");
+    cpi::set_mma_encoding(int(enc));
+    return CPI_OK;
+  });
+}
+
+cpi_mma_encoding cpi_get_mma_encoding(void) {
+  return cpi_mma_encoding(cpi::get_mma_encoding());
+}
+
 // ---------------------------------------------------------------------------
 // Streaming
 // ---------------------------------------------------------------------------

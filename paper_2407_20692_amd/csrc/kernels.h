@@ -80,6 +80,10 @@ struct GemmArgs {
 // bits: operands are bit rows; otherwise int8 rows.
 hipError_t gemm_correlate(const GemmArgs& a, bool bits, hipStream_t s);
 
+// Matrix-core encoding of bit rows (a cpi_mma_encoding value), process-wide.
+void set_mma_encoding(int enc);
+int get_mma_encoding();
+
 // Gamma from a streaming state (view-major int32 or int64 S_ab, raw sums).
 hipError_t state_gamma(const void* sab, bool sab64, const int64_t* sum_a, const int64_t* sum_b,
                        int64_t n, int64_t pa, int64_t pb, int layout, double* gamma,

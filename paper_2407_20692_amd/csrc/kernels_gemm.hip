@@ -1,4 +1,4 @@
-// Sum of products S_ab = A^T B on int8 matrix cores (v_mfma_i32_16x16x64_i8),
+// Sum of products S_ab = A^T B on matrix cores (int8 or FP4 operands),
 // followed by the exact combination of Eq. (1):
 //     numer = N * S_ab - S_a * S_b        (int64)
 //     gamma = fl64(fl64(numer) / fl64(N * N))
@@ -18,10 +18,20 @@
 // MFMA operand and every word feeds two MFMAs.  Both operands use the same
 // lane/byte -> frame assignment, so every product pairs A and B of the same
 // frame, whatever order the hardware sums the K index in.
+//
+// Bit rows can instead feed the FP4 matrix-core op
+// (v_mfma_f32_16x16x128_f8f6f4 with E2M1 operands, no block scales): 0 and
+// 1 are exact E2M1 values (codes 0b0000, 0b0010), every product is 0 or 1 and
+// the FP32 accumulator holds integers exactly up to 2^24, so the sums equal
+// the int8 ones bit for bit as long as one launch covers at most 2^24 frames.
+// Word w of a lane supplies the lane's 32 K values of one such op: nibble k
+// of dword d is bit 4k + d of w, moved to bit 1 of the nibble.
 #include <hip/hip_runtime.h>
 
-#include <cstdio>
+#include <atomic>
 #include <cstdlib>
+#include <cstring>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -30,6 +40,19 @@ namespace cpi {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Scale operands 0 select the unscaled form of the op (plain products),
+// which issues faster than the block-scaled one.
+constexpr int kNoScale = 0;
+constexpr int kFmtE2M1 = 4;
+
+// The four E2M1 dwords (32 K values) of bit word x: value 1 <-> code 0b0010.
+__device__ __forceinline__ v8i fp4_operand(uint32_t x) {
+  const uint32_t m = 0x22222222u;
+  return v8i{int((x << 1) & m), int(x & m), int((x >> 1) & m), int((x >> 2) & m), 0, 0, 0, 0};
+}
 
 // Work-group b executes on XCD b % 8.  Give each XCD a contiguous range of
 // output tiles so that tiles sharing operand rows share that XCD's L2.
@@ -100,8 +123,9 @@ __device__ __forceinline__ void store_result(const Epi& g, int64_t q, int64_t p,
   if (g.numer) g.numer[idx] = numer;
 }
 
-template <int FM, int FN, bool BITS, int MODE, int SCHED, bool PF = true>
+template <int FM, int FN, bool BITS, int MODE, bool F4 = false>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  static_assert(BITS || !F4, "FP4 operands come from bit rows");
   if (g.cond) {
     const uint32_t mx = g.stats[0];
     if ((g.cond == 1) != (mx <= 1u)) return;
@@ -118,11 +142,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const uint8_t* pn = g.opn + (n0 + r) * g.row_bytes + g.k_byte_off + kg * 16;
   const int64_t fstride = 16 * g.row_bytes;
 
-  v4i acc[FM][FN];
+  using Acc = std::conditional_t<F4, v4f, v4i>;
+  Acc acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
   v4i am[FM], bn[FN];
 #pragma unroll
@@ -131,17 +156,30 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   for (int j = 0; j < FN; ++j) bn[j] = *reinterpret_cast<const v4i*>(pn + j * fstride);
 
   for (int64_t kb = 0; kb < g.kblocks; ++kb) {
-    // next block's operands: loaded now (PF) or at the end of the iteration
+    // next block's operands, loaded while this block is multiplied
     const int64_t nx = (kb + 1 < g.kblocks ? kb + 1 : kb) * 64;
     v4i am2[FM], bn2[FN];
-    if constexpr (PF) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i) am2[i] = *reinterpret_cast<const v4i*>(pm + i * fstride + nx);
+    for (int i = 0; i < FM; ++i) am2[i] = *reinterpret_cast<const v4i*>(pm + i * fstride + nx);
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bn2[j] = *reinterpret_cast<const v4i*>(pn + j * fstride + nx);
-    }
+    for (int j = 0; j < FN; ++j) bn2[j] = *reinterpret_cast<const v4i*>(pn + j * fstride + nx);
 
-    if constexpr (BITS) {
+    if constexpr (F4) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        v8i ea[FM], eb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) ea[i] = fp4_operand(uint32_t(am[i][w]));
+#pragma unroll
+        for (int j = 0; j < FN; ++j) eb[j] = fp4_operand(uint32_t(bn[j][w]));
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                ea[i], eb[j], acc[i][j], kFmtE2M1, kFmtE2M1, 0, kNoScale, 0, kNoScale);
+      }
+    } else if constexpr (BITS) {
       const int mask = 0x01010101;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
@@ -165,15 +203,6 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
             for (int j = 0; j < FN; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ea[i], eb[j], acc[i][j], 0, 0, 0);
-          if constexpr (SCHED > 0) {
-            // one matrix-core op, then SCHED vector ops (the next step's bit
-            // expansion), repeated over the step's FM*FN products
-#pragma unroll
-            for (int q = 0; q < FM * FN; ++q) {
-              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-              __builtin_amdgcn_sched_group_barrier(0x002, SCHED, 0);
-            }
-          }
         }
       }
     } else {
@@ -182,12 +211,6 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(am[i], bn[j], acc[i][j], 0, 0, 0);
-    }
-    if constexpr (!PF) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i) am2[i] = *reinterpret_cast<const v4i*>(pm + i * fstride + nx);
-#pragma unroll
-      for (int j = 0; j < FN; ++j) bn2[j] = *reinterpret_cast<const v4i*>(pn + j * fstride + nx);
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i) am[i] = am2[i];
@@ -209,6 +232,147 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         const int64_t q = m0 + 16 * i + 4 * kg + t;
         const int64_t p = n0 + 16 * j + r;
         if (q < e.pb && p < e.pa) store_result<MODE>(e, q, p, int64_t(acc[i][j][t]), o);
+      }
+}
+
+// ---- FP4 contraction fed through an LDS pipeline --------------------------
+// A work-group computes a 128 x 128 tile (2 x 2 waves of 64 x 64).  Each
+// 512-frame block needs 256 operand rows x 64 bytes = 16 KB, which direct
+// global->LDS copies (no registers) bring into one of S stages, S - 1 blocks
+// ahead of the block being multiplied; one barrier per block.  Each row
+// segment is fetched once per work-group.
+//
+// Stage layout: 16 groups of 16 rows (groups 0-7: M rows, 8-15: N rows),
+// 1 KB each, one copy instruction per group.  Chunk c (16 bytes) of row r of
+// a group sits at slot 4r + (c ^ ((r >> 2) & 3)), so the 16 lanes reading one
+// chunk column of a fragment touch 16 distinct 4-bank groups.
+//
+// LDS reads are issued by inline asm: the compiler would otherwise wait for
+// every outstanding global->LDS copy before each LDS read, serializing the
+// pipeline.  Ordering is explicit instead: each wave waits for its own copies
+// of the block (vmcnt), then a barrier makes every wave's copies visible and
+// guarantees that the stage about to be refilled has been read by all waves.
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Eight 16-byte LDS reads and the wait for them, as one unit.
+__device__ __forceinline__ void lds_read8(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3,
+                                          uint32_t a4, uint32_t a5, uint32_t a6, uint32_t a7,
+                                          v4i (&x)[4], v4i (&y)[4]) {
+  asm volatile(
+      "ds_read_b128 %0, %8\n"
+      "ds_read_b128 %1, %9\n"
+      "ds_read_b128 %2, %10\n"
+      "ds_read_b128 %3, %11\n"
+      "ds_read_b128 %4, %12\n"
+      "ds_read_b128 %5, %13\n"
+      "ds_read_b128 %6, %14\n"
+      "ds_read_b128 %7, %15\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(y[0]), "=&v"(y[1]),
+        "=&v"(y[2]), "=&v"(y[3])
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4), "v"(a5), "v"(a6), "v"(a7));
+}
+
+template <int S>
+__device__ __forceinline__ void wait_copies() {
+  // s_waitcnt vmcnt(4 * (S - 2)), expcnt and lgkmcnt left open
+  static_assert(S >= 2 && 4 * (S - 2) < 16, "stage count");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (4 * (S - 2)));
+}
+
+template <int MODE, int S>
+__global__ __launch_bounds__(256) void k_gemm_f4lds(GemmArgs g) {
+  if (g.cond) {
+    const uint32_t mx = g.stats[0];
+    if ((g.cond == 1) != (mx <= 1u)) return;
+  }
+  constexpr int kStage = 16384;
+  __shared__ __attribute__((aligned(16))) uint8_t stage[S * kStage];
+  const int tiles_m = int(g.m_pad / 128);
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int tm = id % tiles_m, tn = id / tiles_m;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t mb = int64_t(tm) * 128, nb = int64_t(tn) * 128;
+
+  // copy side: waves 0-1 copy the 128 M rows, waves 2-3 the 128 N rows, 64
+  // rows (4 groups) each; lane -> (row, chunk) within a group
+  const int cr = lane >> 2;
+  const int cc = (lane & 3) ^ ((cr >> 2) & 3);
+  const uint8_t* wbase = wave < 2 ? g.opm + (mb + 64 * wave) * g.row_bytes
+                                  : g.opn + (nb + 64 * (wave - 2)) * g.row_bytes;
+  // wave-uniform base + 32-bit lane offset (scalar-base addressing)
+  const uint8_t* ubase = wbase + g.k_byte_off;
+  const uint32_t loff = uint32_t(cr * g.row_bytes + 16 * cc);
+  const int64_t gstride = 16 * g.row_bytes;
+  const uint32_t lds0 = uint32_t(reinterpret_cast<uintptr_t>(stage));
+  auto copy_block = [&](int64_t kb, int st) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      __builtin_amdgcn_global_load_lds(ubase + (q * gstride + kb * 64) + loff,
+                                       (lds_ptr_t)(stage + st * kStage + (wave * 4 + q) * 1024),
+                                       16, 0, 0);
+  };
+
+  // read side
+  const int wm = wave & 1, wn = wave >> 1;
+  const int r = lane & 15, kg = lane >> 4;
+  const uint32_t roff = uint32_t(r * 64 + 16 * (kg ^ ((r >> 2) & 3)));
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+  const int64_t last = g.kblocks - 1;
+#pragma unroll
+  for (int p = 0; p < S - 1; ++p) copy_block(p < last ? p : last, p);
+
+  int st = 0;
+  for (int64_t kb = 0; kb < g.kblocks; ++kb) {
+    wait_copies<S>();
+    __builtin_amdgcn_s_barrier();
+    {
+      const int64_t nxt = kb + S - 1;
+      const int ns = st == 0 ? S - 1 : st - 1;   // (kb + S - 1) % S
+      copy_block(nxt < last ? nxt : last, ns);
+    }
+    const uint32_t base = lds0 + uint32_t(st * kStage) + roff;
+    const uint32_t ba = base + wm * 4096, bb = base + 8192 + wn * 4096;
+    v4i am[4], bn[4];
+    lds_read8(ba, ba + 1024, ba + 2048, ba + 3072, bb, bb + 1024, bb + 2048, bb + 3072, am, bn);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      v8i ea[4], eb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ea[i] = fp4_operand(uint32_t(am[i][w]));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) eb[j] = fp4_operand(uint32_t(bn[j][w]));
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+              ea[i], eb[j], acc[i][j], kFmtE2M1, kFmtE2M1, 0, kNoScale, 0, kNoScale);
+    }
+    st = st == S - 1 ? 0 : st + 1;
+  }
+  // the last copies (clamped repeats of the final block) are still in flight
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+
+  const Epi e{g.mode,   g.layout, g.pa,        g.pb,    g.n,     g.kchunk, g.sum_a, g.sum_b,
+              g.csum_a, g.csum_b, g.gamma,     g.gamma_f32, g.numer, g.acc64,  g.acc32};
+  const int64_t m0 = mb + wm * 64, n0 = nb + wn * 64;
+#pragma clang loop unroll(full)
+  for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+    for (int j = 0; j < 4; ++j)
+#pragma clang loop unroll(full)
+      for (int t = 0; t < 4; ++t) {
+        const int64_t q = m0 + 16 * i + 4 * kg + t;
+        const int64_t p = n0 + 16 * j + r;
+        if (q < e.pb && p < e.pa) store_result<MODE>(e, q, p, int64_t(acc[i][j][t]), 0);
       }
 }
 
@@ -236,48 +400,55 @@ __global__ __launch_bounds__(256) void k_state_gamma(const void* __restrict__ sa
   }
 }
 
-struct TileChoice {
-  int fm, fn, sched, pf;
-};
-
-// Contraction tile of the bit-row kernel: wave tile 16*fm x 16*fn, the
-// interleave of bit expansion with matrix-core ops, register prefetch of the
-// next operand block.  CPI_GEMM_TILE="FMxFN[sS][pP]" overrides the default
-// (measurement runs).
-TileChoice tile_choice() {
-  static TileChoice t = [] {
-    TileChoice c{4, 4, 0, 1};
-    if (const char* v = std::getenv("CPI_GEMM_TILE")) {
-      int fm = 0, fn = 0, sc = 0, pf = 1;
-      if (std::sscanf(v, "%dx%ds%dp%d", &fm, &fn, &sc, &pf) >= 2) c = TileChoice{fm, fn, sc, pf};
-    }
-    return c;
+// CPI_GEMM_FEED=regs selects the register-fed FP4 kernel (measurement runs);
+// the default feeds the matrix cores through the LDS pipeline.
+bool fp4_from_registers() {
+  static const bool on = [] {
+    const char* v = std::getenv("CPI_GEMM_FEED");
+    return v && std::strcmp(v, "regs") == 0;
   }();
-  return t;
+  return on;
 }
 
-template <int FM, int FN, bool BITS, int MODE, int SCHED, bool PF = true>
+template <int FM, int FN, bool BITS, int MODE, bool F4 = false>
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
   const int64_t tiles_m = a.m_pad / (32 * FM);
   const int64_t tiles_n = a.n_pad / (32 * FN);
   if (tiles_m * (32 * FM) != a.m_pad || tiles_n * (32 * FN) != a.n_pad) return hipErrorInvalidValue;
   const int64_t nwg = tiles_m * tiles_n;
   if (nwg <= 0 || nwg > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm<FM, FN, BITS, MODE, SCHED, PF>), dim3(unsigned(nwg)), dim3(256), 0, s,
-                     a);
+  hipLaunchKernelGGL((k_gemm<FM, FN, BITS, MODE, F4>), dim3(unsigned(nwg)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Matrix-core encoding of bit rows (CPI_MMA_AUTO or CPI_MMA_INT8), process-wide.
+std::atomic<int> g_mma_encoding{[] {
+  const char* v = std::getenv("CPI_GEMM_ENC");
+  return (v && std::strcmp(v, "int8") == 0) ? int(CPI_MMA_INT8) : int(CPI_MMA_AUTO);
+}()};
+
+bool fp4_enabled() { return g_mma_encoding.load(std::memory_order_relaxed) == CPI_MMA_AUTO; }
+
+constexpr int64_t kFp4MaxFrames = int64_t(1) << 24;
+
+template <int MODE, int S>
+hipError_t launch_f4lds(const GemmArgs& a, hipStream_t s) {
+  const int64_t tiles_m = a.m_pad / 128, tiles_n = a.n_pad / 128;
+  if (tiles_m * 128 != a.m_pad || tiles_n * 128 != a.n_pad || a.kblocks < 1)
+    return hipErrorInvalidValue;
+  const int64_t nwg = tiles_m * tiles_n;
+  if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gemm_f4lds<MODE, S>), dim3(unsigned(nwg)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 template <int MODE>
 hipError_t launch_bits(const GemmArgs& a, hipStream_t s) {
-  const TileChoice t = tile_choice();
-  if (t.fm == 8 && t.fn == 4) return launch_gemm<8, 4, true, MODE, 0>(a, s);
-  if (t.fm == 4 && t.fn == 4 && t.sched == 0 && t.pf == 0)
-    return launch_gemm<4, 4, true, MODE, 0, false>(a, s);
-  if (t.fm == 4 && t.fn == 4 && t.sched == 2) return launch_gemm<4, 4, true, MODE, 2>(a, s);
-  if (t.fm == 2 && t.fn == 4) return launch_gemm<2, 4, true, MODE, 0>(a, s);
-  if (t.fm == 4 && t.fn == 2) return launch_gemm<4, 2, true, MODE, 0>(a, s);
-  return launch_gemm<4, 4, true, MODE, 0>(a, s);
+  if (fp4_enabled() && a.kblocks * 512 <= kFp4MaxFrames) {
+    if (fp4_from_registers()) return launch_gemm<4, 4, true, MODE, true>(a, s);
+    return launch_f4lds<MODE, 3>(a, s);
+  }
+  return launch_gemm<4, 4, true, MODE>(a, s);
 }
 
 }  // namespace
@@ -285,23 +456,26 @@ hipError_t launch_bits(const GemmArgs& a, hipStream_t s) {
 hipError_t gemm_correlate(const GemmArgs& a, bool bits, hipStream_t s) {
   switch (a.mode) {
     case EPI_FINAL:
-      return bits ? launch_bits<EPI_FINAL>(a, s) : launch_gemm<4, 4, false, EPI_FINAL, 0>(a, s);
+      return bits ? launch_bits<EPI_FINAL>(a, s) : launch_gemm<4, 4, false, EPI_FINAL>(a, s);
     case EPI_STREAM32:
       return bits ? launch_bits<EPI_STREAM32>(a, s)
-                  : launch_gemm<4, 4, false, EPI_STREAM32, 0>(a, s);
+                  : launch_gemm<4, 4, false, EPI_STREAM32>(a, s);
     case EPI_FINAL_ACC64:
-      return launch_gemm<4, 4, false, EPI_FINAL_ACC64, 0>(a, s);
+      return launch_gemm<4, 4, false, EPI_FINAL_ACC64>(a, s);
     case EPI_STORE64:
-      return launch_gemm<4, 4, false, EPI_STORE64, 0>(a, s);
+      return launch_gemm<4, 4, false, EPI_STORE64>(a, s);
     case EPI_ADD64:
-      return launch_gemm<4, 4, false, EPI_ADD64, 0>(a, s);
+      return launch_gemm<4, 4, false, EPI_ADD64>(a, s);
     case EPI_STREAM64:
-      return bits ? launch_gemm<4, 4, true, EPI_STREAM64, 0>(a, s)
-                  : launch_gemm<4, 4, false, EPI_STREAM64, 0>(a, s);
+      return bits ? launch_bits<EPI_STREAM64>(a, s)
+                  : launch_gemm<4, 4, false, EPI_STREAM64>(a, s);
     default:
       return hipErrorInvalidValue;
   }
 }
+
+void set_mma_encoding(int enc) { g_mma_encoding.store(enc, std::memory_order_relaxed); }
+int get_mma_encoding() { return g_mma_encoding.load(std::memory_order_relaxed); }
 
 hipError_t state_gamma(const void* sab, bool sab64, const int64_t* sum_a, const int64_t* sum_b,
                        int64_t n, int64_t pa, int64_t pb, int layout, double* gamma,

@@ -12,6 +12,7 @@
 // nothing to any product.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "kernels.h"
@@ -39,23 +40,22 @@ __global__ void k_add_i64(int64_t* __restrict__ dst, const int64_t* __restrict__
     dst[i] += src[i];
 }
 
-// Lane-indexed insert of a wave-uniform value: lane L of `old` becomes v.
-// Written as a per-lane select so that the compiler sees an ordinary
-// lane-wise operation (a hand-placed v_writelane would be invisible to its
-// EXEC-masked register copies).
+// Lane-indexed insert of a wave-uniform value: lane L of `old` becomes v
+// (v_writelane_b32 through its LLVM intrinsic, so that the compiler knows the
+// operation).  Callers keep it out of divergent control flow: every lane of
+// the wave is active wherever it is used.
+extern "C" __device__ uint32_t cpi_llvm_writelane(uint32_t v, uint32_t lane, uint32_t old) __asm(
+    "llvm.amdgcn.writelane.i32");
+
 template <int L>
 __device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t v) {
-  return (threadIdx.x & 63) == L ? v : old;
+  return cpi_llvm_writelane(v, uint32_t(L), old);
 }
 
-// Bit of pixel J (0..127) in this lane's frame: 16 packed bytes or 128 bytes.
+// Bit of pixel J (0..127) in this lane's 16 packed bytes of one frame.
 template <int J>
 __device__ __forceinline__ uint32_t pixel_bit(const uint32_t (&d)[4]) {
   return (d[J >> 5] >> (J & 31)) & 1u;
-}
-template <int J>
-__device__ __forceinline__ uint32_t pixel_bit(const uint32_t (&d)[32]) {
-  return (d[J >> 2] >> (8 * (J & 3))) & 1u;
 }
 
 // One ballot per pixel J: bit l of the result is pixel J in frame f0 + l.
@@ -127,21 +127,31 @@ __global__ __launch_bounds__(64) void k_ingest_bits(
       w0[i] = 0;
       w1[i] = 0;
     }
+    // Branch-free: frames beyond n and bytes beyond the frame read valid
+    // addresses and are masked to zero, so the wave stays fully active.
     auto load = [&](int sub, uint32_t(&d)[4]) {
-      d[0] = d[1] = d[2] = d[3] = 0u;
       const int64_t f = kb * 512 + sub * 64 + lane;
-      if (f < n) {
-        const uint8_t* src = frames + f * fbytes + byte0;
-        if (vec) {
-          const uint4 v = *reinterpret_cast<const uint4*>(src);
-          d[0] = v.x;
-          d[1] = v.y;
-          d[2] = v.z;
-          d[3] = v.w;
-        } else {
-          for (int b = 0; b < 16; ++b)
-            if (byte0 + b < fbytes) d[b >> 2] |= uint32_t(src[b]) << (8 * (b & 3));
+      const bool fin = f < n;
+      const uint8_t* src = frames + (fin ? f : 0) * fbytes;
+      const uint32_t m = fin ? 0xffffffffu : 0u;
+      if (vec) {
+        const uint4 v = *reinterpret_cast<const uint4*>(src + byte0);
+        d[0] = v.x & m;
+        d[1] = v.y & m;
+        d[2] = v.z & m;
+        d[3] = v.w & m;
+      } else {
+        d[0] = d[1] = d[2] = d[3] = 0u;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          const bool ok = byte0 + b < fbytes;
+          const uint32_t x = src[ok ? byte0 + b : 0];
+          d[b >> 2] |= (ok ? x : 0u) << (8 * (b & 3));
         }
+        d[0] &= m;
+        d[1] &= m;
+        d[2] &= m;
+        d[3] &= m;
       }
     };
     transpose_block<4>(load, w0, w1, std::make_integer_sequence<int, 8>{});
@@ -162,68 +172,110 @@ __global__ __launch_bounds__(64) void k_ingest_bits(
   atomicAdd(&sums[p0 + 64 + lane], s1);
 }
 
-// Byte frames -> bit rows, as k_ingest_bits with each lane reading 128 bytes
-// of its frame.  The bit is the byte's low bit; the OR of all bytes goes to
-// stats[0], so the rows (and the popcount sums) are valid exactly when that
-// OR is at most 1.
-__global__ __launch_bounds__(64) void k_u8_to_bits(
-    const uint8_t* __restrict__ frames, int64_t n, int64_t npix, uint32_t* __restrict__ out,
-    int64_t kw, int64_t nblocks, int64_t blocks_per_slice, unsigned long long* __restrict__ sums,
-    uint32_t* __restrict__ stats) {
-  const int lane = threadIdx.x;
-  const int64_t p0 = int64_t(blockIdx.x) * 128;
+// Byte frames -> bit rows.  Each wave owns 256 consecutive pixels (lane l:
+// pixels 4l .. 4l+3, one dword of every frame row, so a wave reads 256
+// contiguous bytes per frame) and a slice of 512-frame blocks.  The low bits
+// of 8 frames are gathered into one byte per pixel (frame j of the 8 at bit
+// j: a mask and a shift-or per frame); four such octets are then regrouped
+// byte-wise into the 32-bit row words of the 4 pixels.  The OR of all bytes
+// goes to stats[0], so the rows (and the popcount sums) are valid exactly
+// when that OR is at most 1.
+__device__ __forceinline__ void bytes_transpose4(const uint32_t (&t)[4], uint32_t (&w)[4]) {
+  // w[k] byte o = t[o] byte k
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    w[k] = ((t[0] >> (8 * k)) & 0xffu) | (((t[1] >> (8 * k)) & 0xffu) << 8) |
+           (((t[2] >> (8 * k)) & 0xffu) << 16) | (((t[3] >> (8 * k)) & 0xffu) << 24);
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(256) void k_u8_to_bits(
+    const uint8_t* __restrict__ frames, int64_t n, int64_t npix, int64_t npix_pad,
+    uint32_t* __restrict__ out, int64_t kw, int64_t nblocks, int64_t blocks_per_slice,
+    unsigned long long* __restrict__ sums, uint32_t* __restrict__ stats) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t p0 = (int64_t(blockIdx.x) * 4 + wave) * 256;
+  if (p0 >= npix_pad || n <= 0) return;
+  const int64_t px = p0 + 4 * lane;
   const int64_t kb0 = int64_t(blockIdx.y) * blocks_per_slice;
   int64_t kb1 = kb0 + blocks_per_slice;
   if (kb1 > nblocks) kb1 = nblocks;
-  const bool vec = ((npix & 15) == 0) && (p0 + 128 <= npix);
   uint32_t any = 0;
-  unsigned long long s0 = 0, s1 = 0;
-  for (int64_t kb = kb0; kb < kb1; ++kb) {
-    uint32_t w0[16], w1[16];
+  uint32_t s[4] = {0u, 0u, 0u, 0u};
+  // Lanes whose pixels lie beyond npix read pixel 0 and mask their results
+  // (rows, sums, OR) to zero; frames beyond n, in the last block only, read
+  // frame 0 and are masked to zero per frame.
+  const bool pin = px < npix;
+  const uint32_t lane_off = uint32_t(pin ? px : 0);
+  const uint32_t pmask = pin ? 0xffffffffu : 0u;
+  auto load = [&](int64_t f) -> uint32_t {
+    const uint8_t* row = frames + f * npix;
+    if constexpr (ALIGNED) {
+      return *reinterpret_cast<const uint32_t*>(row + lane_off);
+    } else {
+      uint32_t v = 0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      w0[i] = 0;
-      w1[i] = 0;
+      for (int b = 0; b < 4; ++b) {
+        const uint32_t o = px + b < npix ? uint32_t(px + b) : 0u;
+        v |= uint32_t(row[o]) << (8 * b);
+      }
+      return v;
     }
-    auto load = [&](int sub, uint32_t(&d)[32]) {
+  };
+  auto block = [&](int64_t kb, auto tail) {
+    constexpr bool TAIL = decltype(tail)::value;
+    // four quarters of 128 frames: one 16-byte store per pixel row each
+    for (int q = 0; q < 4; ++q) {
+      uint32_t w[4][4];
 #pragma unroll
-      for (int i = 0; i < 32; ++i) d[i] = 0u;
-      const int64_t f = kb * 512 + sub * 64 + lane;
-      if (f < n) {
-        const uint8_t* src = frames + f * npix + p0;
-        if (vec) {
+      for (int g = 0; g < 4; ++g) {
+        const int64_t f0 = kb * 512 + q * 128 + g * 32;
+        uint32_t d[32];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const uint4 v = reinterpret_cast<const uint4*>(src)[q];
-            d[4 * q] = v.x;
-            d[4 * q + 1] = v.y;
-            d[4 * q + 2] = v.z;
-            d[4 * q + 3] = v.w;
+        for (int j = 0; j < 32; ++j) {
+          if constexpr (TAIL) {
+            const bool fin = f0 + j < n;
+            d[j] = load(fin ? f0 + j : 0) & (fin ? 0xffffffffu : 0u);
+          } else {
+            d[j] = load(f0 + j);
           }
-        } else {
-          for (int b = 0; b < 128; ++b)
-            if (p0 + b < npix) d[b >> 2] |= uint32_t(src[b]) << (8 * (b & 3));
         }
+        uint32_t t[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+          uint32_t acc = 0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            any |= d[8 * o + j];
+            acc |= (d[8 * o + j] & 0x01010101u) << j;
+          }
+          t[o] = acc;
+        }
+        uint32_t wk[4];
+        bytes_transpose4(t, wk);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k][g] = wk[k] & pmask;
       }
 #pragma unroll
-      for (int i = 0; i < 32; ++i) any |= d[i];
-    };
-    transpose_block<32>(load, w0, w1, std::make_integer_sequence<int, 8>{});
-    uint4* o0 = reinterpret_cast<uint4*>(out + (p0 + lane) * kw + kb * 16);
-    uint4* o1 = reinterpret_cast<uint4*>(out + (p0 + 64 + lane) * kw + kb * 16);
+      for (int k = 0; k < 4; ++k) {
+        *reinterpret_cast<uint4*>(out + (px + k) * kw + kb * 16 + q * 4) =
+            make_uint4(w[k][0], w[k][1], w[k][2], w[k][3]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      o0[q] = make_uint4(w0[4 * q], w0[4 * q + 1], w0[4 * q + 2], w0[4 * q + 3]);
-      o1[q] = make_uint4(w1[4 * q], w1[4 * q + 1], w1[4 * q + 2], w1[4 * q + 3]);
+        for (int g = 0; g < 4; ++g) s[k] += __popc(w[k][g]);
+      }
     }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      s0 += __popc(w0[i]);
-      s1 += __popc(w1[i]);
-    }
+  };
+  for (int64_t kb = kb0; kb < kb1; ++kb) {
+    if (kb * 512 + 512 <= n)
+      block(kb, std::false_type{});
+    else
+      block(kb, std::true_type{});
   }
-  atomicAdd(&sums[p0 + lane], s0);
-  atomicAdd(&sums[p0 + 64 + lane], s1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (s[k]) atomicAdd(&sums[px + k], (unsigned long long)s[k]);
+  any &= pmask;
   any = (any | (any >> 8) | (any >> 16) | (any >> 24)) & 0xffu;
   for (int off = 32; off > 0; off >>= 1) any |= __shfl_xor(any, off, 64);
   if (lane == 0 && any) atomicOr(stats, any);
@@ -392,13 +444,17 @@ hipError_t add_select_i64(int64_t* dst, const int64_t* from_bits, const int64_t*
 hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
                       uint8_t* out, int64_t kpad_bits, int64_t* sums, uint32_t* stats,
                       hipStream_t s) {
-  const int64_t groups = npix_pad / 128;
+  // a wave covers 256 rows: the padded row count must be a multiple of it
+  if (npix_pad % 256 != 0 || npix_pad < npix) return hipErrorInvalidValue;
+  const int64_t waves = npix_pad / 256;
+  const int64_t groups = (waves + 3) / 4;
   const int64_t nblocks = kpad_bits / 512;
-  const int64_t slices = slices_for(groups, nblocks, 8192);
+  const int64_t slices = slices_for(waves, nblocks, 8192);
   const int64_t bps = (nblocks + slices - 1) / slices;
   const int64_t used = (nblocks + bps - 1) / bps;
-  hipLaunchKernelGGL(k_u8_to_bits, dim3(unsigned(groups), unsigned(used)), dim3(64), 0, s,
-                     frames, n, npix, reinterpret_cast<uint32_t*>(out), kpad_bits / 32, nblocks,
+  auto* kern = (npix & 3) == 0 ? k_u8_to_bits<true> : k_u8_to_bits<false>;
+  hipLaunchKernelGGL(kern, dim3(unsigned(groups), unsigned(used)), dim3(256), 0, s, frames, n,
+                     npix, npix_pad, reinterpret_cast<uint32_t*>(out), kpad_bits / 32, nblocks,
                      bps, reinterpret_cast<unsigned long long*>(sums), stats);
   return hipGetLastError();
 }

@@ -119,3 +119,16 @@ def test_default_geometry(cpi):
     g = cpi.geometry_default(128, 96, 64, 32)
     assert (g.mag_x, g.mag_y, g.ca_x, g.ca_y, g.cb_x, g.cb_y) == (2.0, 3.0, 63.5, 47.5, 31.5, 15.5)
     assert (g.out_w, g.out_h) == (128, 96)
+
+
+def test_mma_encoding_switch(cpi):
+    before = cpi.get_mma_encoding()
+    try:
+        cpi.set_mma_encoding(cpi.MMA_INT8)
+        assert cpi.get_mma_encoding() == cpi.MMA_INT8
+        cpi.set_mma_encoding(cpi.MMA_AUTO)
+        assert cpi.get_mma_encoding() == cpi.MMA_AUTO
+        assert cpi.lib.cpi_set_mma_encoding(7) == 1          # CPI_ERR_INVALID_ARG
+        assert cpi.get_mma_encoding() == cpi.MMA_AUTO
+    finally:
+        cpi.set_mma_encoding(before)

@@ -111,6 +111,34 @@ def test_binary_bytes_match_packed_bits(cpi):
     assert_bit_exact(g1, g2)
 
 
+@pytest.mark.parametrize("enc", ["auto", "int8"])
+@pytest.mark.parametrize("n,pa,pb,kind", [(777, 1001, 77, "bits"), (1536, 512, 512, "bits"),
+                                          (4099, 300, 260, "u8_binary"), (1, 33, 18, "bits")])
+def test_binary_encodings(cpi, enc, n, pa, pb, kind):
+    """Binary frames through either matrix-core encoding (FP4 with FP32 sums,
+    int8 with int32 sums) give the oracle's results bit for bit; every frame
+    of one column pair set, so a sum reaches n."""
+    rng = np.random.default_rng(n + pa)
+    a = (rng.random((n, pa)) < 0.2).astype(np.uint8)
+    b = (rng.random((n, pb)) < 0.2).astype(np.uint8)
+    a[:, pa - 1] = 1
+    b[:, 0] = 1
+    fmt = cpi.FRAMES_BIT1 if kind == "bits" else cpi.FRAMES_U8
+    fa = pack_bits_lsb(a) if kind == "bits" else a
+    fb = pack_bits_lsb(b) if kind == "bits" else b
+    fa = np.concatenate([fa.reshape(-1), np.zeros(16, np.uint8)])
+    fb = np.concatenate([fb.reshape(-1), np.zeros(16, np.uint8)])
+    log(f"case encoding={enc} n={n} pa={pa} pb={pb} kind={kind}")
+    ref = oracle.correlation(fa, fb, n, pa, pb, fmt)
+    before = cpi.get_mma_encoding()
+    cpi.set_mma_encoding(cpi.MMA_INT8 if enc == "int8" else cpi.MMA_AUTO)
+    try:
+        got = run_correlate(cpi, fa, fb, n, pa, pb, fmt, cpi.GAMMA_VIEW_MAJOR)
+    finally:
+        cpi.set_mma_encoding(before)
+    assert_bit_exact(got, oracle_in_layout(ref, cpi.GAMMA_VIEW_MAJOR))
+
+
 @pytest.mark.parametrize("n", [131008, 131073, 270000])
 def test_int32_flush_passes(cpi, n):
     """Byte frames beyond 131008 frames fold int32 partial sums into int64."""
