@@ -62,6 +62,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nwg) {
   return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + i;
 }
 
+// Tile of work-group b: XCD-contiguous ranges, walked in groups of 8 tile
+// rows, so that the work-groups resident on one XCD at a time cover about
+// 8 x 8 tiles and re-use each other's operand rows in its L2.
+__device__ __forceinline__ void tile_of(int b, int nwg, int tiles_m, int* tm, int* tn) {
+  constexpr int kGroup = 8;
+  const int id = xcd_remap(b, nwg);
+  const int tiles_n = nwg / tiles_m;
+  const int per_group = kGroup * tiles_n;
+  const int grp = id / per_group;
+  const int m0 = grp * kGroup;
+  const int gm = (tiles_m - m0) < kGroup ? (tiles_m - m0) : kGroup;
+  const int in = id - grp * per_group;
+  *tm = m0 + in % gm;
+  *tn = in / gm;
+}
+
 // Epilogue fields, copied out of the kernel argument block into registers.
 struct Epi {
   int mode, layout;
@@ -123,6 +139,85 @@ __device__ __forceinline__ void store_result(const Epi& g, int64_t q, int64_t p,
   if (g.numer) g.numer[idx] = numer;
 }
 
+// Four consecutive detector-A pixels p..p+3 of view q, s[] in the operand
+// domain without offset (bit operands).  Vector loads and stores when the
+// quad is whole and 16-byte aligned in view-major order, else per element.
+template <int MODE>
+__device__ __forceinline__ void store_quad(const Epi& g, int64_t q, int64_t p, const int32_t (&s)[4],
+                                           bool vec) {
+  if (!vec) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (p + k < g.pa) store_result<MODE>(g, q, p + k, int64_t(s[k]), 0);
+    return;
+  }
+  const int64_t idx_vm = q * g.pa + p;
+  int64_t t[4];
+  if constexpr (MODE == EPI_STREAM32) {
+    int4 a = *reinterpret_cast<const int4*>(g.acc32 + idx_vm);
+    a.x += s[0];
+    a.y += s[1];
+    a.z += s[2];
+    a.w += s[3];
+    *reinterpret_cast<int4*>(g.acc32 + idx_vm) = a;
+    t[0] = a.x;
+    t[1] = a.y;
+    t[2] = a.z;
+    t[3] = a.w;
+  } else if constexpr (MODE == EPI_STREAM64) {
+    longlong2 a0 = *reinterpret_cast<const longlong2*>(g.acc64 + idx_vm);
+    longlong2 a1 = *reinterpret_cast<const longlong2*>(g.acc64 + idx_vm + 2);
+    a0.x += s[0];
+    a0.y += s[1];
+    a1.x += s[2];
+    a1.y += s[3];
+    *reinterpret_cast<longlong2*>(g.acc64 + idx_vm) = a0;
+    *reinterpret_cast<longlong2*>(g.acc64 + idx_vm + 2) = a1;
+    t[0] = a0.x;
+    t[1] = a0.y;
+    t[2] = a1.x;
+    t[3] = a1.y;
+  } else {
+    static_assert(MODE == EPI_FINAL, "quad epilogue modes");
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = s[k];
+  }
+  const int64_t n = g.n;
+  const int64_t sb = g.sum_b[q];
+  const longlong2 sa01 = *reinterpret_cast<const longlong2*>(g.sum_a + p);
+  const longlong2 sa23 = *reinterpret_cast<const longlong2*>(g.sum_a + p + 2);
+  const int64_t sa[4] = {sa01.x, sa01.y, sa23.x, sa23.y};
+  const double nn = double(n) * double(n);
+  int64_t num[4];
+  double gam[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    num[k] = n * t[k] - sa[k] * sb;
+    gam[k] = double(num[k]) / nn;
+  }
+  if (g.layout == CPI_GAMMA_VIEW_MAJOR) {
+    if (g.gamma) {
+      *reinterpret_cast<double2*>(g.gamma + idx_vm) = make_double2(gam[0], gam[1]);
+      *reinterpret_cast<double2*>(g.gamma + idx_vm + 2) = make_double2(gam[2], gam[3]);
+    }
+    if (g.gamma_f32)
+      *reinterpret_cast<float4*>(g.gamma_f32 + idx_vm) =
+          make_float4(float(gam[0]), float(gam[1]), float(gam[2]), float(gam[3]));
+    if (g.numer) {
+      *reinterpret_cast<longlong2*>(g.numer + idx_vm) = make_longlong2(num[0], num[1]);
+      *reinterpret_cast<longlong2*>(g.numer + idx_vm + 2) = make_longlong2(num[2], num[3]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t idx = (p + k) * g.pb + q;
+      if (g.gamma) g.gamma[idx] = gam[k];
+      if (g.gamma_f32) g.gamma_f32[idx] = float(gam[k]);
+      if (g.numer) g.numer[idx] = num[k];
+    }
+  }
+}
+
 template <int FM, int FN, bool BITS, int MODE, bool F4 = false>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   static_assert(BITS || !F4, "FP4 operands come from bit rows");
@@ -132,8 +227,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   }
   constexpr int WM = 16 * FM, WN = 16 * FN;
   const int tiles_m = int(g.m_pad / (2 * WM));
-  const int id = xcd_remap(blockIdx.x, gridDim.x);
-  const int tm = id % tiles_m, tn = id / tiles_m;
+  int tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, &tm, &tn);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, kg = lane >> 4;
   const int64_t m0 = int64_t(tm) * (2 * WM) + (wave & 1) * WM;
@@ -289,8 +384,8 @@ __global__ __launch_bounds__(256) void k_gemm_f4lds(GemmArgs g) {
   constexpr int kStage = 16384;
   __shared__ __attribute__((aligned(16))) uint8_t stage[S * kStage];
   const int tiles_m = int(g.m_pad / 128);
-  const int id = xcd_remap(blockIdx.x, gridDim.x);
-  const int tm = id % tiles_m, tn = id / tiles_m;
+  int tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, &tm, &tn);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t mb = int64_t(tm) * 128, nb = int64_t(tn) * 128;
@@ -358,22 +453,46 @@ __global__ __launch_bounds__(256) void k_gemm_f4lds(GemmArgs g) {
     }
     st = st == S - 1 ? 0 : st + 1;
   }
-  // the last copies (clamped repeats of the final block) are still in flight
+  // the last copies (clamped repeats of the final block) are still in flight;
+  // every wave must also be done with the stages before they are reused
   __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
 
+  // Epilogue through LDS, one half of the tile (64 rows) at a time: the two
+  // waves owning those rows store their sums (exact integers) into a padded
+  // row-major tile, then every thread finishes four consecutive columns of
+  // one row, so that state and output accesses are contiguous vectors.
+  constexpr int kPitch = 132;   // ints per staged row: 128 + 4 (bank spread)
+  static_assert(64 * kPitch * 4 <= S * kStage, "epilogue tile fits the stages");
+  int32_t* tile = reinterpret_cast<int32_t*>(stage);
   const Epi e{g.mode,   g.layout, g.pa,        g.pb,    g.n,     g.kchunk, g.sum_a, g.sum_b,
               g.csum_a, g.csum_b, g.gamma,     g.gamma_f32, g.numer, g.acc64,  g.acc32};
-  const int64_t m0 = mb + wm * 64, n0 = nb + wn * 64;
-#pragma clang loop unroll(full)
-  for (int i = 0; i < 4; ++i)
-#pragma clang loop unroll(full)
-    for (int j = 0; j < 4; ++j)
-#pragma clang loop unroll(full)
-      for (int t = 0; t < 4; ++t) {
-        const int64_t q = m0 + 16 * i + 4 * kg + t;
-        const int64_t p = n0 + 16 * j + r;
-        if (q < e.pb && p < e.pa) store_result<MODE>(e, q, p, int64_t(acc[i][j][t]), 0);
-      }
+  const bool vec = (g.pa & 3) == 0;
+  const int t = threadIdx.x;
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    if (wm == h) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            tile[(16 * i + 4 * kg + u) * kPitch + wn * 64 + 16 * j + r] = int32_t(acc[i][j][u]);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int step = 0; step < 8; ++step) {
+      const int row = step * 8 + (t >> 5);
+      const int cq = (t & 31) * 4;
+      const int64_t q = mb + 64 * h + row;
+      const int64_t p = nb + cq;
+      const int4 v = *reinterpret_cast<const int4*>(tile + row * kPitch + cq);
+      const int32_t sv[4] = {v.x, v.y, v.z, v.w};
+      if (q < e.pb && p < e.pa) store_quad<MODE>(e, q, p, sv, vec);
+    }
+    __syncthreads();
+  }
 }
 
 // One thread per Gamma element of a streaming state.
