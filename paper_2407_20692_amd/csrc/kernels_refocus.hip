@@ -223,11 +223,14 @@ __global__ __launch_bounds__(256) void k_ref_bounds(GeomI g, const int32_t* __re
 // memory into LDS (global_load_lds, no registers), double-buffered: the copy
 // of view v+1 is in flight while view v is interpolated, with one barrier per
 // view.  Rows have a fixed stride of kWinStride floats, so the two taps of a
-// row are adjacent and the next row is a constant offset away.  A view whose
-// window does not fit is read with direct paired gathers instead; both paths
-// give identical results.  Column coordinates are computed per lane for the
-// wave's own plane and reused for its RW rows; row coordinates come from the
-// row table as wave-uniform (scalar) values.
+// row are adjacent and the next row is a constant offset away.  When view
+// rows are a multiple of 4 floats long, the window starts on a 4-float
+// boundary and each copy instruction moves two window rows, 16 bytes per
+// lane; otherwise one float per lane.  A view whose window does not fit is
+// read with direct paired gathers instead; both paths give identical results.
+// Column coordinates are computed per lane for the wave's own plane and
+// reused for its RW rows; row coordinates come from the row table as
+// wave-uniform (scalar) values.
 constexpr int kWinStride = 128;           // LDS row stride (floats) = max window width
 constexpr int kWinRows = 64;              // max window height
 
@@ -274,19 +277,34 @@ __global__ __launch_bounds__(NW * 64) void k_ref_batched(
   const int2* bxw = bx + (int64_t(grp) * tiles_x + tile_x) * g.wb;
   const int2* byw = by + (int64_t(grp) * tiles_y + tile_y) * g.hb;
 
+  const bool quad = (g.wa & 3) == 0;
   auto window = [&](int yb, int xb) {
     const int2 cx = bxw[xb], cy = byw[yb];
     Window w;
-    w.x0 = cx.x;
+    w.x0 = quad ? (cx.x & ~3) : cx.x;
     w.y0 = cy.x;
-    w.w = cx.y - cx.x + 1;
+    w.w = cx.y - w.x0 + 1;
+    if (quad) w.w = (w.w + 3) & ~3;   // stays within the view: wa is a multiple of 4
     w.h = cy.y - cy.x + 1;
     w.fits = w.w <= kWinStride && w.h <= kWinRows;
     return w;
   };
-  // Copy a window into LDS: wave w copies rows w, w+NW, ...; lane l columns l
-  // and l+64 (lanes beyond the window width stay idle).
+  // Copy a window into LDS.  16-byte copies: instruction i (waves take turns)
+  // moves window rows 2i (lanes 0-31) and 2i+1 (lanes 32-63), 4 floats per
+  // lane, which land in LDS exactly at those rows' kWinStride-float slots.
+  // 4-byte copies: wave w copies rows w, w+NW, ...; lane l columns l and l+64.
+  // Lanes beyond the window stay idle.
   auto copy_window = [&](const float* view, const Window& w, float* buf) {
+    if (quad) {
+      const int half = lane >> 5, c4 = (lane & 31) * 4;
+      for (int i = wave; 2 * i < w.h; i += NW) {
+        const int row = 2 * i + half;
+        if (row < w.h && c4 < w.w)
+          __builtin_amdgcn_global_load_lds(view + int64_t(w.y0 + row) * g.wa + w.x0 + c4,
+                                           (lds_ptr_t)(buf + 2 * i * kWinStride), 16, 0, 0);
+      }
+      return;
+    }
     for (int row = wave; row < w.h; row += NW) {
       const float* src = view + int64_t(w.y0 + row) * g.wa + w.x0;
       float* drow = buf + row * kWinStride;
