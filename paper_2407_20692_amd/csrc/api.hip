@@ -150,14 +150,20 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
   g.gamma_f32 = gamma_f32;
   g.numer = numer;
 
+  // matrix-core encoding of the bit contraction, decided once for this call:
+  // FP4 needs the M rows (detector B) with bits 0 and 2 of each group swapped
+  const bool fp4 = cpi::bits_use_fp4(pl.kpad_bits / cpi::kBitBlock);
   if (pl.fmt == CPI_FRAMES_BIT1) {
     {
       ProfScope ps("ingest", st);
-      CPI_HIP(cpi::ingest_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, st), "ingest");
-      CPI_HIP(cpi::ingest_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, st), "ingest");
+      CPI_HIP(cpi::ingest_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, false, st),
+              "ingest");
+      CPI_HIP(cpi::ingest_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, fp4, st),
+              "ingest");
     }
     g.row_bytes = pl.row_bytes_bits;
     g.kblocks = pl.kpad_bits / cpi::kBitBlock;
+    g.fp4 = fp4 ? 1 : 0;
     g.mode = cpi::EPI_FINAL;
     ProfScope ps("gemm", st);
     CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
@@ -174,8 +180,10 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
     ProfScope ps("ingest", st);
     CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum2_a), pl.pa_pad, 0, st), "fill");
     CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum2_b), pl.pb_pad, 0, st), "fill");
-    CPI_HIP(cpi::u8_to_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, stats, st), "ingest");
-    CPI_HIP(cpi::u8_to_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, stats, st), "ingest");
+    CPI_HIP(cpi::u8_to_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, stats, false, st),
+            "ingest");
+    CPI_HIP(cpi::u8_to_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, stats, fp4, st),
+            "ingest");
     CPI_HIP(cpi::u8_sums(fa, pl.n, pl.pa, sum2_a, stats, st), "sums");
     CPI_HIP(cpi::u8_sums(fb, pl.n, pl.pb, sum2_b, stats, st), "sums");
     CPI_HIP(cpi::u8_to_bytes(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bytes, stats, st), "ingest");
@@ -188,6 +196,7 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
   gb.kblocks = pl.kpad_bits / cpi::kBitBlock;
   gb.mode = cpi::EPI_FINAL;
   gb.cond = 1;
+  gb.fp4 = fp4 ? 1 : 0;
   CPI_HIP(cpi::gemm_correlate(gb, true, st), "gemm");
 
   cpi::GemmArgs gy = g;
@@ -600,11 +609,15 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
   g.stats = stats;
   g.gamma_f32 = reinterpret_cast<float*>(h->ws + h->plan.off_gamma32);
 
+  const bool fp4 = cpi::bits_use_fp4(cp.kpad_bits / cpi::kBitBlock);
+  g.fp4 = fp4 ? 1 : 0;
   if (h->fmt == CPI_FRAMES_BIT1) {
     {
       ProfScope ps("ingest", st);
-      CPI_HIP(cpi::ingest_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, st), "ingest");
-      CPI_HIP(cpi::ingest_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, st), "ingest");
+      CPI_HIP(cpi::ingest_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, false, st),
+              "ingest");
+      CPI_HIP(cpi::ingest_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, fp4, st),
+              "ingest");
       CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
       CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
     }
@@ -621,8 +634,10 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
       ProfScope ps("ingest", st);
       CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum2_a), cp.pa_pad, 0, st), "fill");
       CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum2_b), cp.pb_pad, 0, st), "fill");
-      CPI_HIP(cpi::u8_to_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, stats, st), "ingest");
-      CPI_HIP(cpi::u8_to_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, stats, st), "ingest");
+      CPI_HIP(cpi::u8_to_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, stats, false, st),
+              "ingest");
+      CPI_HIP(cpi::u8_to_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, stats, fp4, st),
+              "ingest");
       CPI_HIP(cpi::u8_sums(fa, k, h->pa, csum2_a, stats, st), "sums");
       CPI_HIP(cpi::u8_sums(fb, k, h->pb, csum2_b, stats, st), "sums");
       CPI_HIP(cpi::add_select_i64(tot_a, csum_a, csum2_a, cp.pa_pad, stats, st), "sums");

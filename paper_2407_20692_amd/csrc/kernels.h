@@ -17,16 +17,19 @@ hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t 
 
 // ---- ingest: frame-major frames -> pixel-major operands ------------------
 // Packed-bit frames -> bit rows (row_bytes = kpad_bits/8), per-pixel popcounts
-// added into sums (int64).  Rows [npix, npix_pad) are written too.
+// added into sums (int64).  Rows [npix, npix_pad) are written too.  swap02:
+// bits 0 and 2 of every 4-bit group of each row word are exchanged (the
+// layout of the M operand of the FP4 contraction).
 hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                       uint8_t* out, int64_t kpad_bits, int64_t* sums, hipStream_t s);
+                       uint8_t* out, int64_t kpad_bits, int64_t* sums, bool swap02,
+                       hipStream_t s);
 // Byte frames -> bit rows (bit = low bit of the byte) with per-pixel popcounts
 // added into sums, and the OR of every byte accumulated into stats[0].  The
 // rows and popcounts are the data exactly when stats[0] <= 1 (binary data);
-// stats[0] > 127 exactly when some byte exceeds 127.
+// stats[0] > 127 exactly when some byte exceeds 127.  swap02 as above.
 hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
                       uint8_t* out, int64_t kpad_bits, int64_t* sums, uint32_t* stats,
-                      hipStream_t s);
+                      bool swap02, hipStream_t s);
 // Per-pixel byte sums (int64, added into sums), executed only when
 // stats[0] > 1.
 hipError_t u8_sums(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
@@ -62,6 +65,7 @@ struct GemmArgs {
   int mode = EPI_FINAL;
   int layout = CPI_GAMMA_VIEW_MAJOR;
   int cond = 0;                     // 0 always; 1 iff stats[0] <= 1; 2 iff stats[0] > 1
+  int fp4 = 0;                      // bit rows as FP4 operands (M rows stored with swap02)
   int offset_from_stats = 0;        // byte operands offset by -128 iff stats[0] > 127
   int64_t pa = 0, pb = 0, n = 0;    // n: frames behind the result
   int64_t kchunk = 0;               // frames of this chunk (EPI_STREAM64)
@@ -79,6 +83,11 @@ struct GemmArgs {
 
 // bits: operands are bit rows; otherwise int8 rows.
 hipError_t gemm_correlate(const GemmArgs& a, bool bits, hipStream_t s);
+
+// Whether a bit-row contraction over kblocks 512-frame blocks takes the FP4
+// encoding (then its M rows must be ingested with swap02) under the current
+// matrix-core encoding setting.  Decided once per call by the caller.
+bool bits_use_fp4(int64_t kblocks);
 
 // Matrix-core encoding of bit rows (a cpi_mma_encoding value), process-wide.
 void set_mma_encoding(int enc);

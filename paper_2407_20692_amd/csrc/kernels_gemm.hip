@@ -20,12 +20,18 @@
 // frame, whatever order the hardware sums the K index in.
 //
 // Bit rows can instead feed the FP4 matrix-core op
-// (v_mfma_f32_16x16x128_f8f6f4 with E2M1 operands, no block scales): 0 and
-// 1 are exact E2M1 values (codes 0b0000, 0b0010), every product is 0 or 1 and
-// the FP32 accumulator holds integers exactly up to 2^24, so the sums equal
-// the int8 ones bit for bit as long as one launch covers at most 2^24 frames.
-// Word w of a lane supplies the lane's 32 K values of one such op: nibble k
-// of dword d is bit 4k + d of w, moved to bit 1 of the nibble.
+// (v_mfma_f32_16x16x128_f8f6f4 with E2M1 operands, no block scales).  Word w
+// of a lane supplies the lane's 32 K values of one such op: nibble k of
+// dword d holds frame 4k + d of the word.  A single set bit is an exact
+// E2M1 value (bit 0: 0.5, bit 1: 1, bit 2: 2), so a dword can often be cut
+// out of the word with one AND: the N operand takes dwords 0, 1, 2 as
+// w & 0x1..., w & 0x2..., w & 0x4... (values 0.5, 1, 2), and the M rows are
+// stored with bits 0 and 2 of every 4-bit group exchanged, so the same ANDs
+// give it values 2, 1, 0.5 for the same frames.  Frame 4k + 3 sits on the
+// sign bit and is shifted to bit 1 (value 1) on both sides.  Every product
+// of two set bits is then exactly 1, the FP32 accumulator holds integers
+// exactly up to 2^24, and the sums equal the int8 ones bit for bit as long
+// as one launch covers at most 2^24 frames.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -48,10 +54,17 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kNoScale = 0;
 constexpr int kFmtE2M1 = 4;
 
-// The four E2M1 dwords (32 K values) of bit word x: value 1 <-> code 0b0010.
-__device__ __forceinline__ v8i fp4_operand(uint32_t x) {
-  const uint32_t m = 0x22222222u;
-  return v8i{int((x << 1) & m), int(x & m), int((x >> 1) & m), int((x >> 2) & m), 0, 0, 0, 0};
+// The four E2M1 dwords (32 K values) of bit word x of an N row (plain
+// layout: frames 4k + 0, 1, 2 at values 0.5, 1, 2; frame 4k + 3 at 1) ...
+__device__ __forceinline__ v8i fp4_operand_n(uint32_t x) {
+  return v8i{int(x & 0x11111111u), int(x & 0x22222222u), int(x & 0x44444444u),
+             int((x >> 2) & 0x22222222u), 0, 0, 0, 0};
+}
+// ... and of an M row stored with bits 0 and 2 of each group exchanged
+// (frames 4k + 0, 1, 2 at values 2, 1, 0.5; frame 4k + 3 at 1).
+__device__ __forceinline__ v8i fp4_operand_m(uint32_t x) {
+  return v8i{int(x & 0x44444444u), int(x & 0x22222222u), int(x & 0x11111111u),
+             int((x >> 2) & 0x22222222u), 0, 0, 0, 0};
 }
 
 // Work-group b executes on XCD b % 8.  Give each XCD a contiguous range of
@@ -264,9 +277,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       for (int w = 0; w < 4; ++w) {
         v8i ea[FM], eb[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) ea[i] = fp4_operand(uint32_t(am[i][w]));
+        for (int i = 0; i < FM; ++i) ea[i] = fp4_operand_m(uint32_t(am[i][w]));
 #pragma unroll
-        for (int j = 0; j < FN; ++j) eb[j] = fp4_operand(uint32_t(bn[j][w]));
+        for (int j = 0; j < FN; ++j) eb[j] = fp4_operand_n(uint32_t(bn[j][w]));
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -441,9 +454,9 @@ __global__ __launch_bounds__(256) void k_gemm_f4lds(GemmArgs g) {
     for (int w = 0; w < 4; ++w) {
       v8i ea[4], eb[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ea[i] = fp4_operand(uint32_t(am[i][w]));
+      for (int i = 0; i < 4; ++i) ea[i] = fp4_operand_m(uint32_t(am[i][w]));
 #pragma unroll
-      for (int j = 0; j < 4; ++j) eb[j] = fp4_operand(uint32_t(bn[j][w]));
+      for (int j = 0; j < 4; ++j) eb[j] = fp4_operand_n(uint32_t(bn[j][w]));
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -563,7 +576,8 @@ hipError_t launch_f4lds(const GemmArgs& a, hipStream_t s) {
 
 template <int MODE>
 hipError_t launch_bits(const GemmArgs& a, hipStream_t s) {
-  if (fp4_enabled() && a.kblocks * 512 <= kFp4MaxFrames) {
+  if (a.fp4) {
+    if (a.kblocks * 512 > kFp4MaxFrames) return hipErrorInvalidValue;
     if (fp4_from_registers()) return launch_gemm<4, 4, true, MODE, true>(a, s);
     return launch_f4lds<MODE, 3>(a, s);
   }
@@ -592,6 +606,8 @@ hipError_t gemm_correlate(const GemmArgs& a, bool bits, hipStream_t s) {
       return hipErrorInvalidValue;
   }
 }
+
+bool bits_use_fp4(int64_t kblocks) { return fp4_enabled() && kblocks * 512 <= kFp4MaxFrames; }
 
 void set_mma_encoding(int enc) { g_mma_encoding.store(enc, std::memory_order_relaxed); }
 int get_mma_encoding() { return g_mma_encoding.load(std::memory_order_relaxed); }

@@ -96,6 +96,11 @@ __device__ __forceinline__ void transpose_block(Load&& load, uint32_t (&w0)[16],
   (transpose_sub<S, ND>(load, w0, w1), ...);
 }
 
+// Exchange bits 0 and 2 of every 4-bit group.
+__device__ __forceinline__ uint32_t swap_bits02(uint32_t x) {
+  return (x & 0xAAAAAAAAu) | ((x & 0x11111111u) << 2) | ((x >> 2) & 0x11111111u);
+}
+
 unsigned grid_for(int64_t count, int threads) {
   int64_t g = (count + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -111,7 +116,7 @@ unsigned grid_for(int64_t count, int threads) {
 __global__ __launch_bounds__(64) void k_ingest_bits(
     const uint8_t* __restrict__ frames, int64_t n, int64_t fbytes, uint32_t* __restrict__ out,
     int64_t kw, int64_t nblocks, int64_t blocks_per_slice,
-    unsigned long long* __restrict__ sums) {
+    unsigned long long* __restrict__ sums, int swap02) {
   const int lane = threadIdx.x;
   const int64_t p0 = int64_t(blockIdx.x) * 128;
   const int64_t byte0 = p0 >> 3;
@@ -155,17 +160,21 @@ __global__ __launch_bounds__(64) void k_ingest_bits(
       }
     };
     transpose_block<4>(load, w0, w1, std::make_integer_sequence<int, 8>{});
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      s0 += __popc(w0[i]);
+      s1 += __popc(w1[i]);
+      if (swap02) {
+        w0[i] = swap_bits02(w0[i]);
+        w1[i] = swap_bits02(w1[i]);
+      }
+    }
     uint4* o0 = reinterpret_cast<uint4*>(out + (p0 + lane) * kw + kb * 16);
     uint4* o1 = reinterpret_cast<uint4*>(out + (p0 + 64 + lane) * kw + kb * 16);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       o0[q] = make_uint4(w0[4 * q], w0[4 * q + 1], w0[4 * q + 2], w0[4 * q + 3]);
       o1[q] = make_uint4(w1[4 * q], w1[4 * q + 1], w1[4 * q + 2], w1[4 * q + 3]);
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      s0 += __popc(w0[i]);
-      s1 += __popc(w1[i]);
     }
   }
   atomicAdd(&sums[p0 + lane], s0);
@@ -192,7 +201,7 @@ template <bool ALIGNED>
 __global__ __launch_bounds__(256) void k_u8_to_bits(
     const uint8_t* __restrict__ frames, int64_t n, int64_t npix, int64_t npix_pad,
     uint32_t* __restrict__ out, int64_t kw, int64_t nblocks, int64_t blocks_per_slice,
-    unsigned long long* __restrict__ sums, uint32_t* __restrict__ stats) {
+    unsigned long long* __restrict__ sums, uint32_t* __restrict__ stats, int swap02) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t p0 = (int64_t(blockIdx.x) * 4 + wave) * 256;
@@ -259,10 +268,13 @@ __global__ __launch_bounds__(256) void k_u8_to_bits(
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          s[k] += __popc(w[k][g]);
+          if (swap02) w[k][g] = swap_bits02(w[k][g]);
+        }
         *reinterpret_cast<uint4*>(out + (px + k) * kw + kb * 16 + q * 4) =
             make_uint4(w[k][0], w[k][1], w[k][2], w[k][3]);
-#pragma unroll
-        for (int g = 0; g < 4; ++g) s[k] += __popc(w[k][g]);
       }
     }
   };
@@ -399,7 +411,8 @@ hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t 
 }
 
 hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                       uint8_t* out, int64_t kpad_bits, int64_t* sums, hipStream_t s) {
+                       uint8_t* out, int64_t kpad_bits, int64_t* sums, bool swap02,
+                       hipStream_t s) {
   const int64_t groups = npix_pad / 128;
   const int64_t nblocks = kpad_bits / 512;
   const int64_t slices = slices_for(groups, nblocks, 8192);
@@ -407,7 +420,7 @@ hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t n
   const int64_t used = (nblocks + bps - 1) / bps;
   hipLaunchKernelGGL(k_ingest_bits, dim3(unsigned(groups), unsigned(used)), dim3(64), 0, s,
                      frames, n, (npix + 7) / 8, reinterpret_cast<uint32_t*>(out), kpad_bits / 32,
-                     nblocks, bps, reinterpret_cast<unsigned long long*>(sums));
+                     nblocks, bps, reinterpret_cast<unsigned long long*>(sums), swap02 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -443,7 +456,7 @@ hipError_t add_select_i64(int64_t* dst, const int64_t* from_bits, const int64_t*
 
 hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
                       uint8_t* out, int64_t kpad_bits, int64_t* sums, uint32_t* stats,
-                      hipStream_t s) {
+                      bool swap02, hipStream_t s) {
   // a wave covers 256 rows: the padded row count must be a multiple of it
   if (npix_pad % 256 != 0 || npix_pad < npix) return hipErrorInvalidValue;
   const int64_t waves = npix_pad / 256;
@@ -455,7 +468,7 @@ hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t np
   auto* kern = (npix & 3) == 0 ? k_u8_to_bits<true> : k_u8_to_bits<false>;
   hipLaunchKernelGGL(kern, dim3(unsigned(groups), unsigned(used)), dim3(256), 0, s, frames, n,
                      npix, npix_pad, reinterpret_cast<uint32_t*>(out), kpad_bits / 32, nblocks,
-                     bps, reinterpret_cast<unsigned long long*>(sums), stats);
+                     bps, reinterpret_cast<unsigned long long*>(sums), stats, swap02 ? 1 : 0);
   return hipGetLastError();
 }
 
