@@ -183,7 +183,7 @@ __global__ __launch_bounds__(64) void k_ingest_bits(
 
 // Byte frames -> bit rows.  Each wave owns 256 consecutive pixels (lane l:
 // pixels 4l .. 4l+3, one dword of every frame row, so a wave reads 256
-// contiguous bytes per frame) and a slice of 512-frame blocks.  The low bits
+// contiguous bytes per frame) and a slice of 128-frame units.  The low bits
 // of 8 frames are gathered into one byte per pixel (frame j of the 8 at bit
 // j: a mask and a shift-or per frame); four such octets are then regrouped
 // byte-wise into the 32-bit row words of the 4 pixels.  The OR of all bytes
@@ -200,16 +200,16 @@ __device__ __forceinline__ void bytes_transpose4(const uint32_t (&t)[4], uint32_
 template <bool ALIGNED>
 __global__ __launch_bounds__(256) void k_u8_to_bits(
     const uint8_t* __restrict__ frames, int64_t n, int64_t npix, int64_t npix_pad,
-    uint32_t* __restrict__ out, int64_t kw, int64_t nblocks, int64_t blocks_per_slice,
+    uint32_t* __restrict__ out, int64_t kw, int64_t nunits, int64_t units_per_slice,
     unsigned long long* __restrict__ sums, uint32_t* __restrict__ stats, int swap02) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t p0 = (int64_t(blockIdx.x) * 4 + wave) * 256;
   if (p0 >= npix_pad || n <= 0) return;
   const int64_t px = p0 + 4 * lane;
-  const int64_t kb0 = int64_t(blockIdx.y) * blocks_per_slice;
-  int64_t kb1 = kb0 + blocks_per_slice;
-  if (kb1 > nblocks) kb1 = nblocks;
+  const int64_t u0 = int64_t(blockIdx.y) * units_per_slice;
+  int64_t u1 = u0 + units_per_slice;
+  if (u1 > nunits) u1 = nunits;
   uint32_t any = 0;
   uint32_t s[4] = {0u, 0u, 0u, 0u};
   // Lanes whose pixels lie beyond npix read pixel 0 and mask their results
@@ -232,14 +232,15 @@ __global__ __launch_bounds__(256) void k_u8_to_bits(
       return v;
     }
   };
-  auto block = [&](int64_t kb, auto tail) {
+  // One unit = 128 frames: four 32-bit row words (one 16-byte store) for
+  // each of the lane's four pixels.
+  auto unit = [&](int64_t u, auto tail) {
     constexpr bool TAIL = decltype(tail)::value;
-    // four quarters of 128 frames: one 16-byte store per pixel row each
-    for (int q = 0; q < 4; ++q) {
+    {
       uint32_t w[4][4];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int64_t f0 = kb * 512 + q * 128 + g * 32;
+        const int64_t f0 = u * 128 + g * 32;
         uint32_t d[32];
 #pragma unroll
         for (int j = 0; j < 32; ++j) {
@@ -273,16 +274,16 @@ __global__ __launch_bounds__(256) void k_u8_to_bits(
           s[k] += __popc(w[k][g]);
           if (swap02) w[k][g] = swap_bits02(w[k][g]);
         }
-        *reinterpret_cast<uint4*>(out + (px + k) * kw + kb * 16 + q * 4) =
+        *reinterpret_cast<uint4*>(out + (px + k) * kw + u * 4) =
             make_uint4(w[k][0], w[k][1], w[k][2], w[k][3]);
       }
     }
   };
-  for (int64_t kb = kb0; kb < kb1; ++kb) {
-    if (kb * 512 + 512 <= n)
-      block(kb, std::false_type{});
+  for (int64_t u = u0; u < u1; ++u) {
+    if (u * 128 + 128 <= n)
+      unit(u, std::false_type{});
     else
-      block(kb, std::true_type{});
+      unit(u, std::true_type{});
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k)
@@ -290,7 +291,13 @@ __global__ __launch_bounds__(256) void k_u8_to_bits(
   any &= pmask;
   any = (any | (any >> 8) | (any >> 16) | (any >> 24)) & 0xffu;
   for (int off = 32; off > 0; off >>= 1) any |= __shfl_xor(any, off, 64);
-  if (lane == 0 && any) atomicOr(stats, any);
+  // Bits of stats[0] only get set during the launch, so a wave whose bits are
+  // all present already (read at device scope, not from a stale cache) has
+  // nothing to add: this keeps most waves off the single contended word.
+  if (lane == 0 && any) {
+    const uint32_t cur = __hip_atomic_load(stats, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((cur | any) != cur) atomicOr(stats, any);
+  }
 }
 
 // Per-pixel byte sums (non-binary data only).  A work-group owns 256
@@ -352,36 +359,43 @@ __global__ void k_select_i64(int64_t* __restrict__ dst, const int64_t* __restric
 
 // Byte frames -> int8 rows through a 64 x 64 LDS tile (only when some byte
 // exceeds 1).  Pads (frames >= n, pixels >= npix) are written as 0, the
-// value of "no photon" in the offset domain.
+// value of "no photon" in the offset domain.  Work-groups stride over the
+// tiles, so that for binary data (nothing to do) only a few thousand
+// work-groups start and exit.
 __global__ __launch_bounds__(256) void k_u8_to_bytes(const uint8_t* __restrict__ frames,
                                                      int64_t n, int64_t npix,
                                                      uint8_t* __restrict__ out, int64_t kpad,
+                                                     int64_t tiles_p, int64_t tiles,
                                                      const uint32_t* __restrict__ stats) {
   const uint32_t mx = stats[0];
   if (mx <= 1u) return;
   const uint32_t xo = mx > 127u ? 0x80u : 0u;
   __shared__ uint8_t tile[64][64 + 4];
   const int t = threadIdx.x;
-  const int64_t p0 = int64_t(blockIdx.x) * 64;
-  const int64_t f0 = int64_t(blockIdx.y) * 64;
-  {
-    const int fl = t >> 2, pc = (t & 3) * 16;
-    const int64_t f = f0 + fl;
+  for (int64_t tt = blockIdx.x; tt < tiles; tt += gridDim.x) {
+    const int64_t p0 = (tt % tiles_p) * 64;
+    const int64_t f0 = (tt / tiles_p) * 64;
+    {
+      const int fl = t >> 2, pc = (t & 3) * 16;
+      const int64_t f = f0 + fl;
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      const int64_t p = p0 + pc + b;
-      uint32_t v = 0;
-      if (f < n && p < npix) v = uint32_t(frames[f * npix + p]) ^ xo;
-      tile[fl][pc + b] = uint8_t(v);
+      for (int b = 0; b < 16; ++b) {
+        const int64_t p = p0 + pc + b;
+        uint32_t v = 0;
+        if (f < n && p < npix) v = uint32_t(frames[f * npix + p]) ^ xo;
+        tile[fl][pc + b] = uint8_t(v);
+      }
     }
-  }
-  __syncthreads();
-  {
-    const int pl = t >> 2, fc = (t & 3) * 16;
-    uint32_t d[4] = {0u, 0u, 0u, 0u};
+    __syncthreads();
+    {
+      const int pl = t >> 2, fc = (t & 3) * 16;
+      uint32_t d[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int b = 0; b < 16; ++b) d[b >> 2] |= uint32_t(tile[fc + b][pl]) << (8 * (b & 3));
-    *reinterpret_cast<uint4*>(out + (p0 + pl) * kpad + f0 + fc) = make_uint4(d[0], d[1], d[2], d[3]);
+      for (int b = 0; b < 16; ++b) d[b >> 2] |= uint32_t(tile[fc + b][pl]) << (8 * (b & 3));
+      *reinterpret_cast<uint4*>(out + (p0 + pl) * kpad + f0 + fc) =
+          make_uint4(d[0], d[1], d[2], d[3]);
+    }
+    __syncthreads();
   }
 }
 
@@ -461,36 +475,26 @@ hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t np
   if (npix_pad % 256 != 0 || npix_pad < npix) return hipErrorInvalidValue;
   const int64_t waves = npix_pad / 256;
   const int64_t groups = (waves + 3) / 4;
-  const int64_t nblocks = kpad_bits / 512;
-  const int64_t slices = slices_for(waves, nblocks, 8192);
-  const int64_t bps = (nblocks + slices - 1) / slices;
-  const int64_t used = (nblocks + bps - 1) / bps;
+  const int64_t nunits = kpad_bits / 128;
+  const int64_t slices = slices_for(waves, nunits, 8192);
+  const int64_t ups = (nunits + slices - 1) / slices;
+  const int64_t used = (nunits + ups - 1) / ups;
   auto* kern = (npix & 3) == 0 ? k_u8_to_bits<true> : k_u8_to_bits<false>;
   hipLaunchKernelGGL(kern, dim3(unsigned(groups), unsigned(used)), dim3(256), 0, s, frames, n,
-                     npix, npix_pad, reinterpret_cast<uint32_t*>(out), kpad_bits / 32, nblocks,
-                     bps, reinterpret_cast<unsigned long long*>(sums), stats, swap02 ? 1 : 0);
+                     npix, npix_pad, reinterpret_cast<uint32_t*>(out), kpad_bits / 32, nunits,
+                     ups, reinterpret_cast<unsigned long long*>(sums), stats, swap02 ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t u8_to_bytes(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
                        uint8_t* out, int64_t kpad_bytes, const uint32_t* stats,
                        hipStream_t s) {
-  const int64_t gx = npix_pad / 64;
-  const int64_t gy = kpad_bytes / 64;
-  if (gy > 65535) {
-    // The frame axis of the grid is limited; cover it in several launches.
-    for (int64_t y0 = 0; y0 < gy; y0 += 65535) {
-      const int64_t cnt = (gy - y0) < 65535 ? (gy - y0) : 65535;
-      const int64_t fo = y0 * 64;
-      hipLaunchKernelGGL(k_u8_to_bytes, dim3(unsigned(gx), unsigned(cnt)), dim3(256), 0, s,
-                         frames + fo * npix, n - fo, npix, out + fo, kpad_bytes, stats);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  }
-  hipLaunchKernelGGL(k_u8_to_bytes, dim3(unsigned(gx), unsigned(gy)), dim3(256), 0, s, frames, n,
-                     npix, out, kpad_bytes, stats);
+  const int64_t tiles_p = npix_pad / 64;
+  const int64_t tiles = tiles_p * (kpad_bytes / 64);
+  const int64_t grid = tiles < 4096 ? tiles : 4096;
+  if (grid < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_u8_to_bytes, dim3(unsigned(grid)), dim3(256), 0, s, frames, n, npix, out,
+                     kpad_bytes, tiles_p, tiles, stats);
   return hipGetLastError();
 }
 
