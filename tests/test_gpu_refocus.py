@@ -139,17 +139,25 @@ def test_autotune_configs_deterministic_and_accurate(cpi, tiny):
     del torch
 
 
-def test_paper_like_full_size(cpi):
-    """Da 128x128, Db 64x64, 32 planes, Gamma from the oracle's exact
-    correlation of the 20000-frame workload; checked at 96 sampled pixels of
-    every plane (including each plane's largest-magnitude pixel)."""
+@pytest.fixture(scope="module")
+def paper_gamma():
+    """Gamma of the 20000-frame paper-like workload from the oracle's exact
+    correlation, view-major, FP64 and its FP32 rounding."""
     w = WORKLOADS["da128_db64_n20000_u8bin"]
     a, b = generate_frames(w)
-    log(f"case {w.name} refocus, oracle Gamma")
+    log(f"case {w.name} oracle Gamma")
     ref = oracle.correlation(a, b, w.n_frames, w.pa, w.pb, oracle.FRAMES_U8)
     g64 = oracle.to_layout(ref["gamma"], oracle.GAMMA_VIEW_MAJOR)
     g32 = oracle.to_layout(ref["gamma_f32"], oracle.GAMMA_VIEW_MAJOR)
-    del ref
+    return w, g64, g32
+
+
+def test_paper_like_full_size(cpi, paper_gamma):
+    """Da 128x128, Db 64x64, 32 planes, Gamma from the oracle's exact
+    correlation of the 20000-frame workload; checked at 96 sampled pixels of
+    every plane (including each plane's largest-magnitude pixel)."""
+    w, g64, g32 = paper_gamma
+    log(f"case {w.name} refocus, 32 planes")
     g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
     al = alphas_for(w)
     got = _run(cpi, cpi.refocus, g32, g, al)
@@ -168,3 +176,31 @@ def test_paper_like_full_size(cpi):
     assert err.max() <= TOL
     plain = _run(cpi, cpi.refocus_plain, g32, g, al)
     assert plane_rel_err(plain[:, ys, xs], want).max() <= TOL
+
+
+@pytest.mark.parametrize("n_alpha", [100, 261, 1000])
+def test_paper_plane_counts(cpi, paper_gamma, n_alpha):
+    """The paper's stack sizes (100, 261 and 1000 planes, alpha in [0.5, 1.5])
+    in one call each at the paper-like geometry: 24 evenly spaced planes
+    (first and last included) checked at 64 sampled pixels plus each checked
+    plane's largest-magnitude pixel."""
+    w, g64, g32 = paper_gamma
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    al = np.linspace(0.5, 1.5, n_alpha)
+    log(f"case {w.name} refocus, {n_alpha} planes")
+    got = _run(cpi, cpi.refocus, g32, g, al)
+    assert np.isfinite(got).all()
+    planes = np.unique(np.linspace(0, n_alpha - 1, 24).round().astype(int))
+    rng = np.random.default_rng(n_alpha)
+    ys = list(rng.integers(0, w.ha, 64))
+    xs = list(rng.integers(0, w.wa, 64))
+    flat = np.abs(got[planes].reshape(planes.size, -1))
+    for k in range(planes.size):
+        yy, xx = np.unravel_index(np.argmax(flat[k]), (w.ha, w.wa))
+        ys.append(yy)
+        xs.append(xx)
+    ys, xs = np.array(ys), np.array(xs)
+    want = oracle.refocus_pixels(g64, g, al[planes], ys, xs)
+    err = plane_rel_err(got[planes][:, ys, xs], want)
+    log(f"{n_alpha} planes: per-plane relative error max {err.max():.3g}")
+    assert err.max() <= TOL
