@@ -237,6 +237,50 @@ cpi_status cpi_stream_load(cpi_stream_t s, const void* host_buf, size_t bytes);
 cpi_status cpi_stream_destroy(cpi_stream_t s);
 
 /* ---------------------------------------------------------------------------
+ * Raw sensor frames holding both detectors side by side, the paper's input
+ * (Section "Input Dataset"): frames of 256 rows x 512 pixels at 1 bit per
+ * pixel, the left 256 columns imaging detector A and the right 256 detector
+ * B; files of 512 such frames back to back, no header.
+ *
+ * cpi_sidebyside: frame_w x frame_h pixels per raw frame (frame_w even) and
+ *   the region of interest, roi_w x roi_h at (roi_x, roi_y) inside each half,
+ *   taken from both halves.  A raw frame is ceil(frame_w*frame_h/8) bytes with
+ *   pixel (y, x) at bit (y*frame_w + x) % 8 of byte (y*frame_w + x) / 8 (the
+ *   least-significant-bit-first reading of the 1-bit format).
+ * cpi_split_sidebyside: n raw frames (device) -> n CPI_FRAMES_BIT1 frames of
+ *   roi_w*roi_h pixels per detector (device, ceil(roi_w*roi_h/8) bytes each),
+ *   enqueued on `stream`.
+ * cpi_file_frames: number of whole raw frames in a file (host only).
+ * cpi_stream_ingest_files: folds every frame of the listed files, in order,
+ *   into a CPI_FRAMES_BIT1 stream whose pa and pb both equal roi_w*roi_h.  The
+ *   calling thread reads pieces of at most min(max_chunk, host_bytes / raw
+ *   frame, dev_bytes / raw frame) frames into host_a and host_b in turn (host
+ *   memory of host_bytes each; pinned memory lets the read of one piece
+ *   overlap the device work on the previous one), copies each into dev_raw
+ *   (caller device scratch of dev_bytes), splits it into the stream's chunk
+ *   buffers and pushes it.  Returns once the last piece is enqueued, with the
+ *   number of frames ingested in *frames (host); host_a, host_b and dev_raw
+ *   stay in use until the stream has reached that point.
+ * Errors: CPI_ERR_INVALID_ARG (null pointers, sizes, a region outside the
+ *   half, a stream whose format or pixel counts do not match, buffers smaller
+ *   than one raw frame, a missing or unreadable file, a file that is not a
+ *   whole number of frames: all files are checked before any is read),
+ *   CPI_ERR_DEVICE, CPI_ERR_OVERFLOW as for cpi_stream_push.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t frame_w, frame_h;
+  int32_t roi_x, roi_y, roi_w, roi_h;
+} cpi_sidebyside;
+
+cpi_status cpi_split_sidebyside(const void* frames, int64_t n, const cpi_sidebyside* f,
+                                void* frames_a, void* frames_b, void* stream);
+cpi_status cpi_file_frames(const char* path, const cpi_sidebyside* f, int64_t* frames);
+cpi_status cpi_stream_ingest_files(cpi_stream_t s, const char* const* paths, int32_t n_paths,
+                                   const cpi_sidebyside* f, void* host_a, void* host_b,
+                                   size_t host_bytes, void* dev_raw, size_t dev_bytes,
+                                   int64_t* frames);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (tracing).  While recording is on, every entry point brackets
  * each group of kernels it enqueues with a pair of HIP events on the caller's
  * stream.  Group names: "ingest" (sums and operand transposition), "gemm"

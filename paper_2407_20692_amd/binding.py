@@ -52,6 +52,24 @@ class Geometry(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class SideBySide(ctypes.Structure):
+    """Raw sensor frames with both detectors side by side (cpi_sidebyside):
+    frame_w x frame_h 1-bit pixels, the region roi_w x roi_h at (roi_x, roi_y)
+    taken from the left half (detector A) and the right half (detector B)."""
+    _fields_ = [
+        ("frame_w", c_int32), ("frame_h", c_int32),
+        ("roi_x", c_int32), ("roi_y", c_int32), ("roi_w", c_int32), ("roi_h", c_int32),
+    ]
+
+    @property
+    def frame_bytes(self) -> int:
+        return (self.frame_w * self.frame_h + 7) // 8
+
+    @property
+    def roi_pixels(self) -> int:
+        return self.roi_w * self.roi_h
+
+
 _SIGS = {
     "cpi_version": (c_char_p, []),
     "cpi_status_string": (c_char_p, [c_int]),
@@ -93,6 +111,12 @@ _SIGS = {
     "cpi_profile_end": (c_int, []),
     "cpi_profile_query": (c_int, [c_char_p, POINTER(c_int64), POINTER(c_double)]),
     "cpi_set_mma_encoding": (c_int, [c_int]),
+    "cpi_split_sidebyside": (c_int, [c_void_p, c_int64, POINTER(SideBySide), c_void_p, c_void_p,
+                                     c_void_p]),
+    "cpi_file_frames": (c_int, [c_char_p, POINTER(SideBySide), POINTER(c_int64)]),
+    "cpi_stream_ingest_files": (c_int, [c_void_p, POINTER(c_char_p), c_int32, POINTER(SideBySide),
+                                        c_void_p, c_void_p, c_size_t, c_void_p, c_size_t,
+                                        POINTER(c_int64)]),
     "cpi_get_mma_encoding": (c_int, []),
 }
 
@@ -309,6 +333,35 @@ def get_mma_encoding() -> int:
 
 
 # ---------------------------------------------------------------------------
+# raw side-by-side sensor frames
+# ---------------------------------------------------------------------------
+
+def sidebyside(frame_w: int, frame_h: int, roi_x: int = 0, roi_y: int = 0, roi_w: int = None,
+               roi_h: int = None) -> SideBySide:
+    """Layout of raw frames; the region defaults to the whole half frame."""
+    return SideBySide(frame_w, frame_h, roi_x, roi_y,
+                      frame_w // 2 if roi_w is None else roi_w,
+                      frame_h if roi_h is None else roi_h)
+
+
+def split_sidebyside(frames, n: int, f: SideBySide, out_a, out_b, stream=None):
+    """n raw frames (device uint8) -> 1-bit frames of both detectors' regions."""
+    torch = _torch()
+    ob = n * ((f.roi_pixels + 7) // 8)
+    _check(lib.cpi_split_sidebyside(
+        _dev_ptr(frames, "frames", torch.uint8, nbytes=n * f.frame_bytes), n, ctypes.byref(f),
+        _dev_ptr(out_a, "out_a", torch.uint8, nbytes=ob),
+        _dev_ptr(out_b, "out_b", torch.uint8, nbytes=ob), _stream(stream)))
+
+
+def file_frames(path: str, f: SideBySide) -> int:
+    """Whole raw frames in a file (host only)."""
+    n = c_int64(0)
+    _check(lib.cpi_file_frames(os.fsencode(path), ctypes.byref(f), ctypes.byref(n)))
+    return n.value
+
+
+# ---------------------------------------------------------------------------
 # kernel timing
 # ---------------------------------------------------------------------------
 
@@ -394,6 +447,24 @@ class Stream:
         if keep:
             # pageable memory: the copy is complete before the call returned
             del keep
+
+    def ingest_files(self, paths, f: SideBySide, host_a, host_b, dev_raw) -> int:
+        """Folds every frame of the raw frame files into the sums (host_a,
+        host_b: CPU uint8 tensors of equal size, pinned for overlap; dev_raw:
+        device uint8 tensor).  Returns the frames ingested; the buffers stay in
+        use until the stream has reached the enqueued work."""
+        torch = _torch()
+        for x, what in ((host_a, "host_a"), (host_b, "host_b")):
+            if x.is_cuda or x.dtype != torch.uint8 or not x.is_contiguous():
+                raise ValueError(f"{what} must be a contiguous CPU uint8 tensor")
+        hb = min(host_a.numel(), host_b.numel())
+        arr = (c_char_p * len(paths))(*[os.fsencode(p) for p in paths])
+        n = c_int64(0)
+        _check(lib.cpi_stream_ingest_files(
+            self.handle, arr, len(paths), ctypes.byref(f), c_void_p(host_a.data_ptr()),
+            c_void_p(host_b.data_ptr()), hb,
+            _dev_ptr(dev_raw, "dev_raw", torch.uint8), dev_raw.numel(), ctypes.byref(n)))
+        return n.value
 
     @property
     def frames(self) -> int:

@@ -5,6 +5,7 @@
 // all scratch lives in the caller's workspace, laid out by plan.cpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -905,6 +906,168 @@ cpi_status cpi_profile_query(const char* group, int64_t* launches, double* total
 cpi_status cpi_stream_destroy(cpi_stream_t s) {
   return guarded([&]() -> cpi_status {
     delete s;
+    return CPI_OK;
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Raw side-by-side sensor frames and frame files
+// ---------------------------------------------------------------------------
+namespace {
+
+cpi_status check_sidebyside(const cpi_sidebyside* f) {
+  if (!f) return set_error(CPI_ERR_INVALID_ARG, "frame layout is null");
+  if (f->frame_w <= 0 || f->frame_h <= 0 || (f->frame_w & 1))
+    return set_error(CPI_ERR_INVALID_ARG, "frame_w must be positive and even, frame_h positive");
+  if (f->roi_w <= 0 || f->roi_h <= 0 || f->roi_x < 0 || f->roi_y < 0 ||
+      int64_t(f->roi_x) + f->roi_w > f->frame_w / 2 || int64_t(f->roi_y) + f->roi_h > f->frame_h)
+    return set_error(CPI_ERR_INVALID_ARG, "region of interest outside the half frame");
+  return CPI_OK;
+}
+
+int64_t raw_frame_bytes(const cpi_sidebyside* f) {
+  return (int64_t(f->frame_w) * f->frame_h + 7) / 8;
+}
+
+// Whole frames in a file; a size that is not a multiple of the frame is an error.
+cpi_status file_frames(const char* path, int64_t fbytes, int64_t* frames) {
+  if (!path) return set_error(CPI_ERR_INVALID_ARG, "file path is null");
+  std::FILE* fp = std::fopen(path, "rb");
+  if (!fp) return set_error(CPI_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  const bool ok = fseeko(fp, 0, SEEK_END) == 0;
+  const off_t size = ok ? ftello(fp) : off_t(-1);
+  std::fclose(fp);
+  if (size < 0) return set_error(CPI_ERR_INVALID_ARG, std::string("cannot size ") + path);
+  if (size % fbytes != 0)
+    return set_error(CPI_ERR_INVALID_ARG,
+                     std::string(path) + " does not hold a whole number of frames");
+  *frames = int64_t(size) / fbytes;
+  return CPI_OK;
+}
+
+// Events and the open file of one ingest call, released on every exit path.
+struct IngestResources {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::FILE* fp = nullptr;
+  ~IngestResources() {
+    for (hipEvent_t e : ev)
+      if (e) hipEventDestroy(e);
+    if (fp) std::fclose(fp);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+cpi_status cpi_split_sidebyside(const void* frames, int64_t n, const cpi_sidebyside* f,
+                                void* frames_a, void* frames_b, void* stream) {
+  return guarded([&]() -> cpi_status {
+    cpi_status c = check_sidebyside(f);
+    if (c != CPI_OK) return c;
+    if (!frames || !frames_a || !frames_b)
+      return set_error(CPI_ERR_INVALID_ARG, "frame pointers must not be null");
+    if (n <= 0) return set_error(CPI_ERR_INVALID_ARG, "n must be positive");
+    CPI_HIP(cpi::split_sidebyside(static_cast<const uint8_t*>(frames), n, f->frame_w, f->frame_h,
+                                  f->roi_x, f->roi_y, f->roi_w, f->roi_h,
+                                  static_cast<uint8_t*>(frames_a), static_cast<uint8_t*>(frames_b),
+                                  static_cast<hipStream_t>(stream)),
+            "split");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_file_frames(const char* path, const cpi_sidebyside* f, int64_t* frames) {
+  return guarded([&]() -> cpi_status {
+    cpi_status c = check_sidebyside(f);
+    if (c != CPI_OK) return c;
+    if (!frames) return set_error(CPI_ERR_INVALID_ARG, "frames is null");
+    return file_frames(path, raw_frame_bytes(f), frames);
+  });
+}
+
+cpi_status cpi_stream_ingest_files(cpi_stream_t s, const char* const* paths, int32_t n_paths,
+                                   const cpi_sidebyside* f, void* host_a, void* host_b,
+                                   size_t host_bytes, void* dev_raw, size_t dev_bytes,
+                                   int64_t* frames) {
+  return guarded([&]() -> cpi_status {
+    if (!s) return set_error(CPI_ERR_INVALID_ARG, "stream handle is null");
+    if (!paths || n_paths < 1 || !host_a || !host_b || !dev_raw || !frames)
+      return set_error(CPI_ERR_INVALID_ARG, "null argument or no files");
+    *frames = 0;
+    cpi_status c = check_sidebyside(f);
+    if (c != CPI_OK) return c;
+    const int64_t roi_px = int64_t(f->roi_w) * f->roi_h;
+    if (s->fmt != CPI_FRAMES_BIT1 || s->pa != roi_px || s->pb != roi_px)
+      return set_error(CPI_ERR_INVALID_ARG,
+                       "stream must hold 1-bit frames of roi_w*roi_h pixels on both detectors");
+    const int64_t fb = raw_frame_bytes(f);
+    int64_t piece = s->plan.max_chunk;
+    piece = std::min<int64_t>(piece, int64_t(host_bytes) / fb);
+    piece = std::min<int64_t>(piece, int64_t(dev_bytes) / fb);
+    if (piece < 1) return set_error(CPI_ERR_INVALID_ARG, "buffers smaller than one raw frame");
+    std::vector<int64_t> nf(size_t(n_paths), 0);
+    for (int32_t i = 0; i < n_paths; ++i) {
+      c = file_frames(paths[i], fb, &nf[size_t(i)]);
+      if (c != CPI_OK) return c;
+    }
+    IngestResources res;
+    for (hipEvent_t& e : res.ev)
+      CPI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    uint8_t* host[2] = {static_cast<uint8_t*>(host_a), static_cast<uint8_t*>(host_b)};
+    bool in_flight[2] = {false, false};
+    uint8_t* raw = static_cast<uint8_t*>(dev_raw);
+    uint8_t* sa = s->ws + s->plan.off_stage_a;
+    uint8_t* sb = s->ws + s->plan.off_stage_b;
+    int32_t file = -1;
+    int64_t left = 0;
+    // Reads the next piece (within one file) into buf; k = 0 when all are read.
+    auto read_piece = [&](uint8_t* buf, int64_t* k) -> cpi_status {
+      *k = 0;
+      while (left == 0) {
+        if (res.fp) {
+          std::fclose(res.fp);
+          res.fp = nullptr;
+        }
+        if (++file >= n_paths) return CPI_OK;
+        left = nf[size_t(file)];
+        if (left > 0) {
+          res.fp = std::fopen(paths[file], "rb");
+          if (!res.fp) return set_error(CPI_ERR_INVALID_ARG, std::string("cannot open ") + paths[file]);
+        }
+      }
+      const int64_t want = std::min(left, piece);
+      if (std::fread(buf, size_t(fb), size_t(want), res.fp) != size_t(want))
+        return set_error(CPI_ERR_INVALID_ARG, std::string("short read from ") + paths[file]);
+      left -= want;
+      *k = want;
+      return CPI_OK;
+    };
+    int slot = 0;
+    int64_t k = 0;
+    c = read_piece(host[0], &k);
+    if (c != CPI_OK) return c;
+    while (k > 0) {
+      CPI_HIP(hipMemcpyAsync(raw, host[slot], size_t(k * fb), hipMemcpyHostToDevice, s->st),
+              "copy frames");
+      CPI_HIP(hipEventRecord(res.ev[slot], s->st), "event");
+      in_flight[slot] = true;
+      CPI_HIP(cpi::split_sidebyside(raw, k, f->frame_w, f->frame_h, f->roi_x, f->roi_y, f->roi_w,
+                                    f->roi_h, sa, sb, s->st),
+              "split");
+      c = stream_push_device(s, sa, sb, k);
+      if (c != CPI_OK) return c;
+      *frames += k;
+      // the other buffer is free once its last copy to the device has completed
+      const int other = slot ^ 1;
+      if (in_flight[other]) CPI_HIP(hipEventSynchronize(res.ev[other]), "event");
+      in_flight[other] = false;
+      c = read_piece(host[other], &k);
+      if (c != CPI_OK) return c;
+      slot = other;
+    }
     return CPI_OK;
   });
 }

@@ -30,6 +30,12 @@ hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t n
 hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
                       uint8_t* out, int64_t kpad_bits, int64_t* sums, uint32_t* stats,
                       bool swap02, hipStream_t s);
+// Side-by-side sensor frames (frame_h rows of frame_w 1-bit pixels, A the left
+// half, B the right) -> BIT1 frames of the roi_w x roi_h region of interest at
+// (roi_x, roi_y) inside each half.  Sizes are validated by the caller.
+hipError_t split_sidebyside(const uint8_t* frames, int64_t n, int frame_w, int frame_h, int roi_x,
+                            int roi_y, int roi_w, int roi_h, uint8_t* out_a, uint8_t* out_b,
+                            hipStream_t s);
 // Per-pixel byte sums (int64, added into sums), executed only when
 // stats[0] > 1.
 hipError_t u8_sums(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,

@@ -399,6 +399,42 @@ __global__ __launch_bounds__(256) void k_u8_to_bytes(const uint8_t* __restrict__
   }
 }
 
+// Side-by-side sensor frames -> the two detectors' bit frames.  A raw frame
+// is frame_h rows of frame_w 1-bit pixels, row-major, pixel (y, x) at bit
+// (y*frame_w + x) % 8 of byte (y*frame_w + x) / 8; detector A is the left
+// half (columns [0, frame_w/2)), detector B the right half.  The same region
+// of interest (roi_w x roi_h at roi_x, roi_y inside each half) is repacked
+// for both, 8 output pixels per thread, in the frame format of the rest of
+// the library (pixel p of a frame at bit p % 8 of byte p / 8).
+__global__ __launch_bounds__(256) void k_split_sbs(const uint8_t* __restrict__ in, int64_t n,
+                                                   int64_t in_fbytes, int frame_w, int roi_x,
+                                                   int roi_y, int roi_w, int roi_h,
+                                                   uint8_t* __restrict__ out_a,
+                                                   uint8_t* __restrict__ out_b,
+                                                   int64_t out_fbytes) {
+  const int64_t per_side = n * out_fbytes;
+  const int64_t npix = int64_t(roi_w) * roi_h;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < 2 * per_side;
+       i += int64_t(gridDim.x) * 256) {
+    const bool right = i >= per_side;
+    const int64_t local = right ? i - per_side : i;
+    const int64_t f = local / out_fbytes, ob = local - f * out_fbytes;
+    const uint8_t* src = in + f * in_fbytes;
+    const int64_t x_off = (right ? frame_w / 2 : 0) + roi_x;
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t p = ob * 8 + k;
+      if (p < npix) {
+        const int64_t y = p / roi_w, x = p - y * roi_w;
+        const int64_t bit = (roi_y + y) * frame_w + x_off + x;
+        v |= uint32_t((src[bit >> 3] >> (bit & 7)) & 1u) << k;
+      }
+    }
+    (right ? out_b : out_a)[f * out_fbytes + ob] = uint8_t(v);
+  }
+}
+
 int64_t slices_for(int64_t groups, int64_t nblocks, int64_t target_waves) {
   int64_t s = (target_waves + groups - 1) / groups;
   if (s < 1) s = 1;
@@ -495,6 +531,17 @@ hipError_t u8_to_bytes(const uint8_t* frames, int64_t n, int64_t npix, int64_t n
   if (grid < 1) return hipSuccess;
   hipLaunchKernelGGL(k_u8_to_bytes, dim3(unsigned(grid)), dim3(256), 0, s, frames, n, npix, out,
                      kpad_bytes, tiles_p, tiles, stats);
+  return hipGetLastError();
+}
+
+hipError_t split_sidebyside(const uint8_t* frames, int64_t n, int frame_w, int frame_h, int roi_x,
+                            int roi_y, int roi_w, int roi_h, uint8_t* out_a, uint8_t* out_b,
+                            hipStream_t s) {
+  const int64_t in_fbytes = (int64_t(frame_w) * frame_h + 7) / 8;
+  const int64_t out_fbytes = (int64_t(roi_w) * roi_h + 7) / 8;
+  const int64_t total = 2 * n * out_fbytes;
+  hipLaunchKernelGGL(k_split_sbs, dim3(grid_for(total, 256)), dim3(256), 0, s, frames, n,
+                     in_fbytes, frame_w, roi_x, roi_y, roi_w, roi_h, out_a, out_b, out_fbytes);
   return hipGetLastError();
 }
 

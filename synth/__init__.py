@@ -14,6 +14,7 @@ from .speckle import (
     pack_bits_lsb,
     chunk_seed_sequences,
 )
+from .rawframes import compose_sidebyside, pack_raw_frames, write_frame_files
 
 __all__ = [
     "WORKLOADS",
@@ -26,4 +27,7 @@ __all__ = [
     "generate_frames",
     "pack_bits_lsb",
     "chunk_seed_sequences",
+    "compose_sidebyside",
+    "pack_raw_frames",
+    "write_frame_files",
 ]
