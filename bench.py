@@ -24,6 +24,9 @@ Printed as ONE JSON line:
   roofline_int8  the same contraction in the int8 encoding against the int8 peak
   roofline_refocus  the batched refocus kernel: algorithmic (footprint) bytes
                  per launch over its duration, against the HBM peak
+  refocus_plane_counts  the paper's stack sizes (100, 261, 1000 planes)
+  file_ingest    raw side-by-side frame files (the paper's 256 x 512 layout,
+                 11 files of 512 frames) streamed into the running sums
   cpu_baseline   the CPU oracle on a bounded sample of the same workload
 """
 import argparse
@@ -103,9 +106,51 @@ def refocus_algorithmic_bytes(geo, alphas):
     return int(total)
 
 
+def file_ingest_bench(cpi, torch, np, dev, n_files=11, roi=128):
+    """Raw-frame file streaming at the paper's layout: n_files files of 512
+    frames of 256 x 512 1-bit pixels (random clicks at occupancy 0.1), the
+    roi x roi region of both halves folded into the running sums, one file per
+    piece; wall time from the first read to the device finishing."""
+    import tempfile
+
+    f = cpi.sidebyside(512, 256, 64, 64, roi, roi)
+    rng = np.random.default_rng(7)
+    block = np.packbits((rng.random((512, 256 * 512)) < 0.1).astype(np.uint8), axis=1,
+                        bitorder="little")
+    d = tempfile.mkdtemp(prefix="cpi_frames_", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    paths = []
+    try:
+        for i in range(n_files):
+            pth = os.path.join(d, f"frames_{i:05d}.bin")
+            block.tofile(pth)
+            paths.append(pth)
+        st = cpi.Stream(f.roi_pixels, f.roi_pixels, cpi.FRAMES_BIT1, max_chunk=512, device=dev)
+        ha = torch.empty(512 * f.frame_bytes, dtype=torch.uint8).pin_memory()
+        hb = torch.empty(512 * f.frame_bytes, dtype=torch.uint8).pin_memory()
+        raw = torch.empty(512 * f.frame_bytes, dtype=torch.uint8, device=dev)
+        st.ingest_files(paths[:1], f, ha, hb, raw)       # warm-up
+        torch.cuda.synchronize()
+        st2 = cpi.Stream(f.roi_pixels, f.roi_pixels, cpi.FRAMES_BIT1, max_chunk=512, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = st2.ingest_files(paths, f, ha, hb, raw)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st.close()
+        st2.close()
+    finally:
+        for pth in paths:
+            os.remove(pth)
+        os.rmdir(d)
+    return {"files": n_files, "frames": k, "frame": "256 x 512 px, 1 bit, A left / B right",
+            "roi": [roi, roi], "seconds": t, "frames_per_s": k / t,
+            "raw_MB_per_s": k * f.frame_bytes / t / 1e6}
+
+
 def cpu_baseline(a, b, w, alphas):
-    """The oracle, as it stands, on a bounded sample: Gamma for a quarter of
-    the detector-A pixels (all views, all frames) and one refocus plane."""
+    """The oracle, as it stands, on a bounded sample of the workload (about
+    12 s of host work): Gamma for every pixel pair over all frames, and 10 of
+    the refocus planes (evenly spaced, first and last included)."""
     import numpy as np
 
     import oracle
@@ -115,26 +160,26 @@ def cpu_baseline(a, b, w, alphas):
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         threads = len(os.sched_getaffinity(0))
-    slab = np.arange(0, w.pa, 4)
     t0 = time.perf_counter()
-    r = oracle.correlation(a, b, w.n_frames, w.pa, w.pb, oracle.FRAMES_U8, rows_a=slab)
+    r = oracle.correlation(a, b, w.n_frames, w.pa, w.pb, oracle.FRAMES_U8)
     t1 = time.perf_counter()
     g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
-    gam = np.zeros((w.pb, w.pa))
-    gam[:, slab] = r["gamma"].T
+    gam = oracle.to_layout(r["gamma"], oracle.GAMMA_VIEW_MAJOR)
+    del r
+    planes = np.unique(np.linspace(0, len(alphas) - 1, 10).round().astype(int))
     t2 = time.perf_counter()
-    oracle.refocus(gam, g, alphas[:1])
+    oracle.refocus(gam, g, np.asarray(alphas)[planes])
     t3 = time.perf_counter()
-    corr_rate = w.n_frames * slab.size * w.pb / (t1 - t0)
+    corr_rate = float(w.n_frames) * w.pa * w.pb / (t1 - t0)
     return {
         "value": corr_rate,
         "unit": "pixel-pair*frames/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"Gamma of {slab.size} of {w.pa} detector-A pixels x {w.pb} views x "
-                   f"{w.n_frames} frames ({t1 - t0:.2f} s); refocus of 1 plane "
+        "sample": (f"Gamma of all {w.pa} x {w.pb} pixel pairs over {w.n_frames} frames "
+                   f"({t1 - t0:.2f} s); refocus of {planes.size} of {len(alphas)} planes "
                    f"({t3 - t2:.2f} s)"),
-        "refocus_planes_per_s": 1.0 / (t3 - t2),
+        "refocus_planes_per_s": planes.size / (t3 - t2),
         "seconds": (t1 - t0) + (t3 - t2),
     }
 
@@ -148,6 +193,8 @@ def main():
     ap.add_argument("--stream-chunks", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the plane-count refocus and raw-file ingest measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", choices=["paper_like", "large"], default="paper_like",
@@ -387,6 +434,27 @@ def main():
             "n_alpha": len(sal),
         }
         st.close()
+
+    if not args.no_next and not large:
+        # the paper's stack sizes (100, 261, 1000 planes) on the same Gamma
+        counts = {}
+        for na in (100, 261, 1000):
+            al = np.linspace(0.5, 1.5, na)
+            o = torch.empty(na * w.pa, dtype=torch.float32, device=dev)
+            ws_n = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, na), dev)
+            cpi.autotune_refocus(g32, geo, al, o, workspace=ws_n)
+            torch.cuda.synchronize()
+            cpi.profile_begin()
+            for _ in range(3):
+                cpi.refocus(g32, geo, al, o, workspace=ws_n)
+            torch.cuda.synchronize()
+            cpi.profile_end()
+            t = sum(cpi.profile_query(gname)[1] for gname in ("refocus_tables", "refocus_batched")) / 3
+            counts[str(na)] = {"ms": t, "planes_per_s": na / (t * 1e-3),
+                               "config_kp_rw_splits": list(cpi.refocus_config(geo, na))}
+            del o, ws_n
+        line["refocus_plane_counts"] = counts
+        line["file_ingest"] = file_ingest_bench(cpi, torch, np, dev)
 
     if not args.no_cpu_baseline and not large:
         log("bench: CPU oracle baseline")
