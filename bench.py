@@ -42,6 +42,7 @@ if ROOT not in sys.path:
 
 WORKLOAD = "da128_db64_n20000_u8bin"
 LARGE_WORKLOAD = "da256_db128_n100000_bit1"
+PAPER_WORKLOAD = "da256_db256_files11_bit1"
 STREAM_WORKLOAD = "da128_db64_stream200x1000_bit1"
 INT8_PEAK = 5.0e15          # dense int8 matrix-core ops/s, MI355X
 FP4_PEAK = 10.1e15          # dense FP4 (and FP6) matrix-core ops/s, MI355X
@@ -197,9 +198,13 @@ def main():
                     help="skip the plane-count refocus and raw-file ingest measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=["paper_like", "large"], default="paper_like",
+    ap.add_argument("--workload", choices=["paper_like", "large", "paper"], default="paper_like",
                     help="paper_like: Da 128x128, Db 64x64, N=20000 bytes (default line); "
-                         "large: Da 256x256, Db 128x128, N=100000 packed bits, 128 planes")
+                         "large: Da 256x256, Db 128x128, N=100000 packed bits, 128 planes; "
+                         "paper: 256x256 on both detectors, --files files of 512 frames, "
+                         "261 planes (the paper's benchmark configuration)")
+    ap.add_argument("--files", type=int, default=11,
+                    help="paper workload: files of 512 frames (the paper uses 11, 100, 500, 7808)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -222,15 +227,27 @@ def main():
     import paper_2407_20692_amd as cpi
     from synth import WORKLOADS, alphas_for, generate_frames, pack_bits_lsb
 
-    large = args.workload == "large"
-    w = WORKLOADS[LARGE_WORKLOAD if large else WORKLOAD]
+    paper = args.workload == "paper"
+    large = args.workload == "large" or paper
+    w = WORKLOADS[PAPER_WORKLOAD if paper else (LARGE_WORKLOAD if large else WORKLOAD)]
     log(f"bench: generating {w.name}")
     alphas = alphas_for(w)
     n, pa, pb = w.n_frames, w.pa, w.pb
+    generated = None
+    if paper:
+        n = args.files * 512
     if large:
         from synth.gpu_speckle import generate_binary_frames_gpu
         fmt = cpi.FRAMES_BIT1
-        pa_bits, pb_bits = generate_binary_frames_gpu(w, device=dev)
+        base = min(n, 25600)
+        pa_bits, pb_bits = generate_binary_frames_gpu(w, count=base, device=dev)
+        if base < n:
+            # more frames than generated: the generated block repeats (the
+            # contraction's work does not depend on the frame contents)
+            reps = (n + base - 1) // base
+            pa_bits = pa_bits.repeat(reps, 1)[:n].contiguous()
+            pb_bits = pb_bits.repeat(reps, 1)[:n].contiguous()
+            generated = base
         da, db = pa_bits.reshape(-1), pb_bits.reshape(-1)
         a = b = None
     else:
@@ -250,9 +267,12 @@ def main():
                       gamma=gamma, gamma_f32=g32, workspace=ws_c)
         cpi.refocus(g32, geo, alphas, out, workspace=ws_r)
 
-    log("bench: autotuning the refocus kernel")
     step()
-    cpi.autotune_refocus(g32, geo, alphas, out, workspace=ws_r)
+    if not paper:
+        # (the paper workload keeps the default configuration: each timed
+        # candidate would take about a second at its size)
+        log("bench: autotuning the refocus kernel")
+        cpi.autotune_refocus(g32, geo, alphas, out, workspace=ws_r)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -294,27 +314,36 @@ def main():
     finally:
         cpi.set_mma_encoding(cpi.MMA_AUTO)
 
-    # plain FP32 comparison path on the same inputs
+    # plain FP32 comparison path on the same inputs (at the paper workload's
+    # size: the correlator up to 51200 frames, whose FP32 copies of the frames
+    # fit, and the one-plane-per-launch refocus on 4 of the planes)
     log("bench: plain FP32 path")
-    g32p = torch.empty(pa * pb, dtype=torch.float32, device=dev)
-    ws_p = cpi.alloc_workspace(cpi.correlate_f32_plain_workspace_size(n, pa, pb, fmt), dev)
-    outp = torch.empty_like(out)
-    cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
-    cpi.refocus_plain(g32, geo, alphas, outp, workspace=ws_r)
+    plain_corr = not (paper and n > 51200)
+    al_p = alphas[:4] if paper else alphas
+    outp = torch.empty(len(al_p) * w.pa, dtype=torch.float32, device=dev)
+    if plain_corr:
+        g32p = torch.empty(pa * pb, dtype=torch.float32, device=dev)
+        ws_p = cpi.alloc_workspace(cpi.correlate_f32_plain_workspace_size(n, pa, pb, fmt), dev)
+        cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
+    cpi.refocus_plain(g32, geo, al_p, outp, workspace=ws_r)
     torch.cuda.synchronize()
     cpi.profile_begin()
     for _ in range(args.plain_steps):
-        cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
-        cpi.refocus_plain(g32, geo, alphas, outp, workspace=ws_r)
+        if plain_corr:
+            cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
+        cpi.refocus_plain(g32, geo, al_p, outp, workspace=ws_r)
     torch.cuda.synchronize()
     cpi.profile_end()
     pg = {}
     for grp in ("unpack_f32", "sgemm_f32", "refocus_tables", "refocus_plain"):
         cnt, tot = cpi.profile_query(grp)
         pg[grp] = tot / max(cnt, 1)
-    ms_corr_p = pg["unpack_f32"] + pg["sgemm_f32"]
-    ms_ref_p = pg["refocus_tables"] + pg["refocus_plain"]
-    del ws_p, g32p, outp
+    ms_corr_p = pg["unpack_f32"] + pg["sgemm_f32"] if plain_corr else float("nan")
+    # plain refocus time per call scaled to the full stack
+    ms_ref_p = (pg["refocus_tables"] + pg["refocus_plain"]) * len(alphas) / len(al_p)
+    if plain_corr:
+        del ws_p, g32p
+    del outp
 
     pairs = float(n) * pa * pb
     line = {
@@ -330,9 +359,11 @@ def main():
         "vs_baseline": None,
         "dtype": "fp4-e2m1 0/1 operands, fp32 sums (exact); int64/fp64 epilogue; fp32 refocus",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_frames": n, "pa": pa, "pb": pb,
-                   "frames": ("1-bit packed, frame-major (generated on the device)" if large
-                              else "uint8 0/1, frame-major"), "n_alpha": len(alphas),
+        "config": {"workload": w.name if not paper else f"{w.name.split('_files')[0]}_files{args.files}_bit1",
+                   "n_frames": n, "pa": pa, "pb": pb,
+                   "frames": ("1-bit packed, frame-major (generated on the device"
+                              + (f"; {generated} distinct frames, repeated)" if generated else ")")
+                              if large else "uint8 0/1, frame-major"), "n_alpha": len(alphas),
                    "alpha_range": [float(alphas[0]), float(alphas[-1])],
                    "gamma_outputs": "FP64 + FP32, view-major"},
         "correlate": {"ms": ms_corr, "ingest_ms": groups["ingest"], "gemm_ms": groups["gemm"],
@@ -340,11 +371,14 @@ def main():
         "refocus": {"ms": ms_ref, "planes_per_s": len(alphas) / (ms_ref * 1e-3),
                     "config_kp_rw_splits": list(cpi.refocus_config(geo, len(alphas)))},
         "fp32_plain": {
-            "correlate_ms": ms_corr_p, "unpack_ms": pg["unpack_f32"], "sgemm_ms": pg["sgemm_f32"],
-            "pixel_pair_frames_per_s": pairs / (ms_corr_p * 1e-3),
-            "sgemm_tflops": 2 * pairs / (pg["sgemm_f32"] * 1e-3) / 1e12,
+            "correlate_ms": ms_corr_p if plain_corr else None,
+            "unpack_ms": pg["unpack_f32"] if plain_corr else None,
+            "sgemm_ms": pg["sgemm_f32"] if plain_corr else None,
+            "pixel_pair_frames_per_s": pairs / (ms_corr_p * 1e-3) if plain_corr else None,
+            "sgemm_tflops": 2 * pairs / (pg["sgemm_f32"] * 1e-3) / 1e12 if plain_corr else None,
             "refocus_ms": ms_ref_p, "planes_per_s": len(alphas) / (ms_ref_p * 1e-3),
-            "mfma_vs_fp32_correlate": ms_corr_p / ms_corr,
+            "refocus_planes_timed": len(al_p),
+            "mfma_vs_fp32_correlate": ms_corr_p / ms_corr if plain_corr else None,
             "batched_vs_plain_refocus": ms_ref_p / ms_ref,
         },
     }

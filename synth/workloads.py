@@ -54,6 +54,10 @@ WORKLOADS = {
                  "binary_packed", 128),
         Workload("da128_db64_stream200x1000_bit1", 3, 128, 128, 64, 64,
                  200000, "binary_packed", 32, chunk=1000),
+        # the paper's benchmark configuration: 256 x 256 regions on both
+        # detectors, 11 files of 512 frames, 261 refocus planes (Section 4.2)
+        Workload("da256_db256_files11_bit1", 4, 256, 256, 256, 256, 11 * 512,
+                 "binary_packed", 261),
     ]
 }
 
