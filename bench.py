@@ -244,9 +244,12 @@ def main():
         if base < n:
             # more frames than generated: the generated block repeats (the
             # contraction's work does not depend on the frame contents)
-            reps = (n + base - 1) // base
-            pa_bits = pa_bits.repeat(reps, 1)[:n].contiguous()
-            pb_bits = pb_bits.repeat(reps, 1)[:n].contiguous()
+            def tiled(x):
+                t = torch.empty((n, x.shape[1]), dtype=x.dtype, device=dev)
+                for lo in range(0, n, base):
+                    t[lo:lo + base] = x[:min(base, n - lo)]
+                return t
+            pa_bits, pb_bits = tiled(pa_bits), tiled(pb_bits)
             generated = base
         da, db = pa_bits.reshape(-1), pb_bits.reshape(-1)
         a = b = None
