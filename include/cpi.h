@@ -281,6 +281,23 @@ cpi_status cpi_stream_ingest_files(cpi_stream_t s, const char* const* paths, int
                                    int64_t* frames);
 
 /* ---------------------------------------------------------------------------
+ * Measured peaks of the current device, to set beside the vendor figures the
+ * rooflines are quoted against: matrix-core ops/s of register-only loops of
+ * the two ops the contraction uses (int8 16x16x64 with int32 sums, FP4
+ * 16x16x128 with FP32 sums, on binary-like operands), and bytes/s read plus
+ * written by a device copy of copy_bytes.
+ * cpi_measure_peaks_scratch_size: device scratch needed for copy_bytes.
+ * cpi_measure_peaks: runs the three measurements on `stream` (synchronises
+ *   it); outputs are host pointers.
+ * Errors: CPI_ERR_INVALID_ARG (null pointers, copy_bytes not a positive
+ *   multiple of 16), CPI_ERR_WORKSPACE, CPI_ERR_DEVICE.
+ * ------------------------------------------------------------------------- */
+cpi_status cpi_measure_peaks_scratch_size(size_t copy_bytes, size_t* bytes);
+cpi_status cpi_measure_peaks(void* scratch, size_t scratch_bytes, size_t copy_bytes,
+                             double* int8_ops_per_s, double* fp4_ops_per_s,
+                             double* copy_bytes_per_s, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (tracing).  While recording is on, every entry point brackets
  * each group of kernels it enqueues with a pair of HIP events on the caller's
  * stream.  Group names: "ingest" (sums and operand transposition), "gemm"

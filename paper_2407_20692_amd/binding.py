@@ -111,6 +111,9 @@ _SIGS = {
     "cpi_profile_end": (c_int, []),
     "cpi_profile_query": (c_int, [c_char_p, POINTER(c_int64), POINTER(c_double)]),
     "cpi_set_mma_encoding": (c_int, [c_int]),
+    "cpi_measure_peaks_scratch_size": (c_int, [c_size_t, POINTER(c_size_t)]),
+    "cpi_measure_peaks": (c_int, [c_void_p, c_size_t, c_size_t, POINTER(c_double),
+                                  POINTER(c_double), POINTER(c_double), c_void_p]),
     "cpi_split_sidebyside": (c_int, [c_void_p, c_int64, POINTER(SideBySide), c_void_p, c_void_p,
                                      c_void_p]),
     "cpi_file_frames": (c_int, [c_char_p, POINTER(SideBySide), POINTER(c_int64)]),
@@ -330,6 +333,20 @@ def set_mma_encoding(enc: int):
 
 def get_mma_encoding() -> int:
     return lib.cpi_get_mma_encoding()
+
+
+def measure_peaks(device=None, copy_bytes: int = 1 << 30, stream=None):
+    """Measured int8 and FP4 matrix-core ops/s and device-copy bytes/s
+    (read + write) of the current device."""
+    torch = _torch()
+    need = c_size_t(0)
+    _check(lib.cpi_measure_peaks_scratch_size(copy_bytes, ctypes.byref(need)))
+    scratch = alloc_workspace(need.value, device)
+    i8, f4, bw = c_double(0), c_double(0), c_double(0)
+    _check(lib.cpi_measure_peaks(_dev_ptr(scratch, "scratch", torch.uint8), need.value, copy_bytes,
+                                 ctypes.byref(i8), ctypes.byref(f4), ctypes.byref(bw),
+                                 _stream(stream)))
+    return {"int8_ops_per_s": i8.value, "fp4_ops_per_s": f4.value, "copy_bytes_per_s": bw.value}
 
 
 # ---------------------------------------------------------------------------

@@ -26,6 +26,7 @@ SOURCES = [
     "kernels_f32.hip",
     "kernels_refocus.hip",
     "autotune.hip",
+    "peaks.hip",
     "api.hip",
 ]
 

@@ -523,6 +523,35 @@ cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha, int32_t* p
   });
 }
 
+cpi_status cpi_measure_peaks_scratch_size(size_t copy_bytes, size_t* bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");
+    if (copy_bytes == 0 || copy_bytes % 16)
+      return set_error(CPI_ERR_INVALID_ARG, "copy_bytes must be a positive multiple of 16");
+    *bytes = cpi::peaks_scratch_bytes(copy_bytes);
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_measure_peaks(void* scratch, size_t scratch_bytes, size_t copy_bytes,
+                             double* int8_ops_per_s, double* fp4_ops_per_s,
+                             double* copy_bytes_per_s, void* stream) {
+  return guarded([&]() -> cpi_status {
+    if (!scratch || !int8_ops_per_s || !fp4_ops_per_s || !copy_bytes_per_s)
+      return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    if (copy_bytes == 0 || copy_bytes % 16)
+      return set_error(CPI_ERR_INVALID_ARG, "copy_bytes must be a positive multiple of 16");
+    if (!aligned16(scratch)) return set_error(CPI_ERR_INVALID_ARG, "scratch must be 16-byte aligned");
+    if (scratch_bytes < cpi::peaks_scratch_bytes(copy_bytes))
+      return set_error(CPI_ERR_WORKSPACE, "scratch smaller than cpi_measure_peaks_scratch_size");
+    CPI_HIP(cpi::measure_peaks(static_cast<uint8_t*>(scratch), copy_bytes,
+                               static_cast<hipStream_t>(stream), int8_ops_per_s, fp4_ops_per_s,
+                               copy_bytes_per_s),
+            "peaks");
+    return CPI_OK;
+  });
+}
+
 cpi_status cpi_set_mma_encoding(cpi_mma_encoding enc) {
   return guarded([&]() -> cpi_status {
     if (enc != CPI_MMA_AUTO && enc != CPI_MMA_INT8)

@@ -99,6 +99,13 @@ bool bits_use_fp4(int64_t kblocks);
 void set_mma_encoding(int enc);
 int get_mma_encoding();
 
+// ---- measured peaks ---------------------------------------------------------
+size_t peaks_scratch_bytes(size_t copy_bytes);
+// Register-only loops of the int8 and FP4 matrix-core ops, and a device copy
+// of copy_bytes; synchronises s.
+hipError_t measure_peaks(uint8_t* scratch, size_t copy_bytes, hipStream_t s, double* int8_ops,
+                         double* fp4_ops, double* copy_bytes_per_s);
+
 // Gamma from a streaming state (view-major int32 or int64 S_ab, raw sums).
 hipError_t state_gamma(const void* sab, bool sab64, const int64_t* sum_a, const int64_t* sum_b,
                        int64_t n, int64_t pa, int64_t pb, int layout, double* gamma,

@@ -193,3 +193,13 @@ def test_paper_like_full_size(cpi):
     again = run_correlate(cpi, a, b, n, pa, pb, cpi.FRAMES_U8, cpi.GAMMA_VIEW_MAJOR)
     assert_bit_exact(again, got, "rerun ")
     del torch
+
+
+def test_measured_peaks_plausible(cpi):
+    """The device microbenchmarks report positive rates below the vendor peaks
+    (with a little margin for clock variation)."""
+    log("case measured peaks")
+    mp = cpi.measure_peaks(copy_bytes=256 << 20)
+    assert 0.5e15 < mp["int8_ops_per_s"] < 5.2e15
+    assert 1.0e15 < mp["fp4_ops_per_s"] < 10.5e15
+    assert 0.5e12 < mp["copy_bytes_per_s"] < 8.5e12
