@@ -314,6 +314,147 @@ cpi_status cpi_profile_begin(void);
 cpi_status cpi_profile_end(void);
 cpi_status cpi_profile_query(const char* group, int64_t* launches, double* total_ms);
 
+/* ---------------------------------------------------------------------------
+ * Learned denoiser.  Not part of the paper: a small network trained on the
+ * pipeline's own output that maps a plane refocused from few frames to the
+ * same plane refocused from many frames; the plain pipeline stays the
+ * reference it is judged against and the fallback where it does not help.
+ *
+ * Model.  Each input plane p is normalised by its own mean mu and population
+ * standard deviation sigma (sigma = 1 for a constant plane):
+ * x = (p - mu) / sigma.  A four-level convolutional encoder-decoder f
+ * (U-Net form, widths 32, 64, 128, 256) computes a correction and the output
+ * is (x + f(x)) * sigma + mu.  Encoder levels: two 3x3 convolutions (zero
+ * padding) each followed by ReLU, levels joined by 2x2 max-pooling; decoder
+ * levels: nearest 2x upsampling, concatenation [upsampled, encoder output of
+ * the level] along channels, two 3x3 convolutions with ReLU; then a 1x1
+ * convolution to one channel.  Training minimises the mean squared error of
+ * x + f(x) against the target plane normalised with the input's (mu, sigma),
+ * over every pixel of the batch, with Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected moments).
+ *
+ * Precision.  Convolutions run on BF16 matrix cores with FP32 sums;
+ * activations and their gradients are stored as bfloat16 (round to nearest
+ * even), the output convolution and the loss in FP32; master weights, their
+ * gradients (FP32 atomics) and the Adam moments are FP32.
+ *
+ * Parameters: one FP32 device array of cpi_denoiser_param_count floats.
+ * Layer i (cpi_denoiser_layer_info, execution order) holds its weights
+ * w[cout][ks][ks][cin] at weight_offset and its biases b[cout] at
+ * bias_offset.  Channel counts are stored padded (the first layer's input to
+ * 8 channels, the output layer to 32); weights of unused channels
+ * (cin_used <= ci < cin, cout_used <= co < cout) must be zero and stay zero
+ * under training.  The caller initialises the parameters and the two Adam
+ * moment arrays (same size, zero at the start).
+ *
+ * Planes: FP32 device arrays [batch][h][w]; h and w positive multiples of 8,
+ * batch * h * w <= 2^26.  Workspace: caller-owned device memory of at least
+ * cpi_denoiser_workspace_size(batch, h, w, train) bytes (train != 0 for
+ * cpi_denoiser_train_step and cpi_denoiser_gradients).
+ *
+ * cpi_denoiser_forward: out = denoised planes (out may not alias planes).
+ * cpi_denoiser_train_step: one Adam step (step number >= 1) on one batch of
+ *   (planes, targets); *loss (device float) receives the batch loss of the
+ *   parameters before the step.  Updates params, adam_m, adam_v in place.
+ * cpi_denoiser_gradients: the batch loss and the gradient of every parameter
+ *   (into grads, same layout as params) without an update.
+ * cpi_image_quality: per plane b, psnr[b] = 10 log10(R^2 / MSE) with R the
+ *   target plane's max - min (+inf when the planes are equal) and ssim[b] =
+ *   mean SSIM over every position of an 11 x 11 Gaussian window (sigma 1.5,
+ *   normalised to sum 1) that fits in the plane, both planes mapped by the
+ *   target's minimum and range to [0, 1] (range 1 for a constant target),
+ *   K1 = 0.01, K2 = 0.03; FP64; planes at least 11 x 11; psnr and ssim are
+ *   device arrays of batch doubles.
+ * Errors: CPI_ERR_INVALID_ARG (null or misaligned pointers, bad sizes, step
+ *   < 1, non-positive learning rate), CPI_ERR_WORKSPACE, CPI_ERR_DEVICE.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  char name[16];
+  int32_t cin, cout, ks;        /* stored channel counts and kernel size */
+  int32_t cin_used, cout_used;  /* channels that carry data */
+  int64_t weight_offset;        /* floats from the start of the parameters */
+  int64_t bias_offset;
+} cpi_denoiser_layer;
+
+cpi_status cpi_denoiser_layer_count(int32_t* count);
+cpi_status cpi_denoiser_layer_info(int32_t index, cpi_denoiser_layer* out);
+cpi_status cpi_denoiser_param_count(int64_t* count);
+cpi_status cpi_denoiser_workspace_size(int32_t batch, int32_t h, int32_t w, int32_t train,
+                                       size_t* bytes);
+cpi_status cpi_denoiser_forward(const float* params, int32_t batch, int32_t h, int32_t w,
+                                const float* planes, float* out, void* workspace,
+                                size_t workspace_bytes, void* stream);
+cpi_status cpi_denoiser_train_step(float* params, float* adam_m, float* adam_v, int64_t step,
+                                   float lr, int32_t batch, int32_t h, int32_t w,
+                                   const float* planes, const float* targets, float* loss,
+                                   void* workspace, size_t workspace_bytes, void* stream);
+cpi_status cpi_denoiser_gradients(const float* params, int32_t batch, int32_t h, int32_t w,
+                                  const float* planes, const float* targets, float* loss,
+                                  float* grads, void* workspace, size_t workspace_bytes,
+                                  void* stream);
+cpi_status cpi_image_quality(const float* pred, const float* target, int32_t batch, int32_t h,
+                             int32_t w, double* psnr, double* ssim, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * The denoiser's kernels one at a time (each used by the network above).
+ * Tensors are NHWC [b][h][w][c] bfloat16 (raw uint16 bits) device arrays,
+ * 16-byte aligned.  All calls only enqueue work on `stream`.
+ *
+ * cpi_nn_pack_weights: FP32 w[cout][ks][ks][cin] -> bfloat16 rows
+ *   w_packed[cout][kpad] (k = (ky*ks + kx)*cin + ci, zero for k >= ks*ks*cin,
+ *   kpad = ks*ks*cin rounded up to a multiple of 32) and, if w_packed_t is not
+ *   null, the backward-data weights w_packed_t[cin][kpad_t] with
+ *   k = (ks*ks - 1 - tap)*cout + co (kpad_t = ks*ks*cout rounded up to 32).
+ * cpi_nn_conv2d: out[p][co] = act(b[co] + sum over taps and ci of
+ *   w[co][tap][ci] * x[p + tap offset][ci]) (zero padding, ks odd), act = ReLU
+ *   if relu != 0; then zeroed where mask[p][co] <= 0 (mask nullable; bias
+ *   nullable).  Output to out (bfloat16) and/or out_f32 (FP32).  cin % 8 == 0,
+ *   cout % 32 == 0.  With (dy, w_packed_t, cin := cout, cout := cin,
+ *   kpad := kpad_t) it is the gradient with respect to the input.
+ * cpi_nn_conv2d_wgrad: dw[co][tap][ci] += sum over pixels p of
+ *   dy[p][co] * x[p + tap offset][ci] (FP32, accumulated into dw).
+ * cpi_nn_bias_grad: db[c] += sum over pixels of dy[p][c].
+ * cpi_nn_maxpool2 / _grad: 2x2 maximum (h, w even); the gradient goes to the
+ *   first maximal position in the order (0,0), (0,1), (1,0), (1,1).
+ * cpi_nn_upsample2 / _grad: nearest 2x upsampling of [b][h][w][c]; the
+ *   gradient sums the four copies and is zeroed where mask <= 0 (nullable).
+ * cpi_nn_concat / cpi_nn_split: out[p] = [a[p], b[p]] and its inverse.
+ * cpi_nn_add_mask: x = x + add (nullable), zeroed where mask <= 0 (nullable).
+ * cpi_nn_mse: z[p] = y[p][0] + residual[p] (y with c FP32 channels per pixel,
+ *   residual nullable); *loss += sum (z - t)^2 / pixels (loss nullable) and
+ *   dy[p][0] = 2 (z - t) / pixels, dy[p][c > 0] = 0 (bfloat16, nullable).
+ * cpi_nn_adam: one Adam step on FP32 arrays (bias correction with `step`).
+ * ------------------------------------------------------------------------- */
+cpi_status cpi_nn_pack_weights(const float* w, int32_t cout, int32_t cin, int32_t ks,
+                               uint16_t* w_packed, uint16_t* w_packed_t, void* stream);
+cpi_status cpi_nn_conv2d(const uint16_t* x, const uint16_t* w_packed, const float* bias,
+                         const uint16_t* mask, int32_t relu, int32_t b, int32_t h, int32_t w,
+                         int32_t cin, int32_t cout, int32_t ks, int32_t kpad, uint16_t* out,
+                         float* out_f32, void* stream);
+cpi_status cpi_nn_conv2d_wgrad(const uint16_t* x, const uint16_t* dy, int32_t b, int32_t h,
+                               int32_t w, int32_t cin, int32_t cout, int32_t ks, float* dw,
+                               void* stream);
+cpi_status cpi_nn_bias_grad(const uint16_t* dy, int64_t pixels, int32_t c, float* db,
+                            void* stream);
+cpi_status cpi_nn_maxpool2(const uint16_t* x, int32_t b, int32_t h, int32_t w, int32_t c,
+                           uint16_t* out, void* stream);
+cpi_status cpi_nn_maxpool2_grad(const uint16_t* x, const uint16_t* dout, int32_t b, int32_t h,
+                                int32_t w, int32_t c, uint16_t* dx, void* stream);
+cpi_status cpi_nn_upsample2(const uint16_t* x, int32_t b, int32_t h, int32_t w, int32_t c,
+                            uint16_t* out, void* stream);
+cpi_status cpi_nn_upsample2_grad(const uint16_t* dout, int32_t b, int32_t h, int32_t w, int32_t c,
+                                 const uint16_t* mask, uint16_t* dx, void* stream);
+cpi_status cpi_nn_concat(const uint16_t* a, const uint16_t* b, int64_t pixels, int32_t ca,
+                         int32_t cb, uint16_t* out, void* stream);
+cpi_status cpi_nn_split(const uint16_t* d, int64_t pixels, int32_t ca, int32_t cb, uint16_t* da,
+                        uint16_t* db, void* stream);
+cpi_status cpi_nn_add_mask(uint16_t* x, const uint16_t* add, const uint16_t* mask, int64_t count,
+                           void* stream);
+cpi_status cpi_nn_mse(const float* y, int32_t c, const float* residual, const float* target,
+                      int64_t pixels, float* loss, uint16_t* dy, void* stream);
+cpi_status cpi_nn_adam(float* w, const float* g, float* m, float* v, int64_t count, int64_t step,
+                       float lr, float beta1, float beta2, float eps, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,6 +121,42 @@ _SIGS = {
                                         c_void_p, c_void_p, c_size_t, c_void_p, c_size_t,
                                         POINTER(c_int64)]),
     "cpi_get_mma_encoding": (c_int, []),
+    "cpi_denoiser_layer_count": (c_int, [POINTER(c_int32)]),
+    "cpi_denoiser_layer_info": (c_int, [c_int32, c_void_p]),
+    "cpi_denoiser_param_count": (c_int, [POINTER(c_int64)]),
+    "cpi_denoiser_workspace_size": (c_int, [c_int32, c_int32, c_int32, c_int32, POINTER(c_size_t)]),
+    "cpi_denoiser_forward": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                     c_void_p, c_size_t, c_void_p]),
+    "cpi_denoiser_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float,
+                                        c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_size_t, c_void_p]),
+    "cpi_denoiser_gradients": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "cpi_image_quality": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                  c_void_p, c_void_p]),
+    "cpi_nn_pack_weights": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                    c_void_p]),
+    "cpi_nn_conv2d": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                              c_int32, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                              c_void_p]),
+    "cpi_nn_conv2d_wgrad": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                    c_int32, c_int32, c_void_p, c_void_p]),
+    "cpi_nn_bias_grad": (c_int, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
+    "cpi_nn_maxpool2": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "cpi_nn_maxpool2_grad": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                     c_void_p, c_void_p]),
+    "cpi_nn_upsample2": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p,
+                                 c_void_p]),
+    "cpi_nn_upsample2_grad": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p,
+                                      c_void_p, c_void_p]),
+    "cpi_nn_concat": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p]),
+    "cpi_nn_split": (c_int, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "cpi_nn_add_mask": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
+    "cpi_nn_mse": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
+                           c_void_p]),
+    "cpi_nn_adam": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int64,
+                            ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            c_void_p]),
 }
 
 EXPORTED = tuple(_SIGS)

@@ -27,7 +27,9 @@ SOURCES = [
     "kernels_refocus.hip",
     "autotune.hip",
     "peaks.hip",
+    "kernels_nn.hip",
     "api.hip",
+    "api_nn.hip",
 ]
 
 FLAGS = [

@@ -17,6 +17,7 @@
 
 #include "autotune.h"
 #include "cpi.h"
+#include "errors.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -84,6 +85,14 @@ cpi_status device_error(hipError_t e, const char* what) {
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   return set_error(CPI_ERR_DEVICE, m);
 }
+
+}  // namespace
+
+namespace cpi {
+cpi_status report_error(cpi_status s, const std::string& msg) { return set_error(s, msg); }
+}  // namespace cpi
+
+namespace {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 

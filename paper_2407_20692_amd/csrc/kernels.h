@@ -148,4 +148,63 @@ hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* 
                            const RefocusConfig& c, float* partial, float* out,
                            hipStream_t s);
 
+// ---- learned denoiser: BF16 matrix-core convolutions and their companions --
+// Activations are NHWC bfloat16 (raw uint16 bits); layers keep Cin % 8 == 0
+// and Cout % 32 == 0.  Weights fed to the matrix cores are bfloat16 rows of
+// length Kpad (a multiple of 32) holding k = tap * Cin + ci, zero beyond
+// ks * ks * Cin.
+struct NnConvArgs {
+  const uint16_t* in = nullptr;    // [B][H][W][Cin]
+  const uint16_t* wk = nullptr;    // [Cout][Kpad]
+  const float* bias = nullptr;     // [Cout] or null
+  const uint16_t* mask = nullptr;  // [B][H][W][Cout]: output zeroed where mask <= 0; or null
+  uint16_t* out = nullptr;         // [B][H][W][Cout] bfloat16, or null
+  float* out_f32 = nullptr;        // [B][H][W][Cout] FP32, or null
+  int B = 0, H = 0, W = 0, Cin = 0, Cout = 0, ks = 0, Kpad = 0;
+  int relu = 0;
+};
+// Forward convolution (zero padding, ks odd); the backward-data
+// convolution is the same call on dY with the flipped, transposed weights.
+hipError_t nn_conv(const NnConvArgs& a, hipStream_t s);
+
+struct NnWgradArgs {
+  const uint16_t* in = nullptr;    // [B][H][W][Cin] layer input
+  const uint16_t* dy = nullptr;    // [B][H][W][Cout] output gradient
+  float* dw = nullptr;             // [Cout][ks*ks*Cin], accumulated into (FP32 atomics)
+  int B = 0, H = 0, W = 0, Cin = 0, Cout = 0, ks = 0, Kpad = 0;
+};
+hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s);
+// db[n] += sum over the M pixels of dy[m][n]
+hipError_t nn_bias_grad(const uint16_t* dy, int64_t M, int C, float* db, hipStream_t s);
+// FP32 weights [Cout][ks*ks][Cin] -> bfloat16 [Cout][kpad] and, if wt is not
+// null, the flipped transposed [Cin][kpad_t] (k = tap' * Cout + co with
+// tap' = ks*ks - 1 - tap) of the backward-data convolution.
+hipError_t nn_pack_weights(const float* w, int Cout, int Cin, int ks, uint16_t* wf, int kpad,
+                           uint16_t* wt, int kpad_t, hipStream_t s);
+hipError_t nn_maxpool(const uint16_t* in, int B, int H, int W, int C, uint16_t* out,
+                      hipStream_t s);
+hipError_t nn_maxpool_bwd(const uint16_t* in, int B, int H, int W, int C, const uint16_t* dout,
+                          uint16_t* din, hipStream_t s);
+// H, W: the input size of the upsampling (output 2H x 2W)
+hipError_t nn_upsample(const uint16_t* in, int B, int H, int W, int C, uint16_t* out,
+                       hipStream_t s);
+hipError_t nn_upsample_bwd(const uint16_t* dout, int B, int H, int W, int C, const uint16_t* mask,
+                           uint16_t* din, hipStream_t s);
+hipError_t nn_concat(const uint16_t* a, const uint16_t* b, int64_t P, int C1, int C2, uint16_t* out,
+                     hipStream_t s);
+hipError_t nn_split(const uint16_t* d, int64_t P, int C1, int C2, uint16_t* da, uint16_t* db,
+                    hipStream_t s);
+hipError_t nn_add_mask(uint16_t* x, const uint16_t* add, const uint16_t* mask, int64_t n,
+                       hipStream_t s);
+hipError_t nn_mse(const float* y, int C, const float* res, const float* t, int64_t P, float* loss,
+                  uint16_t* dy, hipStream_t s);
+hipError_t nn_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                   float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t nn_normalize(const float* planes, int B, int64_t hw, int C, uint16_t* out, float* xf,
+                        const float* targets, float* tnorm, float* stats, hipStream_t s);
+hipError_t nn_denormalize(const float* x, int C, const float* res, const float* stats, int64_t hw,
+                          int B, float* y, hipStream_t s);
+hipError_t nn_quality(const float* pred, const float* target, int B, int H, int W, double* psnr,
+                      double* ssim, hipStream_t s);
+
 }  // namespace cpi

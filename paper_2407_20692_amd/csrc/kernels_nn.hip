@@ -1,0 +1,648 @@
+// Kernels of the learned denoiser: a convolutional encoder-decoder on BF16
+// matrix cores (v_mfma_f32_16x16x32_bf16, FP32 sums), trained with Adam on
+// FP32 master weights.
+//
+// Activations are NHWC bfloat16 tensors [B][H][W][C] (C innermost).  A
+// convolution is an implicit GEMM: M = B*H*W output pixels, N = Cout output
+// channels, K = KS*KS*Cin with k = tap*Cin + ci (tap = ky*KS + kx), zero
+// padding of (KS-1)/2 pixels.  Weights are stored [Cout][Kpad] (K contiguous,
+// zero-padded to a multiple of 32).  Every layer has Cin % 8 == 0 and
+// Cout % 32 == 0 (narrower layers carry zero channels), so the 8 consecutive
+// K values a lane feeds to one matrix-core op are 8 consecutive channels of
+// one input pixel: one 16-byte load.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace cpi {
+
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// Round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+unsigned grid1(int64_t n, int threads = 256) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return unsigned(g);
+}
+
+// ---- convolution, forward and backward-data ---------------------------------
+// A work-group of 4 waves covers 128 pixels x 32 output channels; a wave
+// 32 x 32 (2 x 2 tiles of 16 x 16).  Lane l holds pixel (or channel) l % 16
+// of a tile and K group l / 16 (8 consecutive K values).
+__global__ __launch_bounds__(256) void k_conv(NnConvArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t M = int64_t(a.B) * a.H * a.W;
+  const int64_t m0 = int64_t(blockIdx.x) * 128 + wave * 32;
+  const int n0 = blockIdx.y * 32;
+  const int K = a.ks * a.ks * a.Cin;
+  const int half = a.ks / 2;
+  // the two pixels this lane loads (one per M tile)
+  int pb[2], py[2], px[2];
+  bool pv[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int64_t m = m0 + 16 * i + r;
+    pv[i] = m < M;
+    const int64_t mm = pv[i] ? m : 0;
+    px[i] = int(mm % a.W);
+    py[i] = int((mm / a.W) % a.H);
+    pb[i] = int(mm / (int64_t(a.W) * a.H));
+  }
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+  for (int kc = 0; kc < a.Kpad; kc += 32) {
+    const int k = kc + 8 * g;
+    uint4 av[2], bv[2];
+    const int tap = k / a.Cin, ci = k - tap * a.Cin;
+    const int dy = tap / a.ks - half, dx = tap % a.ks - half;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      av[i] = make_uint4(0, 0, 0, 0);
+      const int yy = py[i] + dy, xx = px[i] + dx;
+      if (pv[i] && k < K && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+        av[i] = *reinterpret_cast<const uint4*>(
+            a.in + ((int64_t(pb[i]) * a.H + yy) * a.W + xx) * a.Cin + ci);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      bv[j] = *reinterpret_cast<const uint4*>(a.wk + int64_t(n0 + 16 * j + r) * a.Kpad + k);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av[i]),
+                                                             __builtin_bit_cast(v8bf, bv[j]),
+                                                             acc[i][j], 0, 0, 0);
+  }
+  // element (pixel 4g + t, channel r) of each tile
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t m = m0 + 16 * i + 4 * g + t;
+        const int n = n0 + 16 * j + r;
+        if (m >= M) continue;
+        float v = acc[i][j][t];
+        if (a.bias) v += a.bias[n];
+        if (a.relu && v < 0.0f) v = 0.0f;
+        const int64_t o = m * a.Cout + n;
+        if (a.mask && !(bf2f(a.mask[o]) > 0.0f)) v = 0.0f;
+        if (a.out) a.out[o] = f2bf(v);
+        if (a.out_f32) a.out_f32[o] = v;
+      }
+}
+
+// ---- convolution, backward-weight -------------------------------------------
+// dW[n][k] += sum over pixels m of dY[m][n] * X(m, k), X the implicit im2col of
+// the input.  A work-group owns a 32 x 32 tile of dW (4 waves, one 16 x 16
+// quadrant each) and a range of pixels, taken 32 at a time: dY and X tiles
+// are loaded with 16-byte loads, stored transposed in LDS ([channel][pixel])
+// so that each lane's 8 consecutive pixels are one 16-byte LDS read, and the
+// work-group's partial tile is added to dW with FP32 atomics.
+__global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t ty[32][32 + 8];   // [n][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t tx[32][32 + 8];   // [k][pixel]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int n0 = blockIdx.x * 32;
+  const int kc = blockIdx.y * 32;
+  const int64_t M = int64_t(a.B) * a.H * a.W;
+  const int64_t per = (M + gridDim.z - 1) / gridDim.z;
+  const int64_t mlo = int64_t(blockIdx.z) * per;
+  const int64_t mhi = mlo + per < M ? mlo + per : M;
+  const int K = a.ks * a.ks * a.Cin;
+  const int half = a.ks / 2;
+  // loader: thread t moves pixel p = t / 8 (of 32), 4 channel slots of 8 ...
+  const int lp = t >> 3, lq = t & 7;   // pixel, 8-channel group (0..3: dY, 4..7: X)
+  const int wn = (wave & 1) * 16, wk = (wave >> 1) * 16;
+  v4f acc = v4f{0, 0, 0, 0};
+  for (int64_t mb = mlo; mb < mhi; mb += 32) {
+    const int64_t m = mb + lp;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (m < mhi) {
+      if (lq < 4) {
+        v = *reinterpret_cast<const uint4*>(a.dy + m * a.Cout + n0 + 8 * lq);
+      } else {
+        const int k = kc + 8 * (lq - 4);
+        if (k < K) {
+          const int tap = k / a.Cin, ci = k - tap * a.Cin;
+          const int x = int(m % a.W), y = int((m / a.W) % a.H);
+          const int b = int(m / (int64_t(a.W) * a.H));
+          const int yy = y + tap / a.ks - half, xx = x + tap % a.ks - half;
+          if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+            v = *reinterpret_cast<const uint4*>(a.in + ((int64_t(b) * a.H + yy) * a.W + xx) * a.Cin +
+                                                ci);
+        }
+      }
+    }
+    const uint16_t* hv = reinterpret_cast<const uint16_t*>(&v);
+    if (lq < 4) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ty[8 * lq + e][lp] = hv[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) tx[8 * (lq - 4) + e][lp] = hv[e];
+    }
+    __syncthreads();
+    const uint4 av = *reinterpret_cast<const uint4*>(&ty[wn + r][8 * g]);
+    const uint4 bv = *reinterpret_cast<const uint4*>(&tx[wk + r][8 * g]);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                  __builtin_bit_cast(v8bf, bv), acc, 0, 0, 0);
+    __syncthreads();
+  }
+  // element (n = wn + 4g + e, k = wk + r)
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int n = n0 + wn + 4 * g + e;
+    const int k = kc + wk + r;
+    if (n < a.Cout && k < K) atomicAdd(&a.dw[int64_t(n) * K + k], acc[e]);
+  }
+}
+
+// db[n] += sum over pixels of dY[m][n]
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int64_t M,
+                                                   int C, float* __restrict__ db) {
+  const int n = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int row = threadIdx.x >> 6;
+  float s = 0.0f;
+  if (n < C)
+    for (int64_t m = int64_t(blockIdx.x) * 4 + row; m < M; m += int64_t(gridDim.x) * 4)
+      s += bf2f(dy[m * C + n]);
+  __shared__ float red[4][64];
+  red[row][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (row == 0 && n < C) atomicAdd(&db[n], red[0][threadIdx.x] + red[1][threadIdx.x] +
+                                               red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// FP32 master weights [Cout][ks*ks][Cin] -> BF16 [Cout][kpad] (forward) and
+// the flipped, transposed [Cin][kpad_t] with K' = tap'*Cout + co, tap' =
+// ks*ks-1-tap (backward-data).
+__global__ __launch_bounds__(256) void k_pack_weights(const float* __restrict__ w, int Cout,
+                                                      int Cin, int ks, uint16_t* __restrict__ wf,
+                                                      int kpad, uint16_t* __restrict__ wt,
+                                                      int kpad_t) {
+  const int taps = ks * ks;
+  const int64_t nf = int64_t(Cout) * kpad, nt = wt ? int64_t(Cin) * kpad_t : 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nf + nt;
+       i += int64_t(gridDim.x) * 256) {
+    if (i < nf) {
+      const int co = int(i / kpad), k = int(i % kpad);
+      wf[i] = k < taps * Cin ? f2bf(w[int64_t(co) * taps * Cin + k]) : uint16_t(0);
+    } else {
+      const int64_t j = i - nf;
+      const int ci = int(j / kpad_t), k = int(j % kpad_t);
+      uint16_t v = 0;
+      if (k < taps * Cout) {
+        const int tp = k / Cout, co = k % Cout;
+        v = f2bf(w[(int64_t(co) * taps + (taps - 1 - tp)) * Cin + ci]);
+      }
+      wt[j] = v;
+    }
+  }
+}
+
+// ---- pooling, upsampling, concatenation, masks ------------------------------
+__global__ __launch_bounds__(256) void k_maxpool(const uint16_t* __restrict__ in, int B, int H,
+                                                 int W, int C, uint16_t* __restrict__ out) {
+  const int Ho = H / 2, Wo = W / 2;
+  const int64_t n = int64_t(B) * Ho * Wo * C;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int c = int(i % C);
+    const int64_t p = i / C;
+    const int x = int(p % Wo), y = int((p / Wo) % Ho), b = int(p / (int64_t(Wo) * Ho));
+    const uint16_t* s = in + ((int64_t(b) * H + 2 * y) * W + 2 * x) * C + c;
+    float m = bf2f(s[0]);
+    m = fmaxf(m, bf2f(s[C]));
+    m = fmaxf(m, bf2f(s[int64_t(W) * C]));
+    m = fmaxf(m, bf2f(s[int64_t(W) * C + C]));
+    out[i] = f2bf(m);
+  }
+}
+
+// Gradient of the 2 x 2 maximum: to the first position (in window order)
+// holding the maximum.
+__global__ __launch_bounds__(256) void k_maxpool_bwd(const uint16_t* __restrict__ in, int B,
+                                                     int H, int W, int C,
+                                                     const uint16_t* __restrict__ dout,
+                                                     uint16_t* __restrict__ din) {
+  const int Ho = H / 2, Wo = W / 2;
+  const int64_t n = int64_t(B) * Ho * Wo * C;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int c = int(i % C);
+    const int64_t p = i / C;
+    const int x = int(p % Wo), y = int((p / Wo) % Ho), b = int(p / (int64_t(Wo) * Ho));
+    const int64_t base = ((int64_t(b) * H + 2 * y) * W + 2 * x) * C + c;
+    const int64_t off[4] = {0, C, int64_t(W) * C, int64_t(W) * C + C};
+    int best = 0;
+    float m = bf2f(in[base]);
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      const float v = bf2f(in[base + off[q]]);
+      if (v > m) {
+        m = v;
+        best = q;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) din[base + off[q]] = q == best ? dout[i] : uint16_t(0);
+  }
+}
+
+// nearest 2x upsampling and its gradient (sum of the 4 copies, zeroed where
+// mask <= 0 if a mask is given)
+__global__ __launch_bounds__(256) void k_upsample(const uint16_t* __restrict__ in, int B, int H,
+                                                  int W, int C, uint16_t* __restrict__ out) {
+  const int64_t n = int64_t(B) * 4 * H * W * C;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int c = int(i % C);
+    const int64_t p = i / C;
+    const int x = int(p % (2 * W)), y = int((p / (2 * W)) % (2 * H)), b = int(p / (4 * int64_t(W) * H));
+    out[i] = in[((int64_t(b) * H + y / 2) * W + x / 2) * C + c];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_upsample_bwd(const uint16_t* __restrict__ dout, int B,
+                                                      int H, int W, int C,
+                                                      const uint16_t* __restrict__ mask,
+                                                      uint16_t* __restrict__ din) {
+  const int64_t n = int64_t(B) * H * W * C;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int c = int(i % C);
+    const int64_t p = i / C;
+    const int x = int(p % W), y = int((p / W) % H), b = int(p / (int64_t(W) * H));
+    const int64_t base = ((int64_t(b) * 2 * H + 2 * y) * 2 * W + 2 * x) * C + c;
+    const float s = (bf2f(dout[base]) + bf2f(dout[base + C])) +
+                    (bf2f(dout[base + int64_t(2 * W) * C]) + bf2f(dout[base + int64_t(2 * W) * C + C]));
+    din[i] = (mask && !(bf2f(mask[i]) > 0.0f)) ? uint16_t(0) : f2bf(s);
+  }
+}
+
+// out[p] = [a[p] (C1 channels), b[p] (C2 channels)]; split is the inverse.
+__global__ __launch_bounds__(256) void k_concat(const uint16_t* __restrict__ a,
+                                                const uint16_t* __restrict__ b, int64_t P, int C1,
+                                                int C2, uint16_t* __restrict__ out, int split) {
+  const int C = C1 + C2;
+  const int64_t n = P * C;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int64_t p = i / C;
+    const int c = int(i % C);
+    if (!split) {
+      out[i] = c < C1 ? a[p * C1 + c] : b[p * C2 + (c - C1)];
+    } else {
+      // here `out` is the concatenated gradient and a, b receive its parts
+      uint16_t* da = const_cast<uint16_t*>(a);
+      uint16_t* db = const_cast<uint16_t*>(b);
+      if (c < C1)
+        da[p * C1 + c] = out[i];
+      else
+        db[p * C2 + (c - C1)] = out[i];
+    }
+  }
+}
+
+// x = (x + add) where mask > 0, 0 elsewhere (add and mask nullable)
+__global__ __launch_bounds__(256) void k_add_mask(uint16_t* __restrict__ x,
+                                                  const uint16_t* __restrict__ add,
+                                                  const uint16_t* __restrict__ mask, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    float v = bf2f(x[i]);
+    if (add) v += bf2f(add[i]);
+    if (mask && !(bf2f(mask[i]) > 0.0f)) v = 0.0f;
+    x[i] = f2bf(v);
+  }
+}
+
+// ---- loss and optimiser ------------------------------------------------------
+// Mean squared error of the prediction z = y[p][0] + res[p] (y with C
+// channels per pixel, res nullable) against t over P pixels:
+// loss += sum (z - t)^2 / P; dy = 2 (z - t) / P in channel 0, 0 elsewhere.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, int C,
+                                             const float* __restrict__ res,
+                                             const float* __restrict__ t, int64_t P,
+                                             float* __restrict__ loss, uint16_t* __restrict__ dy) {
+  float s = 0.0f;
+  const float inv = 1.0f / float(P);
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < P * C;
+       i += int64_t(gridDim.x) * 256) {
+    const int64_t p = i / C;
+    const int c = int(i % C);
+    float g = 0.0f;
+    if (c == 0) {
+      const float d = (res ? y[i] + res[p] : y[i]) - t[p];
+      s += d * d;
+      g = 2.0f * d * inv;
+    }
+    if (dy) dy[i] = f2bf(g);
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, red[0] * inv);
+}
+
+// Adam on FP32 master parameters (bias-corrected moments).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              int64_t n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// Planes [B][H*W] (FP32) -> x = (p - mu) / sigma with the plane's own mean
+// and population standard deviation (sigma = 1 for a constant plane): as FP32
+// [B][H*W] in xf and as BF16 channel 0 of [B][H*W][C] (channels 1..C-1 zero);
+// stats[2b], stats[2b+1] = mu, sigma.  Targets, if given, take their plane's
+// input transform (FP32, tnorm).
+__global__ __launch_bounds__(256) void k_normalize(const float* __restrict__ planes, int64_t hw,
+                                                   int C, uint16_t* __restrict__ out,
+                                                   float* __restrict__ xf,
+                                                   const float* __restrict__ targets,
+                                                   float* __restrict__ tnorm,
+                                                   float* __restrict__ stats) {
+  const int b = blockIdx.x;
+  const float* p = planes + int64_t(b) * hw;
+  __shared__ double red[2][256];
+  double s = 0.0, s2 = 0.0;
+  for (int64_t i = threadIdx.x; i < hw; i += 256) {
+    const double v = p[i];
+    s += v;
+    s2 += v * v;
+  }
+  red[0][threadIdx.x] = s;
+  red[1][threadIdx.x] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double mean = red[0][0] / double(hw);
+  const double var = red[1][0] / double(hw) - mean * mean;
+  const float sd = float(var > 0.0 ? sqrt(var) : 1.0);
+  const float mu = float(mean);
+  if (threadIdx.x == 0 && stats) {
+    stats[2 * b] = mu;
+    stats[2 * b + 1] = sd;
+  }
+  for (int64_t i = threadIdx.x; i < hw; i += 256) {
+    uint16_t* o = out + (int64_t(b) * hw + i) * C;
+    const float x = (p[i] - mu) / sd;
+    xf[int64_t(b) * hw + i] = x;
+    o[0] = f2bf(x);
+    for (int c = 1; c < C; ++c) o[c] = 0;
+    if (targets) tnorm[int64_t(b) * hw + i] = (targets[int64_t(b) * hw + i] - mu) / sd;
+  }
+}
+
+// y[b][i] = (x[b][i][0] + res[b][i]) * sigma_b + mu_b (back to the plane's
+// own scale)
+__global__ __launch_bounds__(256) void k_denormalize(const float* __restrict__ x, int C,
+                                                     const float* __restrict__ res,
+                                                     const float* __restrict__ stats, int64_t hw,
+                                                     int B, float* __restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < int64_t(B) * hw;
+       i += int64_t(gridDim.x) * 256) {
+    const int b = int(i / hw);
+    y[i] = (x[i * C] + res[i]) * stats[2 * b + 1] + stats[2 * b];
+  }
+}
+
+// ---- image quality -------------------------------------------------------------
+// One work-group per plane, FP64: PSNR with the target's data range
+// max(t) - min(t) (infinite when the planes are equal), and SSIM with an
+// 11 x 11 Gaussian window (sigma 1.5, normalised to sum 1) over every position
+// where the window fits, both planes mapped to [0, 1] by the target's minimum
+// and range (range 1 for a constant target), K1 = 0.01, K2 = 0.03.
+__global__ __launch_bounds__(256) void k_quality(const float* __restrict__ pred,
+                                                 const float* __restrict__ target, int H, int W,
+                                                 double* __restrict__ psnr,
+                                                 double* __restrict__ ssim) {
+  const int b = blockIdx.x;
+  const int64_t hw = int64_t(H) * W;
+  const float* p = pred + int64_t(b) * hw;
+  const float* t = target + int64_t(b) * hw;
+  __shared__ double red[3][256];
+  __shared__ double win[11];
+  double lo = __builtin_huge_val(), hi = -__builtin_huge_val(), se = 0.0;
+  for (int64_t i = threadIdx.x; i < hw; i += 256) {
+    const double tv = t[i];
+    lo = fmin(lo, tv);
+    hi = fmax(hi, tv);
+    const double d = double(p[i]) - tv;
+    se += d * d;
+  }
+  red[0][threadIdx.x] = lo;
+  red[1][threadIdx.x] = hi;
+  red[2][threadIdx.x] = se;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+      red[2][threadIdx.x] += red[2][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  lo = red[0][0];
+  const double range = red[1][0] - lo;
+  se = red[2][0];
+  if (threadIdx.x == 0) {
+    psnr[b] = se == 0.0 ? __builtin_huge_val()
+                        : 10.0 * log10(range * range / (se / double(hw)));
+    double g[11], sum = 0.0;
+    for (int i = 0; i < 11; ++i) {
+      const double r = double(i - 5);
+      g[i] = exp(-(r * r) / (2.0 * 1.5 * 1.5));
+      sum += g[i];
+    }
+    for (int i = 0; i < 11; ++i) win[i] = g[i] / sum;   // 2-D window = win x win
+  }
+  __syncthreads();
+  const double inv = 1.0 / (range == 0.0 ? 1.0 : range);
+  const double c1 = 0.01 * 0.01, c2 = 0.03 * 0.03;
+  const int ny = H - 10, nx = W - 10;
+  double acc = 0.0;
+  for (int64_t q = threadIdx.x; q < int64_t(ny) * nx; q += 256) {
+    const int y0 = int(q / nx), x0 = int(q % nx);
+    double sa = 0, sb = 0, saa = 0, sbb = 0, sab = 0;
+    for (int i = 0; i < 11; ++i) {
+      for (int j = 0; j < 11; ++j) {
+        const double w = win[i] * win[j];
+        const int64_t o = int64_t(y0 + i) * W + x0 + j;
+        const double a = (double(p[o]) - lo) * inv;
+        const double c = (double(t[o]) - lo) * inv;
+        sa += w * a;
+        sb += w * c;
+        saa += w * a * a;
+        sbb += w * c * c;
+        sab += w * a * c;
+      }
+    }
+    const double va = saa - sa * sa, vb = sbb - sb * sb, cab = sab - sa * sb;
+    acc += ((2.0 * sa * sb + c1) * (2.0 * cab + c2)) /
+           ((sa * sa + sb * sb + c1) * (va + vb + c2));
+  }
+  __syncthreads();
+  red[2][threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) red[2][threadIdx.x] += red[2][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ssim[b] = red[2][0] / double(int64_t(ny) * nx);
+}
+
+}  // namespace
+
+hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
+  const int64_t M = int64_t(a.B) * a.H * a.W;
+  hipLaunchKernelGGL(k_conv, dim3(unsigned((M + 127) / 128), unsigned(a.Cout / 32)), dim3(256), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
+  const int64_t M = int64_t(a.B) * a.H * a.W;
+  const unsigned gx = unsigned(a.Cout / 32), gy = unsigned(a.Kpad / 32);
+  // split the pixels so that the grid holds about 2048 work-groups
+  int64_t z = 2048 / (int64_t(gx) * gy);
+  if (z < 1) z = 1;
+  if (z > (M + 31) / 32) z = (M + 31) / 32;
+  if (z > 65535) z = 65535;
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(gx, gy, unsigned(z)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t nn_bias_grad(const uint16_t* dy, int64_t M, int C, float* db, hipStream_t s) {
+  int64_t gx = (M + 3) / 4;
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(k_bias_grad, dim3(unsigned(gx), unsigned((C + 63) / 64)), dim3(256), 0, s, dy,
+                     M, C, db);
+  return hipGetLastError();
+}
+
+hipError_t nn_pack_weights(const float* w, int Cout, int Cin, int ks, uint16_t* wf, int kpad,
+                           uint16_t* wt, int kpad_t, hipStream_t s) {
+  const int64_t n = int64_t(Cout) * kpad + (wt ? int64_t(Cin) * kpad_t : 0);
+  hipLaunchKernelGGL(k_pack_weights, dim3(grid1(n)), dim3(256), 0, s, w, Cout, Cin, ks, wf, kpad,
+                     wt, kpad_t);
+  return hipGetLastError();
+}
+
+hipError_t nn_maxpool(const uint16_t* in, int B, int H, int W, int C, uint16_t* out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_maxpool, dim3(grid1(int64_t(B) * (H / 2) * (W / 2) * C)), dim3(256), 0, s,
+                     in, B, H, W, C, out);
+  return hipGetLastError();
+}
+
+hipError_t nn_maxpool_bwd(const uint16_t* in, int B, int H, int W, int C, const uint16_t* dout,
+                          uint16_t* din, hipStream_t s) {
+  hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid1(int64_t(B) * (H / 2) * (W / 2) * C)), dim3(256), 0,
+                     s, in, B, H, W, C, dout, din);
+  return hipGetLastError();
+}
+
+hipError_t nn_upsample(const uint16_t* in, int B, int H, int W, int C, uint16_t* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_upsample, dim3(grid1(int64_t(B) * 4 * H * W * C)), dim3(256), 0, s, in, B, H,
+                     W, C, out);
+  return hipGetLastError();
+}
+
+hipError_t nn_upsample_bwd(const uint16_t* dout, int B, int H, int W, int C, const uint16_t* mask,
+                           uint16_t* din, hipStream_t s) {
+  hipLaunchKernelGGL(k_upsample_bwd, dim3(grid1(int64_t(B) * H * W * C)), dim3(256), 0, s, dout, B,
+                     H, W, C, mask, din);
+  return hipGetLastError();
+}
+
+hipError_t nn_concat(const uint16_t* a, const uint16_t* b, int64_t P, int C1, int C2, uint16_t* out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_concat, dim3(grid1(P * (C1 + C2))), dim3(256), 0, s, a, b, P, C1, C2, out, 0);
+  return hipGetLastError();
+}
+
+hipError_t nn_split(const uint16_t* d, int64_t P, int C1, int C2, uint16_t* da, uint16_t* db,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_concat, dim3(grid1(P * (C1 + C2))), dim3(256), 0, s, da, db, P, C1, C2,
+                     const_cast<uint16_t*>(d), 1);
+  return hipGetLastError();
+}
+
+hipError_t nn_add_mask(uint16_t* x, const uint16_t* add, const uint16_t* mask, int64_t n,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_add_mask, dim3(grid1(n)), dim3(256), 0, s, x, add, mask, n);
+  return hipGetLastError();
+}
+
+hipError_t nn_mse(const float* y, int C, const float* res, const float* t, int64_t P, float* loss,
+                  uint16_t* dy, hipStream_t s) {
+  int64_t g = (P * C + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_mse, dim3(unsigned(g)), dim3(256), 0, s, y, C, res, t, P, loss, dy);
+  return hipGetLastError();
+}
+
+hipError_t nn_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                   float b2, float eps, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t nn_normalize(const float* planes, int B, int64_t hw, int C, uint16_t* out, float* xf,
+                        const float* targets, float* tnorm, float* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize, dim3(unsigned(B)), dim3(256), 0, s, planes, hw, C, out, xf,
+                     targets, tnorm, stats);
+  return hipGetLastError();
+}
+
+hipError_t nn_denormalize(const float* x, int C, const float* res, const float* stats, int64_t hw,
+                          int B, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_denormalize, dim3(grid1(int64_t(B) * hw)), dim3(256), 0, s, x, C, res, stats,
+                     hw, B, y);
+  return hipGetLastError();
+}
+
+hipError_t nn_quality(const float* pred, const float* target, int B, int H, int W, double* psnr,
+                      double* ssim, hipStream_t s) {
+  hipLaunchKernelGGL(k_quality, dim3(unsigned(B)), dim3(256), 0, s, pred, target, H, W, psnr, ssim);
+  return hipGetLastError();
+}
+
+}  // namespace cpi

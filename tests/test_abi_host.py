@@ -132,3 +132,42 @@ def test_mma_encoding_switch(cpi):
         assert cpi.get_mma_encoding() == cpi.MMA_AUTO
     finally:
         cpi.set_mma_encoding(before)
+
+
+def test_denoiser_host_validation(cpi):
+    """Layer table, parameter layout and argument checks of the denoiser
+    entry points (host logic only, nothing is launched)."""
+    import paper_2407_20692_amd.denoiser as dn_lib
+    import oracle.denoiser as dn_ref
+
+    infos = dn_lib.layers()
+    assert [L.name for L in infos] == [L.name for L in dn_ref.layers()]
+    total = dn_lib.param_count()
+    end = 0
+    for L in infos:
+        assert L.weight_offset >= end and L.bias_offset >= L.weight_offset + L.weight_count
+        end = L.bias_offset + L.cout
+    assert end <= total
+    assert dn_lib.workspace_size(16, 128, 128, True) > dn_lib.workspace_size(16, 128, 128, False)
+    lib = cpi.lib
+    out = ctypes.c_size_t(0)
+    assert lib.cpi_denoiser_workspace_size(0, 16, 16, 0, ctypes.byref(out)) == 1
+    assert lib.cpi_denoiser_workspace_size(1, 12, 16, 0, ctypes.byref(out)) == 1
+    assert lib.cpi_denoiser_workspace_size(1 << 12, 1024, 1024, 0, ctypes.byref(out)) == 1
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.cpi_denoiser_forward(fake, 1, 16, 16, fake, fake, fake, 16, None) == 4
+    assert lib.cpi_denoiser_train_step(fake, fake, fake, 0, 1e-3, 1, 16, 16, fake, fake, fake,
+                                       fake, 1 << 40, None) == 1
+    assert lib.cpi_denoiser_train_step(fake, fake, fake, 1, 0.0, 1, 16, 16, fake, fake, fake,
+                                       fake, 1 << 40, None) == 1
+    # conv channel rules: cin % 8, cout % 32, odd ks, kpad consistent
+    assert lib.cpi_nn_conv2d(fake, fake, None, None, 0, 1, 4, 4, 12, 32, 3, 128, fake, None,
+                             None) == 1
+    assert lib.cpi_nn_conv2d(fake, fake, None, None, 0, 1, 4, 4, 8, 48, 3, 96, fake, None,
+                             None) == 1
+    assert lib.cpi_nn_conv2d(fake, fake, None, None, 0, 1, 4, 4, 8, 32, 2, 32, fake, None,
+                             None) == 1
+    assert lib.cpi_nn_conv2d(fake, fake, None, None, 0, 1, 4, 4, 8, 32, 3, 64, fake, None,
+                             None) == 1
+    assert lib.cpi_nn_maxpool2(fake, 1, 5, 4, 8, fake, None) == 1
+    assert lib.cpi_image_quality(fake, fake, 1, 10, 16, fake, fake, None) == 1
