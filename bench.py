@@ -28,6 +28,8 @@ Printed as ONE JSON line:
   file_ingest    raw side-by-side frame files (the paper's 256 x 512 layout,
                  11 files of 512 frames) streamed into the running sums
   measured_peaks the device's sustained matrix-core and copy rates (microbenchmarks)
+  denoiser       the learned denoiser's training step (16 planes of 128 x 128)
+                 and inference (32 planes): time and algorithmic BF16 FLOP rate
   cpu_baseline   the CPU oracle on a bounded sample of the same workload
 """
 import argparse
@@ -45,6 +47,8 @@ WORKLOAD = "da128_db64_n20000_u8bin"
 LARGE_WORKLOAD = "da256_db128_n100000_bit1"
 PAPER_WORKLOAD = "da256_db256_files11_bit1"
 STREAM_WORKLOAD = "da128_db64_stream200x1000_bit1"
+DENOISE_WORKLOAD = "da128_db64_denoise500to50000_bit1"
+BF16_PEAK = 2.5e15          # dense bfloat16 matrix-core FLOP/s, MI355X
 INT8_PEAK = 5.0e15          # dense int8 matrix-core ops/s, MI355X
 FP4_PEAK = 10.1e15          # dense FP4 (and FP6) matrix-core ops/s, MI355X
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemm_f4lds_da128_db64_n20000_pmc.txt")
@@ -186,6 +190,226 @@ def cpu_baseline(a, b, w, alphas):
     }
 
 
+def _layer_level(name):
+    return {"enc1": 0, "dec1": 0, "out": 0, "enc2": 1, "dec2": 1, "enc3": 2, "dec3": 2,
+            "mid_": 3}[name[:4] if not name.startswith("out") else "out"]
+
+
+def denoiser_forward_flops(dn, h, w):
+    """Algorithmic FLOPs of one forward pass on one h x w plane: two per
+    multiply-add of every convolution at its logical channel counts."""
+    total = 0
+    for L in dn.layers():
+        lv = _layer_level(L.name)
+        total += 2 * (h >> lv) * (w >> lv) * L.cout_used * L.ks * L.ks * L.cin_used
+    return total
+
+
+def denoiser_train_flops(dn, h, w):
+    """One training step per plane: forward, weight gradients, and input
+    gradients of every layer but the first."""
+    first = dn.layers()[0]
+    f0 = 2 * h * w * first.cout_used * first.ks * first.ks * first.cin_used
+    return 3 * denoiser_forward_flops(dn, h, w) - f0
+
+
+def denoiser_timing(torch, np, dev, batch=16, planes=32, h=128, w=128, reps=20):
+    """Training-step and inference time of the denoiser on synthetic planes,
+    with the algorithmic BF16 FLOP rate of each against the matrix-core peak."""
+    import paper_2407_20692_amd.denoiser as dn
+
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    x = torch.randn(planes, h, w, generator=gen, device=dev)
+    t = torch.randn(planes, h, w, generator=gen, device=dev)
+    net = dn.Denoiser(seed=11, device=dev)
+    xb, tb = x[:batch].contiguous(), t[:batch].contiguous()
+    out = torch.empty_like(x)
+    for _ in range(3):
+        net.train_step(xb, tb, 1e-4)
+        net.forward(x, out=out)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        net.train_step(xb, tb, 1e-4)
+    e[1].record()
+    e[2].record()
+    for _ in range(reps):
+        net.forward(x, out=out)
+    e[3].record()
+    torch.cuda.synchronize()
+    ms_step = e[0].elapsed_time(e[1]) / reps
+    ms_inf = e[2].elapsed_time(e[3]) / reps
+    f_step = denoiser_train_flops(dn, h, w) * batch
+    f_inf = denoiser_forward_flops(dn, h, w) * planes
+    return {
+        "plane": [h, w], "batch": batch, "planes_inferred": planes,
+        "train_step_ms": ms_step,
+        "train_tflops": f_step / (ms_step * 1e-3) / 1e12,
+        "train_frac_bf16_peak": f_step / (ms_step * 1e-3) / BF16_PEAK,
+        "inference_ms": ms_inf,
+        "inference_tflops": f_inf / (ms_inf * 1e-3) / 1e12,
+        "inference_frac_bf16_peak": f_inf / (ms_inf * 1e-3) / BF16_PEAK,
+        "flops_note": "algorithmic: 2 per multiply-add at logical channel counts",
+    }
+
+
+def denoise_bench(args, cpi, torch, np, dev):
+    """Learned denoiser on pairs made by the pipeline itself, and the
+    comparison with the plain pipeline at equal wall time."""
+    import paper_2407_20692_amd.denoiser as dn
+    import paper_2407_20692_amd.denoise_pipeline as dp
+    from synth import WORKLOADS, workload_seed
+    from synth.gpu_speckle import generate_binary_frames_gpu
+
+    w = WORKLOADS[DENOISE_WORKLOAD]
+    n_few, n_full, na = 500, w.n_frames, w.n_alpha
+    geo = cpi.geometry_default(w.wa, w.ha, w.wb, w.hb)
+    runs = max(4, args.runs)
+    n_test = max(2, runs // 10)
+    n_train = runs - n_test
+    base = workload_seed(w)
+
+    def frames(r):
+        return generate_binary_frames_gpu(w, count=n_full, seed=base + 1000 * r, device=dev,
+                                          chunk=2500, mask_seed_value=base + 1000 * r + 7)
+
+    def alphas(r):
+        rng = np.random.default_rng(base + 1000 * r + 3)
+        return np.sort(rng.uniform(w.alpha_lo, w.alpha_hi, na))
+
+    # -- training pairs -------------------------------------------------------------
+    t0 = time.time()
+    inputs, targets = dp.make_pairs(frames, alphas, n_train, w.pa, w.pb, geo, n_few, n_full,
+                                    log=log)
+    torch.cuda.synchronize()
+    t_pairs = time.time() - t0
+    log(f"denoise: {inputs.shape[0]} training pairs in {t_pairs:.1f} s")
+
+    # -- training ---------------------------------------------------------------------
+    net = dn.Denoiser(seed=base, device=dev)
+    batch = 16
+    # time the training step alone (HIP events), then train
+    xb, tb = inputs[:batch].contiguous(), targets[:batch].contiguous()
+    for _ in range(3):
+        net.train_step(xb, tb, 1e-3)
+    net = dn.Denoiser(seed=base, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    reps = 20
+    for _ in range(reps):
+        net.train_step(xb, tb, 1e-3)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / reps
+    net = dn.Denoiser(seed=base, device=dev)
+    t0 = time.time()
+    history = dp.train(net, inputs, targets, args.epochs, batch=batch, lr=1e-3, seed=base, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    del inputs, targets
+
+    # -- wall time of the plain pipeline and of inference ---------------------------------
+    fa, fb = frames(runs)          # a run used for timing only
+    al = alphas(runs)
+    out = torch.empty(na, w.ha, w.wa, dtype=torch.float32, device=dev)
+
+    def plain_ms(n, reps=3):
+        ts = []
+        for _ in range(reps):
+            st = cpi.Stream(w.pa, w.pb, cpi.FRAMES_BIT1, 10000)
+            ws = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, na), dev)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            pos = 0
+            while pos < n:
+                k = min(10000, n - pos)
+                st.push(fa[pos:pos + k], fb[pos:pos + k], k)
+                pos += k
+            st.refocus(geo, al, out, workspace=ws)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+            st.close()
+        return sorted(ts)[len(ts) // 2]
+
+    ns = [500, 1000, 2000, 5000, 10000, 20000, 50000]
+    ts = [plain_ms(n) for n in ns]
+    a_ms, b_ms = dp.fit_linear(ns, ts)
+    few_planes = torch.empty_like(out)
+    dp.prefix_planes(fa, fb, w.pa, w.pb, geo, al, [n_few], [few_planes])
+    den = torch.empty_like(out)
+    for _ in range(3):
+        net.forward(few_planes, out=den)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        net.forward(few_planes, out=den)
+    e1.record()
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / 10
+    t_budget = ts[0] + t_inf
+    n_eq = dp.equal_time_frames(t_budget, a_ms, b_ms, n_few, n_full)
+    # acquisition-limited view: frames arrive at the sensor's rate
+    rate = 1.0e5
+    n_eq_acq = dp.equal_time_frames(n_few / rate * 1e3 + t_budget, a_ms, b_ms + 1e3 / rate,
+                                    n_few, n_full)
+    del fa, fb
+
+    # -- evaluation on held-out runs -----------------------------------------------------
+    res = {"few": [], "den": [], "eq": [], "acq": []}
+    for r in range(n_train, runs):
+        fa, fb = frames(r)
+        al = alphas(r)
+        counts = sorted({n_few, n_eq, n_eq_acq, n_full})
+        outs = {c: torch.empty(na, w.ha, w.wa, dtype=torch.float32, device=dev) for c in counts}
+        dp.prefix_planes(fa, fb, w.pa, w.pb, geo, al, counts, [outs[c] for c in counts])
+        tgt = outs[n_full]
+        d = dp.denoise_batched(net, outs[n_few])
+        for key, pred in (("few", outs[n_few]), ("den", d), ("eq", outs[n_eq]),
+                          ("acq", outs[n_eq_acq])):
+            p, s, _, _ = dp.quality(pred, tgt)
+            res[key].append((p, s))
+        del fa, fb
+    mean = {k: (float(np.mean([x[0] for x in v])), float(np.mean([x[1] for x in v])))
+            for k, v in res.items()}
+    pol = dp.decide(mean["den"][0], mean["den"][1], mean["eq"][0], mean["eq"][1], n_few, n_eq)
+    pol_acq = dp.decide(mean["den"][0], mean["den"][1], mean["acq"][0], mean["acq"][1], n_few,
+                        n_eq_acq)
+    fwd = denoiser_forward_flops(dn, w.ha, w.wa)
+    step_flops = denoiser_train_flops(dn, w.ha, w.wa) * batch
+    return {
+        "metric": "denoiser_psnr_ssim_at_equal_time",
+        "workload": w.name,
+        "n_few": n_few, "n_full": n_full, "planes_per_run": na,
+        "train_pairs": n_train * na, "test_pairs": n_test * na, "epochs": args.epochs,
+        "batch": batch, "loss_per_epoch": history,
+        "seconds": {"pairs": round(t_pairs, 1), "train": round(t_train, 1)},
+        "train_step_ms": ms_step,
+        "train_tflops": step_flops / (ms_step * 1e-3) / 1e12,
+        "train_frac_bf16_peak": step_flops / (ms_step * 1e-3) / BF16_PEAK,
+        "inference_ms_32_planes": t_inf,
+        "inference_tflops": fwd * na / (t_inf * 1e-3) / 1e12,
+        "plain_ms": dict(zip([str(n) for n in ns], ts)),
+        "plain_fit_ms": {"a": a_ms, "b_per_frame": b_ms},
+        "equal_time": {"budget_ms": t_budget, "n_eq": n_eq},
+        "acquisition_limited": {"frames_per_s": rate, "n_eq": n_eq_acq},
+        "quality_vs_full": {
+            "plain_500": {"psnr": mean["few"][0], "ssim": mean["few"][1]},
+            "denoised_500": {"psnr": mean["den"][0], "ssim": mean["den"][1]},
+            f"plain_{n_eq}_equal_compute": {"psnr": mean["eq"][0], "ssim": mean["eq"][1]},
+            f"plain_{n_eq_acq}_equal_acquisition": {"psnr": mean["acq"][0],
+                                                     "ssim": mean["acq"][1]},
+        },
+        "policy_equal_compute": {"use_denoiser": pol.use_denoiser, "reason": pol.reason},
+        "policy_equal_acquisition": {"use_denoiser": pol_acq.use_denoiser,
+                                     "reason": pol_acq.reason},
+        "dtype": "bf16 matrix cores, fp32 sums and master weights",
+        "data": "synthetic",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,11 +423,20 @@ def main():
                     help="skip the plane-count refocus and raw-file ingest measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=["paper_like", "large", "paper"], default="paper_like",
+    ap.add_argument("--workload", choices=["paper_like", "large", "paper", "denoise",
+                                           "denoise_step"],
+                    default="paper_like",
                     help="paper_like: Da 128x128, Db 64x64, N=20000 bytes (default line); "
                          "large: Da 256x256, Db 128x128, N=100000 packed bits, 128 planes; "
                          "paper: 256x256 on both detectors, --files files of 512 frames, "
-                         "261 planes (the paper's benchmark configuration)")
+                         "261 planes (the paper's benchmark configuration); "
+                         "denoise: train the learned denoiser on pipeline-made pairs "
+                         "(500 -> 50000 frames) and compare with the plain pipeline at "
+                         "equal wall time; denoise_step: time the denoiser's training "
+                         "step and inference only")
+    ap.add_argument("--runs", type=int, default=625,
+                    help="denoise workload: streams of 50000 frames (32 pairs each)")
+    ap.add_argument("--epochs", type=int, default=4, help="denoise workload: training epochs")
     ap.add_argument("--files", type=int, default=11,
                     help="paper workload: files of 512 frames (the paper uses 11, 100, 500, 7808)")
     args = ap.parse_args()
@@ -227,6 +460,13 @@ def main():
 
     import paper_2407_20692_amd as cpi
     from synth import WORKLOADS, alphas_for, generate_frames, pack_bits_lsb
+
+    if args.workload == "denoise":
+        print(json.dumps(denoise_bench(args, cpi, torch, np, dev)))
+        return
+    if args.workload == "denoise_step":
+        print(json.dumps(denoiser_timing(torch, np, dev)))
+        return
 
     paper = args.workload == "paper"
     large = args.workload == "large" or paper
@@ -505,6 +745,8 @@ def main():
             del o, ws_n
         line["refocus_plane_counts"] = counts
         line["file_ingest"] = file_ingest_bench(cpi, torch, np, dev)
+        log("bench: denoiser training step and inference")
+        line["denoiser"] = denoiser_timing(torch, np, dev)
 
     if not args.no_cpu_baseline and not large:
         log("bench: CPU oracle baseline")

@@ -406,19 +406,24 @@ cpi_status cpi_image_quality(const float* pred, const float* target, int32_t bat
  *   null, the backward-data weights w_packed_t[cin][kpad_t] with
  *   k = (ks*ks - 1 - tap)*cout + co (kpad_t = ks*ks*cout rounded up to 32).
  * cpi_nn_conv2d: out[p][co] = act(b[co] + sum over taps and ci of
- *   w[co][tap][ci] * x[p + tap offset][ci]) (zero padding, ks odd), act = ReLU
+ *   w[co][tap][ci] * x[p + tap offset][ci]) (zero padding), act = ReLU
  *   if relu != 0; then zeroed where mask[p][co] <= 0 (mask nullable; bias
  *   nullable).  Output to out (bfloat16) and/or out_f32 (FP32).  cin % 8 == 0,
- *   cout % 32 == 0.  With (dy, w_packed_t, cin := cout, cout := cin,
+ *   cout % 32 == 0, ks 1 or 3.  With (dy, w_packed_t, cin := cout, cout := cin,
  *   kpad := kpad_t) it is the gradient with respect to the input.
  * cpi_nn_conv2d_wgrad: dw[co][tap][ci] += sum over pixels p of
- *   dy[p][co] * x[p + tap offset][ci] (FP32, accumulated into dw).
+ *   dy[p][co] * x[p + tap offset][ci] (FP32, accumulated into dw), and, if db
+ *   is not null, db[co] += sum over pixels of dy[p][co].
  * cpi_nn_bias_grad: db[c] += sum over pixels of dy[p][c].
  * cpi_nn_maxpool2 / _grad: 2x2 maximum (h, w even); the gradient goes to the
  *   first maximal position in the order (0,0), (0,1), (1,0), (1,1).
  * cpi_nn_upsample2 / _grad: nearest 2x upsampling of [b][h][w][c]; the
  *   gradient sums the four copies and is zeroed where mask <= 0 (nullable).
  * cpi_nn_concat / cpi_nn_split: out[p] = [a[p], b[p]] and its inverse.
+ * cpi_nn_upsample2_concat / _grad: out = [upsample2(low) (c1 channels),
+ *   skip (c2 channels)] for low [b][h][w][c1] and skip [b][2h][2w][c2]
+ *   (c1, c2 multiples of 8); the gradient gives dskip and dlow (the four
+ *   copies summed, zeroed where mask <= 0, mask nullable).
  * cpi_nn_add_mask: x = x + add (nullable), zeroed where mask <= 0 (nullable).
  * cpi_nn_mse: z[p] = y[p][0] + residual[p] (y with c FP32 channels per pixel,
  *   residual nullable); *loss += sum (z - t)^2 / pixels (loss nullable) and
@@ -433,7 +438,7 @@ cpi_status cpi_nn_conv2d(const uint16_t* x, const uint16_t* w_packed, const floa
                          float* out_f32, void* stream);
 cpi_status cpi_nn_conv2d_wgrad(const uint16_t* x, const uint16_t* dy, int32_t b, int32_t h,
                                int32_t w, int32_t cin, int32_t cout, int32_t ks, float* dw,
-                               void* stream);
+                               float* db, void* stream);
 cpi_status cpi_nn_bias_grad(const uint16_t* dy, int64_t pixels, int32_t c, float* db,
                             void* stream);
 cpi_status cpi_nn_maxpool2(const uint16_t* x, int32_t b, int32_t h, int32_t w, int32_t c,
@@ -446,6 +451,11 @@ cpi_status cpi_nn_upsample2_grad(const uint16_t* dout, int32_t b, int32_t h, int
                                  const uint16_t* mask, uint16_t* dx, void* stream);
 cpi_status cpi_nn_concat(const uint16_t* a, const uint16_t* b, int64_t pixels, int32_t ca,
                          int32_t cb, uint16_t* out, void* stream);
+cpi_status cpi_nn_upsample2_concat(const uint16_t* low, const uint16_t* skip, int32_t b, int32_t h,
+                                  int32_t w, int32_t c1, int32_t c2, uint16_t* out, void* stream);
+cpi_status cpi_nn_upsample2_concat_grad(const uint16_t* d, int32_t b, int32_t h, int32_t w,
+                                       int32_t c1, int32_t c2, const uint16_t* mask,
+                                       uint16_t* dlow, uint16_t* dskip, void* stream);
 cpi_status cpi_nn_split(const uint16_t* d, int64_t pixels, int32_t ca, int32_t cb, uint16_t* da,
                         uint16_t* db, void* stream);
 cpi_status cpi_nn_add_mask(uint16_t* x, const uint16_t* add, const uint16_t* mask, int64_t count,

@@ -140,7 +140,11 @@ _SIGS = {
                               c_int32, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                               c_void_p]),
     "cpi_nn_conv2d_wgrad": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
-                                    c_int32, c_int32, c_void_p, c_void_p]),
+                                    c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "cpi_nn_upsample2_concat": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                        c_int32, c_void_p, c_void_p]),
+    "cpi_nn_upsample2_concat_grad": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32,
+                                             c_void_p, c_void_p, c_void_p, c_void_p]),
     "cpi_nn_bias_grad": (c_int, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "cpi_nn_maxpool2": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "cpi_nn_maxpool2_grad": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,

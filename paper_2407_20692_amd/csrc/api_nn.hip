@@ -16,6 +16,7 @@
 #include <cstring>
 #include <exception>
 #include <string>
+#include <utility>
 
 #include "cpi.h"
 #include "errors.h"
@@ -103,7 +104,6 @@ struct Net {
   uint16_t* x8;
   uint16_t* act[kNumLayers - 1];  // outputs of the ReLU layers
   uint16_t* pool[3];
-  uint16_t* up[3];
   uint16_t* cat[3];
   float* outf;
   float* xf;
@@ -136,7 +136,6 @@ Net plan_net(uint8_t* base, int B, int H, int W, bool train) {
   const int wid[4] = {32, 64, 128, 256};
   for (int l = 0; l < 3; ++l) {
     n.pool[l] = static_cast<uint16_t*>(take(size_t(P(l + 1)) * wid[l] * 2));
-    n.up[l] = static_cast<uint16_t*>(take(size_t(P(l)) * wid[l + 1] * 2));
     n.cat[l] = static_cast<uint16_t*>(take(size_t(P(l)) * (wid[l + 1] + wid[l]) * 2));
   }
   n.outf = static_cast<float*>(take(size_t(P0) * 32 * 4));
@@ -210,9 +209,8 @@ struct Pass {
     w.Cout = L.cout;
     w.ks = L.ks;
     w.Kpad = pl.kpad[i];
+    w.db = n.grads + pl.b_off[i];
     hipError_t e = cpi::nn_conv_wgrad(w, s);
-    if (e != hipSuccess) return e;
-    e = cpi::nn_bias_grad(g, P(L.level), L.cout, n.grads + pl.b_off[i], s);
     if (e != hipSuccess || !gin) return e;
     cpi::NnConvArgs a;
     a.in = g;
@@ -259,8 +257,8 @@ struct Pass {
     h = n.act[MIDB];
     for (int l = 2; l >= 0; --l) {
       const int da = DEC3A + 2 * (2 - l);
-      NN_STEP(cpi::nn_upsample(h, B, hl(l + 1), wl(l + 1), wid[l + 1], n.up[l], s));
-      NN_STEP(cpi::nn_concat(n.up[l], n.act[2 * l + 1], P(l), wid[l + 1], wid[l], n.cat[l], s));
+      NN_STEP(cpi::nn_upcat(h, n.act[2 * l + 1], B, hl(l + 1), wl(l + 1), wid[l + 1], wid[l],
+                            n.cat[l], s));
       NN_STEP(conv(da, n.cat[l], n.act[da], nullptr, true));
       NN_STEP(conv(da + 1, n.act[da], n.act[da + 1], nullptr, true));
       h = n.act[da + 1];
@@ -284,8 +282,9 @@ struct Pass {
       const int da = DEC1A - 2 * l;
       NN_STEP(back(da + 1, n.act[da], g1, g0, n.act[da]));
       NN_STEP(back(da, n.cat[l], g0, g1, nullptr));
-      NN_STEP(cpi::nn_split(g1, P(l), wid[l + 1], wid[l], g0, n.skip[l], s));
-      NN_STEP(cpi::nn_upsample_bwd(g0, B, hl(l + 1), wl(l + 1), wid[l + 1], below[l], g1, s));
+      NN_STEP(cpi::nn_upcat_grad(g1, B, hl(l + 1), wl(l + 1), wid[l + 1], wid[l], below[l], g0,
+                                 n.skip[l], s));
+      std::swap(g0, g1);
     }
     NN_STEP(back(MIDB, n.act[MIDA], g1, g0, n.act[MIDA]));
     NN_STEP(back(MIDA, n.pool[2], g0, g1, nullptr));
@@ -462,7 +461,7 @@ cpi_status check_conv(int32_t b, int32_t h, int32_t w, int32_t cin, int32_t cout
   if (b < 1 || h < 1 || w < 1) return bad("sizes must be positive");
   if (cin < 8 || cin % 8) return bad("cin must be a positive multiple of 8");
   if (cout < 32 || cout % 32) return bad("cout must be a positive multiple of 32");
-  if (ks < 1 || ks % 2 == 0 || ks > 7) return bad("ks must be 1, 3, 5 or 7");
+  if (ks != 1 && ks != 3) return bad("ks must be 1 or 3");
   if (int64_t(b) * h * w > (int64_t(1) << 28)) return bad("batch * h * w must not exceed 2^28");
   return CPI_OK;
 }
@@ -501,7 +500,7 @@ cpi_status cpi_nn_conv2d(const uint16_t* x, const uint16_t* w_packed, const floa
 
 cpi_status cpi_nn_conv2d_wgrad(const uint16_t* x, const uint16_t* dy, int32_t b, int32_t h,
                                int32_t w, int32_t cin, int32_t cout, int32_t ks, float* dw,
-                               void* stream) {
+                               float* db, void* stream) {
   return guarded([&]() -> cpi_status {
     cpi_status st = check_conv(b, h, w, cin, cout, ks);
     if (st != CPI_OK) return st;
@@ -511,6 +510,7 @@ cpi_status cpi_nn_conv2d_wgrad(const uint16_t* x, const uint16_t* dy, int32_t b,
     a.in = x;
     a.dy = dy;
     a.dw = dw;
+    a.db = db;
     a.B = b;
     a.H = h;
     a.W = w;
@@ -585,6 +585,35 @@ cpi_status cpi_nn_upsample2_grad(const uint16_t* dout, int32_t b, int32_t h, int
     if (!dout || !dx) return bad("null device pointer");
     NN_HIP(cpi::nn_upsample_bwd(dout, b, h, w, c, mask, dx, static_cast<hipStream_t>(stream)),
            "upsample grad");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_nn_upsample2_concat(const uint16_t* low, const uint16_t* skip, int32_t b, int32_t h,
+                                  int32_t w, int32_t c1, int32_t c2, uint16_t* out, void* stream) {
+  return guarded([&]() -> cpi_status {
+    if (b < 1 || h < 1 || w < 1 || c1 < 8 || c2 < 8 || c1 % 8 || c2 % 8)
+      return bad("sizes must be positive and channel counts multiples of 8");
+    if (!low || !skip || !out) return bad("null device pointer");
+    if (!al16(low) || !al16(skip) || !al16(out)) return bad("pointers must be 16-byte aligned");
+    NN_HIP(cpi::nn_upcat(low, skip, b, h, w, c1, c2, out, static_cast<hipStream_t>(stream)),
+           "upsample concat");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_nn_upsample2_concat_grad(const uint16_t* d, int32_t b, int32_t h, int32_t w,
+                                       int32_t c1, int32_t c2, const uint16_t* mask,
+                                       uint16_t* dlow, uint16_t* dskip, void* stream) {
+  return guarded([&]() -> cpi_status {
+    if (b < 1 || h < 1 || w < 1 || c1 < 8 || c2 < 8 || c1 % 8 || c2 % 8)
+      return bad("sizes must be positive and channel counts multiples of 8");
+    if (!d || !dlow || !dskip) return bad("null device pointer");
+    if (!al16(d) || !al16(dlow) || !al16(dskip) || (mask && !al16(mask)))
+      return bad("pointers must be 16-byte aligned");
+    NN_HIP(cpi::nn_upcat_grad(d, b, h, w, c1, c2, mask, dlow, dskip,
+                              static_cast<hipStream_t>(stream)),
+           "upsample concat grad");
     return CPI_OK;
   });
 }

@@ -171,6 +171,7 @@ struct NnWgradArgs {
   const uint16_t* in = nullptr;    // [B][H][W][Cin] layer input
   const uint16_t* dy = nullptr;    // [B][H][W][Cout] output gradient
   float* dw = nullptr;             // [Cout][ks*ks*Cin], accumulated into (FP32 atomics)
+  float* db = nullptr;             // [Cout] bias gradient accumulated into, or null
   int B = 0, H = 0, W = 0, Cin = 0, Cout = 0, ks = 0, Kpad = 0;
 };
 hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s);
@@ -194,6 +195,13 @@ hipError_t nn_concat(const uint16_t* a, const uint16_t* b, int64_t P, int C1, in
                      hipStream_t s);
 hipError_t nn_split(const uint16_t* d, int64_t P, int C1, int C2, uint16_t* da, uint16_t* db,
                     hipStream_t s);
+// Nearest 2x upsampling of low [B][H][W][C1] concatenated with skip
+// [B][2H][2W][C2] into out [B][2H][2W][C1+C2], and its gradient (dlow masked
+// by mask <= 0 if given); C1, C2 multiples of 8.
+hipError_t nn_upcat(const uint16_t* low, const uint16_t* skip, int B, int H, int W, int C1, int C2,
+                    uint16_t* out, hipStream_t s);
+hipError_t nn_upcat_grad(const uint16_t* d, int B, int H, int W, int C1, int C2,
+                         const uint16_t* mask, uint16_t* dlow, uint16_t* dskip, hipStream_t s);
 hipError_t nn_add_mask(uint16_t* x, const uint16_t* add, const uint16_t* mask, int64_t n,
                        hipStream_t s);
 hipError_t nn_mse(const float* y, int C, const float* res, const float* t, int64_t P, float* loss,

@@ -25,9 +25,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
-// Round to nearest even (finite inputs).
+// Round to nearest even; NaN stays a (quiet) NaN.
 __device__ __forceinline__ uint16_t f2bf(float f) {
   const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return uint16_t((u >> 16) | 0x40u);
   return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
@@ -39,64 +40,96 @@ unsigned grid1(int64_t n, int threads = 256) {
 }
 
 // ---- convolution, forward and backward-data ---------------------------------
-// A work-group of 4 waves covers 128 pixels x 32 output channels; a wave
-// 32 x 32 (2 x 2 tiles of 16 x 16).  Lane l holds pixel (or channel) l % 16
-// of a tile and K group l / 16 (8 consecutive K values).
+// A work-group of 4 waves covers 64*TM pixels x 16*TN output channels; wave w
+// owns pixels [16*TM*w, 16*TM*(w+1)) of it and all 16*TN channels, as TM x TN
+// tiles of 16 x 16.  Lane l holds pixel (or channel) l % 16 of a tile and K
+// group l / 16 (8 consecutive K values: 8 channels of one input pixel at one
+// tap).  The fragments of the next K step are loaded before the matrix-core
+// ops of the current one.
+template <int KS, int TM, int TN>
 __global__ __launch_bounds__(256) void k_conv(NnConvArgs a) {
+  constexpr int HALF = KS / 2;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int64_t M = int64_t(a.B) * a.H * a.W;
-  const int64_t m0 = int64_t(blockIdx.x) * 128 + wave * 32;
-  const int n0 = blockIdx.y * 32;
-  const int K = a.ks * a.ks * a.Cin;
-  const int half = a.ks / 2;
-  // the two pixels this lane loads (one per M tile)
-  int pb[2], py[2], px[2];
-  bool pv[2];
+  const int64_t m0 = int64_t(blockIdx.x) * (64 * TM) + wave * (16 * TM);
+  const int n0 = blockIdx.y * (16 * TN);
+  const int Cin = a.Cin;
+  int py[TM], px[TM];
+  const uint16_t* pbase[TM];
+  bool pv[TM];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < TM; ++i) {
     const int64_t m = m0 + 16 * i + r;
     pv[i] = m < M;
     const int64_t mm = pv[i] ? m : 0;
     px[i] = int(mm % a.W);
     py[i] = int((mm / a.W) % a.H);
-    pb[i] = int(mm / (int64_t(a.W) * a.H));
+    const int64_t b = mm / (int64_t(a.W) * a.H);
+    pbase[i] = a.in + b * a.H * a.W * int64_t(Cin);
   }
-  v4f acc[2][2];
+  const uint16_t* wrow[TN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < TN; ++j) wrow[j] = a.wk + int64_t(n0 + 16 * j + r) * a.Kpad + 8 * g;
+  // this lane's K position (tap, ci) for k = kc + 8 g
+  int tap = (8 * g) / Cin, ci = (8 * g) % Cin;
+
+  uint4 a0[TM], b0[TN], a1[TM], b1[TN];
+  auto load = [&](uint4 (&av)[TM], uint4 (&bv)[TN], int kc) {
+    const int dy = tap / KS - HALF, dx = tap % KS - HALF;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0, 0, 0, 0};
-  for (int kc = 0; kc < a.Kpad; kc += 32) {
-    const int k = kc + 8 * g;
-    uint4 av[2], bv[2];
-    const int tap = k / a.Cin, ci = k - tap * a.Cin;
-    const int dy = tap / a.ks - half, dx = tap % a.ks - half;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      av[i] = make_uint4(0, 0, 0, 0);
+    for (int i = 0; i < TM; ++i) {
       const int yy = py[i] + dy, xx = px[i] + dx;
-      if (pv[i] && k < K && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-        av[i] = *reinterpret_cast<const uint4*>(
-            a.in + ((int64_t(pb[i]) * a.H + yy) * a.W + xx) * a.Cin + ci);
+      av[i] = make_uint4(0, 0, 0, 0);
+      if (pv[i] && tap < KS * KS && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+        av[i] = *reinterpret_cast<const uint4*>(pbase[i] + (int64_t(yy) * a.W + xx) * Cin + ci);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      bv[j] = *reinterpret_cast<const uint4*>(a.wk + int64_t(n0 + 16 * j + r) * a.Kpad + k);
+    for (int j = 0; j < TN; ++j) bv[j] = *reinterpret_cast<const uint4*>(wrow[j] + kc);
+  };
+  auto advance = [&]() {
+    ci += 32;
+    while (ci >= Cin) {
+      ci -= Cin;
+      ++tap;
+    }
+  };
+  v4f acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+  auto mma = [&](const uint4 (&av)[TM], const uint4 (&bv)[TN]) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av[i]),
-                                                             __builtin_bit_cast(v8bf, bv[j]),
-                                                             acc[i][j], 0, 0, 0);
+                                                            __builtin_bit_cast(v8bf, bv[j]),
+                                                            acc[i][j], 0, 0, 0);
+  };
+  // two register stages: fragments of step kc + 32 load while step kc computes
+  load(a0, b0, 0);
+  for (int kc = 0; kc < a.Kpad; kc += 64) {
+    const bool more1 = kc + 32 < a.Kpad;
+    if (more1) {
+      advance();
+      load(a1, b1, kc + 32);
+    }
+    mma(a0, b0);
+    if (!more1) break;
+    if (kc + 64 < a.Kpad) {
+      advance();
+      load(a0, b0, kc + 64);
+    }
+    mma(a1, b1);
   }
   // element (pixel 4g + t, channel r) of each tile
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t m = m0 + 16 * i + 4 * g + t;
@@ -114,70 +147,118 @@ __global__ __launch_bounds__(256) void k_conv(NnConvArgs a) {
 
 // ---- convolution, backward-weight -------------------------------------------
 // dW[n][k] += sum over pixels m of dY[m][n] * X(m, k), X the implicit im2col of
-// the input.  A work-group owns a 32 x 32 tile of dW (4 waves, one 16 x 16
-// quadrant each) and a range of pixels, taken 32 at a time: dY and X tiles
-// are loaded with 16-byte loads, stored transposed in LDS ([channel][pixel])
-// so that each lane's 8 consecutive pixels are one 16-byte LDS read, and the
-// work-group's partial tile is added to dW with FP32 atomics.
+// the input.  A work-group owns an NT x 64 tile of dW (NT = 32 or 64 output
+// channels, 64 K values) and a range of pixels, taken 64 at a time: dY and X
+// blocks are loaded with 16-byte loads and stored transposed in LDS
+// ([channel][pixel]) so that each lane's 8 consecutive pixels are one 16-byte
+// LDS read.  Wave w owns the 16 x 16 blocks (nb, kb) with kb = w (NT = 32) or
+// nb in {0, 1} + 2 (w & 1) and kb in {0, 1} + 2 (w >> 1) (NT = 64); the
+// work-group's partial tile is added to dW with FP32 atomics.  Work-groups of
+// the first K tile also sum their dY block over pixels into db (if given).
+template <int KS, int NT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t ty[32][32 + 8];   // [n][pixel]
-  __shared__ __attribute__((aligned(16))) uint16_t tx[32][32 + 8];   // [k][pixel]
+  constexpr int HALF = KS / 2;
+  constexpr int PB = 64;                 // pixels per block
+  constexpr int LP = PB + 8;             // LDS row pitch (elements)
+  __shared__ __attribute__((aligned(16))) uint16_t ty[NT][LP];
+  __shared__ __attribute__((aligned(16))) uint16_t tx[64][LP];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int r = lane & 15, g = lane >> 4;
-  const int n0 = blockIdx.x * 32;
-  const int kc = blockIdx.y * 32;
+  const int n0 = blockIdx.x * NT;
+  const int kc = blockIdx.y * 64;
   const int64_t M = int64_t(a.B) * a.H * a.W;
-  const int64_t per = (M + gridDim.z - 1) / gridDim.z;
+  const int64_t per = ((M + gridDim.z - 1) / gridDim.z + PB - 1) / PB * PB;
   const int64_t mlo = int64_t(blockIdx.z) * per;
   const int64_t mhi = mlo + per < M ? mlo + per : M;
-  const int K = a.ks * a.ks * a.Cin;
-  const int half = a.ks / 2;
-  // loader: thread t moves pixel p = t / 8 (of 32), 4 channel slots of 8 ...
-  const int lp = t >> 3, lq = t & 7;   // pixel, 8-channel group (0..3: dY, 4..7: X)
-  const int wn = (wave & 1) * 16, wk = (wave >> 1) * 16;
-  v4f acc = v4f{0, 0, 0, 0};
-  for (int64_t mb = mlo; mb < mhi; mb += 32) {
-    const int64_t m = mb + lp;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (m < mhi) {
-      if (lq < 4) {
-        v = *reinterpret_cast<const uint4*>(a.dy + m * a.Cout + n0 + 8 * lq);
-      } else {
-        const int k = kc + 8 * (lq - 4);
-        if (k < K) {
-          const int tap = k / a.Cin, ci = k - tap * a.Cin;
-          const int x = int(m % a.W), y = int((m / a.W) % a.H);
-          const int b = int(m / (int64_t(a.W) * a.H));
-          const int yy = y + tap / a.ks - half, xx = x + tap % a.ks - half;
-          if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-            v = *reinterpret_cast<const uint4*>(a.in + ((int64_t(b) * a.H + yy) * a.W + xx) * a.Cin +
-                                                ci);
-        }
+  const int Cin = a.Cin;
+  const int K = KS * KS * Cin;
+  // wave's blocks: NT = 64 -> n blocks 2 (w&1) + {0,1}, k blocks 2 (w>>1) + {0,1};
+  //                NT = 32 -> n blocks {0,1}, k block w
+  int nbs[2], kbs[2];
+  if (NT == 64) {
+    nbs[0] = 32 * (wave & 1);
+    nbs[1] = nbs[0] + 16;
+    kbs[0] = 32 * (wave >> 1);
+    kbs[1] = kbs[0] + 16;
+  } else {
+    nbs[0] = 0;
+    nbs[1] = 16;
+    kbs[0] = 16 * wave;
+    kbs[1] = 16 * wave;
+  }
+  constexpr int NKB = NT == 64 ? 2 : 1;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+  const bool bias = a.db && blockIdx.y == 0;
+  float bsum = 0.0f;
+  for (int64_t mb = mlo; mb < mhi; mb += PB) {
+    // dY block: PB pixels x NT channels, NT/8 chunks per pixel
+    for (int c = t; c < PB * (NT / 8); c += 256) {
+      const int p = c / (NT / 8), q = c % (NT / 8);
+      const int64_t m = mb + p;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (m < mhi && n0 + 8 * q < a.Cout)
+        v = *reinterpret_cast<const uint4*>(a.dy + m * a.Cout + n0 + 8 * q);
+      const uint16_t* hv = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ty[8 * q + e][p] = hv[e];
+    }
+    // X block: PB pixels x 64 K values, 8 chunks per pixel
+    for (int c = t; c < PB * 8; c += 256) {
+      const int p = c >> 3, q = c & 7;
+      const int64_t m = mb + p;
+      const int k = kc + 8 * q;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (m < mhi && k < K) {
+        const int tap = k / Cin, ci = k - tap * Cin;
+        const int x = int(m % a.W), y = int((m / a.W) % a.H);
+        const int64_t b = m / (int64_t(a.W) * a.H);
+        const int yy = y + tap / KS - HALF, xx = x + tap % KS - HALF;
+        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+          v = *reinterpret_cast<const uint4*>(a.in + ((b * a.H + yy) * a.W + xx) * Cin + ci);
       }
-    }
-    const uint16_t* hv = reinterpret_cast<const uint16_t*>(&v);
-    if (lq < 4) {
+      const uint16_t* hv = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ty[8 * lq + e][lp] = hv[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) tx[8 * (lq - 4) + e][lp] = hv[e];
+      for (int e = 0; e < 8; ++e) tx[8 * q + e][p] = hv[e];
     }
     __syncthreads();
-    const uint4 av = *reinterpret_cast<const uint4*>(&ty[wn + r][8 * g]);
-    const uint4 bv = *reinterpret_cast<const uint4*>(&tx[wk + r][8 * g]);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
-                                                  __builtin_bit_cast(v8bf, bv), acc, 0, 0, 0);
+    if (bias && t < NT)
+      for (int p = 0; p < PB; ++p) bsum += bf2f(ty[t][p]);
+#pragma unroll
+    for (int s = 0; s < PB / 32; ++s) {
+      uint4 av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        av[i] = *reinterpret_cast<const uint4*>(&ty[nbs[i] + r][32 * s + 8 * g]);
+#pragma unroll
+      for (int j = 0; j < NKB; ++j)
+        bv[j] = *reinterpret_cast<const uint4*>(&tx[kbs[j] + r][32 * s + 8 * g]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NKB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av[i]),
+                                                              __builtin_bit_cast(v8bf, bv[j]),
+                                                              acc[i][j], 0, 0, 0);
+    }
     __syncthreads();
   }
-  // element (n = wn + 4g + e, k = wk + r)
+  // element (n = nb + 4g + e, k = kb + r)
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int n = n0 + wn + 4 * g + e;
-    const int k = kc + wk + r;
-    if (n < a.Cout && k < K) atomicAdd(&a.dw[int64_t(n) * K + k], acc[e]);
-  }
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NKB; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int n = n0 + nbs[i] + 4 * g + e;
+        const int k = kc + kbs[j] + r;
+        if (n < a.Cout && k < K) atomicAdd(&a.dw[int64_t(n) * K + k], acc[i][j][e]);
+      }
+  if (bias && t < NT && n0 + t < a.Cout) atomicAdd(&a.db[n0 + t], bsum);
 }
 
 // db[n] += sum over pixels of dY[m][n]
@@ -318,6 +399,81 @@ __global__ __launch_bounds__(256) void k_concat(const uint16_t* __restrict__ a,
         da[p * C1 + c] = out[i];
       else
         db[p * C2 + (c - C1)] = out[i];
+    }
+  }
+}
+
+// out[b][y][x] = [up[b][y/2][x/2] (C1 channels), skip[b][y][x] (C2 channels)]
+// for the 2H x 2W output (nearest 2x upsampling of the H x W input, then
+// concatenation); 8 channels (16 bytes) per thread.  C1 % 8 == C2 % 8 == 0.
+__global__ __launch_bounds__(256) void k_upcat(const uint16_t* __restrict__ low,
+                                               const uint16_t* __restrict__ skip, int B, int H,
+                                               int W, int C1, int C2,
+                                               uint16_t* __restrict__ out) {
+  const int q1 = C1 / 8, qt = (C1 + C2) / 8;
+  const int64_t n = int64_t(B) * 4 * H * W * qt;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int q = int(i % qt);
+    const int64_t p = i / qt;  // output pixel
+    uint4 v;
+    if (q < q1) {
+      const int x = int(p % (2 * W)), y = int((p / (2 * W)) % (2 * H));
+      const int64_t b = p / (4 * int64_t(W) * H);
+      v = *reinterpret_cast<const uint4*>(low + ((b * H + y / 2) * W + x / 2) * C1 + 8 * q);
+    } else {
+      v = *reinterpret_cast<const uint4*>(skip + p * C2 + 8 * (q - q1));
+    }
+    *reinterpret_cast<uint4*>(out + i * 8) = v;
+  }
+}
+
+// Gradient of k_upcat: dskip = the last C2 channels of d; dlow[b][y][x][c] =
+// sum of d over the 4 output pixels of (y, x) in channel c < C1 (FP32, then
+// bfloat16), zeroed where mask <= 0 (nullable).  One thread per 8 channels of
+// one output pixel of either part.
+__global__ __launch_bounds__(256) void k_upcat_grad(const uint16_t* __restrict__ d, int B, int H,
+                                                    int W, int C1, int C2,
+                                                    const uint16_t* __restrict__ mask,
+                                                    uint16_t* __restrict__ dlow,
+                                                    uint16_t* __restrict__ dskip) {
+  const int q1 = C1 / 8, q2 = C2 / 8, qt = q1 + q2;
+  const int64_t nlow = int64_t(B) * H * W * q1;
+  const int64_t nskip = int64_t(B) * 4 * H * W * q2;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nlow + nskip;
+       i += int64_t(gridDim.x) * 256) {
+    if (i < nlow) {
+      const int q = int(i % q1);
+      const int64_t p = i / q1;  // low-resolution pixel
+      const int x = int(p % W), y = int((p / W) % H);
+      const int64_t b = p / (int64_t(W) * H);
+      const int64_t o00 = ((b * 2 * H + 2 * y) * 2 * W + 2 * x) * (C1 + C2) + 8 * q;
+      const int64_t row = int64_t(2 * W) * (C1 + C2);
+      const uint4 v0 = *reinterpret_cast<const uint4*>(d + o00);
+      const uint4 v1 = *reinterpret_cast<const uint4*>(d + o00 + (C1 + C2));
+      const uint4 v2 = *reinterpret_cast<const uint4*>(d + o00 + row);
+      const uint4 v3 = *reinterpret_cast<const uint4*>(d + o00 + row + (C1 + C2));
+      const uint16_t* h0 = reinterpret_cast<const uint16_t*>(&v0);
+      const uint16_t* h1 = reinterpret_cast<const uint16_t*>(&v1);
+      const uint16_t* h2 = reinterpret_cast<const uint16_t*>(&v2);
+      const uint16_t* h3 = reinterpret_cast<const uint16_t*>(&v3);
+      uint4 mv = make_uint4(0x3F80u * 0x10001u, 0x3F80u * 0x10001u, 0x3F80u * 0x10001u,
+                            0x3F80u * 0x10001u);  // 1.0 in every lane of the mask
+      if (mask) mv = *reinterpret_cast<const uint4*>(mask + p * C1 + 8 * q);
+      const uint16_t* hm = reinterpret_cast<const uint16_t*>(&mv);
+      uint4 r;
+      uint16_t* hr = reinterpret_cast<uint16_t*>(&r);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float s = (bf2f(h0[e]) + bf2f(h1[e])) + (bf2f(h2[e]) + bf2f(h3[e]));
+        hr[e] = bf2f(hm[e]) > 0.0f ? f2bf(s) : uint16_t(0);
+      }
+      *reinterpret_cast<uint4*>(dlow + p * C1 + 8 * q) = r;
+    } else {
+      const int64_t j = i - nlow;
+      const int q = int(j % q2);
+      const int64_t p = j / q2;  // output pixel
+      *reinterpret_cast<uint4*>(dskip + p * C2 + 8 * q) =
+          *reinterpret_cast<const uint4*>(d + p * (C1 + C2) + 8 * (q1 + q));
     }
   }
 }
@@ -529,22 +685,63 @@ __global__ __launch_bounds__(256) void k_quality(const float* __restrict__ pred,
 
 }  // namespace
 
-hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
+template <int KS, int TM, int TN>
+void launch_conv(const NnConvArgs& a, hipStream_t s) {
   const int64_t M = int64_t(a.B) * a.H * a.W;
-  hipLaunchKernelGGL(k_conv, dim3(unsigned((M + 127) / 128), unsigned(a.Cout / 32)), dim3(256), 0,
-                     s, a);
+  hipLaunchKernelGGL((k_conv<KS, TM, TN>), dim3(unsigned((M + 64 * TM - 1) / (64 * TM)),
+                                                unsigned(a.Cout / (16 * TN))),
+                     dim3(256), 0, s, a);
+}
+
+template <int KS>
+void conv_ks(const NnConvArgs& a, hipStream_t s) {
+  // the largest tile whose grid still holds ~2 work-groups per compute unit
+  const int64_t M = int64_t(a.B) * a.H * a.W;
+  auto groups = [&](int tm, int tn) { return ((M + 64 * tm - 1) / (64 * tm)) * (a.Cout / (16 * tn)); };
+  constexpr int64_t kMin = 512;
+  if (a.Cout % 64 == 0 && groups(4, 4) >= kMin)
+    launch_conv<KS, 4, 4>(a, s);
+  else if (a.Cout % 64 == 0 && groups(2, 4) >= kMin)
+    launch_conv<KS, 2, 4>(a, s);
+  else if (groups(4, 2) >= kMin)
+    launch_conv<KS, 4, 2>(a, s);
+  else if (groups(2, 2) >= kMin)
+    launch_conv<KS, 2, 2>(a, s);
+  else
+    launch_conv<KS, 1, 2>(a, s);
+}
+
+hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
+  if (a.ks == 3)
+    conv_ks<3>(a, s);
+  else if (a.ks == 1)
+    conv_ks<1>(a, s);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
+template <int KS, int NT>
+void launch_wgrad(const NnWgradArgs& a, hipStream_t s) {
   const int64_t M = int64_t(a.B) * a.H * a.W;
-  const unsigned gx = unsigned(a.Cout / 32), gy = unsigned(a.Kpad / 32);
+  const unsigned gx = unsigned((a.Cout + NT - 1) / NT), gy = unsigned((a.Kpad + 63) / 64);
   // split the pixels so that the grid holds about 2048 work-groups
   int64_t z = 2048 / (int64_t(gx) * gy);
   if (z < 1) z = 1;
-  if (z > (M + 31) / 32) z = (M + 31) / 32;
+  if (z > (M + 63) / 64) z = (M + 63) / 64;
   if (z > 65535) z = 65535;
-  hipLaunchKernelGGL(k_conv_wgrad, dim3(gx, gy, unsigned(z)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_conv_wgrad<KS, NT>), dim3(gx, gy, unsigned(z)), dim3(256), 0, s, a);
+}
+
+hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
+  const bool wide = a.Cout % 64 == 0;
+  if (a.ks == 3) {
+    if (wide) launch_wgrad<3, 64>(a, s); else launch_wgrad<3, 32>(a, s);
+  } else if (a.ks == 1) {
+    if (wide) launch_wgrad<1, 64>(a, s); else launch_wgrad<1, 32>(a, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -602,6 +799,21 @@ hipError_t nn_split(const uint16_t* d, int64_t P, int C1, int C2, uint16_t* da, 
                     hipStream_t s) {
   hipLaunchKernelGGL(k_concat, dim3(grid1(P * (C1 + C2))), dim3(256), 0, s, da, db, P, C1, C2,
                      const_cast<uint16_t*>(d), 1);
+  return hipGetLastError();
+}
+
+hipError_t nn_upcat(const uint16_t* low, const uint16_t* skip, int B, int H, int W, int C1, int C2,
+                    uint16_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_upcat, dim3(grid1(int64_t(B) * 4 * H * W * ((C1 + C2) / 8))), dim3(256), 0,
+                     s, low, skip, B, H, W, C1, C2, out);
+  return hipGetLastError();
+}
+
+hipError_t nn_upcat_grad(const uint16_t* d, int B, int H, int W, int C1, int C2,
+                         const uint16_t* mask, uint16_t* dlow, uint16_t* dskip, hipStream_t s) {
+  const int64_t n = int64_t(B) * H * W * (C1 / 8) + int64_t(B) * 4 * H * W * (C2 / 8);
+  hipLaunchKernelGGL(k_upcat_grad, dim3(grid1(n)), dim3(256), 0, s, d, B, H, W, C1, C2, mask, dlow,
+                     dskip);
   return hipGetLastError();
 }
 

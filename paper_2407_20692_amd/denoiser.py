@@ -208,15 +208,18 @@ def conv2d(x, w_packed, ks: int, cout: int, bias=None, mask=None, relu=False, ou
     return out if out is not None else out_f32
 
 
-def conv2d_wgrad(x, dy, ks: int, dw, stream=None):
-    """dw [cout, ks, ks, cin] FP32 += weight gradient."""
+def conv2d_wgrad(x, dy, ks: int, dw, db=None, stream=None):
+    """dw [cout, ks, ks, cin] FP32 += weight gradient (and db [cout] += bias
+    gradient if given)."""
     torch = _torch()
     b, h, w, cin = x.shape
     cout = dy.shape[3]
     _check(lib.cpi_nn_conv2d_wgrad(_bf(x, "x"), _bf(dy, "dy", b * h * w * cout), b, h, w, cin,
                                    cout, ks,
                                    _dev_ptr(dw, "dw", dtype=torch.float32,
-                                            numel=cout * ks * ks * cin), _stream(stream)))
+                                            numel=cout * ks * ks * cin),
+                                   _dev_ptr(db, "db", dtype=torch.float32, numel=cout)
+                                   if db is not None else None, _stream(stream)))
     return dw
 
 
@@ -271,6 +274,31 @@ def concat(a, b, stream=None):
     _check(lib.cpi_nn_concat(_bf(a, "a"), _bf(b, "b", p * cb), p, ca, cb, _bf(out, "out"),
                              _stream(stream)))
     return out
+
+
+def upsample2_concat(low, skip, stream=None):
+    """[upsample2(low), skip] along channels."""
+    torch = _torch()
+    b, h, w, c1 = low.shape
+    c2 = skip.shape[3]
+    out = torch.empty(b, 2 * h, 2 * w, c1 + c2, dtype=torch.bfloat16, device=low.device)
+    _check(lib.cpi_nn_upsample2_concat(_bf(low, "low"), _bf(skip, "skip", b * 4 * h * w * c2),
+                                       b, h, w, c1, c2, _bf(out, "out"), _stream(stream)))
+    return out
+
+
+def upsample2_concat_grad(d, c1: int, mask=None, stream=None):
+    """(dlow, dskip) of upsample2_concat for its output gradient d."""
+    torch = _torch()
+    b, h2, w2, c = d.shape
+    dlow = torch.empty(b, h2 // 2, w2 // 2, c1, dtype=torch.bfloat16, device=d.device)
+    dskip = torch.empty(b, h2, w2, c - c1, dtype=torch.bfloat16, device=d.device)
+    _check(lib.cpi_nn_upsample2_concat_grad(_bf(d, "d"), b, h2 // 2, w2 // 2, c1, c - c1,
+                                            _bf(mask, "mask", dlow.numel())
+                                            if mask is not None else None,
+                                            _bf(dlow, "dlow"), _bf(dskip, "dskip"),
+                                            _stream(stream)))
+    return dlow, dskip
 
 
 def split(d, ca: int, stream=None):

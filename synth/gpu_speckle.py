@@ -34,8 +34,11 @@ def pack_bits_lsb_torch(x):
 
 
 def generate_binary_frames_gpu(w: Workload, count: int | None = None, seed: int | None = None,
-                               device="cuda", chunk: int = 2000):
+                               device="cuda", chunk: int = 2000, mask_seed_value: int | None = None):
     """Binary frames (clicks) of workload ``w`` on the device, packed 8 per byte.
+
+    ``mask_seed_value`` replaces the workload's slit-mask seed (a different
+    object per run).
 
     Returns (frames_a, frames_b) as uint8 device tensors of shape
     (count, ceil(Pa/8)) and (count, ceil(Pb/8)).
@@ -47,7 +50,8 @@ def generate_binary_frames_gpu(w: Workload, count: int | None = None, seed: int 
     dev = torch.device(device)
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
-    mask = torch.from_numpy(slit_mask(w.wa, w.ha, mask_seed(w))).to(dev, torch.float32)
+    ms = mask_seed(w) if mask_seed_value is None else mask_seed_value
+    mask = torch.from_numpy(slit_mask(w.wa, w.ha, ms)).to(dev, torch.float32)
     hp, wp = w.ha + 2 * PAD, w.wa + 2 * PAD
     gt = _transfer(torch, hp, wp, dev)
     mean_int = 2.0 * float((gt.double() ** 2).mean())

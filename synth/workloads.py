@@ -58,6 +58,11 @@ WORKLOADS = {
         # detectors, 11 files of 512 frames, 261 refocus planes (Section 4.2)
         Workload("da256_db256_files11_bit1", 4, 256, 256, 256, 256, 11 * 512,
                  "binary_packed", 261),
+        # learned denoiser: planes from the first 500 frames of a stream mapped
+        # to the same planes from its first 50000 frames, 32 planes per run with
+        # alphas drawn in [0.5, 1.5] and a different slit mask per run
+        Workload("da128_db64_denoise500to50000_bit1", 5, 128, 128, 64, 64, 50000,
+                 "binary_packed", 32),
     ]
 }
 

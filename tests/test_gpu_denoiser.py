@@ -112,14 +112,17 @@ def test_conv_weight_and_bias_grad(nn, case):
     dy = rand_bf16(rng, (b, h, w, cout))
     dw0 = rng.standard_normal((cout, ks, ks, cin)).astype(np.float32)
     dw = torch.from_numpy(dw0.copy()).to(dev())
-    nn.conv2d_wgrad(bf16_tensor(x), bf16_tensor(dy), ks, dw)
+    db0 = rng.standard_normal(cout).astype(np.float32)
+    dbf = torch.from_numpy(db0.copy()).to(dev())
+    nn.conv2d_wgrad(bf16_tensor(x), bf16_tensor(dy), ks, dw, db=dbf)
     ref = dw0 + dn.conv2d_grad_weight(x, dy, ks)
     S = np.abs(dw0) + dn.conv2d_grad_weight(np.abs(x), np.abs(dy), ks)
     M = b * h * w
     assert np.all(np.abs(host(dw) - ref) <= (M + 2) * 2.0 ** -23 * S)
+    Sb = np.abs(dy).sum(axis=(0, 1, 2))
+    assert np.all(np.abs(host(dbf) - db0 - dn.bias_grad(dy)) <= (M + 2) * 2.0 ** -23 * (Sb + np.abs(db0)))
     db = torch.zeros(cout, dtype=torch.float32, device=dev())
     nn.bias_grad(bf16_tensor(dy), db)
-    Sb = np.abs(dy).sum(axis=(0, 1, 2))
     assert np.all(np.abs(host(db) - dn.bias_grad(dy)) <= (M + 2) * 2.0 ** -23 * Sb)
 
 
@@ -139,6 +142,10 @@ def test_routing_kernels_bit_exact(nn):
     assert np.array_equal(host(cat), np.concatenate([a, c], axis=3))
     da, dc = nn.split(cat, 64)
     assert np.array_equal(host(da), a) and np.array_equal(host(dc), c)
+    # fused upsampling + concatenation
+    skip = rand_bf16(rng, (2, 6, 10, 32))
+    uc = nn.upsample2_concat(bf16_tensor(u), bf16_tensor(skip))
+    assert np.array_equal(host(uc), np.concatenate([dn.upsample2(u), skip], axis=3))
 
 
 def test_upsample_grad_and_add_mask(nn):
@@ -149,6 +156,14 @@ def test_upsample_grad_and_add_mask(nn):
     got = host(nn.upsample2_grad(bf16_tensor(g), mask=bf16_tensor(mask)))
     S = dn.upsample2_grad(np.abs(g))
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 4 * 2.0 ** -23 * S)
+    # fused gradient of upsampling + concatenation
+    d = rand_bf16(rng, (2, 8, 6, 96))
+    m2 = rand_bf16(rng, (2, 4, 3, 64))
+    dlow, dskip = nn.upsample2_concat_grad(bf16_tensor(d), 64, mask=bf16_tensor(m2))
+    assert np.array_equal(host(dskip), d[..., 64:])
+    ref2 = dn.round_bf16(dn.upsample2_grad(d[..., :64])) * (m2 > 0)
+    S2 = dn.upsample2_grad(np.abs(d[..., :64]))
+    assert np.all(np.abs(host(dlow) - ref2) <= 2.0 ** -8 * np.abs(ref2) + 4 * 2.0 ** -23 * S2)
     a = rand_bf16(rng, (3, 5, 32))
     b = rand_bf16(rng, (3, 5, 32))
     m = rand_bf16(rng, (3, 5, 32))
