@@ -29,7 +29,8 @@ from .correlation import (
     to_layout,
     overflow_ok,
 )
-from .refocus import Geometry, default_geometry, refocus, refocus_pixels
+from .refocus import (Geometry, LensSampling, default_geometry, refocus, refocus_pixels,
+                      refocus_resampled, refocus_resampled_pixels)
 
 __all__ = [
     "FRAMES_U8",
@@ -45,4 +46,7 @@ __all__ = [
     "default_geometry",
     "refocus",
     "refocus_pixels",
+    "LensSampling",
+    "refocus_resampled",
+    "refocus_resampled_pixels",
 ]

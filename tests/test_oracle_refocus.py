@@ -206,3 +206,120 @@ def test_point_object_frames_end_to_end():
     stack = oracle.refocus(gam, g, grid)
     best = grid[np.argmax(stack.reshape(grid.size, -1).max(axis=1))]
     assert abs(best - alpha_star) <= 0.02 + 1e-9
+
+
+# ---- resampled lens-plane grid (general 4-D multilinear interpolation) -------------
+def _multilinear_4d_fraction_sampled(gam_vm, g, s, alpha, xr, yr):
+    """Exact 4-D multilinear interpolation of Gamma at every lens-plane sample
+    point (fractional x_b, y_b), summed over the samples."""
+    a = Fraction(alpha)
+    gv = gam_vm.reshape(g.hb, g.wb, g.ha, g.wa)
+
+    def val(x, y, xb, yb):
+        if 0 <= x < g.wa and 0 <= y < g.ha and 0 <= xb < g.wb and 0 <= yb < g.hb:
+            return Fraction(gv[yb, xb, y, x])
+        return Fraction(0)
+
+    total = Fraction(0)
+    for j in range(s.ny):
+        for i in range(s.nx):
+            xb = Fraction(s.ox) + i * Fraction(s.sx)
+            yb = Fraction(s.oy) + j * Fraction(s.sy)
+            ux = a * (xr - Fraction(g.ca_x)) + Fraction(g.ca_x) + (1 - a) * Fraction(g.mag_x) * (xb - Fraction(g.cb_x))
+            uy = a * (yr - Fraction(g.ca_y)) + Fraction(g.ca_y) + (1 - a) * Fraction(g.mag_y) * (yb - Fraction(g.cb_y))
+            pts = [ux, uy, xb, yb]
+            lo = [math.floor(p) for p in pts]
+            fr = [p - l for p, l in zip(pts, lo)]
+            for corner in range(16):
+                w = Fraction(1)
+                idx = []
+                for d in range(4):
+                    bit = (corner >> d) & 1
+                    w *= fr[d] if bit else 1 - fr[d]
+                    idx.append(lo[d] + bit)
+                if w:
+                    total += w * val(*idx)
+    return total
+
+
+@pytest.mark.parametrize("alpha", [0.4, 0.77, 1.0, 1.3, 2.2])
+def test_resampled_bruteforce_fraction(alpha):
+    g = Geometry(5, 4, 3, 3, 1.7, 1.3, 2.1, 1.5, 1.0, 1.25, 5, 4)
+    s = oracle.LensSampling(4, 3, -0.25, 0.5, 0.75, 0.625)
+    rng = np.random.default_rng(int(abs(alpha) * 100) + 11)
+    gam = rng.standard_normal((g.hb * g.wb, g.ha * g.wa))
+    got = oracle.refocus_resampled(gam, g, s, [alpha])[0]
+    scale = np.abs(gam).sum()
+    for yr in range(g.out_h):
+        for xr in range(g.out_w):
+            want = float(_multilinear_4d_fraction_sampled(gam, g, s, alpha, xr, yr))
+            assert abs(got[yr, xr] - want) <= 1e-13 * scale
+    pix = oracle.refocus_resampled_pixels(gam, g, s, [alpha], [0, 3, 2], [4, 1, 2])[0]
+    assert np.allclose(pix, [got[0, 4], got[3, 1], got[2, 2]], rtol=0, atol=1e-14 * scale)
+
+
+def test_resampled_integer_grid_is_refocus():
+    g = default_geometry(12, 10, 6, 5)
+    rng = np.random.default_rng(12)
+    gam = rng.standard_normal((g.hb * g.wb, g.ha * g.wa))
+    s = oracle.LensSampling(g.wb, g.hb, 0.0, 0.0, 1.0, 1.0)
+    al = [0.5, 0.9, 1.0, 1.45]
+    assert np.allclose(oracle.refocus_resampled(gam, g, s, al), oracle.refocus(gam, g, al),
+                       rtol=1e-13, atol=1e-13)
+
+
+def test_resampled_half_step_alpha_one_closed_form():
+    """alpha = 1 puts every sample at u = output pixel, so each view enters with
+    the total weight of the samples around it: on the grid 0, 0.5, ..., W_b - 1
+    that is 2 for inner views and 1.5 for the two end views, per axis."""
+    g = default_geometry(8, 6, 4, 3)
+    rng = np.random.default_rng(13)
+    gam = rng.standard_normal((g.hb * g.wb, g.ha * g.wa))
+    s = oracle.LensSampling(2 * g.wb - 1, 2 * g.hb - 1, 0.0, 0.0, 0.5, 0.5)
+    wx = np.full(g.wb, 2.0)
+    wx[[0, -1]] = 1.5
+    wy = np.full(g.hb, 2.0)
+    wy[[0, -1]] = 1.5
+    views = gam.reshape(g.hb, g.wb, g.ha, g.wa)
+    want = np.einsum("j,i,jiyx->yx", wy, wx, views)
+    got = oracle.refocus_resampled(gam, g, s, [1.0])[0]
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13)
+
+
+def test_resampled_reproduces_multilinear_data():
+    """Gamma sampled from a function affine in each of its four coordinates is
+    reproduced exactly by the interpolation wherever all 16 corners lie inside
+    both detectors, so the stack is the sum of that function over the samples."""
+    g = Geometry(20, 18, 6, 5, 2.0, 2.0, 9.5, 8.5, 2.5, 2.0, 20, 18)
+    c = np.array([0.3, -0.2, 0.5, 1.1, 0.7])
+
+    def f(x, y, xb, yb):
+        return (c[0] + c[1] * x) * (1.0 + 0.05 * y) * (c[2] + c[3] * xb) * (c[4] + 0.1 * yb)
+
+    yy, xx = np.mgrid[0:g.ha, 0:g.wa]
+    gam = np.stack([f(xx, yy, xb, yb) for yb in range(g.hb) for xb in range(g.wb)])
+    s = oracle.LensSampling(5, 4, 0.5, 0.25, 0.875, 0.9)   # inside [0, 4] x [0, 3.7]
+    alpha = 0.9
+    got = oracle.refocus_resampled(gam.reshape(g.hb * g.wb, -1), g, s, [alpha])[0]
+    for yr in range(6, 12):
+        for xr in range(6, 14):
+            want = 0.0
+            for j in range(s.ny):
+                for i in range(s.nx):
+                    xb, yb = s.ox + i * s.sx, s.oy + j * s.sy
+                    ux = alpha * (xr - g.ca_x) + g.ca_x + (1 - alpha) * g.mag_x * (xb - g.cb_x)
+                    uy = alpha * (yr - g.ca_y) + g.ca_y + (1 - alpha) * g.mag_y * (yb - g.cb_y)
+                    want += f(ux, uy, xb, yb)
+            assert abs(got[yr, xr] - want) <= 1e-12 * abs(want) + 1e-12
+
+
+def test_resampled_linearity():
+    g = default_geometry(8, 8, 4, 4)
+    rng = np.random.default_rng(14)
+    g1 = rng.standard_normal((g.hb * g.wb, g.ha * g.wa))
+    g2 = rng.standard_normal((g.hb * g.wb, g.ha * g.wa))
+    s = oracle.LensSampling(5, 6, -0.3, 0.2, 0.8, 0.6)
+    al = [0.6, 1.2]
+    lhs = oracle.refocus_resampled(2.0 * g1 - 3.0 * g2, g, s, al)
+    rhs = 2.0 * oracle.refocus_resampled(g1, g, s, al) - 3.0 * oracle.refocus_resampled(g2, g, s, al)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12)
