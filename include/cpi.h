@@ -187,6 +187,47 @@ cpi_status cpi_set_mma_encoding(cpi_mma_encoding enc);
 cpi_mma_encoding cpi_get_mma_encoding(void);
 
 /* ---------------------------------------------------------------------------
+ * Refocusing with a resampled lens-plane grid: the general form of the
+ * multilinear interpolation of Gamma (Section 4.1, refocusing optimisation),
+ * in which the lens-plane coordinate rho_b is also interpolated.  The sum over
+ * detector-B pixels becomes a sum over the sample points
+ *   x_b(i) = ox + i * sx (i < nx),   y_b(j) = oy + j * sy (j < ny)
+ * (detector-B pixel units, sx, sy > 0), u_x, u_y are formed with these
+ * fractional x_b, y_b, and every sample is the 4-D multilinear interpolant of
+ * Gamma at (u_x, u_y, x_b, y_b): 16 corners weighted by products of linear
+ * weights, corners outside either detector contributing zero.  The integer
+ * grid (0, 0, 1, 1, Wb, Hb) gives cpi_refocus.
+ *
+ * Because the interpolant is linear in Gamma, it is computed in two steps:
+ *   cpi_resample_views: views[j * nx + i][.] (FP32, nx * ny views of Pa values)
+ *     = the bilinear interpolant along rho_b of the views of gamma (FP32
+ *     view-major) at (x_b(i), y_b(j)); independent of alpha;
+ *   refocusing of those views (cpi_refocus, batched) under the geometry of
+ *     cpi_lens_sampling_geometry: Wb -> nx, Hb -> ny, mag -> mag * s,
+ *     cb -> (cb - o) / s.
+ * cpi_refocus_resampled does both; its workspace holds the views first.
+ * Errors: CPI_ERR_INVALID_ARG (bad sample grid: counts outside [1, 65536],
+ *   spacings not positive, non-finite or |value| >= 2^20; as cpi_refocus),
+ *   CPI_ERR_WORKSPACE, CPI_ERR_DEVICE.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t nx, ny;     /* sample counts along x_b and y_b */
+  double ox, oy;      /* first sample point */
+  double sx, sy;      /* sample spacing (> 0) */
+} cpi_lens_sampling;
+
+cpi_status cpi_lens_sampling_geometry(const cpi_geometry* g, const cpi_lens_sampling* s,
+                                      cpi_geometry* out);
+cpi_status cpi_resample_views(const float* gamma, const cpi_geometry* g,
+                              const cpi_lens_sampling* s, float* views, void* stream);
+cpi_status cpi_refocus_resampled_workspace_size(const cpi_geometry* g, const cpi_lens_sampling* s,
+                                                int32_t n_alpha, size_t* bytes);
+cpi_status cpi_refocus_resampled(const float* gamma, const cpi_geometry* g,
+                                 const cpi_lens_sampling* s, const double* alphas,
+                                 int32_t n_alpha, float* out, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Streaming: frame chunks folded into device-resident sums as rank-k updates
  * (the sums of Eq. (1) are additive over frames), so Gamma for all frames so
  * far is available after every chunk.
@@ -303,7 +344,7 @@ cpi_status cpi_measure_peaks(void* scratch, size_t scratch_bytes, size_t copy_by
  * stream.  Group names: "ingest" (sums and operand transposition), "gemm"
  * (matrix-core contraction with its epilogue), "unpack_f32", "sgemm_f32",
  * "refocus_tables", "refocus_batched" (including the reduction of split
- * partial sums), "refocus_plain", "state_gamma".
+ * partial sums), "refocus_plain", "refocus_resample", "state_gamma".
  * cpi_profile_begin clears earlier records and starts recording;
  * cpi_profile_end stops it; cpi_profile_query waits for the recorded events
  * and returns the number of launches and their summed duration for one group.

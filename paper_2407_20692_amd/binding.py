@@ -52,6 +52,13 @@ class Geometry(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LensSampling(ctypes.Structure):
+    """Lens-plane sample grid (cpi_lens_sampling): x_b = ox + i sx, i < nx;
+    y_b = oy + j sy, j < ny."""
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("ox", c_double), ("oy", c_double),
+                ("sx", c_double), ("sy", c_double)]
+
+
 class SideBySide(ctypes.Structure):
     """Raw sensor frames with both detectors side by side (cpi_sidebyside):
     frame_w x frame_h 1-bit pixels, the region roi_w x roi_h at (roi_x, roi_y)
@@ -121,6 +128,15 @@ _SIGS = {
                                         c_void_p, c_void_p, c_size_t, c_void_p, c_size_t,
                                         POINTER(c_int64)]),
     "cpi_get_mma_encoding": (c_int, []),
+    "cpi_lens_sampling_geometry": (c_int, [POINTER(Geometry), POINTER(LensSampling),
+                                           POINTER(Geometry)]),
+    "cpi_resample_views": (c_int, [c_void_p, POINTER(Geometry), POINTER(LensSampling), c_void_p,
+                                   c_void_p]),
+    "cpi_refocus_resampled_workspace_size": (c_int, [POINTER(Geometry), POINTER(LensSampling),
+                                                     c_int32, POINTER(c_size_t)]),
+    "cpi_refocus_resampled": (c_int, [c_void_p, POINTER(Geometry), POINTER(LensSampling),
+                                      POINTER(c_double), c_int32, c_void_p, c_void_p, c_size_t,
+                                      c_void_p]),
     "cpi_denoiser_layer_count": (c_int, [POINTER(c_int32)]),
     "cpi_denoiser_layer_info": (c_int, [c_int32, c_void_p]),
     "cpi_denoiser_param_count": (c_int, [POINTER(c_int64)]),
@@ -350,6 +366,52 @@ def refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
 def refocus_plain(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
     """One-plane-per-launch refocus (the comparison path)."""
     return _refocus_call(lib.cpi_refocus_plain, gamma, g, alphas, out, workspace, stream)
+
+
+def lens_sampling(nx: int, ny: int, ox: float, oy: float, sx: float, sy: float) -> LensSampling:
+    return LensSampling(nx, ny, ox, oy, sx, sy)
+
+
+def lens_sampling_geometry(g: Geometry, s: LensSampling) -> Geometry:
+    """Geometry under which the resampled views refocus as the sample grid."""
+    out = Geometry()
+    _check(lib.cpi_lens_sampling_geometry(ctypes.byref(g), ctypes.byref(s), ctypes.byref(out)))
+    return out
+
+
+def resample_views(gamma, g: Geometry, s: LensSampling, views=None, stream=None):
+    """FP32 views [ny * nx, Pa] of gamma (FP32 view-major) at the sample grid."""
+    torch = _torch()
+    pa = g.wa * g.ha
+    if views is None:
+        views = torch.empty(s.nx * s.ny * pa, dtype=torch.float32, device=gamma.device)
+    _check(lib.cpi_resample_views(
+        _dev_ptr(gamma, "gamma", torch.float32, numel=pa * g.wb * g.hb), ctypes.byref(g),
+        ctypes.byref(s), _dev_ptr(views, "views", torch.float32, numel=s.nx * s.ny * pa),
+        _stream(stream)))
+    return views
+
+
+def refocus_resampled_workspace_size(g: Geometry, s: LensSampling, n_alpha: int) -> int:
+    out = c_size_t(0)
+    _check(lib.cpi_refocus_resampled_workspace_size(ctypes.byref(g), ctypes.byref(s), n_alpha,
+                                                    ctypes.byref(out)))
+    return out.value
+
+
+def refocus_resampled(gamma, g: Geometry, s: LensSampling, alphas, out, workspace=None,
+                      stream=None):
+    torch = _torch()
+    a, ap, na = _alphas(alphas)
+    need = refocus_resampled_workspace_size(g, s, na)
+    if workspace is None:
+        workspace = alloc_workspace(need, gamma.device)
+    _check(lib.cpi_refocus_resampled(
+        _dev_ptr(gamma, "gamma", torch.float32, numel=g.wa * g.ha * g.wb * g.hb), ctypes.byref(g),
+        ctypes.byref(s), ap, na, _dev_ptr(out, "out", torch.float32, numel=na * g.out_w * g.out_h),
+        _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need, _stream(stream)))
+    del a
+    return workspace
 
 
 def refocus_config(g: Geometry, n_alpha: int):

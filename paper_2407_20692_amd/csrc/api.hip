@@ -532,6 +532,121 @@ cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha, int32_t* p
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Geometry under which refocusing the resampled views (view j * nx + i at
+// lens-plane point (ox + i sx, oy + j sy)) is refocusing with that sample
+// grid: (1 - alpha) M (x_b - c_b) = (1 - alpha) (M sx) (i - (c_b - ox) / sx).
+cpi_status lens_geometry(const cpi_geometry* g, const cpi_lens_sampling* s, cpi_geometry* gs) {
+  if (!g || !s || !gs) return set_error(CPI_ERR_INVALID_ARG, "null argument");
+  if (s->nx < 1 || s->ny < 1 || s->nx > 65536 || s->ny > 65536)
+    return set_error(CPI_ERR_INVALID_ARG, "sample counts must be in [1, 65536]");
+  const double v[4] = {s->ox, s->oy, s->sx, s->sy};
+  for (double x : v)
+    if (!std::isfinite(x) || std::fabs(x) > 1048576.0)
+      return set_error(CPI_ERR_INVALID_ARG, "sample grid parameters must be finite and below 2^20");
+  if (!(s->sx > 0.0) || !(s->sy > 0.0))
+    return set_error(CPI_ERR_INVALID_ARG, "sample spacings must be positive");
+  *gs = *g;
+  gs->wb = s->nx;
+  gs->hb = s->ny;
+  gs->mag_x = g->mag_x * s->sx;
+  gs->mag_y = g->mag_y * s->sy;
+  gs->cb_x = (g->cb_x - s->ox) / s->sx;
+  gs->cb_y = (g->cb_y - s->oy) / s->sy;
+  return CPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpi_status cpi_lens_sampling_geometry(const cpi_geometry* g, const cpi_lens_sampling* s,
+                                      cpi_geometry* out) {
+  return guarded([&]() -> cpi_status {
+    cpi::RefocusPlan pl;
+    std::string why;
+    cpi_status st = cpi::plan_refocus(g, 1, &pl, &why);
+    if (st != CPI_OK) return set_error(st, why);
+    cpi_geometry gs;
+    st = lens_geometry(g, s, &gs);
+    if (st != CPI_OK) return st;
+    st = cpi::plan_refocus(&gs, 1, &pl, &why);
+    if (st != CPI_OK) return set_error(st, "resampled views: " + why);
+    if (!out) return set_error(CPI_ERR_INVALID_ARG, "out is null");
+    *out = gs;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_resample_views(const float* gamma, const cpi_geometry* g,
+                              const cpi_lens_sampling* s, float* views, void* stream) {
+  return guarded([&]() -> cpi_status {
+    cpi_geometry gs;
+    cpi_status st = cpi_lens_sampling_geometry(g, s, &gs);
+    if (st != CPI_OK) return st;
+    if (!gamma || !views) return set_error(CPI_ERR_INVALID_ARG, "null device pointer");
+    if (!aligned16(gamma) || !aligned16(views))
+      return set_error(CPI_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
+    hipStream_t sm = static_cast<hipStream_t>(stream);
+    ProfScope ps("refocus_resample", sm);
+    CPI_HIP(cpi::resample_views(gamma, int64_t(g->wa) * g->ha, g->wb, g->hb, s->nx, s->ny, s->ox,
+                                s->oy, s->sx, s->sy, views, sm),
+            "resample views");
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_refocus_resampled_workspace_size(const cpi_geometry* g, const cpi_lens_sampling* s,
+                                                int32_t n_alpha, size_t* bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");
+    cpi_geometry gs;
+    cpi_status st = cpi_lens_sampling_geometry(g, s, &gs);
+    if (st != CPI_OK) return st;
+    cpi::RefocusPlan pl;
+    std::string why;
+    st = cpi::plan_refocus(&gs, n_alpha, &pl, &why);
+    if (st != CPI_OK) return set_error(st, why);
+    const size_t vb = (size_t(gs.wb) * gs.hb * size_t(g->wa) * g->ha * 4 + 255) / 256 * 256;
+    *bytes = vb + pl.total;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_refocus_resampled(const float* gamma, const cpi_geometry* g,
+                                 const cpi_lens_sampling* s, const double* alphas,
+                                 int32_t n_alpha, float* out, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+  return guarded([&]() -> cpi_status {
+    size_t need = 0;
+    cpi_status st = cpi_refocus_resampled_workspace_size(g, s, n_alpha, &need);
+    if (st != CPI_OK) return st;
+    if (!workspace || !aligned16(workspace))
+      return set_error(CPI_ERR_INVALID_ARG, "workspace must be a 16-byte aligned device pointer");
+    if (workspace_bytes < need)
+      return set_error(CPI_ERR_WORKSPACE,
+                       "refocus workspace too small: need " + std::to_string(need) + " bytes");
+    cpi_geometry gs;
+    st = cpi_lens_sampling_geometry(g, s, &gs);
+    if (st != CPI_OK) return st;
+    std::string why;
+    st = cpi::validate_alphas(&gs, alphas, n_alpha, &why);
+    if (st != CPI_OK) return set_error(st, why);
+    if (!out || !aligned16(out))
+      return set_error(CPI_ERR_INVALID_ARG, "out must be a 16-byte aligned device pointer");
+    float* views = static_cast<float*>(workspace);
+    const size_t vb = (size_t(gs.wb) * gs.hb * size_t(g->wa) * g->ha * 4 + 255) / 256 * 256;
+    st = cpi_resample_views(gamma, g, s, views, stream);
+    if (st != CPI_OK) return st;
+    return cpi::refocus_enqueue(views, &gs, alphas, n_alpha, out,
+                                static_cast<uint8_t*>(workspace) + vb, workspace_bytes - vb,
+                                static_cast<hipStream_t>(stream), nullptr, false);
+  });
+}
+
 cpi_status cpi_measure_peaks_scratch_size(size_t copy_bytes, size_t* bytes) {
   return guarded([&]() -> cpi_status {
     if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");

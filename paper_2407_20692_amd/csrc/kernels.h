@@ -148,6 +148,12 @@ hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* 
                            const RefocusConfig& c, float* partial, float* out,
                            hipStream_t s);
 
+// Gamma views resampled on a lens-plane sample grid (x_b, y_b) = (ox + i sx,
+// oy + j sy), i < nx, j < ny: out[j * nx + i][.] = bilinear interpolant of the
+// pb = wb * hb views of pa values at that point (zero outside detector B).
+hipError_t resample_views(const float* gamma, int64_t pa, int wb, int hb, int nx, int ny, double ox,
+                          double oy, double sx, double sy, float* out, hipStream_t s);
+
 // ---- learned denoiser: BF16 matrix-core convolutions and their companions --
 // Activations are NHWC bfloat16 (raw uint16 bits); layers keep Cin % 8 == 0
 // and Cout % 32 == 0.  Weights fed to the matrix cores are bfloat16 rows of

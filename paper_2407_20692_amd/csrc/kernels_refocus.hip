@@ -449,6 +449,65 @@ hipError_t launch_batched(const float* gamma, const GeomI& gi, const int32_t* it
   return hipGetLastError();
 }
 
+// Views of Gamma resampled along the lens-plane coordinate: output view
+// s = j * nx + i is the bilinear interpolant of the views at the sample point
+// (x_b, y_b) = (ox + i sx, oy + j sy), i.e. the sum over its four neighbouring
+// views (x_b0 + ex, y_b0 + ey) weighted by (1 - f or f) products, views outside
+// detector B contributing zero.  Sample parameters are FP64, weights FP32.
+// One work-group row per sample (grid-stride over samples), 4 values per
+// thread when pa % 4 == 0.
+__global__ __launch_bounds__(256) void k_resample_views(const float* __restrict__ gamma,
+                                                        int64_t pa, int wb, int hb, int nx,
+                                                        int ny, double ox, double oy, double sx,
+                                                        double sy, float* __restrict__ out) {
+  const int64_t ns = int64_t(nx) * ny;
+  for (int64_t s = blockIdx.y; s < ns; s += gridDim.y) {
+    const int i = int(s % nx), j = int(s / nx);
+    const double xb = ox + double(i) * sx, yb = oy + double(j) * sy;
+    const double fxb = floor(xb), fyb = floor(yb);
+    const int x0 = int(fxb), y0 = int(fyb);
+    const double fx = xb - fxb, fy = yb - fyb;
+    const float* src[4];
+    float w[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int ex = c & 1, ey = c >> 1;
+      const int cx = x0 + ex, cy = y0 + ey;
+      const double wd = (ey ? fy : 1.0 - fy) * (ex ? fx : 1.0 - fx);
+      const bool in = cx >= 0 && cx < wb && cy >= 0 && cy < hb && wd != 0.0;
+      w[c] = in ? float(wd) : 0.0f;
+      src[c] = in ? gamma + (int64_t(cy) * wb + cx) * pa : nullptr;
+    }
+    float* dst = out + s * pa;
+    if ((pa & 3) == 0) {
+      const int64_t n4 = pa >> 2;
+      for (int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x; q < n4;
+           q += int64_t(gridDim.x) * 256) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (!src[c]) continue;
+          const float4 v = reinterpret_cast<const float4*>(src[c])[q];
+          acc.x = fmaf(w[c], v.x, acc.x);
+          acc.y = fmaf(w[c], v.y, acc.y);
+          acc.z = fmaf(w[c], v.z, acc.z);
+          acc.w = fmaf(w[c], v.w, acc.w);
+        }
+        reinterpret_cast<float4*>(dst)[q] = acc;
+      }
+    } else {
+      for (int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x; q < pa;
+           q += int64_t(gridDim.x) * 256) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (src[c]) acc = fmaf(w[c], src[c][q], acc);
+        dst[q] = acc;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t refocus_tables(const RefGeom& g, const double* alphas, int first, int count,
@@ -503,6 +562,17 @@ hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* 
   CPI_REF_CASE(16, 16)
 #undef CPI_REF_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t resample_views(const float* gamma, int64_t pa, int wb, int hb, int nx, int ny, double ox,
+                          double oy, double sx, double sy, float* out, hipStream_t s) {
+  const int64_t ns = int64_t(nx) * ny;
+  int64_t gx = (((pa & 3) == 0 ? pa / 4 : pa) + 255) / 256;
+  if (gx > 64) gx = 64;
+  const int64_t gy = ns < 65535 ? ns : 65535;
+  hipLaunchKernelGGL(k_resample_views, dim3(unsigned(gx), unsigned(gy)), dim3(256), 0, s, gamma, pa,
+                     wb, hb, nx, ny, ox, oy, sx, sy, out);
+  return hipGetLastError();
 }
 
 }  // namespace cpi

@@ -171,3 +171,24 @@ def test_denoiser_host_validation(cpi):
                              None) == 1
     assert lib.cpi_nn_maxpool2(fake, 1, 5, 4, 8, fake, None) == 1
     assert lib.cpi_image_quality(fake, fake, 1, 10, 16, fake, fake, None) == 1
+
+
+def test_resampled_refocus_host_validation(cpi):
+    lib = cpi.lib
+    g = cpi.geometry_default(16, 16, 8, 8)
+    ok = cpi.lens_sampling(15, 15, 0.0, 0.0, 0.5, 0.5)
+    gs = cpi.lens_sampling_geometry(g, ok)
+    assert (gs.wb, gs.hb, gs.mag_x, gs.cb_x) == (15, 15, 1.0, 7.0)
+    need = cpi.refocus_resampled_workspace_size(g, ok, 4)
+    assert need >= 15 * 15 * 256 * 4
+    out = ctypes.c_size_t(0)
+    for bad in (cpi.lens_sampling(0, 3, 0, 0, 1, 1), cpi.lens_sampling(3, 3, 0, 0, 0.0, 1),
+                cpi.lens_sampling(3, 3, float("nan"), 0, 1, 1),
+                cpi.lens_sampling(3, 3, 0, 0, 1, -2.0)):
+        assert lib.cpi_refocus_resampled_workspace_size(ctypes.byref(g), ctypes.byref(bad), 4,
+                                                        ctypes.byref(out)) == 1
+    fake = ctypes.c_void_p(1 << 20)
+    al = (ctypes.c_double * 2)(0.5, 1.0)
+    assert lib.cpi_refocus_resampled(fake, ctypes.byref(g), ctypes.byref(ok), al, 2, fake, fake,
+                                     16, None) == 4
+    assert lib.cpi_resample_views(None, ctypes.byref(g), ctypes.byref(ok), fake, None) == 1
