@@ -28,6 +28,8 @@ Printed as ONE JSON line:
   file_ingest    raw side-by-side frame files (the paper's 256 x 512 layout,
                  11 files of 512 frames) streamed into the running sums
   measured_peaks the device's sustained matrix-core and copy rates (microbenchmarks)
+  refocus_resampled  refocusing with the lens plane sampled at half-pixel steps
+                 (general 4-D multilinear interpolation): view resampling + refocus
   denoiser       the learned denoiser's training step (16 planes of 128 x 128)
                  and inference (32 planes): time and algorithmic BF16 FLOP rate
   cpu_baseline   the CPU oracle on a bounded sample of the same workload
@@ -211,6 +213,42 @@ def denoiser_train_flops(dn, h, w):
     first = dn.layers()[0]
     f0 = 2 * h * w * first.cout_used * first.ks * first.ks * first.cin_used
     return 3 * denoiser_forward_flops(dn, h, w) - f0
+
+
+def resampled_refocus_bench(cpi, torch, np, dev, g32, geo, w, alphas, reps=3):
+    """Refocus with the lens plane sampled at half-pixel steps (2x oversampled,
+    (2 Wb - 1) x (2 Hb - 1) samples): the view-resampling kernel against the
+    HBM peak (algorithmic bytes: every input view read once, every resampled
+    view written once) and the batched refocus over the resampled views."""
+    ls = cpi.lens_sampling(2 * w.wb - 1, 2 * w.hb - 1, 0.0, 0.0, 0.5, 0.5)
+    gs = cpi.lens_sampling_geometry(geo, ls)
+    na = len(alphas)
+    ns = ls.nx * ls.ny
+    views = torch.empty(ns * w.pa, dtype=torch.float32, device=dev)
+    out = torch.empty(na * w.pa, dtype=torch.float32, device=dev)
+    ws = cpi.alloc_workspace(cpi.refocus_workspace_size(gs, na), dev)
+    cpi.resample_views(g32, geo, ls, views)
+    cpi.autotune_refocus(views, gs, alphas, out, workspace=ws)
+    torch.cuda.synchronize()
+    cpi.profile_begin()
+    for _ in range(reps):
+        cpi.resample_views(g32, geo, ls, views)
+        cpi.refocus(views, gs, alphas, out, workspace=ws)
+    torch.cuda.synchronize()
+    cpi.profile_end()
+    t_res = cpi.profile_query("refocus_resample")[1] / reps
+    t_ref = sum(cpi.profile_query(gname)[1] for gname in ("refocus_tables", "refocus_batched")) / reps
+    alg = (w.pb + ns) * w.pa * 4
+    del views, out, ws
+    return {
+        "lens_samples": [ls.nx, ls.ny], "step": 0.5, "planes": na,
+        "resample_ms": t_res, "refocus_ms": t_ref, "total_ms": t_res + t_ref,
+        "resample_roofline": {"bound": "hbm", "achieved": alg / (t_res * 1e-3) / 1e9,
+                              "peak": 8000.0, "unit": "GB/s",
+                              "frac": alg / (t_res * 1e-3) / 8e12,
+                              "algorithmic_bytes": alg},
+        "config_kp_rw_splits": list(cpi.refocus_config(gs, na)),
+    }
 
 
 def denoiser_timing(torch, np, dev, batch=16, planes=32, h=128, w=128, reps=20):
@@ -744,6 +782,8 @@ def main():
                                "config_kp_rw_splits": list(cpi.refocus_config(geo, na))}
             del o, ws_n
         line["refocus_plane_counts"] = counts
+        line["refocus_resampled"] = resampled_refocus_bench(cpi, torch, np, dev, g32, geo, w,
+                                                            alphas)
         line["file_ingest"] = file_ingest_bench(cpi, torch, np, dev)
         log("bench: denoiser training step and inference")
         line["denoiser"] = denoiser_timing(torch, np, dev)

@@ -145,6 +145,112 @@ __global__ __launch_bounds__(256) void k_conv(NnConvArgs a) {
       }
 }
 
+// ---- 3x3 convolution with LDS-staged tiles ------------------------------------
+// For Cin % 32 == 0.  A work-group computes a block of TH = WM*TM output rows
+// x 16 columns of one image and NT = WN*TN*16 output channels with 4 waves
+// (WM x WN); wave (wm, wn) owns rows [wm*TM, (wm+1)*TM) (one 16-pixel
+// fragment per row) and channels [wn*16*TN, (wn+1)*16*TN).  Per chunk of 32
+// input channels the block's input pixels with their one-pixel halo
+// ((TH + 2) x 18 pixels) are staged in LDS once; per kernel row ky the
+// weights of its three taps for the NT channels are staged beside them, and
+// the three taps run from LDS.  Pixel and weight rows are padded to 40
+// elements (80 bytes) to spread LDS banks.
+template <int TM, int TN, int WM, int WN>
+__global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
+  constexpr int TH = WM * TM, TW = 16, NT = WN * TN * 16;
+  constexpr int HW = TW + 2, HH = TH + 2;
+  constexpr int PITCH = 40;  // elements per staged pixel / weight row
+  __shared__ __attribute__((aligned(16))) uint16_t halo[HH * HW * PITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t slab[3 * NT * PITCH];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int wm = wave / WN, wn = wave % WN;
+  const int cols = (a.W + TW - 1) / TW, rows = (a.H + TH - 1) / TH;
+  int blk = blockIdx.x;
+  const int bx = blk % cols;
+  blk /= cols;
+  const int by = blk % rows;
+  const int b = blk / rows;
+  const int x0 = bx * TW, y0 = by * TH;
+  const int n0 = blockIdx.y * NT;
+  const int Cin = a.Cin;
+  const uint16_t* img = a.in + int64_t(b) * a.H * a.W * Cin;
+
+  v4f acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+  for (int c0 = 0; c0 < Cin; c0 += 32) {
+    __syncthreads();  // previous chunk's reads are done
+    // halo tile: HH*HW pixels x 4 chunks of 8 channels
+    for (int q = t; q < HH * HW * 4; q += 256) {
+      const int px = q >> 2, part = q & 3;
+      const int hy = px / HW, hx = px % HW;
+      const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+        v = *reinterpret_cast<const uint4*>(img + (int64_t(yy) * a.W + xx) * Cin + c0 + 8 * part);
+      *reinterpret_cast<uint4*>(&halo[px * PITCH + 8 * part]) = v;
+    }
+#pragma unroll 1
+    for (int ky = 0; ky < 3; ++ky) {
+      if (ky > 0) __syncthreads();  // previous slab's reads are done
+      // weight slab: taps (ky, 0..2) x NT channels x 4 chunks of 8 channels
+      for (int q = t; q < 3 * NT * 4; q += 256) {
+        const int part = q & 3, row = q >> 2;  // row = kx * NT + n
+        const int kx = row / NT, n = row % NT;
+        const int k = (ky * 3 + kx) * Cin + c0 + 8 * part;
+        *reinterpret_cast<uint4*>(&slab[row * PITCH + 8 * part]) =
+            *reinterpret_cast<const uint4*>(a.wk + int64_t(n0 + n) * a.Kpad + k);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        uint4 av[TM], bv[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          av[i] = *reinterpret_cast<const uint4*>(
+              &halo[((wm * TM + i + ky) * HW + r + kx) * PITCH + 8 * g]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          bv[j] = *reinterpret_cast<const uint4*>(
+              &slab[(kx * NT + wn * 16 * TN + 16 * j + r) * PITCH + 8 * g]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(v8bf, av[i]), __builtin_bit_cast(v8bf, bv[j]), acc[i][j], 0,
+                0, 0);
+      }
+    }
+  }
+  // element (column 4g + e of row wm*TM + i, channel r of tile j)
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int yy = y0 + wm * TM + i;
+    if (yy >= a.H) continue;
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int xx = x0 + 4 * g + e;
+        if (xx >= a.W) continue;
+        const int n = n0 + wn * 16 * TN + 16 * j + r;
+        float v = acc[i][j][e];
+        if (a.bias) v += a.bias[n];
+        if (a.relu && v < 0.0f) v = 0.0f;
+        const int64_t o = ((int64_t(b) * a.H + yy) * a.W + xx) * a.Cout + n;
+        if (a.mask && !(bf2f(a.mask[o]) > 0.0f)) v = 0.0f;
+        if (a.out) a.out[o] = f2bf(v);
+        if (a.out_f32) a.out_f32[o] = v;
+      }
+  }
+}
+
 // ---- convolution, backward-weight -------------------------------------------
 // dW[n][k] += sum over pixels m of dY[m][n] * X(m, k), X the implicit im2col of
 // the input.  A work-group owns an NT x 64 tile of dW (NT = 32 or 64 output
@@ -711,13 +817,39 @@ void conv_ks(const NnConvArgs& a, hipStream_t s) {
     launch_conv<KS, 1, 2>(a, s);
 }
 
+template <int TM, int TN, int WM, int WN>
+void launch_conv3_lds(const NnConvArgs& a, hipStream_t s) {
+  constexpr int TH = WM * TM, NT = WN * TN * 16;
+  const int64_t blocks = int64_t((a.W + 15) / 16) * ((a.H + TH - 1) / TH) * a.B;
+  hipLaunchKernelGGL((k_conv3_lds<TM, TN, WM, WN>), dim3(unsigned(blocks), unsigned(a.Cout / NT)),
+                     dim3(256), 0, s, a);
+}
+
+// Work-groups of the LDS-staged 3x3 kernel for a tile of TH rows and NT channels.
+int64_t lds_groups(const NnConvArgs& a, int th, int nt) {
+  return int64_t((a.W + 15) / 16) * ((a.H + th - 1) / th) * a.B * (a.Cout / nt);
+}
+
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
-  if (a.ks == 3)
+  if (a.ks == 3 && a.Cin % 32 == 0) {
+    constexpr int64_t kMin = 256;
+    if (a.Cout % 128 == 0 && lds_groups(a, 8, 128) >= kMin)
+      launch_conv3_lds<4, 4, 2, 2>(a, s);
+    else if (a.Cout % 64 == 0 && lds_groups(a, 8, 64) >= kMin)
+      launch_conv3_lds<4, 2, 2, 2>(a, s);
+    else if (lds_groups(a, 16, 32) >= kMin)
+      launch_conv3_lds<4, 2, 4, 1>(a, s);
+    else if (lds_groups(a, 8, 32) >= kMin)
+      launch_conv3_lds<2, 2, 4, 1>(a, s);
+    else
+      conv_ks<3>(a, s);
+  } else if (a.ks == 3) {
     conv_ks<3>(a, s);
-  else if (a.ks == 1)
+  } else if (a.ks == 1) {
     conv_ks<1>(a, s);
-  else
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -53,12 +53,18 @@ def rand_bf16(rng, shape, scale=1.0):
 
 
 CONV_CASES = [
-    # b, h, w, cin, cout, ks
+    # b, h, w, cin, cout, ks -- small grids: register-fed kernel
     (2, 9, 13, 8, 32, 3),
     (1, 16, 16, 32, 64, 3),
     (2, 7, 11, 96, 32, 3),
     (1, 12, 10, 32, 32, 1),
     (1, 4, 4, 384, 128, 3),
+    # grids of >= 256 work-groups: LDS-staged 3x3 kernel, one case per tile
+    # shape (rows x channels 8 x 128, 8 x 64, 16 x 32, 8 x 32), ragged edges
+    (8, 64, 64, 32, 128, 3),
+    (8, 60, 62, 64, 64, 3),
+    (16, 64, 64, 32, 32, 3),
+    (8, 64, 60, 96, 32, 3),
 ]
 
 
