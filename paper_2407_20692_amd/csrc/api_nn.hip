@@ -109,6 +109,7 @@ struct Net {
   float* xf;
   float* tn;
   float* stats;
+  double* norm_scratch;
   float* loss_scratch;
   uint16_t* g0;
   uint16_t* g1;
@@ -141,6 +142,7 @@ Net plan_net(uint8_t* base, int B, int H, int W, bool train) {
   n.outf = static_cast<float*>(take(size_t(P0) * 32 * 4));
   n.xf = static_cast<float*>(take(size_t(P0) * 4));
   n.stats = static_cast<float*>(take(size_t(B) * 2 * 4));
+  n.norm_scratch = static_cast<double*>(take(cpi::nn_normalize_scratch_bytes(B)));
   n.wpack = static_cast<uint16_t*>(take(size_t(pl.packed_total) * 2));
   if (train) {
     n.tn = static_cast<float*>(take(size_t(P0) * 4));
@@ -228,15 +230,26 @@ struct Pass {
   }
 
   hipError_t pack(bool transposed) const {
+    cpi::NnPackTable tab;
+    int64_t begin = 0;
     for (int i = 0; i < kNumLayers; ++i) {
       const Layer& L = kLayers[i];
-      const bool t = transposed && i != ENC1A;
-      hipError_t e = cpi::nn_pack_weights(params + pl.w_off[i], L.cout, L.cin, L.ks,
-                                          n.wpack + pl.wf_off[i], pl.kpad[i],
-                                          t ? n.wpack + pl.wt_off[i] : nullptr, pl.kpad_t[i], s);
-      if (e != hipSuccess) return e;
+      cpi::NnPackLayer& d = tab.layer[i];
+      d.w_off = pl.w_off[i];
+      d.wf_off = pl.wf_off[i];
+      d.wt_off = pl.wt_off[i];
+      d.cout = L.cout;
+      d.cin = L.cin;
+      d.ks = L.ks;
+      d.kpad = pl.kpad[i];
+      d.kpad_t = pl.kpad_t[i];
+      d.transposed = transposed && i != ENC1A;
+      d.begin = begin;
+      begin += int64_t(L.cout) * d.kpad + (d.transposed ? int64_t(L.cin) * d.kpad_t : 0);
     }
-    return hipSuccess;
+    tab.n = kNumLayers;
+    tab.total = begin;
+    return cpi::nn_pack_all(params, n.wpack, tab, s);
   }
 
   hipError_t forward() const {
@@ -363,7 +376,8 @@ cpi_status cpi_denoiser_forward(const float* params, int32_t batch, int32_t h, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Pass ps{pl, n, params, batch, h, w, s};
     const int64_t hw = int64_t(h) * w;
-    NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, nullptr, nullptr, n.stats, s),
+    NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, nullptr, nullptr, n.stats,
+                             n.norm_scratch, s),
            "denoiser normalise");
     NN_HIP(ps.pack(false), "denoiser weights");
     NN_HIP(ps.forward(), "denoiser forward");
@@ -394,7 +408,8 @@ cpi_status cpi_denoiser_train_step(float* params, float* adam_m, float* adam_v, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Pass ps{pl, n, params, batch, h, w, s};
     const int64_t hw = int64_t(h) * w, P0 = int64_t(batch) * hw;
-    NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, targets, n.tn, n.stats, s),
+    NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, targets, n.tn, n.stats,
+                             n.norm_scratch, s),
            "denoiser normalise");
     NN_HIP(ps.pack(true), "denoiser weights");
     NN_HIP(ps.forward(), "denoiser forward");
@@ -432,7 +447,8 @@ cpi_status cpi_denoiser_gradients(const float* params, int32_t batch, int32_t h,
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Pass ps{pl, n, params, batch, h, w, s};
     const int64_t hw = int64_t(h) * w, P0 = int64_t(batch) * hw;
-    NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, targets, n.tn, n.stats, s),
+    NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, targets, n.tn, n.stats,
+                             n.norm_scratch, s),
            "denoiser normalise");
     NN_HIP(ps.pack(true), "denoiser weights");
     NN_HIP(ps.forward(), "denoiser forward");

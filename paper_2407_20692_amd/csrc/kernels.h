@@ -214,8 +214,26 @@ hipError_t nn_mse(const float* y, int C, const float* res, const float* t, int64
                   uint16_t* dy, hipStream_t s);
 hipError_t nn_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                    float b2, float eps, float c1, float c2, hipStream_t s);
+// scratch: nn_normalize_scratch_bytes(B) bytes of device memory (partial sums)
+size_t nn_normalize_scratch_bytes(int B);
 hipError_t nn_normalize(const float* planes, int B, int64_t hw, int C, uint16_t* out, float* xf,
-                        const float* targets, float* tnorm, float* stats, hipStream_t s);
+                        const float* targets, float* tnorm, float* stats, double* scratch,
+                        hipStream_t s);
+// Weight packing of every layer of a network in one launch: layer l's
+// forward rows go to packed + wf_off and, if transposed, its backward-data
+// rows to packed + wt_off; its elements are [begin, begin + cout * kpad
+// (+ cin * kpad_t)) of the launch's index range.
+struct NnPackLayer {
+  int64_t w_off = 0, wf_off = 0, wt_off = 0, begin = 0;
+  int cout = 0, cin = 0, ks = 0, kpad = 0, kpad_t = 0, transposed = 0;
+};
+struct NnPackTable {
+  NnPackLayer layer[16];
+  int n = 0;
+  int64_t total = 0;
+};
+hipError_t nn_pack_all(const float* params, uint16_t* packed, const NnPackTable& tab,
+                       hipStream_t s);
 hipError_t nn_denormalize(const float* x, int C, const float* res, const float* stats, int64_t hw,
                           int B, float* y, hipStream_t s);
 hipError_t nn_quality(const float* pred, const float* target, int B, int H, int W, double* psnr,

@@ -183,49 +183,98 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0, 0, 0, 0};
 
-  for (int c0 = 0; c0 < Cin; c0 += 32) {
-    __syncthreads();  // previous chunk's reads are done
-    // halo tile: HH*HW pixels x 4 chunks of 8 channels
-    for (int q = t; q < HH * HW * 4; q += 256) {
-      const int px = q >> 2, part = q & 3;
-      const int hy = px / HW, hx = px % HW;
-      const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+  // Phases p = 3 * chunk + ky.  The global loads of phase p + 1 (the halo
+  // when a new chunk starts, and the weight slab) are issued into registers
+  // before the matrix-core ops of phase p and written to LDS after them.
+  constexpr int HQ = (HH * HW * 4 + 255) / 256;   // halo pieces per thread
+  constexpr int SQ = (3 * NT * 4 + 255) / 256;    // slab pieces per thread
+  uint4 hreg[HQ], sreg[SQ];
+  auto load_halo = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < HQ; ++u) {
+      const int q = t + 256 * u;
       uint4 v = make_uint4(0, 0, 0, 0);
-      if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-        v = *reinterpret_cast<const uint4*>(img + (int64_t(yy) * a.W + xx) * Cin + c0 + 8 * part);
-      *reinterpret_cast<uint4*>(&halo[px * PITCH + 8 * part]) = v;
+      if (q < HH * HW * 4) {
+        const int px = q >> 2, part = q & 3;
+        const int hy = px / HW, hx = px % HW;
+        const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+          v = *reinterpret_cast<const uint4*>(img + (int64_t(yy) * a.W + xx) * Cin + c0 +
+                                              8 * part);
+      }
+      hreg[u] = v;
     }
-#pragma unroll 1
-    for (int ky = 0; ky < 3; ++ky) {
-      if (ky > 0) __syncthreads();  // previous slab's reads are done
-      // weight slab: taps (ky, 0..2) x NT channels x 4 chunks of 8 channels
-      for (int q = t; q < 3 * NT * 4; q += 256) {
+  };
+  auto store_halo = [&]() {
+#pragma unroll
+    for (int u = 0; u < HQ; ++u) {
+      const int q = t + 256 * u;
+      if (q < HH * HW * 4)
+        *reinterpret_cast<uint4*>(&halo[(q >> 2) * PITCH + 8 * (q & 3)]) = hreg[u];
+    }
+  };
+  auto load_slab = [&](int c0, int ky) {
+#pragma unroll
+    for (int u = 0; u < SQ; ++u) {
+      const int q = t + 256 * u;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (q < 3 * NT * 4) {
         const int part = q & 3, row = q >> 2;  // row = kx * NT + n
         const int kx = row / NT, n = row % NT;
         const int k = (ky * 3 + kx) * Cin + c0 + 8 * part;
-        *reinterpret_cast<uint4*>(&slab[row * PITCH + 8 * part]) =
-            *reinterpret_cast<const uint4*>(a.wk + int64_t(n0 + n) * a.Kpad + k);
+        v = *reinterpret_cast<const uint4*>(a.wk + int64_t(n0 + n) * a.Kpad + k);
       }
-      __syncthreads();
+      sreg[u] = v;
+    }
+  };
+  auto store_slab = [&]() {
 #pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        uint4 av[TM], bv[TN];
+    for (int u = 0; u < SQ; ++u) {
+      const int q = t + 256 * u;
+      if (q < 3 * NT * 4)
+        *reinterpret_cast<uint4*>(&slab[(q >> 2) * PITCH + 8 * (q & 3)]) = sreg[u];
+    }
+  };
+
+  const int phases = (Cin / 32) * 3;
+  load_halo(0);
+  load_slab(0, 0);
+  store_halo();
+  store_slab();
+  __syncthreads();
+#pragma unroll 1
+  for (int p = 0; p < phases; ++p) {
+    const int ky = p % 3;
+    const bool next = p + 1 < phases;
+    const int pn = p + 1, cn = 32 * (pn / 3), kyn = pn % 3;
+    if (next) {
+      if (kyn == 0) load_halo(cn);
+      load_slab(cn, kyn);
+    }
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-          av[i] = *reinterpret_cast<const uint4*>(
-              &halo[((wm * TM + i + ky) * HW + r + kx) * PITCH + 8 * g]);
+    for (int kx = 0; kx < 3; ++kx) {
+      uint4 av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        av[i] = *reinterpret_cast<const uint4*>(
+            &halo[((wm * TM + i + ky) * HW + r + kx) * PITCH + 8 * g]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bv[j] = *reinterpret_cast<const uint4*>(
+            &slab[(kx * NT + wn * 16 * TN + 16 * j + r) * PITCH + 8 * g]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          bv[j] = *reinterpret_cast<const uint4*>(
-              &slab[(kx * NT + wn * 16 * TN + 16 * j + r) * PITCH + 8 * g]);
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(v8bf, av[i]), __builtin_bit_cast(v8bf, bv[j]), acc[i][j], 0,
-                0, 0);
-      }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(v8bf, av[i]), __builtin_bit_cast(v8bf, bv[j]), acc[i][j], 0, 0,
+              0);
+    }
+    if (next) {
+      __syncthreads();  // every wave is done reading phase p's tiles
+      if (kyn == 0) store_halo();
+      store_slab();
+      __syncthreads();
     }
   }
   // element (column 4g + e of row wm*TM + i, channel r of tile j)
@@ -253,115 +302,134 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
 
 // ---- convolution, backward-weight -------------------------------------------
 // dW[n][k] += sum over pixels m of dY[m][n] * X(m, k), X the implicit im2col of
-// the input.  A work-group owns an NT x 64 tile of dW (NT = 32 or 64 output
-// channels, 64 K values) and a range of pixels, taken 64 at a time: dY and X
-// blocks are loaded with 16-byte loads and stored transposed in LDS
-// ([channel][pixel]) so that each lane's 8 consecutive pixels are one 16-byte
-// LDS read.  Wave w owns the 16 x 16 blocks (nb, kb) with kb = w (NT = 32) or
-// nb in {0, 1} + 2 (w & 1) and kb in {0, 1} + 2 (w >> 1) (NT = 64); the
-// work-group's partial tile is added to dW with FP32 atomics.  Work-groups of
-// the first K tile also sum their dY block over pixels into db (if given).
-template <int KS, int NT>
+// the input.  A work-group owns an NT x KT tile of dW (NT = 32 or 64 output
+// channels, KT = 64, 128 or 256 K values) and a range of pixels, taken 64 at
+// a time: dY and X blocks are loaded with 16-byte loads and stored transposed
+// in LDS ([channel][pixel]) so that each lane's 8 consecutive pixels are one
+// 16-byte LDS read.  NT = 64: wave w owns channels 32 (w & 1) + [0, 32) and K
+// values (KT / 2) (w >> 1) + [0, KT / 2); NT = 32: all 32 channels and K
+// values (KT / 4) w + [0, KT / 4).  The work-group's partial tile is added to
+// dW with FP32 atomics.  Work-groups of the first K tile also sum their dY
+// block over pixels into db (if given).  KT = 64 is used: wider K tiles re-read
+// fewer dY blocks but measured slower (their transposing LDS writes and
+// registers grow with KT).
+template <int KS, int NT, int KT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
   constexpr int HALF = KS / 2;
   constexpr int PB = 64;                 // pixels per block
   constexpr int LP = PB + 8;             // LDS row pitch (elements)
+  constexpr int KW = NT == 64 ? KT / 2 : KT / 4;  // K values per wave
+  constexpr int NKB = KW / 16;                    // 16-wide K blocks per wave
   __shared__ __attribute__((aligned(16))) uint16_t ty[NT][LP];
-  __shared__ __attribute__((aligned(16))) uint16_t tx[64][LP];
+  __shared__ __attribute__((aligned(16))) uint16_t tx[KT][LP];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int n0 = blockIdx.x * NT;
-  const int kc = blockIdx.y * 64;
+  const int kc = blockIdx.y * KT;
   const int64_t M = int64_t(a.B) * a.H * a.W;
   const int64_t per = ((M + gridDim.z - 1) / gridDim.z + PB - 1) / PB * PB;
   const int64_t mlo = int64_t(blockIdx.z) * per;
   const int64_t mhi = mlo + per < M ? mlo + per : M;
   const int Cin = a.Cin;
   const int K = KS * KS * Cin;
-  // wave's blocks: NT = 64 -> n blocks 2 (w&1) + {0,1}, k blocks 2 (w>>1) + {0,1};
-  //                NT = 32 -> n blocks {0,1}, k block w
-  int nbs[2], kbs[2];
-  if (NT == 64) {
-    nbs[0] = 32 * (wave & 1);
-    nbs[1] = nbs[0] + 16;
-    kbs[0] = 32 * (wave >> 1);
-    kbs[1] = kbs[0] + 16;
-  } else {
-    nbs[0] = 0;
-    nbs[1] = 16;
-    kbs[0] = 16 * wave;
-    kbs[1] = 16 * wave;
-  }
-  constexpr int NKB = NT == 64 ? 2 : 1;
-  v4f acc[2][2];
+  const int nb0 = NT == 64 ? 32 * (wave & 1) : 0;
+  const int kb0 = NT == 64 ? KW * (wave >> 1) : KW * wave;
+  v4f acc[2][NKB];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+    for (int j = 0; j < NKB; ++j) acc[i][j] = v4f{0, 0, 0, 0};
   const bool bias = a.db && blockIdx.y == 0;
   float bsum = 0.0f;
-  for (int64_t mb = mlo; mb < mhi; mb += PB) {
-    // dY block: PB pixels x NT channels, NT/8 chunks per pixel
-    for (int c = t; c < PB * (NT / 8); c += 256) {
-      const int p = c / (NT / 8), q = c % (NT / 8);
-      const int64_t m = mb + p;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (m < mhi && n0 + 8 * q < a.Cout)
-        v = *reinterpret_cast<const uint4*>(a.dy + m * a.Cout + n0 + 8 * q);
-      const uint16_t* hv = reinterpret_cast<const uint16_t*>(&v);
+  // A block's loads all go out before any of its LDS writes, and the next
+  // block's loads are issued before the current block's matrix-core ops.
+  // Piece c covers pixel c % PB and channel group c / PB: the 64 lanes of a
+  // wave hold 64 consecutive pixels of one group, so their transposed 2-byte
+  // LDS writes fall on consecutive addresses (no bank conflicts).
+  constexpr int YQ = PB * (NT / 8) / 256;   // dY pieces per thread
+  constexpr int XQ = PB * (KT / 8) / 256;   // X pieces per thread
+  static_assert(YQ >= 1 && XQ >= 1, "tile too small for 256 threads");
+  uint4 yv[YQ], xv[XQ];
+  auto load = [&](int64_t mb) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ty[8 * q + e][p] = hv[e];
+    for (int u = 0; u < YQ; ++u) {
+      const int c = t + 256 * u;
+      const int p = c % PB, q = c / PB;
+      const int64_t m = mb + p;
+      yv[u] = make_uint4(0, 0, 0, 0);
+      if (m < mhi && n0 + 8 * q < a.Cout)
+        yv[u] = *reinterpret_cast<const uint4*>(a.dy + m * a.Cout + n0 + 8 * q);
     }
-    // X block: PB pixels x 64 K values, 8 chunks per pixel
-    for (int c = t; c < PB * 8; c += 256) {
-      const int p = c >> 3, q = c & 7;
+#pragma unroll
+    for (int u = 0; u < XQ; ++u) {
+      const int c = t + 256 * u;
+      const int p = c % PB, q = c / PB;
       const int64_t m = mb + p;
       const int k = kc + 8 * q;
-      uint4 v = make_uint4(0, 0, 0, 0);
+      xv[u] = make_uint4(0, 0, 0, 0);
       if (m < mhi && k < K) {
         const int tap = k / Cin, ci = k - tap * Cin;
         const int x = int(m % a.W), y = int((m / a.W) % a.H);
         const int64_t b = m / (int64_t(a.W) * a.H);
         const int yy = y + tap / KS - HALF, xx = x + tap % KS - HALF;
         if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-          v = *reinterpret_cast<const uint4*>(a.in + ((b * a.H + yy) * a.W + xx) * Cin + ci);
+          xv[u] = *reinterpret_cast<const uint4*>(a.in + ((b * a.H + yy) * a.W + xx) * Cin + ci);
       }
-      const uint16_t* hv = reinterpret_cast<const uint16_t*>(&v);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < YQ; ++u) {
+      const int c = t + 256 * u;
+      const int p = c % PB, q = c / PB;
+      const uint16_t* hv = reinterpret_cast<const uint16_t*>(&yv[u]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ty[8 * q + e][p] = hv[e];
+    }
+#pragma unroll
+    for (int u = 0; u < XQ; ++u) {
+      const int c = t + 256 * u;
+      const int p = c % PB, q = c / PB;
+      const uint16_t* hv = reinterpret_cast<const uint16_t*>(&xv[u]);
 #pragma unroll
       for (int e = 0; e < 8; ++e) tx[8 * q + e][p] = hv[e];
     }
+  };
+  if (mlo < mhi) load(mlo);
+  for (int64_t mb = mlo; mb < mhi; mb += PB) {
+    store();
     __syncthreads();
+    if (mb + PB < mhi) load(mb + PB);
     if (bias && t < NT)
       for (int p = 0; p < PB; ++p) bsum += bf2f(ty[t][p]);
 #pragma unroll
     for (int s = 0; s < PB / 32; ++s) {
-      uint4 av[2], bv[2];
+      uint4 av[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        av[i] = *reinterpret_cast<const uint4*>(&ty[nbs[i] + r][32 * s + 8 * g]);
+        av[i] = *reinterpret_cast<const uint4*>(&ty[nb0 + 16 * i + r][32 * s + 8 * g]);
 #pragma unroll
-      for (int j = 0; j < NKB; ++j)
-        bv[j] = *reinterpret_cast<const uint4*>(&tx[kbs[j] + r][32 * s + 8 * g]);
+      for (int j = 0; j < NKB; ++j) {
+        const uint4 bv = *reinterpret_cast<const uint4*>(&tx[kb0 + 16 * j + r][32 * s + 8 * g]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < NKB; ++j)
+        for (int i = 0; i < 2; ++i)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av[i]),
-                                                              __builtin_bit_cast(v8bf, bv[j]),
+                                                              __builtin_bit_cast(v8bf, bv),
                                                               acc[i][j], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
-  // element (n = nb + 4g + e, k = kb + r)
+  // element (n = nb0 + 16 i + 4g + e, k = kb0 + 16 j + r)
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < NKB; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int n = n0 + nbs[i] + 4 * g + e;
-        const int k = kc + kbs[j] + r;
+        const int n = n0 + nb0 + 16 * i + 4 * g + e;
+        const int k = kc + kb0 + 16 * j + r;
         if (n < a.Cout && k < K) atomicAdd(&a.dw[int64_t(n) * K + k], acc[i][j][e]);
       }
   if (bias && t < NT && n0 + t < a.Cout) atomicAdd(&a.db[n0 + t], bsum);
@@ -406,6 +474,36 @@ __global__ __launch_bounds__(256) void k_pack_weights(const float* __restrict__ 
         v = f2bf(w[(int64_t(co) * taps + (taps - 1 - tp)) * Cin + ci]);
       }
       wt[j] = v;
+    }
+  }
+}
+
+// The same packing for every layer of a network in one launch; element i of
+// the concatenated packed arrays belongs to the last layer whose begin <= i.
+__global__ __launch_bounds__(256) void k_pack_all(const float* __restrict__ params,
+                                                  uint16_t* __restrict__ packed, NnPackTable tab) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < tab.total;
+       i += int64_t(gridDim.x) * 256) {
+    int l = 0;
+    while (l + 1 < tab.n && tab.layer[l + 1].begin <= i) ++l;
+    const NnPackLayer& L = tab.layer[l];
+    const int taps = L.ks * L.ks;
+    const float* w = params + L.w_off;
+    const int64_t j = i - L.begin;
+    const int64_t nf = int64_t(L.cout) * L.kpad;
+    if (j < nf) {
+      const int co = int(j / L.kpad), k = int(j % L.kpad);
+      packed[L.wf_off + j] =
+          k < taps * L.cin ? f2bf(w[int64_t(co) * taps * L.cin + k]) : uint16_t(0);
+    } else {
+      const int64_t jt = j - nf;
+      const int ci = int(jt / L.kpad_t), k = int(jt % L.kpad_t);
+      uint16_t v = 0;
+      if (k < taps * L.cout) {
+        const int tp = k / L.cout, co = k % L.cout;
+        v = f2bf(w[(int64_t(co) * taps + (taps - 1 - tp)) * L.cin + ci]);
+      }
+      packed[L.wt_off + jt] = v;
     }
   }
 }
@@ -644,25 +742,29 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float
 }
 
 // Planes [B][H*W] (FP32) -> x = (p - mu) / sigma with the plane's own mean
-// and population standard deviation (sigma = 1 for a constant plane): as FP32
-// [B][H*W] in xf and as BF16 channel 0 of [B][H*W][C] (channels 1..C-1 zero);
-// stats[2b], stats[2b+1] = mu, sigma.  Targets, if given, take their plane's
-// input transform (FP32, tnorm).
-__global__ __launch_bounds__(256) void k_normalize(const float* __restrict__ planes, int64_t hw,
-                                                   int C, uint16_t* __restrict__ out,
-                                                   float* __restrict__ xf,
-                                                   const float* __restrict__ targets,
-                                                   float* __restrict__ tnorm,
-                                                   float* __restrict__ stats) {
-  const int b = blockIdx.x;
+// and population standard deviation (sigma = 1 for a constant plane), in two
+// kernels.  k_norm_partial: work-group (b, s) sums slice s of plane b (FP64
+// sum and sum of squares) into part[(b * S + s) * 2 + {0, 1}].
+// k_norm_apply: every thread adds the S partials of its plane in slice order
+// (the same result for every thread of the plane) and writes x as FP32 [B][H*W]
+// in xf and as BF16 channel 0 of [B][H*W][C] (channels 1..C-1 zero); the
+// plane's first thread writes stats[2b], stats[2b+1] = mu, sigma.  Targets, if
+// given, take their plane's input transform (FP32, tnorm).
+constexpr int kNormSlices = 16;
+
+__global__ __launch_bounds__(256) void k_norm_partial(const float* __restrict__ planes,
+                                                      int64_t hw, double* __restrict__ part) {
+  const int b = blockIdx.x, sl = blockIdx.y;
+  const int64_t per = (hw + kNormSlices - 1) / kNormSlices;
+  const int64_t lo = sl * per, hi = lo + per < hw ? lo + per : hw;
   const float* p = planes + int64_t(b) * hw;
-  __shared__ double red[2][256];
   double s = 0.0, s2 = 0.0;
-  for (int64_t i = threadIdx.x; i < hw; i += 256) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
     const double v = p[i];
     s += v;
     s2 += v * v;
   }
+  __shared__ double red[2][256];
   red[0][threadIdx.x] = s;
   red[1][threadIdx.x] = s2;
   __syncthreads();
@@ -673,21 +775,45 @@ __global__ __launch_bounds__(256) void k_normalize(const float* __restrict__ pla
     }
     __syncthreads();
   }
-  const double mean = red[0][0] / double(hw);
-  const double var = red[1][0] / double(hw) - mean * mean;
-  const float sd = float(var > 0.0 ? sqrt(var) : 1.0);
-  const float mu = float(mean);
-  if (threadIdx.x == 0 && stats) {
-    stats[2 * b] = mu;
-    stats[2 * b + 1] = sd;
+  if (threadIdx.x == 0) {
+    part[(int64_t(b) * kNormSlices + sl) * 2] = red[0][0];
+    part[(int64_t(b) * kNormSlices + sl) * 2 + 1] = red[1][0];
   }
-  for (int64_t i = threadIdx.x; i < hw; i += 256) {
-    uint16_t* o = out + (int64_t(b) * hw + i) * C;
-    const float x = (p[i] - mu) / sd;
-    xf[int64_t(b) * hw + i] = x;
-    o[0] = f2bf(x);
-    for (int c = 1; c < C; ++c) o[c] = 0;
-    if (targets) tnorm[int64_t(b) * hw + i] = (targets[int64_t(b) * hw + i] - mu) / sd;
+}
+
+__global__ __launch_bounds__(256) void k_norm_apply(const float* __restrict__ planes, int B,
+                                                    int64_t hw, int C,
+                                                    const double* __restrict__ part,
+                                                    uint16_t* __restrict__ out,
+                                                    float* __restrict__ xf,
+                                                    const float* __restrict__ targets,
+                                                    float* __restrict__ tnorm,
+                                                    float* __restrict__ stats) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < int64_t(B) * hw;
+       i += int64_t(gridDim.x) * 256) {
+    const int b = int(i / hw);
+    double s = 0.0, s2 = 0.0;
+    for (int k = 0; k < kNormSlices; ++k) {
+      s += part[(int64_t(b) * kNormSlices + k) * 2];
+      s2 += part[(int64_t(b) * kNormSlices + k) * 2 + 1];
+    }
+    const double mean = s / double(hw);
+    const double var = s2 / double(hw) - mean * mean;
+    const float sd = float(var > 0.0 ? sqrt(var) : 1.0);
+    const float mu = float(mean);
+    if (i % hw == 0 && stats) {
+      stats[2 * b] = mu;
+      stats[2 * b + 1] = sd;
+    }
+    const float x = (planes[i] - mu) / sd;
+    xf[i] = x;
+    if (C == 8) {
+      *reinterpret_cast<uint4*>(out + i * 8) = make_uint4(f2bf(x), 0u, 0u, 0u);
+    } else {
+      out[i * C] = f2bf(x);
+      for (int c = 1; c < C; ++c) out[i * C + c] = 0;
+    }
+    if (targets) tnorm[i] = (targets[i] - mu) / sd;
   }
 }
 
@@ -832,15 +958,20 @@ int64_t lds_groups(const NnConvArgs& a, int th, int nt) {
 
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
   if (a.ks == 3 && a.Cin % 32 == 0) {
+    // the first tile shape (rows x channels) whose grid holds >= 256 work-groups
     constexpr int64_t kMin = 256;
     if (a.Cout % 128 == 0 && lds_groups(a, 8, 128) >= kMin)
       launch_conv3_lds<4, 4, 2, 2>(a, s);
     else if (a.Cout % 64 == 0 && lds_groups(a, 8, 64) >= kMin)
       launch_conv3_lds<4, 2, 2, 2>(a, s);
+    else if (a.Cout % 64 == 0 && lds_groups(a, 4, 64) >= kMin)
+      launch_conv3_lds<2, 2, 2, 2>(a, s);
     else if (lds_groups(a, 16, 32) >= kMin)
       launch_conv3_lds<4, 2, 4, 1>(a, s);
     else if (lds_groups(a, 8, 32) >= kMin)
       launch_conv3_lds<2, 2, 4, 1>(a, s);
+    else if (lds_groups(a, 4, 32) >= kMin)
+      launch_conv3_lds<1, 2, 4, 1>(a, s);
     else
       conv_ks<3>(a, s);
   } else if (a.ks == 3) {
@@ -853,24 +984,25 @@ hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int KS, int NT>
+template <int KS, int NT, int KT>
 void launch_wgrad(const NnWgradArgs& a, hipStream_t s) {
   const int64_t M = int64_t(a.B) * a.H * a.W;
-  const unsigned gx = unsigned((a.Cout + NT - 1) / NT), gy = unsigned((a.Kpad + 63) / 64);
-  // split the pixels so that the grid holds about 2048 work-groups
+  const unsigned gx = unsigned((a.Cout + NT - 1) / NT), gy = unsigned((a.Kpad + KT - 1) / KT);
+  // split the pixels so that the grid holds up to ~2048 work-groups, each of
+  // at least 512 pixels (every split adds one FP32 atomic per dW element)
   int64_t z = 2048 / (int64_t(gx) * gy);
+  if (z > M / 512) z = M / 512;
   if (z < 1) z = 1;
-  if (z > (M + 63) / 64) z = (M + 63) / 64;
   if (z > 65535) z = 65535;
-  hipLaunchKernelGGL((k_conv_wgrad<KS, NT>), dim3(gx, gy, unsigned(z)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_conv_wgrad<KS, NT, KT>), dim3(gx, gy, unsigned(z)), dim3(256), 0, s, a);
 }
 
 hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
   const bool wide = a.Cout % 64 == 0;
   if (a.ks == 3) {
-    if (wide) launch_wgrad<3, 64>(a, s); else launch_wgrad<3, 32>(a, s);
+    if (wide) launch_wgrad<3, 64, 64>(a, s); else launch_wgrad<3, 32, 64>(a, s);
   } else if (a.ks == 1) {
-    if (wide) launch_wgrad<1, 64>(a, s); else launch_wgrad<1, 32>(a, s);
+    if (wide) launch_wgrad<1, 64, 64>(a, s); else launch_wgrad<1, 32, 64>(a, s);
   } else {
     return hipErrorInvalidValue;
   }
@@ -969,10 +1101,21 @@ hipError_t nn_adam(float* w, const float* g, float* m, float* v, int64_t n, floa
   return hipGetLastError();
 }
 
+size_t nn_normalize_scratch_bytes(int B) { return size_t(B) * kNormSlices * 2 * sizeof(double); }
+
 hipError_t nn_normalize(const float* planes, int B, int64_t hw, int C, uint16_t* out, float* xf,
-                        const float* targets, float* tnorm, float* stats, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize, dim3(unsigned(B)), dim3(256), 0, s, planes, hw, C, out, xf,
-                     targets, tnorm, stats);
+                        const float* targets, float* tnorm, float* stats, double* scratch,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_partial, dim3(unsigned(B), unsigned(kNormSlices)), dim3(256), 0, s,
+                     planes, hw, scratch);
+  hipLaunchKernelGGL(k_norm_apply, dim3(grid1(int64_t(B) * hw)), dim3(256), 0, s, planes, B, hw, C,
+                     scratch, out, xf, targets, tnorm, stats);
+  return hipGetLastError();
+}
+
+hipError_t nn_pack_all(const float* params, uint16_t* packed, const NnPackTable& tab,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_all, dim3(grid1(tab.total)), dim3(256), 0, s, params, packed, tab);
   return hipGetLastError();
 }
 

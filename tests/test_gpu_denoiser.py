@@ -59,12 +59,18 @@ CONV_CASES = [
     (2, 7, 11, 96, 32, 3),
     (1, 12, 10, 32, 32, 1),
     (1, 4, 4, 384, 128, 3),
-    # grids of >= 256 work-groups: LDS-staged 3x3 kernel, one case per tile
-    # shape (rows x channels 8 x 128, 8 x 64, 16 x 32, 8 x 32), ragged edges
+    # 1x1 layers whose weight gradients span several K tiles
+    (2, 9, 13, 128, 64, 1),
+    (1, 12, 10, 160, 32, 1),
+    # LDS-staged 3x3 kernel: the first tile shape (rows x channels) whose
+    # grid holds >= 256 work-groups; one case per shape (8 x 128, 8 x 64,
+    # 4 x 64, 16 x 32, 8 x 32, 4 x 32), ragged edges
     (8, 64, 64, 32, 128, 3),
     (8, 60, 62, 64, 64, 3),
+    (16, 16, 16, 128, 256, 3),
     (16, 64, 64, 32, 32, 3),
     (8, 64, 60, 96, 32, 3),
+    (16, 32, 32, 32, 32, 3),
 ]
 
 
