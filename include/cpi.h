@@ -94,7 +94,9 @@ cpi_status cpi_geometry_default(int32_t wa, int32_t ha, int32_t wb, int32_t hb,
  * Correlation function, Eq. (1), exact.
  *
  * cpi_correlate_workspace_size: bytes of device workspace cpi_correlate needs
- *   for these sizes (written to *bytes, a host pointer).
+ *   for these sizes in one shot (written to *bytes, a host pointer); when the
+ *   environment variable CPI_WORKSPACE_LIMIT (bytes) is below that, the size
+ *   of the blocked plan that fits the limit (see below).
  *
  * cpi_correlate: Gamma for n frame pairs.
  *   frames_a  n frames of pa pixels (detector A), format `fmt`
@@ -108,6 +110,14 @@ cpi_status cpi_geometry_default(int32_t wa, int32_t ha, int32_t wb, int32_t hb,
  *   packed bits; other uint8 data from bytes (offset by -128 when a value
  *   exceeds 127, which leaves numer unchanged); int32 partial sums are folded
  *   into int64 whenever the next block of frames could overflow them.
+ *   Memory-adaptive blocking (Section 4.1 splits the work into blocks sized
+ *   by the memory available): when workspace_bytes, capped by
+ *   CPI_WORKSPACE_LIMIT if set, is below the one-shot size, the frames are
+ *   folded in blocks of F frames through the running sums of the streaming
+ *   calls (F the largest multiple of 512 whose state, see
+ *   cpi_stream_workspace_size, fits); the results are identical and the call
+ *   stays asynchronous (one push per block is enqueued).  A workspace below
+ *   the state for F = 512 gives CPI_ERR_WORKSPACE.
  *   Errors: CPI_ERR_INVALID_ARG (null frames/workspace, n, pa or pb <= 0,
  *   bad enum, misalignment, all outputs null), CPI_ERR_OVERFLOW (n*n*255*255
  *   >= 2^63 for U8, n*n >= 2^53 for either format), CPI_ERR_WORKSPACE,

@@ -280,11 +280,14 @@ def correlate_workspace_size(n: int, pa: int, pb: int, fmt: int) -> int:
 def correlate(frames_a, frames_b, n: int, pa: int, pb: int, fmt: int,
               layout: int = GAMMA_VIEW_MAJOR, gamma=None, gamma_f32=None, numer=None,
               sum_a=None, sum_b=None, workspace=None, stream=None):
-    """Exact Gamma of Eq. (1) into the given device tensors (see cpi_correlate)."""
+    """Exact Gamma of Eq. (1) into the given device tensors (see cpi_correlate).
+
+    A given workspace smaller than correlate_workspace_size makes the library
+    work in blocks of frames that fit it (or report CPI_ERR_WORKSPACE)."""
     torch = _torch()
-    need = correlate_workspace_size(n, pa, pb, fmt)
     if workspace is None:
-        workspace = alloc_workspace(need, frames_a.device)
+        workspace = alloc_workspace(correlate_workspace_size(n, pa, pb, fmt), frames_a.device)
+    have = workspace.numel() * workspace.element_size()
     _check(lib.cpi_correlate(
         _dev_ptr(frames_a, "frames_a", torch.uint8, nbytes=n * frame_bytes(pa, fmt)),
         _dev_ptr(frames_b, "frames_b", torch.uint8, nbytes=n * frame_bytes(pb, fmt)),
@@ -294,7 +297,7 @@ def correlate(frames_a, frames_b, n: int, pa: int, pb: int, fmt: int,
         _dev_ptr(numer, "numer", torch.int64, numel=pa * pb),
         _dev_ptr(sum_a, "sum_a", torch.int64, numel=pa),
         _dev_ptr(sum_b, "sum_b", torch.int64, numel=pb),
-        _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need, _stream(stream)))
+        _dev_ptr(workspace, "workspace", torch.uint8), have, _stream(stream)))
     return workspace
 
 

@@ -350,6 +350,57 @@ cpi_status cpi_geometry_default(int32_t wa, int32_t ha, int32_t wb, int32_t hb, 
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workspace bytes cpi_correlate may use: the caller's, capped by the
+// environment variable CPI_WORKSPACE_LIMIT (a byte count) when it is set.
+size_t usable_workspace(size_t given) {
+  const char* v = std::getenv("CPI_WORKSPACE_LIMIT");
+  if (!v || !*v) return given;
+  char* end = nullptr;
+  const unsigned long long x = std::strtoull(v, &end, 10);
+  if (end == v) return given;
+  return size_t(x) < given ? size_t(x) : given;
+}
+
+constexpr int64_t kBlockUnit = 512;   // frames; keeps every block 16-byte aligned
+
+// Memory-adaptive blocking: the largest multiple of kBlockUnit frames (at most
+// n rounded up) whose running-sum state fits in `bytes`, and that state's
+// size; 0 when not even kBlockUnit frames fit.
+int64_t block_frames(int64_t n, int64_t pa, int64_t pb, cpi_frame_format fmt, size_t bytes,
+                     size_t* need) {
+  auto size_for = [&](int64_t units, size_t* b) {
+    cpi::StreamPlan sp;
+    std::string why;
+    if (cpi::plan_stream(pa, pb, int(fmt), units * kBlockUnit, &sp, &why) != CPI_OK) return false;
+    *b = sp.total;
+    return true;
+  };
+  int64_t lo = 0, hi = (n + kBlockUnit - 1) / kBlockUnit;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    size_t b = 0;
+    if (size_for(mid, &b) && b <= bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  if (lo == 0) {
+    size_t b = 0;
+    *need = size_for(1, &b) ? b : 0;
+    return 0;
+  }
+  size_for(lo, need);
+  return lo * kBlockUnit;
+}
+
+}  // namespace
+
+extern "C" {
+
 cpi_status cpi_correlate_workspace_size(int64_t n, int64_t pa, int64_t pb, cpi_frame_format fmt,
                                         size_t* bytes) {
   return guarded([&]() -> cpi_status {
@@ -359,6 +410,12 @@ cpi_status cpi_correlate_workspace_size(int64_t n, int64_t pa, int64_t pb, cpi_f
     cpi_status s = cpi::plan_correlate(n, pa, pb, int(fmt), &pl, &why);
     if (s != CPI_OK) return set_error(s, why);
     *bytes = pl.total;
+    const size_t limit = usable_workspace(pl.total);
+    if (limit < pl.total) {
+      size_t need = 0;
+      block_frames(n, pa, pb, fmt, limit, &need);
+      if (need > 0 && need < pl.total) *bytes = need;
+    }
     return CPI_OK;
   });
 }
@@ -384,9 +441,32 @@ cpi_status cpi_correlate(const void* frames_a, const void* frames_b, int64_t n, 
       if (o && !aligned16(o)) return set_error(CPI_ERR_INVALID_ARG, "outputs must be 16-byte aligned");
     if (!workspace || !aligned16(workspace))
       return set_error(CPI_ERR_INVALID_ARG, "workspace must be a 16-byte aligned device pointer");
-    if (workspace_bytes < pl.total)
-      return set_error(CPI_ERR_WORKSPACE,
-                       "correlate workspace too small: need " + std::to_string(pl.total) + " bytes");
+    const size_t usable = usable_workspace(workspace_bytes);
+    if (usable < pl.total) {
+      // memory-adaptive blocking: fold the frames in blocks through the
+      // running sums of the streaming path (exact, same result)
+      size_t need = 0;
+      const int64_t f = block_frames(n, pa, pb, fmt, usable, &need);
+      if (f == 0)
+        return set_error(CPI_ERR_WORKSPACE, "correlate workspace too small: need " +
+                                                std::to_string(pl.total) +
+                                                " bytes, or at least " + std::to_string(need) +
+                                                " to work in blocks of 512 frames");
+      cpi_stream_t h = nullptr;
+      s = cpi_stream_create(pa, pb, fmt, f, workspace, usable, stream, &h);
+      if (s != CPI_OK) return s;
+      const int64_t fa = cpi::frame_bytes(pa, int(fmt)), fb = cpi::frame_bytes(pb, int(fmt));
+      const uint8_t* a8 = static_cast<const uint8_t*>(frames_a);
+      const uint8_t* b8 = static_cast<const uint8_t*>(frames_b);
+      for (int64_t f0 = 0; f0 < n && s == CPI_OK; f0 += f) {
+        const int64_t k = n - f0 < f ? n - f0 : f;
+        s = cpi_stream_push(h, a8 + f0 * fa, b8 + f0 * fb, k);
+      }
+      if (s == CPI_OK) s = cpi_stream_gamma(h, layout, gamma, gamma_f32, numer, sum_a, sum_b);
+      const std::string err = s == CPI_OK ? std::string() : std::string(cpi_last_error());
+      cpi_stream_destroy(h);
+      return s == CPI_OK ? CPI_OK : set_error(s, err);
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     s = enqueue_correlate(pl, static_cast<const uint8_t*>(frames_a),

@@ -192,3 +192,23 @@ def test_resampled_refocus_host_validation(cpi):
     assert lib.cpi_refocus_resampled(fake, ctypes.byref(g), ctypes.byref(ok), al, 2, fake, fake,
                                      16, None) == 4
     assert lib.cpi_resample_views(None, ctypes.byref(g), ctypes.byref(ok), fake, None) == 1
+
+
+def test_memory_adaptive_workspace_host(cpi):
+    """CPI_WORKSPACE_LIMIT lowers the reported correlate workspace to a blocked
+    plan that fits, and a workspace below even one 512-frame block is refused
+    before anything is launched."""
+    import os
+    n, pa, pb = 100000, 1024, 1024
+    full = cpi.correlate_workspace_size(n, pa, pb, cpi.FRAMES_BIT1)
+    os.environ["CPI_WORKSPACE_LIMIT"] = "12000000"
+    try:
+        lim = cpi.correlate_workspace_size(n, pa, pb, cpi.FRAMES_BIT1)
+    finally:
+        del os.environ["CPI_WORKSPACE_LIMIT"]
+    assert lim <= 12000000 < full
+    fake = ctypes.c_void_p(1 << 20)
+    st = cpi.lib.cpi_correlate(fake, fake, n, pa, pb, 1, 0, fake, None, None, None, None, fake,
+                               4096, None)
+    assert st == 4
+    assert b"blocks of 512 frames" in cpi.lib.cpi_last_error()

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from synth import WORKLOADS, generate_frames, pack_bits_lsb
-from tests.gpu_util import assert_bit_exact, log, oracle_in_layout, run_correlate
+from tests.gpu_util import assert_bit_exact, dev, log, oracle_in_layout, run_correlate, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -203,3 +203,66 @@ def test_measured_peaks_plausible(cpi):
     assert 0.5e15 < mp["int8_ops_per_s"] < 5.2e15
     assert 1.0e15 < mp["fp4_ops_per_s"] < 10.5e15
     assert 0.5e12 < mp["copy_bytes_per_s"] < 8.5e12
+
+
+@pytest.mark.parametrize("fmt_name", ["bit1", "u8"])
+def test_memory_adaptive_blocks(cpi, fmt_name):
+    """A workspace below the single-shot plan makes cpi_correlate fold the
+    frames in blocks (the largest multiple of 512 frames whose running-sum state
+    fits); Gamma, the numerator and the sums are bit-identical to the
+    single-shot call.  Also forced through CPI_WORKSPACE_LIMIT."""
+    import os
+    import torch
+    rng = np.random.default_rng(77)
+    n, pa, pb = 40000, 1024, 256
+    if fmt_name == "bit1":
+        fmt = cpi.FRAMES_BIT1
+        fa = rng.integers(0, 256, (n, pa // 8), dtype=np.uint8)
+        fb = rng.integers(0, 256, (n, pb // 8), dtype=np.uint8)
+        limit = 3_000_000
+    else:
+        fmt = cpi.FRAMES_U8
+        fa = rng.poisson(3.0, (n, pa)).clip(0, 255).astype(np.uint8)
+        fb = rng.poisson(3.0, (n, pb)).clip(0, 255).astype(np.uint8)
+        fa[7, 5] = 255
+        limit = 8_000_000
+    full = cpi.correlate_workspace_size(n, pa, pb, fmt)
+    assert full > limit
+    log(f"blocks {fmt_name}: single-shot workspace {full} bytes, limit {limit}")
+    da, db = to_dev(fa), to_dev(fb)
+
+    def run(ws_bytes):
+        outs = dict(gamma=torch.empty(pa * pb, dtype=torch.float64, device=dev()),
+                    gamma_f32=torch.empty(pa * pb, dtype=torch.float32, device=dev()),
+                    numer=torch.empty(pa * pb, dtype=torch.int64, device=dev()),
+                    sum_a=torch.empty(pa, dtype=torch.int64, device=dev()),
+                    sum_b=torch.empty(pb, dtype=torch.int64, device=dev()))
+        ws = cpi.alloc_workspace(ws_bytes, dev())
+        cpi.correlate(da, db, n, pa, pb, fmt, cpi.GAMMA_VIEW_MAJOR, workspace=ws, **outs)
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in outs.items()}
+
+    ref = run(full)
+    got = run(limit)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+    os.environ["CPI_WORKSPACE_LIMIT"] = str(limit)
+    try:
+        need = cpi.correlate_workspace_size(n, pa, pb, fmt)
+        assert need <= limit
+        got2 = run(full)
+    finally:
+        del os.environ["CPI_WORKSPACE_LIMIT"]
+    for k in ref:
+        assert np.array_equal(ref[k], got2[k]), k
+    # the numerator itself against the oracle's definition on a few entries
+    q = rng.integers(0, pb, 6)
+    p = rng.integers(0, pa, 6)
+    of = oracle.FRAMES_BIT1 if fmt_name == "bit1" else oracle.FRAMES_U8
+    A = oracle.unpack_frames(fa, n, pa, of)
+    B = oracle.unpack_frames(fb, n, pb, of)
+    for qq, pp in zip(q, p):
+        a = A[:, pp].astype(np.int64)
+        b = B[:, qq].astype(np.int64)
+        num = n * int(a @ b) - int(a.sum()) * int(b.sum())
+        assert ref["numer"][qq * pa + pp] == num
