@@ -180,6 +180,43 @@ cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha,
                               int32_t* planes_per_group, int32_t* rows_per_wave,
                               int32_t* view_splits);
 
+/* Kernels of the batched refocus path.  Both evaluate the same sum (the
+ * bilinear sample of every view at the plane's shifted point, summed over
+ * the views); they differ in summation order only.
+ *   CPI_REFOCUS_ROWS: every output row interpolates its two view rows, for
+ *     every view, and sums over the views.
+ *   CPI_REFOCUS_COLUMN_SUMS: for each lens-plane row y_b, the column
+ *     interpolants of every view row the tile touches are summed over x_b
+ *     first; the row weights (which depend on y_b and the output row, not on
+ *     x_b) are applied once per y_b. */
+typedef enum { CPI_REFOCUS_ROWS = 0, CPI_REFOCUS_COLUMN_SUMS = 1 } cpi_refocus_kernel;
+
+/* A batched-refocus configuration: planes per work-group and output rows per
+ * tile, (4, 8), (4, 16), (8, 8), (8, 16), (8, 32), (16, 8), (16, 16) for
+ * both kernels and also (1, 16), (2, 16), (2, 32), (4, 32) for
+ * CPI_REFOCUS_COLUMN_SUMS; view-row splits (1..16);
+ * the kernel (cpi_refocus_kernel) and, for CPI_REFOCUS_COLUMN_SUMS, the number
+ * of view windows staged in LDS (2, 3 or 4; ignored by CPI_REFOCUS_ROWS). */
+typedef struct {
+  int32_t planes_per_group;
+  int32_t rows_per_wave;
+  int32_t view_splits;
+  int32_t kernel;
+  int32_t stages;
+} cpi_refocus_tiles;
+
+/* The configuration cpi_refocus uses for this shape on the current device
+ * (cached by cpi_autotune_refocus, or the default).  `out` is a host pointer. */
+cpi_status cpi_refocus_get_tiles(const cpi_geometry* g, int32_t n_alpha,
+                                 cpi_refocus_tiles* out);
+/* cpi_refocus with an explicit configuration `tiles` (host pointer) instead
+ * of the cached one; CPI_ERR_UNSUPPORTED for a combination that is not built.
+ * Results are bitwise reproducible for a given configuration. */
+cpi_status cpi_refocus_tiled(const float* gamma, const cpi_geometry* g,
+                             const double* alphas, int32_t n_alpha, float* out,
+                             const cpi_refocus_tiles* tiles, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
 /* Matrix-core encoding of binary frames (CPI_FRAMES_BIT1, and CPI_FRAMES_U8
  * data whose bytes are all 0 or 1).
  *   CPI_MMA_AUTO (default): FP4 (E2M1) operands with FP32 accumulation when

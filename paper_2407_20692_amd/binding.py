@@ -52,6 +52,19 @@ class Geometry(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RefocusTiles(ctypes.Structure):
+    _fields_ = [("planes_per_group", c_int32), ("rows_per_wave", c_int32),
+                ("view_splits", c_int32), ("kernel", c_int32), ("stages", c_int32)]
+
+    def as_tuple(self):
+        return (self.planes_per_group, self.rows_per_wave, self.view_splits, self.kernel,
+                self.stages)
+
+
+REFOCUS_ROWS = 0
+REFOCUS_COLUMN_SUMS = 1
+
+
 class LensSampling(ctypes.Structure):
     """Lens-plane sample grid (cpi_lens_sampling): x_b = ox + i sx, i < nx;
     y_b = oy + j sy, j < ny."""
@@ -99,6 +112,10 @@ _SIGS = {
                                      c_void_p, c_void_p, c_size_t, c_void_p]),
     "cpi_refocus_config": (c_int, [POINTER(Geometry), c_int32, POINTER(c_int32), POINTER(c_int32),
                                    POINTER(c_int32)]),
+    "cpi_refocus_get_tiles": (c_int, [POINTER(Geometry), c_int32, POINTER(RefocusTiles)]),
+    "cpi_refocus_tiled": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
+                                  c_void_p, POINTER(RefocusTiles), c_void_p, c_size_t,
+                                  c_void_p]),
     "cpi_stream_workspace_size": (c_int, [c_int64, c_int64, c_int, c_int64, POINTER(c_size_t)]),
     "cpi_stream_create": (c_int, [c_int64, c_int64, c_int, c_int64, c_void_p, c_size_t, c_void_p,
                                   POINTER(c_void_p)]),
@@ -423,6 +440,36 @@ def refocus_config(g: Geometry, n_alpha: int):
     _check(lib.cpi_refocus_config(ctypes.byref(g), n_alpha, ctypes.byref(kp), ctypes.byref(rw),
                                   ctypes.byref(sp)))
     return kp.value, rw.value, sp.value
+
+
+def refocus_tiles(g: Geometry, n_alpha: int):
+    """(planes per work-group, rows per wave, view splits, kernel, stages) used by
+    refocus()."""
+    t = RefocusTiles()
+    _check(lib.cpi_refocus_get_tiles(ctypes.byref(g), n_alpha, ctypes.byref(t)))
+    return t.as_tuple()
+
+
+def refocus_tiled(gamma, g: Geometry, alphas, out, tiles, workspace=None, stream=None):
+    """Batched refocus with an explicit configuration (planes per work-group,
+    rows per wave, view splits, kernel[, stages]); stages default to 3."""
+    vals = [int(v) for v in tiles]
+    if len(vals) == 4:
+        vals.append(3)
+    t = RefocusTiles(*vals)
+    torch = _torch()
+    a, ap, na = _alphas(alphas)
+    need = refocus_workspace_size(g, na)
+    if workspace is None:
+        workspace = alloc_workspace(need, gamma.device)
+    pa = g.wa * g.ha
+    pb = g.wb * g.hb
+    _check(lib.cpi_refocus_tiled(
+        _dev_ptr(gamma, "gamma", torch.float32, numel=pa * pb), ctypes.byref(g), ap, na,
+        _dev_ptr(out, "out", torch.float32, numel=na * g.out_w * g.out_h), ctypes.byref(t),
+        _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need, _stream(stream)))
+    del a
+    return workspace
 
 
 def autotune_refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):

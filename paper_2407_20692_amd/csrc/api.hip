@@ -612,6 +612,41 @@ cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha, int32_t* p
   });
 }
 
+cpi_status cpi_refocus_get_tiles(const cpi_geometry* g, int32_t n_alpha, cpi_refocus_tiles* out) {
+  return guarded([&]() -> cpi_status {
+    cpi::RefocusPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_refocus(g, n_alpha, &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    if (!out) return set_error(CPI_ERR_INVALID_ARG, "null argument");
+    const cpi::RefocusConfig c = cpi::refocus_config_for(g, n_alpha);
+    out->planes_per_group = c.kp;
+    out->rows_per_wave = c.rw;
+    out->view_splits = c.splits;
+    out->kernel = c.mode;
+    out->stages = c.mode == 1 ? c.stages : 0;
+    return CPI_OK;
+  });
+}
+
+cpi_status cpi_refocus_tiled(const float* gamma, const cpi_geometry* g, const double* alphas,
+                             int32_t n_alpha, float* out, const cpi_refocus_tiles* tiles,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  return guarded([&]() -> cpi_status {
+    if (!tiles) return set_error(CPI_ERR_INVALID_ARG, "null tiles");
+    cpi::RefocusConfig c;
+    c.kp = tiles->planes_per_group;
+    c.rw = tiles->rows_per_wave;
+    c.splits = tiles->view_splits;
+    c.mode = tiles->kernel;
+    c.stages = tiles->stages;
+    if (!cpi::refocus_config_supported(c))
+      return set_error(CPI_ERR_UNSUPPORTED, "refocus configuration is not built");
+    return cpi::refocus_enqueue(gamma, g, alphas, n_alpha, out, workspace, workspace_bytes,
+                                static_cast<hipStream_t>(stream), &c, false);
+  });
+}
+
 }  // extern "C"
 
 namespace {

@@ -3,12 +3,13 @@
 // kernel (planes per work-group, output rows per wave, view-row splits) is
 // chosen by timing the candidates on the caller's inputs.  Results are kept
 // per (shape, device) in memory and, when CPI_AUTOTUNE_CACHE names a file, in
-// a text cache of lines "key kp rw splits microseconds".
+// a text cache of lines "key kp rw splits kernel stages microseconds".
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -67,7 +68,8 @@ void load_cache_locked() {
     std::string key;
     RefocusConfig c;
     double us = 0;
-    if (!(is >> key >> c.kp >> c.rw >> c.splits >> us) || !refocus_config_supported(c)) {
+    if (!(is >> key >> c.kp >> c.rw >> c.splits >> c.mode >> c.stages >> us) ||
+        !refocus_config_supported(c)) {
       if (log_level() > 0)
         std::fprintf(stderr, "cpi: ignoring malformed autotune cache %s\n", path);
       return;
@@ -82,7 +84,9 @@ void store_cache_locked(const std::string& key, const RefocusConfig& c, double u
   const char* path = std::getenv("CPI_AUTOTUNE_CACHE");
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
-  if (f) f << key << ' ' << c.kp << ' ' << c.rw << ' ' << c.splits << ' ' << us << '\n';
+  if (f)
+    f << key << ' ' << c.kp << ' ' << c.rw << ' ' << c.splits << ' ' << c.mode << ' '
+      << c.stages << ' ' << us << '\n';
 }
 
 int64_t workgroups(const cpi_geometry* g, int32_t n_alpha, const RefocusConfig& c) {
@@ -123,15 +127,16 @@ cpi_status autotune_refocus(const float* gamma, const cpi_geometry* g, const dou
                             hipStream_t st, std::string* why) {
   std::vector<RefocusConfig> cands;
   const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
-  for (int kp : {4, 8, 16})
-    for (int rw : {8, 16, 32})
-      for (int sp = 1; sp <= max_splits; sp *= 2) {
-        RefocusConfig c{kp, rw, sp};
-        if (!refocus_config_supported(c)) continue;
-        if (kp > 4 && kp / 2 >= n_alpha) continue;        // planes beyond n_alpha
-        if (rw > 8 && rw / 2 >= g->out_h) continue;       // rows beyond out_h
-        cands.push_back(c);
-      }
+  for (int mode : {0, 1})
+    for (int kp : {1, 2, 4, 8, 16})
+      for (int rw : {8, 16, 32})
+        for (int sp = 1; sp <= max_splits; sp *= 2) {
+          RefocusConfig c{kp, rw, sp, mode, 3};
+          if (!refocus_config_supported(c)) continue;
+          if (kp > 4 && kp / 2 >= n_alpha) continue;        // planes beyond n_alpha
+          if (rw > 8 && rw / 2 >= g->out_h) continue;       // rows beyond out_h
+          cands.push_back(c);
+        }
   if (g->wa < 2 || g->ha < 2) cands.clear();
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -140,29 +145,66 @@ cpi_status autotune_refocus(const float* gamma, const cpi_geometry* g, const dou
   }
   RefocusConfig best = default_refocus_config(g, n_alpha);
   double best_us = 1e300;
-  for (const RefocusConfig& c : cands) {
+  // Times one candidate (a warm-up call, then the mean of 3); < 0 if it
+  // cannot run here.
+  auto time_of = [&](const RefocusConfig& c, double* us) -> cpi_status {
+    *us = -1.0;
     cpi_status s = refocus_enqueue(gamma, g, alphas, n_alpha, out, ws, ws_bytes, st, &c, false);
-    if (s != CPI_OK) continue;
+    if (s != CPI_OK) return CPI_OK;
     const int reps = 3;
     hipEventRecord(e0, st);
     for (int r = 0; r < reps; ++r)
       refocus_enqueue(gamma, g, alphas, n_alpha, out, ws, ws_bytes, st, &c, false);
     hipEventRecord(e1, st);
     if (hipEventSynchronize(e1) != hipSuccess) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
       if (why) *why = "autotune: device failure while timing";
       return CPI_ERR_DEVICE;
     }
     float ms = 0.f;
     hipEventElapsedTime(&ms, e0, e1);
-    const double us = 1000.0 * ms / reps;
+    *us = 1000.0 * ms / reps;
     if (log_level() > 1)
-      std::fprintf(stderr, "cpi: autotune kp=%d rw=%d splits=%d %.1f us\n", c.kp, c.rw, c.splits, us);
+      std::fprintf(stderr, "cpi: autotune kernel=%d stages=%d kp=%d rw=%d splits=%d %.1f us\n",
+                   c.mode, c.mode ? c.stages : 0, c.kp, c.rw, c.splits, *us);
+    return CPI_OK;
+  };
+  // Phase 1: every shape and split count of both kernels (column sums with
+  // three stages); phase 2: the three fastest column-sum candidates with two
+  // and four stages.
+  std::vector<std::pair<double, RefocusConfig>> sep_times;
+  cpi_status fail = CPI_OK;
+  for (const RefocusConfig& c : cands) {
+    double us;
+    fail = time_of(c, &us);
+    if (fail != CPI_OK) break;
+    if (us < 0) continue;
+    if (c.mode == 1) sep_times.push_back({us, c});
     if (us < best_us) {
       best_us = us;
       best = c;
     }
+  }
+  if (fail == CPI_OK) {
+    std::sort(sep_times.begin(), sep_times.end(),
+              [](const std::pair<double, RefocusConfig>& a,
+                 const std::pair<double, RefocusConfig>& b) { return a.first < b.first; });
+    for (size_t k = 0; k < sep_times.size() && k < 3 && fail == CPI_OK; ++k)
+      for (int stg : {2, 4}) {
+        RefocusConfig c = sep_times[k].second;
+        c.stages = stg;
+        double us;
+        fail = time_of(c, &us);
+        if (fail != CPI_OK) break;
+        if (us >= 0 && us < best_us) {
+          best_us = us;
+          best = c;
+        }
+      }
+  }
+  if (fail != CPI_OK) {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return fail;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

@@ -137,11 +137,14 @@ struct RefocusConfig {
   int kp = 4;        // planes per work-group (one wave per plane)
   int rw = 8;        // output rows per work-group tile
   int splits = 1;    // view-row splits (partial sums reduced afterwards)
+  int mode = 0;      // 0: per-row interpolation (k_ref_batched); 1: column sums over x_b
+                     // first, row weights once per y_b (k_ref_sep)
+  int stages = 3;    // mode 1: view windows staged in LDS (2, 3 or 4)
 };
 bool refocus_config_supported(const RefocusConfig& c);
 // bounds: workspace for the window bounds per (plane group, tile column,
 // view column) and (plane group, tile row, view row), two ints each; sized
-// for plane groups of at least 4 planes and tiles of at least 64 x 8.
+// for plane groups of at least 1 plane and tiles of at least 64 x 8.
 hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* itab,
                            const float* ftab, const void* ytab, void* bounds, int64_t stride,
                            int n_alpha,

@@ -176,10 +176,11 @@ cpi_status plan_refocus(const cpi_geometry* g, int32_t n_alpha, RefocusPlan* p,
   off = align256(off + size_t(n_alpha) * size_t(q.table_stride) * 4);
   q.off_ytab = off;
   off = align256(off + size_t(n_alpha) * size_t(g->hb) * size_t(g->out_h) * 16);
-  // window bounds of the batched kernel: at most n_alpha/4 plane groups,
-  // ceil(out_w/64) tile columns and ceil(out_h/8) tile rows
+  // window bounds of the batched kernels: at most n_alpha plane groups (one
+  // plane per work-group), ceil(out_w/64) tile columns and ceil(out_h/8) tile
+  // rows
   q.off_bounds = off;
-  const size_t groups = size_t((n_alpha + 3) / 4);
+  const size_t groups = size_t(n_alpha);
   off = align256(off + groups * (size_t((g->out_w + 63) / 64) * size_t(g->wb) +
                                  size_t((g->out_h + 7) / 8) * size_t(g->hb)) * 8);
   q.off_partial = off;

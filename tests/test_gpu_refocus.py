@@ -139,6 +139,91 @@ def test_autotune_configs_deterministic_and_accurate(cpi, tiny):
     del torch
 
 
+TILE_SHAPES = [(4, 8), (4, 16), (8, 8), (8, 16), (8, 32), (16, 8), (16, 16)]
+SEP_ONLY_SHAPES = [(1, 16), (2, 16), (2, 32), (4, 32)]   # column-sum kernel only
+
+
+KERNELS = [(0, 0), (1, 2), (1, 3), (1, 4)]   # (kernel, copy stages)
+# (8 planes x 32 rows with 4 staged windows would need more LDS than a CU has)
+CONFIGS = [(shape, k) for shape in TILE_SHAPES for k in KERNELS
+           if (shape, k) != ((8, 32), (1, 4))] + \
+    [(shape, k) for shape in SEP_ONLY_SHAPES for k in KERNELS[1:]]
+
+
+@pytest.mark.parametrize("shape,kernel", CONFIGS)
+def test_every_tile_config(cpi, tiny, shape, kernel):
+    """Both batched kernels (per-row interpolation; column sums over x_b
+    first, with 2, 3 and 4 staged view windows) in every built tile shape and
+    with 1, 2 and 5 view-row splits: within the tolerance of the oracle and
+    bitwise reproducible."""
+    w, g64, g32 = tiny
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    al = np.linspace(0.5, 1.5, 13)
+    want = oracle.refocus(g64, g, al)
+    kp, rw = shape
+    for splits in (1, 2, 5):
+        tiles = (kp, rw, splits) + kernel
+        log(f"case tiles {tiles}")
+        fn = lambda gam, geo, a, out: cpi.refocus_tiled(gam, geo, a, out, tiles)  # noqa: E731
+        got = _run(cpi, fn, g32, g, al)
+        assert plane_rel_err(got, want).max() <= TOL, tiles
+        assert np.array_equal(got, _run(cpi, fn, g32, g, al)), tiles
+
+
+WINDOW_GEOMS = [
+    # views wider than the 128-float LDS rows: at |alpha| >= 2 the column
+    # windows do not fit and the kernels gather directly from Gamma
+    oracle.Geometry(136, 40, 4, 3, 2.0, 2.0, 67.5, 19.5, 1.5, 1.0, 136, 40),
+    # view rows not a multiple of 4 floats (4-byte window copies); tall
+    # row windows at large alpha
+    oracle.Geometry(30, 53, 5, 3, 1.7, 2.3, 14.5, 26.0, 2.0, 1.0, 30, 53),
+]
+WINDOW_ALPHAS = [2.6, -0.8, 1.0, 0.5, 1.5, 0.0, 1.9]
+
+
+@pytest.fixture(scope="module")
+def window_cases():
+    cases = []
+    for gi, g in enumerate(WINDOW_GEOMS):
+        rng = np.random.default_rng(100 + gi)
+        gam32 = rng.standard_normal((g.hb * g.wb, g.ha * g.wa)).astype(np.float32)
+        want = oracle.refocus(gam32.astype(np.float64), g, WINDOW_ALPHAS)
+        cases.append((g, gam32, want))
+    return cases
+
+
+@pytest.mark.parametrize("shape,kernel", CONFIGS)
+def test_tile_configs_window_paths(cpi, window_cases, shape, kernel):
+    """Every tile shape of both kernels where some windows do not fit in LDS
+    (wide views, large |alpha|) and where view rows are not a multiple of 4
+    floats; one and three view-row splits."""
+    kp, rw = shape
+    for gi, (g, gam32, want) in enumerate(window_cases):
+        for splits in (1, 3):
+            tiles = (kp, rw, splits) + kernel
+            log(f"case window geometry {gi} tiles {tiles}")
+            fn = lambda gam, geo, a, out: cpi.refocus_tiled(gam, geo, a, out, tiles)  # noqa: E731
+            got = _run(cpi, fn, gam32, g, WINDOW_ALPHAS)
+            err = np.abs(got - want).max(axis=(1, 2))
+            scale = np.maximum(np.abs(want).max(axis=(1, 2)), np.abs(gam32).sum() * 1e-3)
+            assert (err / scale).max() <= TOL, (gi, tiles, err / scale)
+
+
+def test_tiles_query_and_unsupported(cpi, tiny):
+    """refocus_tiles reports a built configuration; an unbuilt one is
+    rejected before any launch."""
+    w, _, g32 = tiny
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    kp, rw, sp, kernel, stages = cpi.refocus_tiles(_geom(cpi, g), 5)
+    assert ((kp, rw), (kernel, stages)) in CONFIGS and 1 <= sp <= 16
+    for bad in [(16, 32, 1, 0, 0), (8, 16, 0, 1, 3), (8, 16, 1, 2, 3), (2, 8, 1, 0, 0),
+                (8, 16, 1, 1, 1), (8, 16, 1, 1, 5), (2, 16, 1, 0, 0), (1, 32, 1, 1, 2),
+                (8, 32, 1, 1, 4)]:
+        fn = lambda gam, geo, a, out: cpi.refocus_tiled(gam, geo, a, out, bad)  # noqa: E731
+        with pytest.raises(cpi.CpiError):
+            _run(cpi, fn, g32, g, [1.0])
+
+
 @pytest.fixture(scope="module")
 def paper_gamma():
     """Gamma of the 20000-frame paper-like workload from the oracle's exact
@@ -176,6 +261,14 @@ def test_paper_like_full_size(cpi, paper_gamma):
     assert err.max() <= TOL
     plain = _run(cpi, cpi.refocus_plain, g32, g, al)
     assert plane_rel_err(plain[:, ys, xs], want).max() <= TOL
+    for tiles in [(8, 16, 4, 1, 3), (16, 16, 2, 1, 4), (8, 32, 2, 1, 2), (4, 8, 8, 1, 3),
+                  (4, 16, 16, 1, 2), (2, 32, 16, 1, 3), (1, 16, 8, 1, 4), (8, 16, 4, 0, 0)]:
+        log(f"case {w.name} refocus, 32 planes, tiles {tiles}")
+        fn = lambda gam, geo, a, out: cpi.refocus_tiled(gam, geo, a, out, tiles)  # noqa: E731
+        got_t = _run(cpi, fn, g32, g, al)
+        err = plane_rel_err(got_t[:, ys, xs], want)
+        log(f"tiles {tiles}: per-plane relative error max {err.max():.3g}")
+        assert err.max() <= TOL, tiles
 
 
 @pytest.mark.parametrize("n_alpha", [100, 261, 1000])
