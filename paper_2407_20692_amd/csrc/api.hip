@@ -190,14 +190,11 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
     ProfScope ps("ingest", st);
     CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum2_a), pl.pa_pad, 0, st), "fill");
     CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum2_b), pl.pb_pad, 0, st), "fill");
-    CPI_HIP(cpi::u8_to_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, stats, false, st),
-            "ingest");
-    CPI_HIP(cpi::u8_to_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, stats, fp4, st),
-            "ingest");
-    CPI_HIP(cpi::u8_sums(fa, pl.n, pl.pa, sum2_a, stats, st), "sums");
-    CPI_HIP(cpi::u8_sums(fb, pl.n, pl.pb, sum2_b, stats, st), "sums");
-    CPI_HIP(cpi::u8_to_bytes(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bytes, stats, st), "ingest");
-    CPI_HIP(cpi::u8_to_bytes(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bytes, stats, st), "ingest");
+    const cpi::U8Job ja{fa, pl.pa, pl.pa_pad, op_a, sum_a, sum2_a, 0};
+    const cpi::U8Job jb{fb, pl.pb, pl.pb_pad, op_b, sum_b, sum2_b, fp4 ? 1 : 0};
+    CPI_HIP(cpi::u8_to_bits(ja, jb, pl.n, pl.kpad_bits, stats, st), "ingest");
+    CPI_HIP(cpi::u8_sums(ja, jb, pl.n, stats, st), "sums");
+    CPI_HIP(cpi::u8_to_bytes(ja, jb, pl.n, pl.kpad_bytes, stats, st), "ingest");
   }
 
   ProfScope ps("gemm", st);
@@ -903,16 +900,13 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
       ProfScope ps("ingest", st);
       CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum2_a), cp.pa_pad, 0, st), "fill");
       CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum2_b), cp.pb_pad, 0, st), "fill");
-      CPI_HIP(cpi::u8_to_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, stats, false, st),
-              "ingest");
-      CPI_HIP(cpi::u8_to_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, stats, fp4, st),
-              "ingest");
-      CPI_HIP(cpi::u8_sums(fa, k, h->pa, csum2_a, stats, st), "sums");
-      CPI_HIP(cpi::u8_sums(fb, k, h->pb, csum2_b, stats, st), "sums");
+      const cpi::U8Job ja{fa, h->pa, cp.pa_pad, op_a, csum_a, csum2_a, 0};
+      const cpi::U8Job jb{fb, h->pb, cp.pb_pad, op_b, csum_b, csum2_b, fp4 ? 1 : 0};
+      CPI_HIP(cpi::u8_to_bits(ja, jb, k, cp.kpad_bits, stats, st), "ingest");
+      CPI_HIP(cpi::u8_sums(ja, jb, k, stats, st), "sums");
       CPI_HIP(cpi::add_select_i64(tot_a, csum_a, csum2_a, cp.pa_pad, stats, st), "sums");
       CPI_HIP(cpi::add_select_i64(tot_b, csum_b, csum2_b, cp.pb_pad, stats, st), "sums");
-      CPI_HIP(cpi::u8_to_bytes(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bytes, stats, st), "ingest");
-      CPI_HIP(cpi::u8_to_bytes(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bytes, stats, st), "ingest");
+      CPI_HIP(cpi::u8_to_bytes(ja, jb, k, cp.kpad_bytes, stats, st), "ingest");
     }
     ProfScope ps("gemm", st);
     g.mode = cpi::EPI_STREAM64;

@@ -98,13 +98,18 @@ int64_t workgroups(const cpi_geometry* g, int32_t n_alpha, const RefocusConfig& 
 
 }  // namespace
 
+// Untuned shapes: the column-sum kernel with 4 planes x 16 rows and two
+// staged windows (the fastest measured on the paper-like and the paper's
+// configurations), view splits until the grid has 8192 work-groups.
 RefocusConfig default_refocus_config(const cpi_geometry* g, int32_t n_alpha) {
   RefocusConfig c;
-  c.kp = n_alpha >= 8 ? 8 : 4;
+  c.mode = 1;
+  c.stages = 2;
+  c.kp = 4;
   c.rw = g->out_h >= 16 ? 16 : 8;
   c.splits = 1;
   const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
-  while (c.splits * 2 <= max_splits && workgroups(g, n_alpha, c) < 1024) c.splits *= 2;
+  while (c.splits * 2 <= max_splits && workgroups(g, n_alpha, c) < 8192) c.splits *= 2;
   return c;
 }
 
@@ -133,6 +138,9 @@ cpi_status autotune_refocus(const float* gamma, const cpi_geometry* g, const dou
         for (int sp = 1; sp <= max_splits; sp *= 2) {
           RefocusConfig c{kp, rw, sp, mode, 3};
           if (!refocus_config_supported(c)) continue;
+          // one plane x 16 rows and two planes x 32 rows: the staged windows
+          // leave a CU four waves (measured 20-50x slower); not searched
+          if ((kp == 1 && rw == 16) || (kp == 2 && rw == 32)) continue;
           if (kp > 4 && kp / 2 >= n_alpha) continue;        // planes beyond n_alpha
           if (rw > 8 && rw / 2 >= g->out_h) continue;       // rows beyond out_h
           cands.push_back(c);

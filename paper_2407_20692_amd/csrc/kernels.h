@@ -23,23 +23,34 @@ hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t 
 hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
                        uint8_t* out, int64_t kpad_bits, int64_t* sums, bool swap02,
                        hipStream_t s);
+// One detector's part of a byte-frame ingest: its frames (n x npix bytes,
+// frame-major), operand rows (npix_pad rows), bit-row popcount sums and
+// byte sums (int64), and whether its bit rows take the FP4 bit exchange.
+// The byte-frame ingest kernels run both detectors' jobs in one launch.
+struct U8Job {
+  const uint8_t* frames;
+  int64_t npix, npix_pad;
+  uint8_t* out;
+  int64_t* sums;    // popcounts of the bit rows
+  int64_t* sums2;   // byte sums (non-binary data)
+  int swap02;
+};
 // Byte frames -> bit rows (bit = low bit of the byte) with per-pixel popcounts
 // added into sums, and the OR of every byte accumulated into stats[0].  The
 // rows and popcounts are the data exactly when stats[0] <= 1 (binary data);
 // stats[0] > 127 exactly when some byte exceeds 127.  swap02 as above.
-hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                      uint8_t* out, int64_t kpad_bits, int64_t* sums, uint32_t* stats,
-                      bool swap02, hipStream_t s);
+hipError_t u8_to_bits(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bits,
+                      uint32_t* stats, hipStream_t s);
 // Side-by-side sensor frames (frame_h rows of frame_w 1-bit pixels, A the left
 // half, B the right) -> BIT1 frames of the roi_w x roi_h region of interest at
 // (roi_x, roi_y) inside each half.  Sizes are validated by the caller.
 hipError_t split_sidebyside(const uint8_t* frames, int64_t n, int frame_w, int frame_h, int roi_x,
                             int roi_y, int roi_w, int roi_h, uint8_t* out_a, uint8_t* out_b,
                             hipStream_t s);
-// Per-pixel byte sums (int64, added into sums), executed only when
+// Per-pixel byte sums (int64, added into sums2), executed only when
 // stats[0] > 1.
-hipError_t u8_sums(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
-                   const uint32_t* stats, hipStream_t s);
+hipError_t u8_sums(const U8Job& a, const U8Job& b, int64_t n, const uint32_t* stats,
+                   hipStream_t s);
 // dst[i] = (stats[0] <= 1 ? from_bits : from_bytes)[i]; and dst[i] += the same.
 hipError_t select_i64(int64_t* dst, const int64_t* from_bits, const int64_t* from_bytes,
                       int64_t count, const uint32_t* stats, hipStream_t s);
@@ -47,9 +58,8 @@ hipError_t add_select_i64(int64_t* dst, const int64_t* from_bits, const int64_t*
                           int64_t count, const uint32_t* stats, hipStream_t s);
 // Byte frames -> int8 rows (row_bytes = kpad_bytes), executed only when
 // stats[0] > 1; values are offset by -128 when stats[0] > 127; pads are 0.
-hipError_t u8_to_bytes(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                       uint8_t* out, int64_t kpad_bytes, const uint32_t* stats,
-                       hipStream_t s);
+hipError_t u8_to_bytes(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bytes,
+                       const uint32_t* stats, hipStream_t s);
 
 // ---- int8 MFMA contraction with the exact epilogue -----------------------
 enum EpiMode : int {

@@ -198,13 +198,23 @@ __device__ __forceinline__ void bytes_transpose4(const uint32_t (&t)[4], uint32_
 }
 
 template <bool ALIGNED>
-__global__ __launch_bounds__(256) void k_u8_to_bits(
-    const uint8_t* __restrict__ frames, int64_t n, int64_t npix, int64_t npix_pad,
-    uint32_t* __restrict__ out, int64_t kw, int64_t nunits, int64_t units_per_slice,
-    unsigned long long* __restrict__ sums, uint32_t* __restrict__ stats, int swap02) {
+__global__ __launch_bounds__(256) void k_u8_to_bits(U8Job j0, U8Job j1, int64_t groups0,
+                                                    int64_t n, int64_t kw, int64_t nunits,
+                                                    int64_t units_per_slice,
+                                                    uint32_t* __restrict__ stats) {
+  // work-groups [0, groups0) take detector job j0, the rest job j1
+  const bool second = int64_t(blockIdx.x) >= groups0;
+  const uint8_t* __restrict__ frames = second ? j1.frames : j0.frames;
+  const int64_t npix = second ? j1.npix : j0.npix;
+  const int64_t npix_pad = second ? j1.npix_pad : j0.npix_pad;
+  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(second ? j1.out : j0.out);
+  unsigned long long* __restrict__ sums =
+      reinterpret_cast<unsigned long long*>(second ? j1.sums : j0.sums);
+  const int swap02 = second ? j1.swap02 : j0.swap02;
+  const int64_t blk = int64_t(blockIdx.x) - (second ? groups0 : 0);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t p0 = (int64_t(blockIdx.x) * 4 + wave) * 256;
+  const int64_t p0 = (blk * 4 + wave) * 256;
   if (p0 >= npix_pad || n <= 0) return;
   const int64_t px = p0 + 4 * lane;
   const int64_t u0 = int64_t(blockIdx.y) * units_per_slice;
@@ -304,15 +314,21 @@ __global__ __launch_bounds__(256) void k_u8_to_bits(
 // consecutive pixels: 16 threads cover them 16 bytes each, and the 16 thread
 // rows walk interleaved frames of the group's frame slice.  Partial sums are
 // reduced in LDS, so each pixel receives one atomic per work-group.
-__global__ __launch_bounds__(256) void k_u8_sums(const uint8_t* __restrict__ frames, int64_t n,
-                                                 int64_t npix, int64_t frames_per_slice,
-                                                 unsigned long long* __restrict__ sums,
+__global__ __launch_bounds__(256) void k_u8_sums(U8Job j0, U8Job j1, int64_t groups0, int64_t n,
+                                                 int64_t frames_per_slice,
                                                  const uint32_t* __restrict__ stats) {
   if (stats[0] <= 1u) return;
+  // work-groups [0, groups0) take detector job j0, the rest job j1
+  const bool second = int64_t(blockIdx.x) >= groups0;
+  const uint8_t* __restrict__ frames = second ? j1.frames : j0.frames;
+  const int64_t npix = second ? j1.npix : j0.npix;
+  unsigned long long* __restrict__ sums =
+      reinterpret_cast<unsigned long long*>(second ? j1.sums2 : j0.sums2);
+  const int64_t blk = int64_t(blockIdx.x) - (second ? groups0 : 0);
   __shared__ uint32_t red[16][256 + 1];
   const int t = threadIdx.x;
   const int col = t & 15, row = t >> 4;
-  const int64_t px = int64_t(blockIdx.x) * 256 + col * 16;
+  const int64_t px = blk * 256 + col * 16;
   const int64_t f0 = int64_t(blockIdx.y) * frames_per_slice;
   int64_t f1 = f0 + frames_per_slice;
   if (f1 > n) f1 = n;
@@ -341,7 +357,7 @@ __global__ __launch_bounds__(256) void k_u8_sums(const uint8_t* __restrict__ fra
 #pragma unroll
   for (int b = 0; b < 16; ++b) red[row][col * 16 + b] = s[b];
   __syncthreads();
-  const int64_t p = int64_t(blockIdx.x) * 256 + t;
+  const int64_t p = blk * 256 + t;
   unsigned long long tot = 0;
 #pragma unroll
   for (int r = 0; r < 16; ++r) tot += red[r][t];
@@ -362,17 +378,23 @@ __global__ void k_select_i64(int64_t* __restrict__ dst, const int64_t* __restric
 // value of "no photon" in the offset domain.  Work-groups stride over the
 // tiles, so that for binary data (nothing to do) only a few thousand
 // work-groups start and exit.
-__global__ __launch_bounds__(256) void k_u8_to_bytes(const uint8_t* __restrict__ frames,
-                                                     int64_t n, int64_t npix,
-                                                     uint8_t* __restrict__ out, int64_t kpad,
-                                                     int64_t tiles_p, int64_t tiles,
+__global__ __launch_bounds__(256) void k_u8_to_bytes(U8Job j0, U8Job j1, int64_t n, int64_t kpad,
+                                                     int64_t tiles_p0, int64_t tiles0,
+                                                     int64_t tiles_p1, int64_t tiles,
                                                      const uint32_t* __restrict__ stats) {
   const uint32_t mx = stats[0];
   if (mx <= 1u) return;
   const uint32_t xo = mx > 127u ? 0x80u : 0u;
   __shared__ uint8_t tile[64][64 + 4];
   const int t = threadIdx.x;
-  for (int64_t tt = blockIdx.x; tt < tiles; tt += gridDim.x) {
+  // tiles [0, tiles0) belong to detector job j0, the rest to job j1
+  for (int64_t tt0 = blockIdx.x; tt0 < tiles; tt0 += gridDim.x) {
+    const bool second = tt0 >= tiles0;
+    const uint8_t* __restrict__ frames = second ? j1.frames : j0.frames;
+    const int64_t npix = second ? j1.npix : j0.npix;
+    uint8_t* __restrict__ out = second ? j1.out : j0.out;
+    const int64_t tiles_p = second ? tiles_p1 : tiles_p0;
+    const int64_t tt = tt0 - (second ? tiles0 : 0);
     const int64_t p0 = (tt % tiles_p) * 64;
     const int64_t f0 = (tt / tiles_p) * 64;
     {
@@ -474,9 +496,10 @@ hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t n
   return hipGetLastError();
 }
 
-hipError_t u8_sums(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums,
-                   const uint32_t* stats, hipStream_t s) {
-  const int64_t groups = (npix + 255) / 256;
+hipError_t u8_sums(const U8Job& a, const U8Job& b, int64_t n, const uint32_t* stats,
+                   hipStream_t s) {
+  const int64_t groups0 = (a.npix + 255) / 256;
+  const int64_t groups = groups0 + (b.npix + 255) / 256;
   int64_t slices = (2048 + groups - 1) / groups;
   if (slices > (n + 15) / 16) slices = (n + 15) / 16;
   if (slices < 1) slices = 1;
@@ -484,9 +507,9 @@ hipError_t u8_sums(const uint8_t* frames, int64_t n, int64_t npix, int64_t* sums
   // a thread row adds at most fps/16 bytes of <= 255 per pixel in uint32
   if (fps > (int64_t(1) << 27)) fps = int64_t(1) << 27;
   slices = (n + fps - 1) / fps;
-  if (slices > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_u8_sums, dim3(unsigned(groups), unsigned(slices)), dim3(256), 0, s,
-                     frames, n, npix, fps, reinterpret_cast<unsigned long long*>(sums), stats);
+  if (slices > 65535 || groups > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_u8_sums, dim3(unsigned(groups), unsigned(slices)), dim3(256), 0, s, a, b,
+                     groups0, n, fps, stats);
   return hipGetLastError();
 }
 
@@ -504,33 +527,35 @@ hipError_t add_select_i64(int64_t* dst, const int64_t* from_bits, const int64_t*
   return hipGetLastError();
 }
 
-hipError_t u8_to_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                      uint8_t* out, int64_t kpad_bits, int64_t* sums, uint32_t* stats,
-                      bool swap02, hipStream_t s) {
-  // a wave covers 256 rows: the padded row count must be a multiple of it
-  if (npix_pad % 256 != 0 || npix_pad < npix) return hipErrorInvalidValue;
-  const int64_t waves = npix_pad / 256;
-  const int64_t groups = (waves + 3) / 4;
+hipError_t u8_to_bits(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bits,
+                      uint32_t* stats, hipStream_t s) {
+  // a wave covers 256 rows: the padded row counts must be multiples of it
+  for (const U8Job* j : {&a, &b})
+    if (j->npix_pad % 256 != 0 || j->npix_pad < j->npix) return hipErrorInvalidValue;
+  const int64_t groups0 = (a.npix_pad / 256 + 3) / 4;
+  const int64_t groups = groups0 + (b.npix_pad / 256 + 3) / 4;
+  const int64_t waves = (a.npix_pad + b.npix_pad) / 256;
   const int64_t nunits = kpad_bits / 128;
   const int64_t slices = slices_for(waves, nunits, 8192);
   const int64_t ups = (nunits + slices - 1) / slices;
   const int64_t used = (nunits + ups - 1) / ups;
-  auto* kern = (npix & 3) == 0 ? k_u8_to_bits<true> : k_u8_to_bits<false>;
-  hipLaunchKernelGGL(kern, dim3(unsigned(groups), unsigned(used)), dim3(256), 0, s, frames, n,
-                     npix, npix_pad, reinterpret_cast<uint32_t*>(out), kpad_bits / 32, nunits,
-                     ups, reinterpret_cast<unsigned long long*>(sums), stats, swap02 ? 1 : 0);
+  if (groups > 0x7fffffff) return hipErrorInvalidValue;
+  auto* kern = ((a.npix | b.npix) & 3) == 0 ? k_u8_to_bits<true> : k_u8_to_bits<false>;
+  hipLaunchKernelGGL(kern, dim3(unsigned(groups), unsigned(used)), dim3(256), 0, s, a, b, groups0,
+                     n, kpad_bits / 32, nunits, ups, stats);
   return hipGetLastError();
 }
 
-hipError_t u8_to_bytes(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                       uint8_t* out, int64_t kpad_bytes, const uint32_t* stats,
-                       hipStream_t s) {
-  const int64_t tiles_p = npix_pad / 64;
-  const int64_t tiles = tiles_p * (kpad_bytes / 64);
+hipError_t u8_to_bytes(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bytes,
+                       const uint32_t* stats, hipStream_t s) {
+  const int64_t fblocks = kpad_bytes / 64;
+  const int64_t tiles_p0 = a.npix_pad / 64, tiles_p1 = b.npix_pad / 64;
+  const int64_t tiles0 = tiles_p0 * fblocks;
+  const int64_t tiles = tiles0 + tiles_p1 * fblocks;
   const int64_t grid = tiles < 4096 ? tiles : 4096;
   if (grid < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_u8_to_bytes, dim3(unsigned(grid)), dim3(256), 0, s, frames, n, npix, out,
-                     kpad_bytes, tiles_p, tiles, stats);
+  hipLaunchKernelGGL(k_u8_to_bytes, dim3(unsigned(grid)), dim3(256), 0, s, a, b, n, kpad_bytes,
+                     tiles_p0, tiles0, tiles_p1, tiles, stats);
   return hipGetLastError();
 }
 

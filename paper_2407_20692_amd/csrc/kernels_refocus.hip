@@ -153,7 +153,8 @@ __global__ __launch_bounds__(256) void k_ref_ytab(GeomI g, const int32_t* __rest
   const float* ft = ftab + int64_t(plane) * stride;
   const int e_by = g.out_w + g.out_h + g.wb;
   const int64_t n = int64_t(g.hb) * g.out_h;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+  for (int64_t e = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; e < n;
+       e += int64_t(gridDim.y) * blockDim.x) {
     const int yb = int(e / g.out_h), yr = int(e % g.out_h);
     int y0 = it[g.out_w + yr] + it[e_by + yb];
     float fy = ft[g.out_w + yr] + ft[e_by + yb];
@@ -911,8 +912,10 @@ hipError_t refocus_tables(const RefGeom& g, const double* alphas, int first, int
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !ytab) return e;
   const GeomI gi{g.wa, g.ha, g.wb, g.hb, g.out_w, g.out_h};
-  hipLaunchKernelGGL(k_ref_ytab, dim3(unsigned(count)), dim3(256), 0, s, gi, itab, ftab, stride,
-                     first, count, static_cast<YEntry*>(ytab));
+  int64_t gy = (int64_t(g.hb) * g.out_h + 255) / 256;   // entries per plane / 256
+  if (gy > 64) gy = 64;
+  hipLaunchKernelGGL(k_ref_ytab, dim3(unsigned(count), unsigned(gy)), dim3(256), 0, s, gi, itab,
+                     ftab, stride, first, count, static_cast<YEntry*>(ytab));
   return hipGetLastError();
 }
 
