@@ -103,6 +103,21 @@ def test_refocus_validation(cpi):
     assert lib.cpi_refocus(fake, ctypes.byref(bad), al, 1, fake, fake, 1 << 30, None) == 1
     huge = (ctypes.c_double * 1)(1e12)
     assert lib.cpi_refocus(fake, ctypes.byref(g), huge, 1, fake, fake, 1 << 30, None) == 1
+    # explicit configurations: a null one is invalid, an unbuilt one unsupported
+    # (CPI_ERR_UNSUPPORTED = 2), both before any launch; argument checks as above
+    assert lib.cpi_refocus_tiled(fake, ctypes.byref(g), al, 1, fake, None, fake, 1 << 30,
+                                 None) == 1
+    for t in [(2, 8, 1, 0, 0), (8, 16, 1, 1, 1), (8, 32, 1, 1, 4), (8, 16, 0, 0, 0),
+              (8, 16, 17, 1, 2), (1, 16, 1, 0, 0)]:
+        tiles = cpi.RefocusTiles(*t)
+        assert lib.cpi_refocus_tiled(fake, ctypes.byref(g), al, 1, fake, ctypes.byref(tiles),
+                                     fake, 1 << 30, None) == 2, t
+    tiles = cpi.RefocusTiles(4, 16, 2, 1, 2)
+    assert lib.cpi_refocus_tiled(fake, ctypes.byref(g), al, 0, fake, ctypes.byref(tiles), fake,
+                                 1 << 30, None) == 1
+    out = cpi.RefocusTiles()
+    assert lib.cpi_refocus_get_tiles(ctypes.byref(g), 5, None) == 1
+    assert lib.cpi_refocus_get_tiles(ctypes.byref(g), 5, ctypes.byref(out)) == 0
 
 
 def test_stream_validation(cpi):
@@ -212,3 +227,42 @@ def test_memory_adaptive_workspace_host(cpi):
                                4096, None)
     assert st == 4
     assert b"blocks of 512 frames" in cpi.lib.cpi_last_error()
+
+
+_TILES_SCRIPT = """
+import sys
+sys.path.insert(0, {root!r})
+import paper_2407_20692_amd as cpi
+g = cpi.geometry_default(32, 32, 16, 16)
+print(*cpi.refocus_tiles(g, 5))
+"""
+
+
+def _tiles_with_cache(tmp_path, lines):
+    """refocus_tiles in a fresh process whose autotune cache file holds
+    `lines` (the cache is read once per process)."""
+    import subprocess
+    import sys
+
+    cache = tmp_path / "cache.txt"
+    cache.write_text("".join(line + "\n" for line in lines))
+    env = dict(os.environ, CPI_AUTOTUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", _TILES_SCRIPT.format(root=ROOT)], env=env,
+                       capture_output=True, text=True, timeout=300, check=True)
+    return tuple(int(v) for v in r.stdout.split())
+
+
+def test_autotune_cache_file(tmp_path):
+    """A cached configuration (planes per group, rows, view splits, kernel,
+    staged windows) is used for its shape; a file with a line in another
+    format or naming a configuration that is not built is ignored as a whole,
+    leaving the default (column-sum kernel, 4 planes x 16 rows, 2 stages).
+    Without a GPU the device part of the key is 'dev?'."""
+    key = "wa32_ha32_wb16_hb16_ow32_oh32_na5@dev?"
+    assert _tiles_with_cache(tmp_path, [f"{key} 8 8 2 1 3 123.0"]) == (8, 8, 2, 1, 3)
+    assert _tiles_with_cache(tmp_path, [f"{key} 16 16 4 0 0 99.5"]) == (16, 16, 4, 0, 0)
+    default = _tiles_with_cache(tmp_path, [])
+    assert default[:2] == (4, 16) and default[3:] == (1, 2) and 1 <= default[2] <= 16
+    # the earlier four-column format, an unbuilt shape, too many stages for LDS
+    for bad in [f"{key} 8 8 2 123.0", f"{key} 2 8 1 1 2 5.0", f"{key} 8 32 1 1 4 5.0"]:
+        assert _tiles_with_cache(tmp_path, [f"{key} 8 8 2 1 3 1.0", bad]) == default
