@@ -55,6 +55,8 @@ INT8_PEAK = 5.0e15          # dense int8 matrix-core ops/s, MI355X
 FP4_PEAK = 10.1e15          # dense FP4 (and FP6) matrix-core ops/s, MI355X
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemm_f4lds_da128_db64_n20000_pmc.txt")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_gemm.hip")
+REF_PMC_SUMMARY = os.path.join(ROOT, "profiles", "ref_sep_da128_db64_32planes_pmc.txt")
+REF_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_refocus.hip")
 
 
 def log(msg):
@@ -66,19 +68,21 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per contraction launch from the committed counter summary,
-    if it was taken on the current kernel source; else None."""
+def measured_traffic(summary=None, source=None):
+    """HBM bytes per launch from a committed counter summary (the contraction's
+    by default), if it was taken on the current kernel source; else None."""
+    summary = summary or PMC_SUMMARY
+    source = source or GEMM_SOURCE
     fields = {}
     try:
-        with open(PMC_SUMMARY) as f:
+        with open(summary) as f:
             for line in f:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     fields[k.strip()] = v.strip()
     except OSError:
         return None
-    if fields.get("kernel_source_sha256_16") != source_hash(GEMM_SOURCE):
+    if fields.get("kernel_source_sha256_16") != source_hash(source):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -699,6 +703,9 @@ def main():
         "frac": ref_bw / 8000.0,
         "algorithmic_bytes_per_launch": ref_bytes,
         "launch_ms": groups["refocus_batched"],
+        # HBM bytes per launch of the tuned column-sum kernel from rocprofv3
+        # FETCH_SIZE / WRITE_SIZE (committed summary; None once the source changed)
+        "traffic": measured_traffic(REF_PMC_SUMMARY, REF_SOURCE) if tiles[3] == 1 else None,
         "note": "footprint bytes of every plane, counted exactly; planes share each staged view "
                 "window, so the kernel is bound by LDS reads and VALU rather than HBM",
     }
@@ -725,8 +732,10 @@ def main():
         "launch_ms": ms_gemm_int8,
     }
 
-    if large:
-        line["roofline"]["traffic"] = None   # counters were taken on the paper-like workload
+    if large or paper:
+        # counters were taken on the paper-like workload
+        line["roofline"]["traffic"] = None
+        line["roofline_refocus"]["traffic"] = None
     if not args.no_stream and not large:
         ws = WORKLOADS[STREAM_WORKLOAD]
         log(f"bench: streaming {args.stream_chunks} chunks of {ws.chunk}")

@@ -426,8 +426,11 @@ __device__ __forceinline__ void wait_vmcnt() {
 // wave's column integer part and fraction, the window's first column and
 // width) sit one per lane for 64 lens-plane columns at a time and are read
 // with readlane; the row entries of the tile sit one per lane and are loaded
-// once per y_b.  A lens-plane row whose windows do not fit is summed from
-// direct paired gathers, as in k_ref_batched.
+// once per y_b.  A lens-plane row whose windows do not fit, and every row of
+// a group whose planes touch more view rows than the registers hold
+// (|alpha| above about 2), is summed from direct paired gathers, as in
+// k_ref_batched.
+
 // Window rows per stage (the union over the group's planes, whose shifts
 // differ): 2 RW, plus 32 for groups of 8 or more planes; a multiple of 2 NW.
 constexpr int sep_window_rows(int nw, int rw) {
