@@ -140,9 +140,20 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
   uint32_t* stats = reinterpret_cast<uint32_t*>(ws + pl.off_stats);
   uint8_t* op_a = ws + pl.off_op_a;
   uint8_t* op_b = ws + pl.off_op_b;
-  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum_a), pl.pa_pad, 0, st), "fill");
-  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum_b), pl.pb_pad, 0, st), "fill");
-  CPI_HIP(cpi::fill_u32(stats, 64, 0, st), "fill");
+  int64_t* sum2_a = reinterpret_cast<int64_t*>(ws + pl.off_sum2_a);
+  int64_t* sum2_b = reinterpret_cast<int64_t*>(ws + pl.off_sum2_b);
+  {
+    // popcount sums, the 64 flag words and (byte frames) the byte sums
+    cpi::ZeroRanges z;
+    z.add(sum_a, pl.pa_pad);
+    z.add(sum_b, pl.pb_pad);
+    z.add(stats, 32);
+    if (pl.fmt != CPI_FRAMES_BIT1) {
+      z.add(sum2_a, pl.pa_pad);
+      z.add(sum2_b, pl.pb_pad);
+    }
+    CPI_HIP(cpi::zero_ranges(z, st), "fill");
+  }
 
   cpi::GemmArgs g;
   g.opm = op_b;
@@ -184,12 +195,8 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
   // Binary data (OR <= 1) is then complete; otherwise the device also runs
   // the byte-sum and int8-row passes and the byte contraction, and skips the
   // bit contraction.  Both branches are enqueued; no host synchronisation.
-  int64_t* sum2_a = reinterpret_cast<int64_t*>(ws + pl.off_sum2_a);
-  int64_t* sum2_b = reinterpret_cast<int64_t*>(ws + pl.off_sum2_b);
   {
     ProfScope ps("ingest", st);
-    CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum2_a), pl.pa_pad, 0, st), "fill");
-    CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(sum2_b), pl.pb_pad, 0, st), "fill");
     const cpi::U8Job ja{fa, pl.pa, pl.pa_pad, op_a, sum_a, sum2_a, 0};
     const cpi::U8Job jb{fb, pl.pb, pl.pb_pad, op_b, sum_b, sum2_b, fp4 ? 1 : 0};
     CPI_HIP(cpi::u8_to_bits(ja, jb, pl.n, pl.kpad_bits, stats, st), "ingest");
@@ -854,9 +861,18 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
   int64_t* tot_a = reinterpret_cast<int64_t*>(h->ws + h->plan.off_sum_a);
   int64_t* tot_b = reinterpret_cast<int64_t*>(h->ws + h->plan.off_sum_b);
   hipStream_t st = h->st;
-  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum_a), cp.pa_pad, 0, st), "fill");
-  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum_b), cp.pb_pad, 0, st), "fill");
-  CPI_HIP(cpi::fill_u32(stats, 64, 0, st), "fill");
+  {
+    // chunk popcount sums, the 64 flag words and (byte frames) the byte sums
+    cpi::ZeroRanges z;
+    z.add(csum_a, cp.pa_pad);
+    z.add(csum_b, cp.pb_pad);
+    z.add(stats, 32);
+    if (h->fmt != CPI_FRAMES_BIT1) {
+      z.add(cws + mp.off_sum2_a, cp.pa_pad);
+      z.add(cws + mp.off_sum2_b, cp.pb_pad);
+    }
+    CPI_HIP(cpi::zero_ranges(z, st), "fill");
+  }
 
   cpi::GemmArgs g;
   g.opm = op_b;
@@ -898,8 +914,6 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
     int64_t* csum2_b = reinterpret_cast<int64_t*>(cws + mp.off_sum2_b);
     {
       ProfScope ps("ingest", st);
-      CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum2_a), cp.pa_pad, 0, st), "fill");
-      CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(csum2_b), cp.pb_pad, 0, st), "fill");
       const cpi::U8Job ja{fa, h->pa, cp.pa_pad, op_a, csum_a, csum2_a, 0};
       const cpi::U8Job jb{fb, h->pb, cp.pb_pad, op_b, csum_b, csum2_b, fp4 ? 1 : 0};
       CPI_HIP(cpi::u8_to_bits(ja, jb, k, cp.kpad_bits, stats, st), "ingest");

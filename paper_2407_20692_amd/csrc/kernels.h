@@ -13,6 +13,19 @@ namespace cpi {
 // ---- fills --------------------------------------------------------------
 hipError_t fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
 hipError_t fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
+// Up to kZeroRanges ranges of 64-bit words (8-byte aligned) zeroed in one launch.
+constexpr int kZeroRanges = 6;
+struct ZeroRanges {
+  uint64_t* ptr[kZeroRanges];
+  int64_t words[kZeroRanges];
+  int count = 0;
+  void add(void* p, int64_t n) {
+    ptr[count] = static_cast<uint64_t*>(p);
+    words[count] = n;
+    ++count;
+  }
+};
+hipError_t zero_ranges(const ZeroRanges& z, hipStream_t s);
 hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t s);
 
 // ---- ingest: frame-major frames -> pixel-major operands ------------------

@@ -33,6 +33,18 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t count, uint64_t v) 
     p[i] = v;
 }
 
+// Zeroes up to kZeroRanges ranges of 64-bit words in one launch; block row
+// blockIdx.y takes range blockIdx.y.
+__global__ void k_zero_ranges(ZeroRanges z) {
+  const int k = blockIdx.y;
+  if (k >= z.count) return;
+  uint64_t* __restrict__ p = z.ptr[k];
+  const int64_t n = z.words[k];
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
 __global__ void k_add_i64(int64_t* __restrict__ dst, const int64_t* __restrict__ src,
                           int64_t count) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
@@ -474,6 +486,16 @@ hipError_t fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s) {
 
 hipError_t fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t zero_ranges(const ZeroRanges& z, hipStream_t s) {
+  if (z.count < 1 || z.count > kZeroRanges) return hipErrorInvalidValue;
+  int64_t most = 0;
+  for (int k = 0; k < z.count; ++k) most = z.words[k] > most ? z.words[k] : most;
+  if (most < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_ranges, dim3(grid_for(most, 256), unsigned(z.count)), dim3(256), 0, s,
+                     z);
   return hipGetLastError();
 }
 
