@@ -251,7 +251,7 @@ def resampled_refocus_bench(cpi, torch, np, dev, g32, geo, w, alphas, reps=3):
                               "peak": 8000.0, "unit": "GB/s",
                               "frac": alg / (t_res * 1e-3) / 8e12,
                               "algorithmic_bytes": alg},
-        "config_kp_rw_splits_kernel": list(cpi.refocus_tiles(gs, na)),
+        "config_kp_rw_splits_kernel_stages": list(cpi.refocus_tiles(gs, na)),
     }
 
 
@@ -661,7 +661,7 @@ def main():
         "correlate": {"ms": ms_corr, "ingest_ms": groups["ingest"], "gemm_ms": groups["gemm"],
                       "pixel_pair_frames_per_s": pairs / (ms_corr * 1e-3)},
         "refocus": {"ms": ms_ref, "planes_per_s": len(alphas) / (ms_ref * 1e-3),
-                    "config_kp_rw_splits_kernel": list(cpi.refocus_tiles(geo, len(alphas)))},
+                    "config_kp_rw_splits_kernel_stages": list(cpi.refocus_tiles(geo, len(alphas)))},
         "fp32_plain": {
             "correlate_ms": ms_corr_p if plain_corr else None,
             "unpack_ms": pg["unpack_f32"] if plain_corr else None,
@@ -695,7 +695,7 @@ def main():
         "kernel": ("k_ref_sep (planes batched per work-group, LDS-staged view windows, column "
                    "interpolants summed over x_b before the row weights)" if tiles[3] == 1 else
                    "k_ref_batched (planes batched per work-group, LDS-staged view windows)"),
-        "tiles_kp_rw_splits_kernel": list(tiles),
+        "tiles_kp_rw_splits_kernel_stages": list(tiles),
         "bound": "hbm",
         "achieved": ref_bw,
         "peak": 8000.0,
@@ -709,18 +709,24 @@ def main():
         "note": "footprint bytes of every plane, counted exactly; planes share each staged view "
                 "window, so the kernel is bound by LDS reads and VALU rather than HBM",
     }
-    # the other batched-refocus kernel with the same tiles (same inputs)
-    other = (tiles[0], tiles[1], tiles[2], 1 - tiles[3])
-    cpi.refocus_tiled(g32, geo, alphas, out, other, workspace=ws_r)
-    torch.cuda.synchronize()
-    cpi.profile_begin()
-    for _ in range(max(3, args.steps // 4)):
+    # the other batched-refocus kernel with the same tiles (same inputs), where
+    # it is built for them (the column-sum kernel also takes shapes the
+    # per-row kernel does not)
+    other = (tiles[0], tiles[1], tiles[2], 1 - tiles[3], 2)
+    try:
         cpi.refocus_tiled(g32, geo, alphas, out, other, workspace=ws_r)
-    torch.cuda.synchronize()
-    cpi.profile_end()
-    cnt, tot = cpi.profile_query("refocus_batched")
-    line["roofline_refocus"]["other_kernel_same_tiles"] = {
-        "tiles_kp_rw_splits_kernel": list(other), "launch_ms": tot / max(cnt, 1)}
+    except cpi.CpiError:
+        other = None
+    if other is not None:
+        torch.cuda.synchronize()
+        cpi.profile_begin()
+        for _ in range(max(3, args.steps // 4)):
+            cpi.refocus_tiled(g32, geo, alphas, out, other, workspace=ws_r)
+        torch.cuda.synchronize()
+        cpi.profile_end()
+        cnt, tot = cpi.profile_query("refocus_batched")
+        line["roofline_refocus"]["other_kernel_same_tiles"] = {
+            "tiles_kp_rw_splits_kernel_stages": list(other), "launch_ms": tot / max(cnt, 1)}
     achieved8 = gemm_ops / (ms_gemm_int8 * 1e-3) / 1e12
     line["roofline_int8"] = {
         "kernel": "k_gemm<bits> (int8 matrix-core contraction, exact epilogue)",
@@ -810,7 +816,7 @@ def main():
             cpi.profile_end()
             t = sum(cpi.profile_query(gname)[1] for gname in ("refocus_tables", "refocus_batched")) / 3
             counts[str(na)] = {"ms": t, "planes_per_s": na / (t * 1e-3),
-                               "config_kp_rw_splits_kernel": list(cpi.refocus_tiles(geo, na))}
+                               "config_kp_rw_splits_kernel_stages": list(cpi.refocus_tiles(geo, na))}
             del o, ws_n
         line["refocus_plane_counts"] = counts
         line["refocus_resampled"] = resampled_refocus_bench(cpi, torch, np, dev, g32, geo, w,
