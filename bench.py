@@ -706,8 +706,10 @@ def main():
         # HBM bytes per launch of the tuned column-sum kernel from rocprofv3
         # FETCH_SIZE / WRITE_SIZE (committed summary; None once the source changed)
         "traffic": measured_traffic(REF_PMC_SUMMARY, REF_SOURCE) if tiles[3] == 1 else None,
-        "note": "footprint bytes of every plane, counted exactly; planes share each staged view "
-                "window, so the kernel is bound by LDS reads and VALU rather than HBM",
+        "note": "achieved = footprint bytes of every plane (counted exactly) / launch time; planes "
+                "share each staged view window, so this exceeds what HBM moves (traffic, from "
+                "rocprofv3 counters) and the kernel is bound by LDS reads and per-view latency "
+                "rather than HBM",
     }
     # the other batched-refocus kernel with the same tiles (same inputs), where
     # it is built for them (the column-sum kernel also takes shapes the
@@ -742,6 +744,12 @@ def main():
         # counters were taken on the paper-like workload
         line["roofline"]["traffic"] = None
         line["roofline_refocus"]["traffic"] = None
+    rt = line["roofline_refocus"]["traffic"]
+    if rt:
+        # what the measured HBM traffic amounts to at this launch time
+        bw = rt / (groups["refocus_batched"] * 1e-3) / 1e9
+        line["roofline_refocus"]["traffic_GBps"] = bw
+        line["roofline_refocus"]["traffic_frac"] = bw / 8000.0
     if not args.no_stream and not large:
         ws = WORKLOADS[STREAM_WORKLOAD]
         log(f"bench: streaming {args.stream_chunks} chunks of {ws.chunk}")
