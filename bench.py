@@ -68,9 +68,10 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(summary=None, source=None):
+def measured_traffic(summary=None, source=None, tiles=None):
     """HBM bytes per launch from a committed counter summary (the contraction's
-    by default), if it was taken on the current kernel source; else None."""
+    by default), if it was taken on the current kernel source (and, for the
+    refocus, with these tiles); else None."""
     summary = summary or PMC_SUMMARY
     source = source or GEMM_SOURCE
     fields = {}
@@ -83,6 +84,9 @@ def measured_traffic(summary=None, source=None):
     except OSError:
         return None
     if fields.get("kernel_source_sha256_16") != source_hash(source):
+        return None
+    if tiles is not None and fields.get("tiles_kp_rw_splits_kernel_stages") != " ".join(
+            str(int(v)) for v in tiles):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -704,8 +708,9 @@ def main():
         "algorithmic_bytes_per_launch": ref_bytes,
         "launch_ms": groups["refocus_batched"],
         # HBM bytes per launch of the tuned column-sum kernel from rocprofv3
-        # FETCH_SIZE / WRITE_SIZE (committed summary; None once the source changed)
-        "traffic": measured_traffic(REF_PMC_SUMMARY, REF_SOURCE) if tiles[3] == 1 else None,
+        # FETCH_SIZE / WRITE_SIZE (committed summary; None once the source
+        # changed or the tuned tiles differ from the profiled ones)
+        "traffic": measured_traffic(REF_PMC_SUMMARY, REF_SOURCE, tiles),
         "note": "achieved = footprint bytes of every plane (counted exactly) / launch time; planes "
                 "share each staged view window, so this exceeds what HBM moves (traffic, from "
                 "rocprofv3 counters) and the kernel is bound by LDS reads and per-view latency "
