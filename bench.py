@@ -85,12 +85,12 @@ def measured_traffic(summary=None, source=None, tiles=None):
         return None
     if fields.get("kernel_source_sha256_16") != source_hash(source):
         return None
-    if tiles is not None and fields.get("tiles_kp_rw_splits_kernel_stages") != " ".join(
-            str(int(v)) for v in tiles):
-        return None
+    key = "hbm_bytes_per_launch"
+    if tiles is not None:
+        key = "hbm_bytes_per_launch_tiles " + " ".join(str(int(v)) for v in tiles)
     try:
-        return float(fields["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+        return float(fields[key].split()[0])
+    except (KeyError, ValueError, IndexError):
         return None
 
 
