@@ -16,9 +16,12 @@
 // taps and their weights.
 //
 // Summation is blocked: samples are summed over x_b for one y_b, and those
-// row sums are summed over y_b (and, for the batched kernel, over view-row
+// row sums are summed over y_b (and, for the batched kernels, over view-row
 // splits in a fixed order), so the result is bitwise reproducible for a
-// given configuration.
+// given configuration.  Three kernels evaluate the sum: k_ref_plain (one
+// plane per launch, direct gathers), k_ref_batched (many planes per launch,
+// each output row interpolating its view rows) and k_ref_sep (many planes
+// per launch, column interpolants summed over x_b before the row weights).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
