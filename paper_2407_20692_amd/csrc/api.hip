@@ -177,10 +177,9 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
   if (pl.fmt == CPI_FRAMES_BIT1) {
     {
       ProfScope ps("ingest", st);
-      CPI_HIP(cpi::ingest_bits(fa, pl.n, pl.pa, pl.pa_pad, op_a, pl.kpad_bits, sum_a, false, st),
-              "ingest");
-      CPI_HIP(cpi::ingest_bits(fb, pl.n, pl.pb, pl.pb_pad, op_b, pl.kpad_bits, sum_b, fp4, st),
-              "ingest");
+      const cpi::IngestJob ja{fa, pl.pa, pl.pa_pad, op_a, sum_a, nullptr, 0};
+      const cpi::IngestJob jb{fb, pl.pb, pl.pb_pad, op_b, sum_b, nullptr, fp4 ? 1 : 0};
+      CPI_HIP(cpi::ingest_bits(ja, jb, pl.n, pl.kpad_bits, st), "ingest");
     }
     g.row_bytes = pl.row_bytes_bits;
     g.kblocks = pl.kpad_bits / cpi::kBitBlock;
@@ -197,8 +196,8 @@ cpi_status enqueue_correlate(const cpi::CorrPlan& pl, const uint8_t* fa, const u
   // bit contraction.  Both branches are enqueued; no host synchronisation.
   {
     ProfScope ps("ingest", st);
-    const cpi::U8Job ja{fa, pl.pa, pl.pa_pad, op_a, sum_a, sum2_a, 0};
-    const cpi::U8Job jb{fb, pl.pb, pl.pb_pad, op_b, sum_b, sum2_b, fp4 ? 1 : 0};
+    const cpi::IngestJob ja{fa, pl.pa, pl.pa_pad, op_a, sum_a, sum2_a, 0};
+    const cpi::IngestJob jb{fb, pl.pb, pl.pb_pad, op_b, sum_b, sum2_b, fp4 ? 1 : 0};
     CPI_HIP(cpi::u8_to_bits(ja, jb, pl.n, pl.kpad_bits, stats, st), "ingest");
     CPI_HIP(cpi::u8_sums(ja, jb, pl.n, stats, st), "sums");
     CPI_HIP(cpi::u8_to_bytes(ja, jb, pl.n, pl.kpad_bytes, stats, st), "ingest");
@@ -896,10 +895,9 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
   if (h->fmt == CPI_FRAMES_BIT1) {
     {
       ProfScope ps("ingest", st);
-      CPI_HIP(cpi::ingest_bits(fa, k, h->pa, cp.pa_pad, op_a, cp.kpad_bits, csum_a, false, st),
-              "ingest");
-      CPI_HIP(cpi::ingest_bits(fb, k, h->pb, cp.pb_pad, op_b, cp.kpad_bits, csum_b, fp4, st),
-              "ingest");
+      const cpi::IngestJob ja{fa, h->pa, cp.pa_pad, op_a, csum_a, nullptr, 0};
+      const cpi::IngestJob jb{fb, h->pb, cp.pb_pad, op_b, csum_b, nullptr, fp4 ? 1 : 0};
+      CPI_HIP(cpi::ingest_bits(ja, jb, k, cp.kpad_bits, st), "ingest");
       CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
       CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
     }
@@ -914,8 +912,8 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
     int64_t* csum2_b = reinterpret_cast<int64_t*>(cws + mp.off_sum2_b);
     {
       ProfScope ps("ingest", st);
-      const cpi::U8Job ja{fa, h->pa, cp.pa_pad, op_a, csum_a, csum2_a, 0};
-      const cpi::U8Job jb{fb, h->pb, cp.pb_pad, op_b, csum_b, csum2_b, fp4 ? 1 : 0};
+      const cpi::IngestJob ja{fa, h->pa, cp.pa_pad, op_a, csum_a, csum2_a, 0};
+      const cpi::IngestJob jb{fb, h->pb, cp.pb_pad, op_b, csum_b, csum2_b, fp4 ? 1 : 0};
       CPI_HIP(cpi::u8_to_bits(ja, jb, k, cp.kpad_bits, stats, st), "ingest");
       CPI_HIP(cpi::u8_sums(ja, jb, k, stats, st), "sums");
       CPI_HIP(cpi::add_select_i64(tot_a, csum_a, csum2_a, cp.pa_pad, stats, st), "sums");

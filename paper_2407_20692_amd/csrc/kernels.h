@@ -29,18 +29,14 @@ hipError_t zero_ranges(const ZeroRanges& z, hipStream_t s);
 hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t s);
 
 // ---- ingest: frame-major frames -> pixel-major operands ------------------
-// Packed-bit frames -> bit rows (row_bytes = kpad_bits/8), per-pixel popcounts
-// added into sums (int64).  Rows [npix, npix_pad) are written too.  swap02:
-// bits 0 and 2 of every 4-bit group of each row word are exchanged (the
-// layout of the M operand of the FP4 contraction).
-hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                       uint8_t* out, int64_t kpad_bits, int64_t* sums, bool swap02,
-                       hipStream_t s);
-// One detector's part of a byte-frame ingest: its frames (n x npix bytes,
-// frame-major), operand rows (npix_pad rows), bit-row popcount sums and
-// byte sums (int64), and whether its bit rows take the FP4 bit exchange.
-// The byte-frame ingest kernels run both detectors' jobs in one launch.
-struct U8Job {
+// One detector's part of an ingest: its frames (n frames of npix pixels,
+// frame-major: bytes, or bits packed 8 per byte with each frame padded to
+// whole bytes), operand rows (npix_pad rows), bit-row popcount sums and byte
+// sums (int64), and whether its bit rows take the FP4 bit exchange (swap02:
+// bits 0 and 2 of every 4-bit group of each row word are exchanged, the
+// layout of the M operand of the FP4 contraction).  The ingest kernels run
+// both detectors' jobs in one launch.
+struct IngestJob {
   const uint8_t* frames;
   int64_t npix, npix_pad;
   uint8_t* out;
@@ -48,11 +44,15 @@ struct U8Job {
   int64_t* sums2;   // byte sums (non-binary data)
   int swap02;
 };
+// Packed-bit frames -> bit rows (row_bytes = kpad_bits/8), per-pixel popcounts
+// added into sums (int64).  Rows [npix, npix_pad) are written too.
+hipError_t ingest_bits(const IngestJob& a, const IngestJob& b, int64_t n, int64_t kpad_bits,
+                       hipStream_t s);
 // Byte frames -> bit rows (bit = low bit of the byte) with per-pixel popcounts
 // added into sums, and the OR of every byte accumulated into stats[0].  The
 // rows and popcounts are the data exactly when stats[0] <= 1 (binary data);
 // stats[0] > 127 exactly when some byte exceeds 127.  swap02 as above.
-hipError_t u8_to_bits(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bits,
+hipError_t u8_to_bits(const IngestJob& a, const IngestJob& b, int64_t n, int64_t kpad_bits,
                       uint32_t* stats, hipStream_t s);
 // Side-by-side sensor frames (frame_h rows of frame_w 1-bit pixels, A the left
 // half, B the right) -> BIT1 frames of the roi_w x roi_h region of interest at
@@ -62,7 +62,7 @@ hipError_t split_sidebyside(const uint8_t* frames, int64_t n, int frame_w, int f
                             hipStream_t s);
 // Per-pixel byte sums (int64, added into sums2), executed only when
 // stats[0] > 1.
-hipError_t u8_sums(const U8Job& a, const U8Job& b, int64_t n, const uint32_t* stats,
+hipError_t u8_sums(const IngestJob& a, const IngestJob& b, int64_t n, const uint32_t* stats,
                    hipStream_t s);
 // dst[i] = (stats[0] <= 1 ? from_bits : from_bytes)[i]; and dst[i] += the same.
 hipError_t select_i64(int64_t* dst, const int64_t* from_bits, const int64_t* from_bytes,
@@ -71,7 +71,7 @@ hipError_t add_select_i64(int64_t* dst, const int64_t* from_bits, const int64_t*
                           int64_t count, const uint32_t* stats, hipStream_t s);
 // Byte frames -> int8 rows (row_bytes = kpad_bytes), executed only when
 // stats[0] > 1; values are offset by -128 when stats[0] > 127; pads are 0.
-hipError_t u8_to_bytes(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bytes,
+hipError_t u8_to_bytes(const IngestJob& a, const IngestJob& b, int64_t n, int64_t kpad_bytes,
                        const uint32_t* stats, hipStream_t s);
 
 // ---- int8 MFMA contraction with the exact epilogue -----------------------

@@ -125,12 +125,19 @@ unsigned grid_for(int64_t count, int threads) {
 // f0 + l; one wave ballot per pixel then yields that pixel's 64 frame bits,
 // which a lane select drops into the register of the lane that owns the pixel
 // (pixel j -> lane j % 64, half j / 64).
-__global__ __launch_bounds__(64) void k_ingest_bits(
-    const uint8_t* __restrict__ frames, int64_t n, int64_t fbytes, uint32_t* __restrict__ out,
-    int64_t kw, int64_t nblocks, int64_t blocks_per_slice,
-    unsigned long long* __restrict__ sums, int swap02) {
+__global__ __launch_bounds__(64) void k_ingest_bits(IngestJob j0, IngestJob j1, int64_t groups0,
+                                                   int64_t n, int64_t kw, int64_t nblocks,
+                                                   int64_t blocks_per_slice) {
+  // work-groups [0, groups0) take detector job j0, the rest job j1
+  const bool second = int64_t(blockIdx.x) >= groups0;
+  const uint8_t* __restrict__ frames = second ? j1.frames : j0.frames;
+  const int64_t fbytes = ((second ? j1.npix : j0.npix) + 7) / 8;
+  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(second ? j1.out : j0.out);
+  unsigned long long* __restrict__ sums =
+      reinterpret_cast<unsigned long long*>(second ? j1.sums : j0.sums);
+  const int swap02 = second ? j1.swap02 : j0.swap02;
   const int lane = threadIdx.x;
-  const int64_t p0 = int64_t(blockIdx.x) * 128;
+  const int64_t p0 = (int64_t(blockIdx.x) - (second ? groups0 : 0)) * 128;
   const int64_t byte0 = p0 >> 3;
   const int64_t kb0 = int64_t(blockIdx.y) * blocks_per_slice;
   int64_t kb1 = kb0 + blocks_per_slice;
@@ -210,7 +217,7 @@ __device__ __forceinline__ void bytes_transpose4(const uint32_t (&t)[4], uint32_
 }
 
 template <bool ALIGNED>
-__global__ __launch_bounds__(256) void k_u8_to_bits(U8Job j0, U8Job j1, int64_t groups0,
+__global__ __launch_bounds__(256) void k_u8_to_bits(IngestJob j0, IngestJob j1, int64_t groups0,
                                                     int64_t n, int64_t kw, int64_t nunits,
                                                     int64_t units_per_slice,
                                                     uint32_t* __restrict__ stats) {
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(256) void k_u8_to_bits(U8Job j0, U8Job j1, int64_t 
 // consecutive pixels: 16 threads cover them 16 bytes each, and the 16 thread
 // rows walk interleaved frames of the group's frame slice.  Partial sums are
 // reduced in LDS, so each pixel receives one atomic per work-group.
-__global__ __launch_bounds__(256) void k_u8_sums(U8Job j0, U8Job j1, int64_t groups0, int64_t n,
+__global__ __launch_bounds__(256) void k_u8_sums(IngestJob j0, IngestJob j1, int64_t groups0, int64_t n,
                                                  int64_t frames_per_slice,
                                                  const uint32_t* __restrict__ stats) {
   if (stats[0] <= 1u) return;
@@ -390,7 +397,7 @@ __global__ void k_select_i64(int64_t* __restrict__ dst, const int64_t* __restric
 // value of "no photon" in the offset domain.  Work-groups stride over the
 // tiles, so that for binary data (nothing to do) only a few thousand
 // work-groups start and exit.
-__global__ __launch_bounds__(256) void k_u8_to_bytes(U8Job j0, U8Job j1, int64_t n, int64_t kpad,
+__global__ __launch_bounds__(256) void k_u8_to_bytes(IngestJob j0, IngestJob j1, int64_t n, int64_t kpad,
                                                      int64_t tiles_p0, int64_t tiles0,
                                                      int64_t tiles_p1, int64_t tiles,
                                                      const uint32_t* __restrict__ stats) {
@@ -504,21 +511,24 @@ hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t ingest_bits(const uint8_t* frames, int64_t n, int64_t npix, int64_t npix_pad,
-                       uint8_t* out, int64_t kpad_bits, int64_t* sums, bool swap02,
+hipError_t ingest_bits(const IngestJob& a, const IngestJob& b, int64_t n, int64_t kpad_bits,
                        hipStream_t s) {
-  const int64_t groups = npix_pad / 128;
+  // a work-group covers 128 rows: the padded row counts must be multiples of it
+  for (const IngestJob* j : {&a, &b})
+    if (j->npix_pad % 128 != 0 || j->npix_pad < j->npix) return hipErrorInvalidValue;
+  const int64_t groups0 = a.npix_pad / 128;
+  const int64_t groups = groups0 + b.npix_pad / 128;
   const int64_t nblocks = kpad_bits / 512;
   const int64_t slices = slices_for(groups, nblocks, 8192);
   const int64_t bps = (nblocks + slices - 1) / slices;
   const int64_t used = (nblocks + bps - 1) / bps;
-  hipLaunchKernelGGL(k_ingest_bits, dim3(unsigned(groups), unsigned(used)), dim3(64), 0, s,
-                     frames, n, (npix + 7) / 8, reinterpret_cast<uint32_t*>(out), kpad_bits / 32,
-                     nblocks, bps, reinterpret_cast<unsigned long long*>(sums), swap02 ? 1 : 0);
+  if (groups > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ingest_bits, dim3(unsigned(groups), unsigned(used)), dim3(64), 0, s, a, b,
+                     groups0, n, kpad_bits / 32, nblocks, bps);
   return hipGetLastError();
 }
 
-hipError_t u8_sums(const U8Job& a, const U8Job& b, int64_t n, const uint32_t* stats,
+hipError_t u8_sums(const IngestJob& a, const IngestJob& b, int64_t n, const uint32_t* stats,
                    hipStream_t s) {
   const int64_t groups0 = (a.npix + 255) / 256;
   const int64_t groups = groups0 + (b.npix + 255) / 256;
@@ -549,10 +559,10 @@ hipError_t add_select_i64(int64_t* dst, const int64_t* from_bits, const int64_t*
   return hipGetLastError();
 }
 
-hipError_t u8_to_bits(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bits,
+hipError_t u8_to_bits(const IngestJob& a, const IngestJob& b, int64_t n, int64_t kpad_bits,
                       uint32_t* stats, hipStream_t s) {
   // a wave covers 256 rows: the padded row counts must be multiples of it
-  for (const U8Job* j : {&a, &b})
+  for (const IngestJob* j : {&a, &b})
     if (j->npix_pad % 256 != 0 || j->npix_pad < j->npix) return hipErrorInvalidValue;
   const int64_t groups0 = (a.npix_pad / 256 + 3) / 4;
   const int64_t groups = groups0 + (b.npix_pad / 256 + 3) / 4;
@@ -568,7 +578,7 @@ hipError_t u8_to_bits(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bi
   return hipGetLastError();
 }
 
-hipError_t u8_to_bytes(const U8Job& a, const U8Job& b, int64_t n, int64_t kpad_bytes,
+hipError_t u8_to_bytes(const IngestJob& a, const IngestJob& b, int64_t n, int64_t kpad_bytes,
                        const uint32_t* stats, hipStream_t s) {
   const int64_t fblocks = kpad_bytes / 64;
   const int64_t tiles_p0 = a.npix_pad / 64, tiles_p1 = b.npix_pad / 64;
