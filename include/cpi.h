@@ -196,7 +196,9 @@ typedef enum { CPI_REFOCUS_ROWS = 0, CPI_REFOCUS_COLUMN_SUMS = 1 } cpi_refocus_k
  * both kernels and also (1, 16), (2, 16), (2, 32), (4, 32) for
  * CPI_REFOCUS_COLUMN_SUMS; view-row splits (1..16);
  * the kernel (cpi_refocus_kernel) and, for CPI_REFOCUS_COLUMN_SUMS, the number
- * of view windows staged in LDS (2, 3 or 4; ignored by CPI_REFOCUS_ROWS). */
+ * of view windows staged in LDS (2, 3 or 4, and 2 or 3 for 8 planes x 32 rows,
+ * whose four windows exceed a CU's LDS; ignored by CPI_REFOCUS_ROWS, and
+ * reported as 0 for it). */
 typedef struct {
   int32_t planes_per_group;
   int32_t rows_per_wave;
@@ -210,8 +212,10 @@ typedef struct {
 cpi_status cpi_refocus_get_tiles(const cpi_geometry* g, int32_t n_alpha,
                                  cpi_refocus_tiles* out);
 /* cpi_refocus with an explicit configuration `tiles` (host pointer) instead
- * of the cached one; CPI_ERR_UNSUPPORTED for a combination that is not built.
- * Results are bitwise reproducible for a given configuration. */
+ * of the cached one.  Errors: CPI_ERR_INVALID_ARG for a null `tiles` and the
+ * argument errors of cpi_refocus; CPI_ERR_UNSUPPORTED for a configuration
+ * that is not built; both before any launch.  Results are bitwise
+ * reproducible for a given configuration. */
 cpi_status cpi_refocus_tiled(const float* gamma, const cpi_geometry* g,
                              const double* alphas, int32_t n_alpha, float* out,
                              const cpi_refocus_tiles* tiles, void* workspace,
