@@ -216,3 +216,47 @@ def test_ssim_closed_forms():
     assert s[0] > s[1] > s[2]
     w = dn.gaussian_window()
     assert w.shape == (11, 11) and math.isclose(w.sum(), 1.0) and w[5, 5] == w.max()
+
+
+def _ramp_ssim_closed_form(w, a, c, sigma, k1, k2, size=11):
+    """SSIM of pred = a*t + c against the ramp t(y, x) = x / (w - 1).
+
+    The target's range is 1 and its minimum 0, so both planes keep their
+    values.  Inside every window the target has mean m = x_c / (w - 1) (x_c the
+    window's centre column: the weights are symmetric) and variance
+    v = sum_r g(r) r^2 / ((w - 1)^2 sum_r g(r)) with g(r) = exp(-r^2 / (2 sigma^2))
+    over r = -(size-1)/2 .. (size-1)/2 (the window is separable and its row
+    factor sums to 1); the prediction has mean a*m + c, variance a^2 v and
+    covariance a v with the target."""
+    h = (size - 1) // 2
+    g = [math.exp(-(r * r) / (2.0 * sigma * sigma)) for r in range(-h, h + 1)]
+    v = sum(gi * r * r for gi, r in zip(g, range(-h, h + 1))) / (sum(g) * (w - 1) ** 2)
+    c1, c2 = k1 * k1, k2 * k2
+    vals = []
+    for x0 in range(w - size + 1):
+        mb = (x0 + h) / (w - 1)
+        ma = a * mb + c
+        vals.append((2 * ma * mb + c1) * (2 * a * v + c2) /
+                    ((ma * ma + mb * mb + c1) * (a * a * v + v + c2)))
+    return sum(vals) / len(vals)
+
+
+def test_ssim_ramp_closed_form_fixes_window_and_constants():
+    """The Gaussian window's sigma (1.5) and the constants K1 = 0.01, K2 = 0.03
+    of the SSIM reading enter a hand-computable value on a linear ramp."""
+    w, hgt = 24, 13
+    t = np.tile(np.arange(w, dtype=np.float64) / (w - 1), (hgt, 1))
+    for a, c in ((0.5, 0.1), (0.8, -0.05), (1.7, 0.3)):
+        pred = a * t + c
+        want = _ramp_ssim_closed_form(w, a, c, 1.5, 0.01, 0.03)
+        assert math.isclose(dn.ssim(pred, t), want, rel_tol=1e-10), (a, c)
+        # the closed form separates the readings: another sigma or K2 moves
+        # the value far beyond the tolerance above
+        for sig, k2 in ((1.0, 0.03), (1.5, 0.01), (2.0, 0.03)):
+            other = _ramp_ssim_closed_form(w, a, c, sig, 0.01, k2)
+            assert abs(other - want) > 1e-4, (a, c, sig, k2)
+            assert math.isclose(dn.ssim(pred, t, sigma=sig, k2=k2), other, rel_tol=1e-10)
+    # an offset-only prediction leaves the contrast term at 1
+    pred = t + 0.2
+    want = _ramp_ssim_closed_form(w, 1.0, 0.2, 1.5, 0.01, 0.03)
+    assert math.isclose(dn.ssim(pred, t), want, rel_tol=1e-10)

@@ -323,3 +323,16 @@ def test_resampled_linearity():
     lhs = oracle.refocus_resampled(2.0 * g1 - 3.0 * g2, g, s, al)
     rhs = 2.0 * oracle.refocus_resampled(g1, g, s, al) - 3.0 * oracle.refocus_resampled(g2, g, s, al)
     assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+
+
+def test_default_geometry_values():
+    """Default geometry: magnification Wa/Wb and Ha/Hb, centres at (W - 1)/2
+    on both detectors, output on detector A's grid."""
+    g = default_geometry(128, 96, 64, 32)
+    assert (g.wa, g.ha, g.wb, g.hb) == (128, 96, 64, 32)
+    assert (g.mag_x, g.mag_y) == (2.0, 3.0)
+    assert (g.ca_x, g.ca_y, g.cb_x, g.cb_y) == (63.5, 47.5, 31.5, 15.5)
+    assert (g.out_w, g.out_h) == (128, 96)
+    g = default_geometry(7, 5, 3, 2)
+    assert (g.mag_x, g.mag_y) == (7 / 3, 2.5)
+    assert (g.ca_x, g.ca_y, g.cb_x, g.cb_y) == (3.0, 2.0, 1.0, 0.5)
