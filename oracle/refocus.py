@@ -53,10 +53,10 @@ def default_geometry(wa: int, ha: int, wb: int, hb: int) -> Geometry:
 
 
 def _views(gamma_vm, g: Geometry) -> np.ndarray:
-    gv = np.asarray(gamma_vm)
+    gv = np.asarray(gamma_vm, dtype=np.float64)
     if gv.size != g.wa * g.ha * g.wb * g.hb:
         raise ValueError("gamma size does not match the geometry")
-    return gv.reshape(g.hb * g.wb, g.ha, g.wa).astype(np.float64)
+    return gv.reshape(g.hb * g.wb, g.ha, g.wa)
 
 
 def _sample_sum(views, g: Geometry, alpha: float, xr: np.ndarray, yr: np.ndarray,
