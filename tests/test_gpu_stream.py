@@ -162,3 +162,99 @@ def test_streaming_workload_final_gamma(cpi):
     assert np.array_equal(num.sum(axis=0), rows_a)
     s.close()
     del torch
+
+
+def _columns(packed, pix):
+    """0/1 values of the listed pixels in every frame, from packed bytes (host)."""
+    pix = np.asarray(pix)
+    return ((packed[:, pix // 8] >> (pix % 8)) & 1).astype(np.uint8)
+
+
+def test_streaming_workload_200_distinct_chunks(cpi):
+    """The whole streamed workload: Da 128x128, Db 64x64, 200 distinct seeded
+    chunks of 1000 1-bit frames (made on the device), folded one by one up to
+    N = 200000.  The final state equals single-shot correlation of the same
+    frames bit for bit over every entry; sampled entries equal the oracle's;
+    every row and column sum of the numerator and a Freivalds product equal
+    their values computed from the frames (exact integers in FP64)."""
+    import torch
+    from synth.gpu_speckle import generate_binary_frames_gpu
+
+    w = WORKLOADS["da128_db64_stream200x1000_bit1"]
+    n, pa, pb, k = w.n_frames, w.pa, w.pb, w.chunk
+    d = dev()
+    log(f"case {w.name}: generating {n} frames on the device")
+    fa, fb = generate_binary_frames_gpu(w, count=n, device=d)
+    s = cpi.Stream(pa, pb, cpi.FRAMES_BIT1, max_chunk=k)
+    for c in range(n // k):
+        s.push(fa[c * k:(c + 1) * k].reshape(-1), fb[c * k:(c + 1) * k].reshape(-1), k)
+        if c % 50 == 49:
+            torch.cuda.synchronize()
+            log(f"case {w.name}: {c + 1} chunks folded")
+    assert s.frames == n
+    st = {
+        "gamma": torch.empty(pa * pb, dtype=torch.float64, device=d),
+        "gamma_f32": torch.empty(pa * pb, dtype=torch.float32, device=d),
+        "numer": torch.empty(pa * pb, dtype=torch.int64, device=d),
+        "sum_a": torch.empty(pa, dtype=torch.int64, device=d),
+        "sum_b": torch.empty(pb, dtype=torch.int64, device=d),
+    }
+    s.gamma(cpi.GAMMA_VIEW_MAJOR, **st)
+    one = {key: torch.empty_like(v) for key, v in st.items()}
+    log(f"case {w.name}: single shot")
+    cpi.correlate(fa.reshape(-1), fb.reshape(-1), n, pa, pb, cpi.FRAMES_BIT1,
+                  cpi.GAMMA_VIEW_MAJOR, **one)
+    torch.cuda.synchronize()
+    s.close()
+    for key in st:
+        assert torch.equal(st[key], one[key]), key
+    # sampled entries against the oracle (from the sampled pixels' frame columns)
+    rng = np.random.default_rng(24)
+    rows = np.sort(rng.choice(pa, 1024, replace=False))
+    views = np.sort(rng.choice(pb, 64, replace=False))
+    ha, hb = fa.cpu().numpy(), fb.cpu().numpy()
+    ref = oracle.correlation(_columns(ha, rows), _columns(hb, views), n, rows.size, views.size,
+                             oracle.FRAMES_U8)
+    num = st["numer"].view(pb, pa)
+    assert np.array_equal(num[views][:, rows].cpu().numpy(), ref["numer"].T)
+    assert np.array_equal(st["gamma"].view(pb, pa)[views][:, rows].cpu().numpy(), ref["gamma"].T)
+    assert np.array_equal(st["sum_a"].cpu().numpy()[rows], ref["sum_a"])
+    assert np.array_equal(st["sum_b"].cpu().numpy()[views], ref["sum_b"])
+    # identities over every entry, from the frames (integers below 2^53 in FP64)
+    log(f"case {w.name}: row/column sums and Freivalds")
+    bits = torch.arange(8, device=d, dtype=torch.uint8)
+
+    def unpacked(packed, npix, step=20000):
+        for lo in range(0, packed.shape[0], step):
+            c = packed[lo:lo + step]
+            yield lo, ((c.unsqueeze(2) >> bits) & 1).reshape(c.shape[0], -1)[:, :npix]
+
+    ta = torch.zeros(n, dtype=torch.float64, device=d)
+    tb = torch.zeros(n, dtype=torch.float64, device=d)
+    for lo, u in unpacked(fa, pa):
+        ta[lo:lo + u.shape[0]] = u.sum(dim=1, dtype=torch.float64)
+    for lo, u in unpacked(fb, pb):
+        tb[lo:lo + u.shape[0]] = u.sum(dim=1, dtype=torch.float64)
+    v = torch.from_numpy(rng.integers(-2, 3, size=pa).astype(np.float64)).to(d)
+    a_tb = torch.zeros(pa, dtype=torch.float64, device=d)
+    a_v = torch.zeros(n, dtype=torch.float64, device=d)
+    sa_f = torch.zeros(pa, dtype=torch.float64, device=d)
+    for lo, u in unpacked(fa, pa):
+        uf = u.to(torch.float64)
+        a_tb += uf.t() @ tb[lo:lo + u.shape[0]]
+        a_v[lo:lo + u.shape[0]] = uf @ v
+        sa_f += uf.sum(dim=0)
+    b_ta = torch.zeros(pb, dtype=torch.float64, device=d)
+    bt_av = torch.zeros(pb, dtype=torch.float64, device=d)
+    sb_f = torch.zeros(pb, dtype=torch.float64, device=d)
+    for lo, u in unpacked(fb, pb):
+        uf = u.to(torch.float64)
+        b_ta += uf.t() @ ta[lo:lo + u.shape[0]]
+        bt_av += uf.t() @ a_v[lo:lo + u.shape[0]]
+        sb_f += uf.sum(dim=0)
+    assert torch.equal(sa_f, st["sum_a"].to(torch.float64))
+    assert torch.equal(sb_f, st["sum_b"].to(torch.float64))
+    numf = num.to(torch.float64)
+    assert torch.equal(numf.sum(dim=0), n * a_tb - sa_f * sb_f.sum())
+    assert torch.equal(numf.sum(dim=1), n * b_ta - sb_f * sa_f.sum())
+    assert torch.equal(numf @ v, n * bt_av - sb_f * (sa_f @ v))

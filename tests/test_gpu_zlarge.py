@@ -8,8 +8,11 @@ computed from those pixels' frame columns only, (b) through integer
 identities over every entry: row sums, column sums and Freivalds products of
 the exact numerator, recovered as rint(Gamma * N^2) (|numer| < 2^52 here).
 Refocusing is checked at full size through the alpha = 1 plane, which equals
-the row sums of Gamma over the views (an identity tied to the frames), and a
-closed-form point phantom at the full geometry.
+the row sums of Gamma over the views (an identity tied to the frames), against
+the FP64 oracle on 25 planes of the 128-plane stack (sampled pixels plus each
+plane's largest-magnitude pixel, on the device Gamma that the identities above
+tie to the frames), and through a closed-form point phantom at the full
+geometry.
 """
 import numpy as np
 import pytest
@@ -124,18 +127,34 @@ def test_integer_identities_over_every_entry(cpi, large):
     assert torch.equal(g32, gamma.to(torch.float32))
 
 
-def test_refocus_alpha_one_is_row_sum(cpi, large):
+def _stack_alphas():
+    al = list(alphas_for(W))
+    al[len(al) // 2] = 1.0
+    return al
+
+
+@pytest.fixture(scope="module")
+def stack(cpi, large):
+    """The 128-plane stack of the workload (its alpha grid with the middle
+    plane set to alpha = 1), refocused in one batched call."""
+    import torch
+
+    fa, fb, gamma, g32, sa, sb = large
+    geo = cpi.geometry_default(W.wa, W.ha, W.wb, W.hb)
+    al = _stack_alphas()
+    out = torch.empty(len(al) * W.pa, dtype=torch.float32, device=dev())
+    log("case large: refocus 128 planes")
+    cpi.refocus(g32, geo, al, out)
+    torch.cuda.synchronize()
+    return al, out
+
+
+def test_refocus_alpha_one_is_row_sum(cpi, large, stack):
     import torch
 
     fa, fb, gamma, g32, sa, sb = large
     n, pa, pb = W.n_frames, W.pa, W.pb
-    geo = cpi.geometry_default(W.wa, W.ha, W.wb, W.hb)
-    al = list(alphas_for(W))
-    al[len(al) // 2] = 1.0
-    out = torch.empty(len(al) * pa, dtype=torch.float32, device=dev())
-    log("case large: refocus 128 planes")
-    cpi.refocus(g32, geo, al, out)
-    torch.cuda.synchronize()
+    al, out = stack
     # alpha = 1 plane against the frames' row sums / N^2 (no Gamma in between)
     tb = torch.zeros(n, dtype=torch.float64, device=dev())
     for lo, u in _unpacked_chunks(torch, fb, pb):
@@ -180,3 +199,33 @@ def test_refocus_point_phantom_full_geometry(cpi):
     img = out.view(g.ha, g.wa)
     assert abs(float(img[yo, xo]) - peak) <= 1e-5 * peak
     assert int(torch.argmax(img)) == yo * g.wa + xo
+
+
+def test_refocus_stack_planes_vs_oracle(cpi, large, stack):
+    """25 planes of the 128-plane stack (24 evenly spaced, first and last
+    included, plus the alpha = 1 plane) against the FP64 oracle at 64 sampled
+    pixels plus each checked plane's largest-magnitude pixel.  The oracle
+    refocuses the device Gamma64, which the tests above show to be the exact
+    Gamma of the frames; per plane, max error / max magnitude <= 1e-5."""
+    fa, fb, gamma, g32, sa, sb = large
+    al, out = stack
+    na = len(al)
+    planes = np.unique(np.concatenate([np.linspace(0, na - 1, 24).round().astype(int),
+                                       [na // 2]]))
+    got = out.view(na, W.ha, W.wa)[planes].cpu().numpy()
+    rng = np.random.default_rng(33)
+    ys = list(rng.integers(0, W.ha, 64))
+    xs = list(rng.integers(0, W.wa, 64))
+    flat = np.abs(got.reshape(planes.size, -1))
+    for k in range(planes.size):
+        yy, xx = np.unravel_index(np.argmax(flat[k]), (W.ha, W.wa))
+        ys.append(yy)
+        xs.append(xx)
+    ys, xs = np.array(ys), np.array(xs)
+    g = oracle.default_geometry(W.wa, W.ha, W.wb, W.hb)
+    log(f"case large: oracle refocus of {planes.size} planes at {ys.size} pixels")
+    want = oracle.refocus_pixels(gamma.cpu().numpy(), g, np.asarray(al)[planes], ys, xs)
+    err = plane_rel_err(got[:, ys, xs], want)
+    for k, e in zip(planes, err):
+        log(f"plane {k} alpha {al[k]:.6f}: relative error {e:.3g}")
+    assert err.max() <= 1e-5

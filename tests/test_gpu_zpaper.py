@@ -8,7 +8,9 @@ through integer identities over every entry: row sums, column sums and
 Freivalds products of the exact numerator, recovered as rint(Gamma * N^2)
 (|numer| < 2^52 here).  The 261-plane refocus is checked at full size through
 the alpha = 1 plane, which equals the row sums of Gamma over the views (an
-identity tied to the frames).
+identity tied to the frames), and against the FP64 oracle on 25 of its planes
+(sampled pixels plus each plane's largest-magnitude pixel, on the device Gamma
+that the identities tie to the frames; three groups of planes, one test each).
 """
 import numpy as np
 import pytest
@@ -115,18 +117,35 @@ def test_integer_identities_over_every_entry(cpi, paper):
     assert torch.equal(g32, gamma.to(torch.float32))
 
 
-def test_refocus_261_planes_alpha_one(cpi, paper):
+@pytest.fixture(scope="module")
+def stack(cpi, paper):
+    """The 261-plane stack, refocused in one batched call."""
+    import torch
+
+    fa, fb, gamma, g32, sa, sb = paper
+    geo = cpi.geometry_default(W.wa, W.ha, W.wb, W.hb)
+    al = list(alphas_for(W))
+    assert al[130] == 1.0          # linspace(0.5, 1.5, 261) holds alpha = 1 exactly
+    out = torch.empty(len(al) * W.pa, dtype=torch.float32, device=dev())
+    log("case paper: refocus 261 planes")
+    cpi.refocus(g32, geo, al, out)
+    torch.cuda.synchronize()
+    return al, out
+
+
+@pytest.fixture(scope="module")
+def gamma_host(paper):
+    """The device Gamma64 on the host, once for the oracle's checks."""
+    log("case paper: Gamma to the host")
+    return paper[2].cpu().numpy()
+
+
+def test_refocus_261_planes_alpha_one(cpi, paper, stack):
     import torch
 
     fa, fb, gamma, g32, sa, sb = paper
     n, pa, pb = W.n_frames, W.pa, W.pb
-    geo = cpi.geometry_default(W.wa, W.ha, W.wb, W.hb)
-    al = list(alphas_for(W))
-    assert al[130] == 1.0          # linspace(0.5, 1.5, 261) holds alpha = 1 exactly
-    out = torch.empty(len(al) * pa, dtype=torch.float32, device=dev())
-    log("case paper: refocus 261 planes")
-    cpi.refocus(g32, geo, al, out)
-    torch.cuda.synchronize()
+    al, out = stack
     assert torch.isfinite(out).all()
     tb = torch.zeros(n, dtype=torch.float64, device=dev())
     for lo, u in _unpacked_chunks(torch, fb, pb):
@@ -138,4 +157,36 @@ def test_refocus_261_planes_alpha_one(cpi, paper):
     got = out.view(len(al), pa)[130].to(torch.float64)
     err = plane_rel_err(got.cpu().numpy()[None], rows.cpu().numpy()[None])
     log(f"alpha=1 plane relative error {err.max():.3g}")
+    assert err.max() <= 1e-5
+
+
+# 24 evenly spaced planes of the 261 (first and last included) plus alpha = 1,
+# in three groups so that each oracle run stays short
+_PLANES = np.unique(np.concatenate([np.linspace(0, 260, 24).round().astype(int), [130]]))
+_GROUPS = [_PLANES[0::3], _PLANES[1::3], _PLANES[2::3]]
+
+
+@pytest.mark.parametrize("group", range(len(_GROUPS)))
+def test_refocus_planes_vs_oracle(cpi, stack, gamma_host, group):
+    """Planes of the 261-plane stack against the FP64 oracle at 48 sampled
+    pixels plus each checked plane's largest-magnitude pixel; per plane, max
+    error / max magnitude <= 1e-5."""
+    al, out = stack
+    planes = _GROUPS[group]
+    got = out.view(len(al), W.ha, W.wa)[planes].cpu().numpy()
+    rng = np.random.default_rng(43 + group)
+    ys = list(rng.integers(0, W.ha, 48))
+    xs = list(rng.integers(0, W.wa, 48))
+    flat = np.abs(got.reshape(planes.size, -1))
+    for k in range(planes.size):
+        yy, xx = np.unravel_index(np.argmax(flat[k]), (W.ha, W.wa))
+        ys.append(yy)
+        xs.append(xx)
+    ys, xs = np.array(ys), np.array(xs)
+    g = oracle.default_geometry(W.wa, W.ha, W.wb, W.hb)
+    log(f"case paper: oracle refocus of planes {list(planes)} at {ys.size} pixels")
+    want = oracle.refocus_pixels(gamma_host, g, np.asarray(al)[planes], ys, xs)
+    err = plane_rel_err(got[:, ys, xs], want)
+    for k, e in zip(planes, err):
+        log(f"plane {k} alpha {al[k]:.6f}: relative error {e:.3g}")
     assert err.max() <= 1e-5
