@@ -1,38 +1,46 @@
 #!/usr/bin/env python3
 """Benchmark of the correlation plenoptic imaging hot path on one MI355X.
 
-Workload: Da 128x128, Db 64x64, N = 20000 binary frames stored as bytes
-(SPAD-like occupancy ~0.1, seeded speckle through a 3-slit mask), 32 refocus
-planes alpha in [0.5, 1.5].  One step is one pass of the hot path with the
-inputs resident in HBM: ingest + matrix-core contraction with the exact
-int64/FP64 epilogue (Gamma in FP64 and FP32) + batched refocus of 32 planes
-with the autotuned configuration (tuned once before timing).  Binary frames
-are contracted as FP4 (E2M1) 0/1 operands with FP32 sums, exact below 2^24
-frames per pass; the int8 encoding of the same contraction is timed beside it.
+Default workload (the headline line): Da 256x256, Db 128x128, N = 100000
+distinct 1-bit frames packed 8 per byte (seeded speckle through a 3-slit mask,
+SPAD-like occupancy ~0.1, generated on the device), 128 refocus planes alpha
+in [0.5, 1.5].  One step is one pass of the hot path with the inputs resident
+in HBM: ingest + matrix-core contraction with the exact int64/FP64 epilogue
+(Gamma in FP64 and FP32) + batched refocus of all planes with the autotuned
+configuration (tuned once before timing).  Binary frames are contracted as FP4
+(E2M1) 0/1 operands with FP32 sums, exact below 2^24 frames per pass; the int8
+encoding of the same step is timed beside it.
 
 Printed as ONE JSON line:
   value          Gamma pixel-pair*frames per second over the whole step
-                 (N * Pa * Pb per step / step time)
-  refocus        refocused planes per second of the batched kernel
+                 (N * Pa * Pb per step / step time), FP4 encoding
+  correlate, refocus  per-kernel-group times of the step (library events)
+  int8_step      the same step with the int8 encoding of the contraction
   fp32_plain     the plain FP32 path on the same inputs (correlator and
-                 one-plane-per-launch refocus) and the int8/FP32 ratios
-  streaming      chunk-to-stack latency p50/p99 and frames/s for 1000-frame
-                 1-bit chunks of the same geometry, each followed by a
-                 32-plane refocus
-  roofline       the contraction kernel (dominant) against the FP4 peak,
-                 its duration measured with HIP events on its stream
+                 one-plane-per-launch refocus, the latter timed on 8 planes
+                 and scaled to the stack) and the ratios to it
+  roofline       the contraction kernel (dominant in the correlator) against
+                 the FP4 peak, its duration measured with the library's HIP
+                 events on its launch stream
   roofline_int8  the same contraction in the int8 encoding against the int8 peak
-  roofline_refocus  the batched refocus kernel: algorithmic (footprint) bytes
-                 per launch over its duration, against the HBM peak
+  roofline_refocus  the batched refocus kernel against the FP32 vector-ALU
+                 peak (two FLOPs per bilinear tap), with its measured HBM and
+                 LDS traffic where counter summaries exist for the current source
+  cpu_baseline   the CPU oracle on a bounded sample of the workload,
+                 extrapolated linearly (the sample is stated)
+  paper_like     the same figures for Da 128x128, Db 64x64, N = 20000 binary
+                 bytes, 32 planes
+  streaming      chunk-to-stack latency p50/p99 and frames/s for 200 distinct
+                 1000-frame 1-bit chunks (Da 128x128, Db 64x64), each pushed
+                 from pinned host memory and followed by a 32-plane refocus
   refocus_plane_counts  the paper's stack sizes (100, 261, 1000 planes)
-  file_ingest    raw side-by-side frame files (the paper's 256 x 512 layout,
-                 11 files of 512 frames) streamed into the running sums
-  measured_peaks the device's sustained matrix-core and copy rates (microbenchmarks)
   refocus_resampled  refocusing with the lens plane sampled at half-pixel steps
                  (general 4-D multilinear interpolation): view resampling + refocus
+  file_ingest    raw side-by-side frame files (the paper's 256 x 512 layout,
+                 11 files of 512 frames) streamed into the running sums
   denoiser       the learned denoiser's training step (16 planes of 128 x 128)
                  and inference (32 planes): time and algorithmic BF16 FLOP rate
-  cpu_baseline   the CPU oracle on a bounded sample of the same workload
+  measured_peaks the device's sustained matrix-core and copy rates (microbenchmarks)
 """
 import argparse
 import hashlib
@@ -53,9 +61,14 @@ DENOISE_WORKLOAD = "da128_db64_denoise500to50000_bit1"
 BF16_PEAK = 2.5e15          # dense bfloat16 matrix-core FLOP/s, MI355X
 INT8_PEAK = 5.0e15          # dense int8 matrix-core ops/s, MI355X
 FP4_PEAK = 10.1e15          # dense FP4 (and FP6) matrix-core ops/s, MI355X
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemm_f4lds_da128_db64_n20000_pmc.txt")
+FP32_VECTOR_PEAK = 157.3e12  # FP32 vector FLOP/s, MI355X (packed FP32 FMA)
+FP32_UNPACKED_PEAK = 78.6e12  # FP32 vector FLOP/s with one FMA per lane per cycle
+# LDS read bandwidth: 128 bytes per clock per CU, 256 CUs, 2.4 GHz
+LDS_PEAK = 128 * 256 * 2.4e9
+# workload keys of the committed counter summaries (contraction, refocus)
+PAPER_LIKE_KEY = ("da128_db64_n20000", "da128_db64_32planes")
+LARGE_KEY = ("da256_db128_n100000", "da256_db128_128planes")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_gemm.hip")
-REF_PMC_SUMMARY = os.path.join(ROOT, "profiles", "ref_sep_da128_db64_32planes_pmc.txt")
 REF_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_refocus.hip")
 
 
@@ -68,12 +81,11 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(summary=None, source=None, tiles=None):
-    """HBM bytes per launch from a committed counter summary (the contraction's
-    by default), if it was taken on the current kernel source (and, for the
-    refocus, with these tiles); else None."""
-    summary = summary or PMC_SUMMARY
-    source = source or GEMM_SOURCE
+def _summary_fields(summary, source):
+    """key: value fields of a committed counter summary, if it was taken on the
+    current kernel source; else None."""
+    if summary is None:
+        return None
     fields = {}
     try:
         with open(summary) as f:
@@ -85,13 +97,31 @@ def measured_traffic(summary=None, source=None, tiles=None):
         return None
     if fields.get("kernel_source_sha256_16") != source_hash(source):
         return None
-    key = "hbm_bytes_per_launch"
+    return fields
+
+
+def _summary_value(summary, source, key, tiles=None):
+    fields = _summary_fields(summary, source)
+    if fields is None:
+        return None
     if tiles is not None:
-        key = "hbm_bytes_per_launch_tiles " + " ".join(str(int(v)) for v in tiles)
+        key = key + "_tiles " + " ".join(str(int(v)) for v in tiles)
     try:
         return float(fields[key].split()[0])
     except (KeyError, ValueError, IndexError):
         return None
+
+
+def measured_traffic(summary, source, tiles=None):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from a
+    committed counter summary taken on the current kernel source (and, for the
+    refocus, with these tiles); else None."""
+    return _summary_value(summary, source, "hbm_bytes_per_launch", tiles)
+
+
+def measured_lds(summary, source, tiles=None):
+    """LDS bytes read per launch from the same kind of summary; else None."""
+    return _summary_value(summary, source, "lds_read_bytes_per_launch", tiles)
 
 
 def refocus_algorithmic_bytes(geo, alphas):
@@ -163,19 +193,24 @@ def file_ingest_bench(cpi, torch, np, dev, n_files=11, roi=128):
             "raw_MB_per_s": k * f.frame_bytes / t / 1e6}
 
 
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        return len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(a, b, w, alphas):
-    """The oracle, as it stands, on a bounded sample of the workload (about
-    12 s of host work): Gamma for every pixel pair over all frames, and 10 of
-    the refocus planes (evenly spaced, first and last included)."""
+    """The oracle, as it stands, on a bounded sample of the paper-like
+    workload (about 12 s of host work): Gamma for every pixel pair over all
+    frames, and 10 of the refocus planes (evenly spaced, first and last
+    included)."""
     import numpy as np
 
     import oracle
 
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        threads = len(os.sched_getaffinity(0))
+    threads = _blas_threads()
     t0 = time.perf_counter()
     r = oracle.correlation(a, b, w.n_frames, w.pa, w.pb, oracle.FRAMES_U8)
     t1 = time.perf_counter()
@@ -196,6 +231,57 @@ def cpu_baseline(a, b, w, alphas):
                    f"({t1 - t0:.2f} s); refocus of {planes.size} of {len(alphas)} planes "
                    f"({t3 - t2:.2f} s)"),
         "refocus_planes_per_s": planes.size / (t3 - t2),
+        "seconds": (t1 - t0) + (t3 - t2),
+    }
+
+
+def cpu_baseline_large(fa, fb, gamma, w, alphas, slab=1024, n_pix=256, n_planes=4):
+    """The oracle, as it stands, on a bounded sample of the large workload,
+    extrapolated linearly to the whole job:
+      * Gamma of the first ``slab`` detector-A pixels (whole bytes of every
+        packed frame) against every detector-B pixel over all N frames; the
+        cost is linear in the detector-A pixel count;
+      * ``n_pix`` sampled output pixels of ``n_planes`` evenly spaced planes,
+        refocused from the device's FP64 Gamma (which the GPU tests show to be
+        the exact Gamma of the frames); the cost is linear in the pixel count.
+    ``fa``, ``fb``: packed frames on the device; ``gamma``: FP64 view-major
+    Gamma on the device."""
+    import numpy as np
+
+    import oracle
+
+    threads = _blas_threads()
+    n = w.n_frames
+    a_slab = fa[:, :slab // 8].cpu().numpy()
+    b_all = fb.cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.correlation(a_slab, b_all, n, slab, w.pb, oracle.FRAMES_BIT1)
+    t1 = time.perf_counter()
+    del a_slab, b_all
+    gam = gamma.cpu().numpy()
+    g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
+    rng = np.random.default_rng(5)
+    ys = rng.integers(0, w.ha, n_pix)
+    xs = rng.integers(0, w.wa, n_pix)
+    planes = np.unique(np.linspace(0, len(alphas) - 1, n_planes).round().astype(int))
+    t2 = time.perf_counter()
+    oracle.refocus_pixels(gam, g, np.asarray(alphas)[planes], ys, xs)
+    t3 = time.perf_counter()
+    del gam
+    t_gamma = (t1 - t0) * (w.pa / slab)
+    t_plane = (t3 - t2) / planes.size * (w.pa / n_pix)
+    return {
+        "value": float(n) * w.pa * w.pb / t_gamma,
+        "unit": "pixel-pair*frames/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"Gamma of {slab} of {w.pa} detector-A pixels x all {w.pb} detector-B pixels "
+                   f"over all {n} frames ({t1 - t0:.2f} s, extrapolated linearly to the whole "
+                   f"Gamma: {t_gamma:.0f} s); refocus of {n_pix} output pixels in each of "
+                   f"{planes.size} planes ({t3 - t2:.2f} s, extrapolated to {w.pa} pixels per "
+                   f"plane: {t_plane:.0f} s per plane)"),
+        "extrapolated": True,
+        "refocus_planes_per_s": 1.0 / t_plane,
         "seconds": (t1 - t0) + (t3 - t2),
     }
 
@@ -456,101 +542,25 @@ def denoise_bench(args, cpi, torch, np, dev):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--stream-chunks", type=int, default=200)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-stream", action="store_true")
-    ap.add_argument("--no-next", action="store_true",
-                    help="skip the plane-count refocus and raw-file ingest measurements")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=["paper_like", "large", "paper", "denoise",
-                                           "denoise_step"],
-                    default="paper_like",
-                    help="paper_like: Da 128x128, Db 64x64, N=20000 bytes (default line); "
-                         "large: Da 256x256, Db 128x128, N=100000 packed bits, 128 planes; "
-                         "paper: 256x256 on both detectors, --files files of 512 frames, "
-                         "261 planes (the paper's benchmark configuration); "
-                         "denoise: train the learned denoiser on pipeline-made pairs "
-                         "(500 -> 50000 frames) and compare with the plain pipeline at "
-                         "equal wall time; denoise_step: time the denoiser's training "
-                         "step and inference only")
-    ap.add_argument("--runs", type=int, default=625,
-                    help="denoise workload: streams of 50000 frames (32 pairs each)")
-    ap.add_argument("--epochs", type=int, default=4, help="denoise workload: training epochs")
-    ap.add_argument("--files", type=int, default=11,
-                    help="paper workload: files of 512 frames (the paper uses 11, 100, 500, 7808)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
+def refocus_taps(geo, n_alpha):
+    """Bilinear taps of a refocus launch: four per (plane, output pixel, view)."""
+    return 4 * int(n_alpha) * geo.out_w * geo.out_h * geo.wb * geo.hb
 
-    import numpy as np
-    import torch
 
-    dev = torch.device("cuda:0")
-    if args.calibrate_copy:
-        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": 1 << 30, "copies": 5}))
-        return
-
-    import paper_2407_20692_amd as cpi
-    from synth import WORKLOADS, alphas_for, generate_frames, pack_bits_lsb
-
-    if args.workload == "denoise":
-        print(json.dumps(denoise_bench(args, cpi, torch, np, dev)))
-        return
-    if args.workload == "denoise_step":
-        print(json.dumps(denoiser_timing(torch, np, dev)))
-        return
-
-    paper = args.workload == "paper"
-    large = args.workload == "large" or paper
-    w = WORKLOADS[PAPER_WORKLOAD if paper else (LARGE_WORKLOAD if large else WORKLOAD)]
-    log(f"bench: generating {w.name}")
-    alphas = alphas_for(w)
-    n, pa, pb = w.n_frames, w.pa, w.pb
-    generated = None
-    if paper:
-        n = args.files * 512
-    if large:
-        from synth.gpu_speckle import generate_binary_frames_gpu
-        fmt = cpi.FRAMES_BIT1
-        base = min(n, 25600)
-        pa_bits, pb_bits = generate_binary_frames_gpu(w, count=base, device=dev)
-        if base < n:
-            # more frames than generated: the generated block repeats (the
-            # contraction's work does not depend on the frame contents)
-            def tiled(x):
-                t = torch.empty((n, x.shape[1]), dtype=x.dtype, device=dev)
-                for lo in range(0, n, base):
-                    t[lo:lo + base] = x[:min(base, n - lo)]
-                return t
-            pa_bits, pb_bits = tiled(pa_bits), tiled(pb_bits)
-            generated = base
-        da, db = pa_bits.reshape(-1), pb_bits.reshape(-1)
-        a = b = None
-    else:
-        fmt = cpi.FRAMES_U8
-        a, b = generate_frames(w)
-        da = torch.from_numpy(a.reshape(-1)).to(dev)
-        db = torch.from_numpy(b.reshape(-1)).to(dev)
+def hot_path(args, cpi, torch, np, dev, w, n, fmt, da, db, alphas, tune=True, plain=True,
+             plain_corr=True, plain_planes=None, traffic_key=None):
+    """One workload's hot path: the timed step (correlate with Gamma in FP64 and
+    FP32, then the batched refocus), per-kernel-group times from the library's
+    events on the launch stream, the int8 encoding of the contraction, the
+    plain FP32 path and the roofline objects.  Returns (figures, state)."""
+    pa, pb = w.pa, w.pb
     gamma = torch.empty(pa * pb, dtype=torch.float64, device=dev)
     g32 = torch.empty(pa * pb, dtype=torch.float32, device=dev)
     ws_c = cpi.alloc_workspace(cpi.correlate_workspace_size(n, pa, pb, fmt), dev)
     geo = cpi.geometry_default(w.wa, w.ha, w.wb, w.hb)
-    out = torch.empty(len(alphas) * w.pa, dtype=torch.float32, device=dev)
-    ws_r = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, len(alphas)), dev)
+    na = len(alphas)
+    out = torch.empty(na * w.pa, dtype=torch.float32, device=dev)
+    ws_r = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, na), dev)
 
     def step():
         cpi.correlate(da, db, n, pa, pb, fmt, cpi.GAMMA_VIEW_MAJOR,
@@ -558,16 +568,14 @@ def main():
         cpi.refocus(g32, geo, alphas, out, workspace=ws_r)
 
     step()
-    if not paper:
-        # (the paper workload keeps the default configuration: each timed
-        # candidate would take about a second at its size)
-        log("bench: autotuning the refocus kernel")
+    if tune:
+        log(f"bench: autotuning the refocus kernel ({w.name})")
         cpi.autotune_refocus(g32, geo, alphas, out, workspace=ws_r)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    log(f"bench: timing {args.steps} steps")
+    log(f"bench: timing {args.steps} steps ({w.name})")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -599,126 +607,108 @@ def main():
         cpi.correlate(da, db, n, pa, pb, fmt, cpi.GAMMA_VIEW_MAJOR,
                       gamma=gamma, gamma_f32=g32, workspace=ws_c)
         torch.cuda.synchronize()
+        reps8 = max(3, args.steps // 4)
         cpi.profile_begin()
-        for _ in range(max(3, args.steps // 4)):
+        e0.record()
+        for _ in range(reps8):
             cpi.correlate(da, db, n, pa, pb, fmt, cpi.GAMMA_VIEW_MAJOR,
                           gamma=gamma, gamma_f32=g32, workspace=ws_c)
+            cpi.refocus(g32, geo, alphas, out, workspace=ws_r)
+        e1.record()
         torch.cuda.synchronize()
         cpi.profile_end()
+        ms_step_int8 = e0.elapsed_time(e1) / reps8
         cnt, tot = cpi.profile_query("gemm")
         ms_gemm_int8 = tot / max(cnt, 1)
     finally:
         cpi.set_mma_encoding(cpi.MMA_AUTO)
 
-    # plain FP32 comparison path on the same inputs (at the paper workload's
-    # size: the correlator up to 51200 frames, whose FP32 copies of the frames
-    # fit, and the one-plane-per-launch refocus on 4 of the planes)
-    log("bench: plain FP32 path")
-    plain_corr = not (paper and n > 51200)
-    al_p = alphas[:4] if paper else alphas
-    outp = torch.empty(len(al_p) * w.pa, dtype=torch.float32, device=dev)
-    if plain_corr:
-        g32p = torch.empty(pa * pb, dtype=torch.float32, device=dev)
-        ws_p = cpi.alloc_workspace(cpi.correlate_f32_plain_workspace_size(n, pa, pb, fmt), dev)
-        cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
-    cpi.refocus_plain(g32, geo, al_p, outp, workspace=ws_r)
-    torch.cuda.synchronize()
-    cpi.profile_begin()
-    for _ in range(args.plain_steps):
-        if plain_corr:
-            cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
-        cpi.refocus_plain(g32, geo, al_p, outp, workspace=ws_r)
-    torch.cuda.synchronize()
-    cpi.profile_end()
-    pg = {}
-    for grp in ("unpack_f32", "sgemm_f32", "refocus_tables", "refocus_plain"):
-        cnt, tot = cpi.profile_query(grp)
-        pg[grp] = tot / max(cnt, 1)
-    ms_corr_p = pg["unpack_f32"] + pg["sgemm_f32"] if plain_corr else float("nan")
-    # plain refocus time per call scaled to the full stack
-    ms_ref_p = (pg["refocus_tables"] + pg["refocus_plain"]) * len(alphas) / len(al_p)
-    if plain_corr:
-        del ws_p, g32p
-    del outp
-
     pairs = float(n) * pa * pb
-    line = {
-        "metric": "Gamma pixel-pair*frames/s and refocused planes/s: int8-MFMA vs plain FP32, 1 GPU",
-        "value": pairs / (ms_step * 1e-3),
-        "unit": "pixel-pair*frames/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    fig = {
+        "workload": w.name,
+        "n_frames": n,
         "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "fp4-e2m1 0/1 operands, fp32 sums (exact); int64/fp64 epilogue; fp32 refocus",
-        "data": "synthetic",
-        "config": {"workload": w.name if not paper else f"{w.name.split('_files')[0]}_files{args.files}_bit1",
-                   "n_frames": n, "pa": pa, "pb": pb,
-                   "frames": ("1-bit packed, frame-major (generated on the device"
-                              + (f"; {generated} distinct frames, repeated)" if generated else ")")
-                              if large else "uint8 0/1, frame-major"), "n_alpha": len(alphas),
-                   "alpha_range": [float(alphas[0]), float(alphas[-1])],
-                   "gamma_outputs": "FP64 + FP32, view-major"},
+        "pixel_pair_frames_per_s": pairs / (ms_step * 1e-3),
         "correlate": {"ms": ms_corr, "ingest_ms": groups["ingest"], "gemm_ms": groups["gemm"],
                       "pixel_pair_frames_per_s": pairs / (ms_corr * 1e-3)},
-        "refocus": {"ms": ms_ref, "planes_per_s": len(alphas) / (ms_ref * 1e-3),
-                    "config_kp_rw_splits_kernel_stages": list(cpi.refocus_tiles(geo, len(alphas)))},
-        "fp32_plain": {
+        "refocus": {"ms": ms_ref, "planes_per_s": na / (ms_ref * 1e-3),
+                    "config_kp_rw_splits_kernel_stages": list(cpi.refocus_tiles(geo, na))},
+        "int8_step": {"ms_per_step": ms_step_int8,
+                      "pixel_pair_frames_per_s": pairs / (ms_step_int8 * 1e-3),
+                      "gemm_ms": ms_gemm_int8},
+    }
+
+    if plain:
+        # plain FP32 comparison path on the same inputs (the one-plane-per-launch
+        # refocus on plain_planes of the planes, scaled to the stack)
+        log("bench: plain FP32 path")
+        al_p = alphas if plain_planes is None else alphas[:plain_planes]
+        outp = torch.empty(len(al_p) * w.pa, dtype=torch.float32, device=dev)
+        if plain_corr:
+            g32p = torch.empty(pa * pb, dtype=torch.float32, device=dev)
+            ws_p = cpi.alloc_workspace(cpi.correlate_f32_plain_workspace_size(n, pa, pb, fmt), dev)
+            cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
+        cpi.refocus_plain(g32, geo, al_p, outp, workspace=ws_r)
+        torch.cuda.synchronize()
+        cpi.profile_begin()
+        for _ in range(args.plain_steps):
+            if plain_corr:
+                cpi.correlate_f32_plain(da, db, n, pa, pb, fmt, g32p, workspace=ws_p)
+            cpi.refocus_plain(g32, geo, al_p, outp, workspace=ws_r)
+        torch.cuda.synchronize()
+        cpi.profile_end()
+        pg = {}
+        for grp in ("unpack_f32", "sgemm_f32", "refocus_tables", "refocus_plain"):
+            cnt, tot = cpi.profile_query(grp)
+            pg[grp] = tot / max(cnt, 1)
+        ms_corr_p = pg["unpack_f32"] + pg["sgemm_f32"] if plain_corr else float("nan")
+        ms_ref_p = (pg["refocus_tables"] + pg["refocus_plain"]) * na / len(al_p)
+        if plain_corr:
+            del ws_p, g32p
+        del outp
+        fig["fp32_plain"] = {
             "correlate_ms": ms_corr_p if plain_corr else None,
             "unpack_ms": pg["unpack_f32"] if plain_corr else None,
             "sgemm_ms": pg["sgemm_f32"] if plain_corr else None,
             "pixel_pair_frames_per_s": pairs / (ms_corr_p * 1e-3) if plain_corr else None,
             "sgemm_tflops": 2 * pairs / (pg["sgemm_f32"] * 1e-3) / 1e12 if plain_corr else None,
-            "refocus_ms": ms_ref_p, "planes_per_s": len(alphas) / (ms_ref_p * 1e-3),
+            "refocus_ms": ms_ref_p, "planes_per_s": na / (ms_ref_p * 1e-3),
             "refocus_planes_timed": len(al_p),
             "mfma_vs_fp32_correlate": ms_corr_p / ms_corr if plain_corr else None,
             "batched_vs_plain_refocus": ms_ref_p / ms_ref,
-        },
-    }
+        }
 
     gemm_ops = 2.0 * pairs
     achieved = gemm_ops / (groups["gemm"] * 1e-3) / 1e12
-    line["roofline"] = {
+    fig["roofline"] = {
         "kernel": "k_gemm_f4lds (FP4 matrix-core contraction, LDS pipeline, exact epilogue)",
         "bound": "mfma",
         "achieved": achieved,
         "peak": FP4_PEAK / 1e12,
         "unit": "TOP/s",
         "frac": achieved * 1e12 / FP4_PEAK,
-        "traffic": measured_traffic(),
+        # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (committed
+        # summary; None once the kernel source changed)
+        "traffic": measured_traffic(pmc_summary("gemm", traffic_key), GEMM_SOURCE),
         "algorithmic_ops_per_launch": gemm_ops,
         "launch_ms": groups["gemm"],
     }
-    ref_bytes = refocus_algorithmic_bytes(geo, alphas)
-    ref_bw = ref_bytes / (groups["refocus_batched"] * 1e-3) / 1e9
-    tiles = cpi.refocus_tiles(geo, len(alphas))
-    line["roofline_refocus"] = {
-        "kernel": ("k_ref_sep (planes batched per work-group, LDS-staged view windows, column "
-                   "interpolants summed over x_b before the row weights)" if tiles[3] == 1 else
-                   "k_ref_batched (planes batched per work-group, LDS-staged view windows)"),
-        "tiles_kp_rw_splits_kernel_stages": list(tiles),
-        "bound": "hbm",
-        "achieved": ref_bw,
-        "peak": 8000.0,
-        "unit": "GB/s",
-        "frac": ref_bw / 8000.0,
-        "algorithmic_bytes_per_launch": ref_bytes,
-        "launch_ms": groups["refocus_batched"],
-        # HBM bytes per launch of the tuned column-sum kernel from rocprofv3
-        # FETCH_SIZE / WRITE_SIZE (committed summary; None once the source
-        # changed or the tuned tiles differ from the profiled ones)
-        "traffic": measured_traffic(REF_PMC_SUMMARY, REF_SOURCE, tiles),
-        "note": "achieved = footprint bytes of every plane (counted exactly) / launch time; planes "
-                "share each staged view window, so this exceeds what HBM moves (traffic, from "
-                "rocprofv3 counters) and the kernel is bound by LDS reads and per-view latency "
-                "rather than HBM",
+    achieved8 = gemm_ops / (ms_gemm_int8 * 1e-3) / 1e12
+    fig["roofline_int8"] = {
+        "kernel": "k_gemm<bits> (int8 matrix-core contraction, exact epilogue)",
+        "bound": "mfma",
+        "achieved": achieved8,
+        "peak": INT8_PEAK / 1e12,
+        "unit": "TOP/s",
+        "frac": achieved8 * 1e12 / INT8_PEAK,
+        "launch_ms": ms_gemm_int8,
     }
+    fig["roofline_refocus"] = refocus_roofline(cpi, geo, alphas, groups["refocus_batched"],
+                                               traffic_key)
     # the other batched-refocus kernel with the same tiles (same inputs), where
     # it is built for them (the column-sum kernel also takes shapes the
     # per-row kernel does not)
+    tiles = cpi.refocus_tiles(geo, na)
     other = (tiles[0], tiles[1], tiles[2], 1 - tiles[3], 2)
     try:
         cpi.refocus_tiled(g32, geo, alphas, out, other, workspace=ws_r)
@@ -732,74 +722,299 @@ def main():
         torch.cuda.synchronize()
         cpi.profile_end()
         cnt, tot = cpi.profile_query("refocus_batched")
-        line["roofline_refocus"]["other_kernel_same_tiles"] = {
+        fig["roofline_refocus"]["other_kernel_same_tiles"] = {
             "tiles_kp_rw_splits_kernel_stages": list(other), "launch_ms": tot / max(cnt, 1)}
-    achieved8 = gemm_ops / (ms_gemm_int8 * 1e-3) / 1e12
-    line["roofline_int8"] = {
-        "kernel": "k_gemm<bits> (int8 matrix-core contraction, exact epilogue)",
-        "bound": "mfma",
-        "achieved": achieved8,
-        "peak": INT8_PEAK / 1e12,
-        "unit": "TOP/s",
-        "frac": achieved8 * 1e12 / INT8_PEAK,
-        "launch_ms": ms_gemm_int8,
-    }
+    state = {"gamma": gamma, "g32": g32, "geo": geo, "out": out, "ws_r": ws_r, "ws_c": ws_c}
+    return fig, state
 
-    if large or paper:
-        # counters were taken on the paper-like workload
-        line["roofline"]["traffic"] = None
-        line["roofline_refocus"]["traffic"] = None
-    rt = line["roofline_refocus"]["traffic"]
-    if rt:
-        # what the measured HBM traffic amounts to at this launch time
-        bw = rt / (groups["refocus_batched"] * 1e-3) / 1e9
-        line["roofline_refocus"]["traffic_GBps"] = bw
-        line["roofline_refocus"]["traffic_frac"] = bw / 8000.0
-    if not args.no_stream and not large:
-        ws = WORKLOADS[STREAM_WORKLOAD]
-        log(f"bench: streaming {args.stream_chunks} chunks of {ws.chunk}")
-        distinct = 20
-        sa_, sb_ = generate_frames(ws, count=distinct * ws.chunk)
-        ca = torch.from_numpy(pack_bits_lsb(sa_)).pin_memory()
-        cb = torch.from_numpy(pack_bits_lsb(sb_)).pin_memory()
-        fa_b, fb_b = cpi.frame_bytes(ws.pa, cpi.FRAMES_BIT1), cpi.frame_bytes(ws.pb, cpi.FRAMES_BIT1)
-        st = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev)
-        sgeo = cpi.geometry_default(ws.wa, ws.ha, ws.wb, ws.hb)
-        sal = alphas_for(ws)
-        sout = torch.empty(len(sal) * ws.pa, dtype=torch.float32, device=dev)
-        sws = cpi.alloc_workspace(cpi.refocus_workspace_size(sgeo, len(sal)), dev)
-        lat = []
-        dev_lat = []
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
+
+def pmc_summary(kind, key):
+    """Committed counter summary of a kernel on a workload (None if no key)."""
+    if key is None:
+        return None
+    name = {"gemm": f"gemm_f4lds_{key[0]}_pmc.txt", "refocus": f"ref_sep_{key[1]}_pmc.txt"}[kind]
+    return os.path.join(ROOT, "profiles", name)
+
+
+def refocus_roofline(cpi, geo, alphas, launch_ms, traffic_key):
+    """The batched refocus kernel against the vector-ALU roof: two FLOPs (one
+    multiply-add) per bilinear tap, four taps per (plane, output pixel, view).
+    Beside it: the measured HBM traffic (counters) and the per-plane footprint
+    bytes (every Gamma element a plane's samples touch, counted exactly), which
+    exceed what HBM moves because the planes of a work-group share each staged
+    view window."""
+    na = len(alphas)
+    taps = refocus_taps(geo, na)
+    flops = 2.0 * taps
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+    tiles = cpi.refocus_tiles(geo, na)
+    foot = refocus_algorithmic_bytes(geo, alphas)
+    traffic = measured_traffic(pmc_summary("refocus", traffic_key), REF_SOURCE, tiles)
+    r = {
+        "kernel": ("k_ref_sep (planes batched per work-group, LDS-staged view windows, column "
+                   "interpolants summed over x_b before the row weights)" if tiles[3] == 1 else
+                   "k_ref_batched (planes batched per work-group, LDS-staged view windows)"),
+        "tiles_kp_rw_splits_kernel_stages": list(tiles),
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": FP32_VECTOR_PEAK / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved * 1e12 / FP32_VECTOR_PEAK,
+        "frac_of_unpacked_fp32": achieved * 1e12 / FP32_UNPACKED_PEAK,
+        "algorithmic_flops_per_launch": flops,
+        "taps_per_launch": taps,
+        "launch_ms": launch_ms,
+        "traffic": traffic,
+        "footprint_bytes_per_launch": foot,
+        "footprint_GBps": foot / (launch_ms * 1e-3) / 1e9,
+    }
+    if traffic:
+        bw = traffic / (launch_ms * 1e-3) / 1e9
+        r["hbm"] = {"GBps": bw, "peak": 8000.0, "frac": bw / 8000.0}
+    lds = measured_lds(pmc_summary("refocus", traffic_key), REF_SOURCE, tiles)
+    if lds:
+        bw = lds / (launch_ms * 1e-3) / 1e12
+        r["lds"] = {"bytes_per_launch": lds, "TBps": bw, "peak": LDS_PEAK / 1e12,
+                    "frac": bw * 1e12 / LDS_PEAK}
+    return r
+
+
+def streaming_bench(args, cpi, torch, np, dev):
+    """The streamed workload: 1000-frame 1-bit chunks (Da 128x128, Db 64x64),
+    all distinct (made on the device, staged in pinned host memory), each
+    pushed from the host and followed by a 32-plane refocus.  Latency per
+    chunk from the push to the stack's completion; sustained frames/s over
+    the whole run."""
+    from synth import WORKLOADS, alphas_for
+    from synth.gpu_speckle import generate_binary_frames_gpu
+
+    ws = WORKLOADS[STREAM_WORKLOAD]
+    chunks = min(args.stream_chunks, ws.n_frames // ws.chunk)
+    log(f"bench: streaming {chunks} distinct chunks of {ws.chunk}")
+    fa, fb = generate_binary_frames_gpu(ws, count=chunks * ws.chunk, device=dev)
+    ca = fa.cpu().pin_memory()
+    cb = fb.cpu().pin_memory()
+    del fa, fb
+    fa_b, fb_b = ca.shape[1], cb.shape[1]
+    st = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev)
+    sgeo = cpi.geometry_default(ws.wa, ws.ha, ws.wb, ws.hb)
+    sal = alphas_for(ws)
+    sout = torch.empty(len(sal) * ws.pa, dtype=torch.float32, device=dev)
+    sws = cpi.alloc_workspace(cpi.refocus_workspace_size(sgeo, len(sal)), dev)
+    # one warm-up chunk on a separate stream object (kernels loaded, tables cached)
+    warm = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev)
+    warm.push_host(ca[:ws.chunk].reshape(-1), cb[:ws.chunk].reshape(-1), ws.chunk)
+    warm.refocus(sgeo, sal, sout, workspace=sws)
+    torch.cuda.synchronize()
+    warm.close()
+    lat, dev_lat = [], []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_start = time.perf_counter()
+    for k in range(chunks):
+        cha = ca[k * ws.chunk:(k + 1) * ws.chunk].reshape(-1)
+        chb = cb[k * ws.chunk:(k + 1) * ws.chunk].reshape(-1)
+        t0 = time.perf_counter()
+        ev0.record()
+        st.push_host(cha, chb, ws.chunk)
+        st.refocus(sgeo, sal, sout, workspace=sws)
+        ev1.record()
+        ev1.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        dev_lat.append(ev0.elapsed_time(ev1))
+    t_total = time.perf_counter() - t_start
+    res = {
+        "workload": ws.name,
+        "chunks": chunks,
+        "chunk_frames": ws.chunk,
+        "frames": f"{chunks} distinct seeded chunks ({chunks * ws.chunk} frames, made on the "
+                  f"device, pushed from pinned host memory)",
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "device_p50_ms": float(np.percentile(dev_lat, 50)),
+        "device_p99_ms": float(np.percentile(dev_lat, 99)),
+        "frames_per_s": chunks * ws.chunk / t_total,
+        "n_alpha": len(sal),
+        "final_frames": st.frames,
+    }
+    st.close()
+    return res
+
+
+def next_rows(cpi, torch, np, dev, g32, geo, w, alphas):
+    """NEXT rows measured on the paper-like Gamma: the paper's stack sizes,
+    the resampled lens plane, raw-file ingest and the denoiser's kernels."""
+    counts = {}
+    for na in (100, 261, 1000):
+        al = np.linspace(0.5, 1.5, na)
+        o = torch.empty(na * w.pa, dtype=torch.float32, device=dev)
+        ws_n = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, na), dev)
+        cpi.autotune_refocus(g32, geo, al, o, workspace=ws_n)
         torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for k in range(args.stream_chunks):
-            j = k % distinct
-            cha = ca.view(-1, fa_b)[j * ws.chunk:(j + 1) * ws.chunk].reshape(-1)
-            chb = cb.view(-1, fb_b)[j * ws.chunk:(j + 1) * ws.chunk].reshape(-1)
-            t0 = time.perf_counter()
-            ev0.record()
-            st.push_host(cha, chb, ws.chunk)
-            st.refocus(sgeo, sal, sout, workspace=sws)
-            ev1.record()
-            ev1.synchronize()
-            lat.append((time.perf_counter() - t0) * 1e3)
-            dev_lat.append(ev0.elapsed_time(ev1))
-        t_total = time.perf_counter() - t_start
-        line["streaming"] = {
-            "workload": ws.name,
-            "chunks": args.stream_chunks,
-            "chunk_frames": ws.chunk,
-            "frames": f"first {distinct} seeded chunks of the workload, cycled",
-            "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)),
-            "device_p50_ms": float(np.percentile(dev_lat, 50)),
-            "device_p99_ms": float(np.percentile(dev_lat, 99)),
-            "frames_per_s": args.stream_chunks * ws.chunk / t_total,
-            "n_alpha": len(sal),
-        }
-        st.close()
+        cpi.profile_begin()
+        for _ in range(3):
+            cpi.refocus(g32, geo, al, o, workspace=ws_n)
+        torch.cuda.synchronize()
+        cpi.profile_end()
+        t = sum(cpi.profile_query(gname)[1] for gname in ("refocus_tables", "refocus_batched")) / 3
+        counts[str(na)] = {"ms": t, "planes_per_s": na / (t * 1e-3),
+                           "config_kp_rw_splits_kernel_stages": list(cpi.refocus_tiles(geo, na))}
+        del o, ws_n
+    res = {"refocus_plane_counts": counts}
+    res["refocus_resampled"] = resampled_refocus_bench(cpi, torch, np, dev, g32, geo, w, alphas)
+    res["file_ingest"] = file_ingest_bench(cpi, torch, np, dev)
+    log("bench: denoiser training step and inference")
+    res["denoiser"] = denoiser_timing(torch, np, dev)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--stream-chunks", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 path")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the paper-like sub-line, plane counts, resampled lens plane, "
+                         "raw-file ingest and denoiser measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--workload", choices=["large", "paper_like", "paper", "denoise",
+                                           "denoise_step"],
+                    default="large",
+                    help="large (default line): Da 256x256, Db 128x128, N=100000 distinct "
+                         "packed-bit frames, 128 planes, with the paper-like workload and the "
+                         "streamed workload as sub-objects; paper_like: Da 128x128, Db 64x64, "
+                         "N=20000 bytes, 32 planes; paper: 256x256 on both detectors, --files "
+                         "files of 512 frames, 261 planes (the paper's benchmark configuration); "
+                         "denoise: train the learned denoiser on pipeline-made pairs "
+                         "(500 -> 50000 frames) and compare with the plain pipeline at "
+                         "equal wall time; denoise_step: time the denoiser's training "
+                         "step and inference only")
+    ap.add_argument("--runs", type=int, default=625,
+                    help="denoise workload: streams of 50000 frames (32 pairs each)")
+    ap.add_argument("--epochs", type=int, default=4, help="denoise workload: training epochs")
+    ap.add_argument("--files", type=int, default=11,
+                    help="paper workload: files of 512 frames (the paper uses 11, 100, 500, 7808)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "copies": 5}))
+        return
+
+    import paper_2407_20692_amd as cpi
+    from synth import WORKLOADS, alphas_for, generate_frames
+
+    if args.workload == "denoise":
+        print(json.dumps(denoise_bench(args, cpi, torch, np, dev)))
+        return
+    if args.workload == "denoise_step":
+        print(json.dumps(denoiser_timing(torch, np, dev)))
+        return
+
+    paper = args.workload == "paper"
+    large = args.workload == "large"
+    w = WORKLOADS[PAPER_WORKLOAD if paper else (LARGE_WORKLOAD if large else WORKLOAD)]
+    log(f"bench: generating {w.name}")
+    alphas = alphas_for(w)
+    n, pa, pb = w.n_frames, w.pa, w.pb
+    a = b = None
+    if paper:
+        n = args.files * 512
+    if large or paper:
+        from synth.gpu_speckle import generate_binary_frames_gpu
+        fmt = cpi.FRAMES_BIT1
+        fa, fb = generate_binary_frames_gpu(w, count=n, device=dev)
+        da, db = fa.reshape(-1), fb.reshape(-1)
+        frames_desc = f"1-bit packed, frame-major, {n} distinct frames generated on the device"
+    else:
+        fmt = cpi.FRAMES_U8
+        a, b = generate_frames(w)
+        da = torch.from_numpy(a.reshape(-1)).to(dev)
+        db = torch.from_numpy(b.reshape(-1)).to(dev)
+        frames_desc = "uint8 0/1, frame-major"
+    name = w.name if not paper else f"{w.name.split('_files')[0]}_files{args.files}_bit1"
+    # (the paper workload keeps the default refocus configuration: each timed
+    # candidate would take about a second at its size; its plain FP32
+    # correlator runs up to 51200 frames, whose FP32 copies fit)
+    fig, state = hot_path(args, cpi, torch, np, dev, w, n, fmt, da, db, alphas,
+                          tune=not paper, plain=not args.no_plain,
+                          plain_corr=not (paper and n > 51200),
+                          plain_planes=(4 if paper else (8 if large else None)),
+                          traffic_key=(LARGE_KEY if large else (PAPER_LIKE_KEY if not paper
+                                                                else None)))
+    pairs = float(n) * pa * pb
+    line = {
+        "metric": "Gamma pixel-pair*frames/s and refocused planes/s: int8-MFMA vs plain FP32, 1 GPU",
+        "value": pairs / (fig["ms_per_step"] * 1e-3),
+        "unit": "pixel-pair*frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fig["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp4-e2m1 0/1 operands, fp32 sums (exact); int64/fp64 epilogue; fp32 refocus",
+        "data": "synthetic",
+        "config": {"workload": name, "n_frames": n, "pa": pa, "pb": pb, "frames": frames_desc,
+                   "n_alpha": len(alphas),
+                   "alpha_range": [float(alphas[0]), float(alphas[-1])],
+                   "gamma_outputs": "FP64 + FP32, view-major",
+                   "contraction_encoding": ("FP4 (E2M1) 0/1 operands on the FP4 matrix cores "
+                                            "(exact); the int8 encoding of the same step is in "
+                                            "int8_step and roofline_int8")},
+    }
+    for k in ("correlate", "refocus", "int8_step", "fp32_plain", "roofline", "roofline_int8",
+              "roofline_refocus"):
+        if k in fig:
+            line[k] = fig[k]
+    line["int8_step"]["vs_fp32_plain_correlate"] = (
+        fig["fp32_plain"]["correlate_ms"] / fig["int8_step"]["gemm_ms"]
+        if fig.get("fp32_plain", {}).get("correlate_ms") else None)
+
+    if large and not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (sample of the large workload)")
+        line["cpu_baseline"] = cpu_baseline_large(fa, fb, state["gamma"], w, alphas)
+    if large or paper:
+        del da, db, fa, fb, state
+        torch.cuda.empty_cache()
+
+    if large and not args.no_next:
+        # the paper-like workload as a sub-object (its own steps and rooflines)
+        wl = WORKLOADS[WORKLOAD]
+        log(f"bench: generating {wl.name}")
+        al2 = alphas_for(wl)
+        a2, b2 = generate_frames(wl)
+        da2 = torch.from_numpy(a2.reshape(-1)).to(dev)
+        db2 = torch.from_numpy(b2.reshape(-1)).to(dev)
+        fig2, st2 = hot_path(args, cpi, torch, np, dev, wl, wl.n_frames, cpi.FRAMES_U8, da2, db2,
+                             al2, tune=True, plain=not args.no_plain, traffic_key=PAPER_LIKE_KEY)
+        line["paper_like"] = fig2
+        line.update(next_rows(cpi, torch, np, dev, st2["g32"], st2["geo"], wl, al2))
+        del da2, db2, st2
+    elif args.workload == "paper_like" and not args.no_next:
+        line.update(next_rows(cpi, torch, np, dev, state["g32"], state["geo"], w, alphas))
+
+    if not args.no_stream and not paper:
+        line["streaming"] = streaming_bench(args, cpi, torch, np, dev)
 
     # the device's own sustained figures beside the vendor peaks
     mp = cpi.measure_peaks(dev)
@@ -810,35 +1025,12 @@ def main():
         "what": "register-only loops of the two matrix-core ops on binary-like operands; "
                 "1 GiB device copy, read + write bytes",
     }
-    line["roofline"]["frac_of_measured_peak"] = achieved * 1e12 / mp["fp4_ops_per_s"]
-    line["roofline_int8"]["frac_of_measured_peak"] = achieved8 * 1e12 / mp["int8_ops_per_s"]
+    line["roofline"]["frac_of_measured_peak"] = (line["roofline"]["achieved"] * 1e12
+                                                 / mp["fp4_ops_per_s"])
+    line["roofline_int8"]["frac_of_measured_peak"] = (line["roofline_int8"]["achieved"] * 1e12
+                                                      / mp["int8_ops_per_s"])
 
-    if not args.no_next and not large:
-        # the paper's stack sizes (100, 261, 1000 planes) on the same Gamma
-        counts = {}
-        for na in (100, 261, 1000):
-            al = np.linspace(0.5, 1.5, na)
-            o = torch.empty(na * w.pa, dtype=torch.float32, device=dev)
-            ws_n = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, na), dev)
-            cpi.autotune_refocus(g32, geo, al, o, workspace=ws_n)
-            torch.cuda.synchronize()
-            cpi.profile_begin()
-            for _ in range(3):
-                cpi.refocus(g32, geo, al, o, workspace=ws_n)
-            torch.cuda.synchronize()
-            cpi.profile_end()
-            t = sum(cpi.profile_query(gname)[1] for gname in ("refocus_tables", "refocus_batched")) / 3
-            counts[str(na)] = {"ms": t, "planes_per_s": na / (t * 1e-3),
-                               "config_kp_rw_splits_kernel_stages": list(cpi.refocus_tiles(geo, na))}
-            del o, ws_n
-        line["refocus_plane_counts"] = counts
-        line["refocus_resampled"] = resampled_refocus_bench(cpi, torch, np, dev, g32, geo, w,
-                                                            alphas)
-        line["file_ingest"] = file_ingest_bench(cpi, torch, np, dev)
-        log("bench: denoiser training step and inference")
-        line["denoiser"] = denoiser_timing(torch, np, dev)
-
-    if not args.no_cpu_baseline and not large:
+    if args.workload == "paper_like" and not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(a, b, w, alphas)
     print(json.dumps(line), flush=True)
