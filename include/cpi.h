@@ -180,7 +180,7 @@ cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha,
                               int32_t* planes_per_group, int32_t* rows_per_wave,
                               int32_t* view_splits);
 
-/* Kernels of the batched refocus path.  Both evaluate the same sum (the
+/* Kernels of the batched refocus path.  All evaluate the same sum (the
  * bilinear sample of every view at the plane's shifted point, summed over
  * the views); they differ in summation order only.
  *   CPI_REFOCUS_ROWS: every output row interpolates its two view rows, for
@@ -188,17 +188,32 @@ cpi_status cpi_refocus_config(const cpi_geometry* g, int32_t n_alpha,
  *   CPI_REFOCUS_COLUMN_SUMS: for each lens-plane row y_b, the column
  *     interpolants of every view row the tile touches are summed over x_b
  *     first; the row weights (which depend on y_b and the output row, not on
- *     x_b) are applied once per y_b. */
-typedef enum { CPI_REFOCUS_ROWS = 0, CPI_REFOCUS_COLUMN_SUMS = 1 } cpi_refocus_kernel;
+ *     x_b) are applied once per y_b.
+ *   CPI_REFOCUS_VIEW_ROWS: the same two sums as CPI_REFOCUS_COLUMN_SUMS in
+ *     two passes: the column interpolants of every view row, summed over x_b,
+ *     are written to the workspace for each (plane, y_b), then the row
+ *     weights fold them over y_b.  Lanes are view rows, so column cells and
+ *     weights are shared by a wave.  Takes views of at most 256 rows and
+ *     plane groups whose sample columns, for the chosen output columns per
+ *     work-group, span at most 64 view columns; cpi_refocus uses the
+ *     column-sum kernel where it does not apply. */
+typedef enum {
+  CPI_REFOCUS_ROWS = 0,
+  CPI_REFOCUS_COLUMN_SUMS = 1,
+  CPI_REFOCUS_VIEW_ROWS = 2
+} cpi_refocus_kernel;
 
 /* A batched-refocus configuration: planes per work-group and output rows per
  * tile, (4, 8), (4, 16), (8, 8), (8, 16), (8, 32), (16, 8), (16, 16) for
- * both kernels and also (1, 16), (2, 16), (2, 32), (4, 32) for
- * CPI_REFOCUS_COLUMN_SUMS; view-row splits (1..16);
- * the kernel (cpi_refocus_kernel) and, for CPI_REFOCUS_COLUMN_SUMS, the number
- * of view windows staged in LDS (2, 3 or 4, and 2 or 3 for 8 planes x 32 rows,
- * whose four windows exceed a CU's LDS; ignored by CPI_REFOCUS_ROWS, and
- * reported as 0 for it). */
+ * both CPI_REFOCUS_ROWS and CPI_REFOCUS_COLUMN_SUMS and also (1, 16),
+ * (2, 16), (2, 32), (4, 32) for CPI_REFOCUS_COLUMN_SUMS; view-row splits
+ * (1..16); the kernel (cpi_refocus_kernel) and, for CPI_REFOCUS_COLUMN_SUMS,
+ * the number of view windows staged in LDS (2, 3 or 4, and 2 or 3 for 8
+ * planes x 32 rows, whose four windows exceed a CU's LDS; ignored by the
+ * other kernels, and reported as 0 for them).  For CPI_REFOCUS_VIEW_ROWS,
+ * rows_per_wave holds the output columns per work-group instead, with
+ * (planes, columns) in (8, 8), (4, 16), (8, 16), (16, 16), (8, 32), and
+ * view_splits is ignored. */
 typedef struct {
   int32_t planes_per_group;
   int32_t rows_per_wave;
@@ -214,7 +229,8 @@ cpi_status cpi_refocus_get_tiles(const cpi_geometry* g, int32_t n_alpha,
 /* cpi_refocus with an explicit configuration `tiles` (host pointer) instead
  * of the cached one.  Errors: CPI_ERR_INVALID_ARG for a null `tiles` and the
  * argument errors of cpi_refocus; CPI_ERR_UNSUPPORTED for a configuration
- * that is not built; both before any launch.  Results are bitwise
+ * that is not built, or a CPI_REFOCUS_VIEW_ROWS configuration that does not
+ * apply to the geometry and planes; all before any launch.  Results are bitwise
  * reproducible for a given configuration. */
 cpi_status cpi_refocus_tiled(const float* gamma, const cpi_geometry* g,
                              const double* alphas, int32_t n_alpha, float* out,

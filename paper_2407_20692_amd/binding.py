@@ -63,6 +63,7 @@ class RefocusTiles(ctypes.Structure):
 
 REFOCUS_ROWS = 0
 REFOCUS_COLUMN_SUMS = 1
+REFOCUS_VIEW_ROWS = 2
 
 
 class LensSampling(ctypes.Structure):

@@ -25,6 +25,7 @@ SOURCES = [
     "kernels_gemm.hip",
     "kernels_f32.hip",
     "kernels_refocus.hip",
+    "kernels_refocus_rows.hip",
     "autotune.hip",
     "peaks.hip",
     "kernels_nn.hip",

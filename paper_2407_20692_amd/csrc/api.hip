@@ -302,6 +302,26 @@ cpi_status refocus_enqueue(const float* gamma, const cpi_geometry* g, const doub
   }
   RefocusConfig c = forced ? *forced : refocus_config_for(g, n_alpha);
   float* partial = reinterpret_cast<float*>(ws + pl.off_partial);
+  if (c.mode == 2) {
+    if (rows_supported(rg, alphas, n_alpha, c.kp, c.rw, pl.rows_chunk)) {
+      RowsWorkspace w;
+      w.head = ws + pl.off_rows_head;
+      w.xe = reinterpret_cast<int32_t*>(ws + pl.off_rows_xe);
+      w.yr = reinterpret_cast<int2*>(ws + pl.off_rows_yr);
+      w.t = partial;
+      w.chunk = int(pl.rows_chunk);
+      w.wout_cap = pl.rows_wout_cap;
+      ProfScope ps("refocus_batched", st);
+      CPI_HIP(refocus_rows(gamma, rg, alphas, itab, ftab, ws + pl.off_ytab, pl.table_stride,
+                           n_alpha, c.kp, c.rw, w, out, st),
+              "refocus");
+      return CPI_OK;
+    }
+    if (forced)
+      return set_error(CPI_ERR_UNSUPPORTED,
+                       "row-lane refocus does not take this geometry or plane set");
+    c = default_sep_config(g, n_alpha);
+  }
   ProfScope ps("refocus_batched", st);
   CPI_HIP(refocus_batched(gamma, rg, itab, ftab, ws + pl.off_ytab, ws + pl.off_bounds,
                           pl.table_stride, n_alpha, c, partial, out, st),

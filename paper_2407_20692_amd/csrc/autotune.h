@@ -14,6 +14,9 @@ namespace cpi {
 // and device if any, else a default sized to fill the device.
 RefocusConfig refocus_config_for(const cpi_geometry* g, int32_t n_alpha);
 RefocusConfig default_refocus_config(const cpi_geometry* g, int32_t n_alpha);
+// The column-sum kernel's default, taken where the row-lane kernel does not
+// run the geometry or plane set.
+RefocusConfig default_sep_config(const cpi_geometry* g, int32_t n_alpha);
 
 // Times every supported configuration on the given inputs, caches the fastest
 // and leaves its result in `out`.  Synchronises `st`.

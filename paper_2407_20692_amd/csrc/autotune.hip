@@ -1,7 +1,8 @@
 // Refocus autotuner.  The paper sizes its refocusing blocks from the device
-// memory available (Section 4.1); here the work decomposition of the batched
-// kernel (planes per work-group, output rows per wave, view-row splits) is
-// chosen by timing the candidates on the caller's inputs.  Results are kept
+// memory available (Section 4.1); here the batched kernel and its work
+// decomposition (planes per work-group, output rows or columns per
+// work-group, view-row splits, staged windows) are chosen by timing the
+// candidates on the caller's inputs.  Results are kept
 // per (shape, device) in memory and, when CPI_AUTOTUNE_CACHE names a file, in
 // a text cache of lines "key kp rw splits kernel stages microseconds".
 #include <hip/hip_runtime.h>
@@ -98,10 +99,9 @@ int64_t workgroups(const cpi_geometry* g, int32_t n_alpha, const RefocusConfig& 
 
 }  // namespace
 
-// Untuned shapes: the column-sum kernel with 4 planes x 16 rows and two
-// staged windows (the fastest measured on the paper-like and the paper's
-// configurations), view splits until the grid has 8192 work-groups.
-RefocusConfig default_refocus_config(const cpi_geometry* g, int32_t n_alpha) {
+// The column-sum kernel with 4 planes x 16 rows and two staged windows, view
+// splits until the grid has 8192 work-groups.
+RefocusConfig default_sep_config(const cpi_geometry* g, int32_t n_alpha) {
   RefocusConfig c;
   c.mode = 1;
   c.stages = 2;
@@ -111,6 +111,12 @@ RefocusConfig default_refocus_config(const cpi_geometry* g, int32_t n_alpha) {
   const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
   while (c.splits * 2 <= max_splits && workgroups(g, n_alpha, c) < 8192) c.splits *= 2;
   return c;
+}
+
+// Untuned shapes: the column-sum kernel's default.  The row-lane kernel is
+// an autotuner candidate.
+RefocusConfig default_refocus_config(const cpi_geometry* g, int32_t n_alpha) {
+  return default_sep_config(g, n_alpha);
 }
 
 RefocusConfig refocus_config_for(const cpi_geometry* g, int32_t n_alpha) {
@@ -132,6 +138,10 @@ cpi_status autotune_refocus(const float* gamma, const cpi_geometry* g, const dou
                             hipStream_t st, std::string* why) {
   std::vector<RefocusConfig> cands;
   const int max_splits = g->hb < kMaxViewSplits ? g->hb : kMaxViewSplits;
+  for (const std::pair<int, int>& t : {std::make_pair(8, 8), std::make_pair(4, 16),
+                                       std::make_pair(8, 16), std::make_pair(16, 16),
+                                       std::make_pair(8, 32)})
+    cands.push_back(RefocusConfig{t.first, t.second, 1, 2, 2});
   for (int mode : {0, 1})
     for (int kp : {1, 2, 4, 8, 16})
       for (int rw : {8, 16, 32})

@@ -161,7 +161,9 @@ struct RefocusConfig {
   int rw = 8;        // output rows per work-group tile
   int splits = 1;    // view-row splits (partial sums reduced afterwards)
   int mode = 0;      // 0: per-row interpolation (k_ref_batched); 1: column sums over x_b
-                     // first, row weights once per y_b (k_ref_sep)
+                     // first, row weights once per y_b (k_ref_sep); 2: row-lane x pass
+                     // and fold (k_ref_rows), with kp planes x rw output columns per
+                     // work-group (splits and stages unused)
   int stages = 3;    // mode 1: view windows staged in LDS (2, 3 or 4)
 };
 bool refocus_config_supported(const RefocusConfig& c);
@@ -173,6 +175,32 @@ hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* 
                            int n_alpha,
                            const RefocusConfig& c, float* partial, float* out,
                            hipStream_t s);
+
+// Row-lane batched refocus (x pass over view rows, then the fold over y_b),
+// planes in chunks of `chunk` (a multiple of 16).  Workspace pieces: window
+// heads and pair entries of one chunk, touched-row ranges, and T of one chunk
+// (chunk * hb * ha * wout_cap floats).
+struct RowsWorkspace {
+  void* head = nullptr;
+  int32_t* xe = nullptr;
+  int2* yr = nullptr;
+  float* t = nullptr;
+  int chunk = 0;
+  int64_t wout_cap = 0;
+};
+bool rows_config_built(int na, int xr);
+// Smallest staged window width (16, 32 or 64 columns) that holds every
+// column cell of every (group of na planes, xr output columns) at any view,
+// or 0 if none does.
+int rows_window_width(const RefGeom& g, const double* alphas, int n_alpha, int na, int xr);
+// Whether the row-lane kernel with na planes x xr columns per work-group runs
+// this geometry and plane set with chunks of `chunk` planes (host check).
+bool rows_supported(const RefGeom& g, const double* alphas, int n_alpha, int na, int xr,
+                    int64_t chunk);
+hipError_t refocus_rows(const float* gamma, const RefGeom& g, const double* alphas,
+                        const int32_t* itab, const float* ftab, const void* ytab, int64_t stride,
+                        int n_alpha, int na, int xr, const RowsWorkspace& w, float* out,
+                        hipStream_t s);
 
 // Gamma views resampled on a lens-plane sample grid (x_b, y_b) = (ox + i sx,
 // oy + j sy), i < nx, j < ny: out[j * nx + i][.] = bilinear interpolant of the

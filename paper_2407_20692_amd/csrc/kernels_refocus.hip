@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "refocus_common.h"
 
 namespace cpi {
 
@@ -32,10 +33,6 @@ namespace {
 
 struct AlphaPack {
   double a[kAlphaPerLaunch];
-};
-
-struct GeomI {
-  int wa, ha, wb, hb, out_w, out_h;
 };
 
 __global__ __launch_bounds__(256) void k_ref_tables(AlphaPack ap, int count, int first,
@@ -123,28 +120,6 @@ __global__ __launch_bounds__(256) void k_ref_plain(const float* __restrict__ gam
   }
   out[int64_t(plane) * opix + pix] = acc;
 }
-
-// Clamp an interpolation cell [i, i+1] into [0, size-2] and move the
-// weights with it, zeroing taps that fall outside [0, size-1].  On return
-// the two loaded taps are at c and c+1 with weights w0 and w1.
-__device__ __forceinline__ void clamp_cell(int i, float f, int size, int& c, float& w0,
-                                           float& w1) {
-  const float a0 = (i >= 0 && i <= size - 1) ? 1.0f - f : 0.0f;   // tap i
-  const float a1 = (i >= -1 && i <= size - 2) ? f : 0.0f;         // tap i + 1
-  c = i < 0 ? 0 : (i > size - 2 ? size - 2 : i);
-  w0 = (i == c) ? a0 : ((i == c - 1) ? a1 : 0.0f);
-  w1 = (i == c) ? a1 : ((i == c + 1) ? a0 : 0.0f);
-}
-
-// Row table of one plane: for output row y_r and lens-plane row y_b, the
-// clamped interpolation row and its two weights (the same arithmetic as the
-// column side below), laid out [plane][y_b][y_r] so that a wave's
-// consecutive output rows are one scalar load.
-struct YEntry {
-  int row;
-  float w0, w1;
-  int pad;
-};
 
 __global__ __launch_bounds__(256) void k_ref_ytab(GeomI g, const int32_t* __restrict__ itab,
                                                   const float* __restrict__ ftab, int64_t stride,
@@ -402,13 +377,6 @@ __global__ __launch_bounds__(NW * 64) void k_ref_batched(
       if (yr < g.out_h) d[int64_t(k0 + wave) * opix + int64_t(yr) * g.out_w + xr] = acc[r];
     }
   }
-}
-
-// Wait until at most N vector-memory operations of this wave are in flight.
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
 }
 
 // Separable batched refocus.  The row side of a sample (clamped row c and
@@ -942,6 +910,7 @@ bool refocus_config_supported(const RefocusConfig& c) {
   // column-sum kernel only: fewer planes per work-group, taller tiles
   const bool sep_pair = (c.kp == 1 && c.rw == 16) || (c.kp == 2 && (c.rw == 16 || c.rw == 32)) ||
                         (c.kp == 4 && c.rw == 32);
+  if (c.mode == 2) return rows_config_built(c.kp, c.rw);
   const bool ok = c.mode == 0 ? pair_ok
                               : (c.mode == 1 && c.stages >= 2 && c.stages <= 4 &&
                                  (pair_ok || sep_pair));

@@ -186,7 +186,30 @@ cpi_status plan_refocus(const cpi_geometry* g, int32_t n_alpha, RefocusPlan* p,
   q.off_partial = off;
   const int64_t splits = std::min<int64_t>(kMaxViewSplits, g->hb);
   q.partial_bytes = size_t(splits) * size_t(n_alpha) * size_t(g->out_w) * size_t(g->out_h) * 4;
+  // Row-lane kernel: T (hb x ha x output columns per plane) of one chunk of
+  // planes shares the partial-sum region.  Every chunk streams all of Gamma
+  // once, so chunks are large: multiples of 16 planes, at most 256, as many
+  // as fit max(partial sums, 4 GiB), and at least 16 while T of 16 planes
+  // stays within 4 GiB.
+  q.rows_wout_cap = round_up(g->out_w, 64);
+  const size_t t_plane = size_t(g->hb) * size_t(g->ha) * size_t(q.rows_wout_cap) * 4;
+  const size_t budget = std::max<size_t>(q.partial_bytes, size_t(4) << 30);
+  int64_t chunk = std::min<int64_t>(round_up(n_alpha, 16), 256);
+  while (chunk > 16 && size_t(chunk) * t_plane > budget) chunk -= 16;
+  if (size_t(chunk) * t_plane > (size_t(4) << 30)) chunk = 0;
+  q.rows_chunk = chunk;
+  q.partial_bytes = std::max(q.partial_bytes, size_t(chunk) * t_plane);
   off = align256(off + q.partial_bytes);
+  // pair entries (3 words per (plane, output column, view column)) and window
+  // heads (at most one per 32 pairs) of one chunk; touched-row ranges (at
+  // most one per plane and lens-plane row)
+  const size_t pairs = size_t(chunk) * size_t(q.rows_wout_cap) * size_t(g->wb);
+  q.off_rows_xe = off;
+  off = align256(off + pairs * 12);
+  q.off_rows_head = off;
+  off = align256(off + pairs / 32 * 8 + 8);
+  q.off_rows_yr = off;
+  off = align256(off + size_t(chunk) * size_t(g->hb) * 8 + 8);
   q.total = off;
   *p = q;
   return CPI_OK;

@@ -68,7 +68,12 @@ cpi_status plan_correlate_plain(int64_t n, int64_t pa, int64_t pb, int fmt,
 struct RefocusPlan {
   int64_t table_stride = 0;         // entries per plane: out_w + out_h + wb + hb
   size_t off_itab = 0, off_ftab = 0, off_ytab = 0, off_bounds = 0, off_partial = 0;
-  size_t partial_bytes = 0;         // capacity reserved for partial sums
+  size_t partial_bytes = 0;         // capacity reserved for partial sums (and the
+                                    // row-lane kernel's T of one plane chunk)
+  // row-lane kernel: planes per chunk (0: T of 16 planes would exceed 4 GiB),
+  // output columns its T rows hold, and its table regions
+  int64_t rows_chunk = 0, rows_wout_cap = 0;
+  size_t off_rows_head = 0, off_rows_xe = 0, off_rows_yr = 0;
   size_t total = 0;
 };
 

@@ -88,7 +88,27 @@ int main() {
   CHECK(rp.off_ftab - rp.off_itab >= size_t(32 * rp.table_stride * 4));
   CHECK(rp.off_bounds - rp.off_ytab >= size_t(32) * 64 * 128 * 16);
   CHECK(rp.total - rp.off_partial >= rp.partial_bytes);
-  CHECK(rp.partial_bytes == size_t(16) * 32 * 128 * 128 * 4);
+  // the split partial sums (16 x 32 planes x 128 x 128 floats) or the
+  // row-lane kernel's T of one chunk (32 planes x hb 64 x ha 128 x 128
+  // output columns), whichever is larger
+  CHECK(rp.rows_chunk == 32 && rp.rows_wout_cap == 128);
+  CHECK(rp.partial_bytes == std::max(size_t(16) * 32 * 128 * 128 * 4,
+                                     size_t(32) * 64 * 128 * 128 * 4));
+  CHECK(rp.off_rows_xe >= rp.off_partial + rp.partial_bytes);
+  CHECK(rp.off_rows_head - rp.off_rows_xe >= size_t(32) * 128 * 64 * 12);
+  CHECK(rp.off_rows_yr > rp.off_rows_head && rp.total - rp.off_rows_yr >= size_t(32) * 64 * 8);
+  CHECK(aligned(rp.off_rows_xe) && aligned(rp.off_rows_head) && aligned(rp.off_rows_yr));
+  // 128 planes at 256 x 256 on both detectors: T of 64 planes (4 GiB)
+  cpi_geometry gp{256, 256, 256, 256, 1.0, 1.0, 127.5, 127.5, 127.5, 127.5, 256, 256};
+  CHECK(plan_refocus(&gp, 128, &rp, &why) == CPI_OK);
+  CHECK(rp.rows_chunk == 64 && rp.partial_bytes == size_t(64) * 256 * 256 * 256 * 4);
+  // 300 planes of a small geometry: chunks of at most 256 planes
+  CHECK(plan_refocus(&g, 300, &rp, &why) == CPI_OK);
+  CHECK(rp.rows_chunk == 256);
+  // views too tall for T of 16 planes within 4 GiB: no row-lane chunks
+  cpi_geometry gt{512, 4096, 128, 128, 4.0, 32.0, 255.5, 2047.5, 63.5, 63.5, 512, 4096};
+  CHECK(plan_refocus(&gt, 8, &rp, &why) == CPI_OK);
+  CHECK(rp.rows_chunk == 0);
   CHECK(plan_refocus(&g, 0, &rp, &why) == CPI_ERR_INVALID_ARG);
   CHECK(plan_refocus(&g, 4097, &rp, &why) == CPI_ERR_INVALID_ARG);
   cpi_geometry bad = g;

@@ -224,7 +224,8 @@ def test_tiles_query_and_unsupported(cpi, tiny):
     g = oracle.default_geometry(w.wa, w.ha, w.wb, w.hb)
     kp, rw, sp, kernel, stages = cpi.refocus_tiles(_geom(cpi, g), 5)
     assert ((kp, rw), (kernel, stages)) in CONFIGS and 1 <= sp <= 16
-    for bad in [(16, 32, 1, 0, 0), (8, 16, 0, 1, 3), (8, 16, 1, 2, 3), (2, 8, 1, 0, 0),
+    for bad in [(16, 32, 1, 0, 0), (8, 16, 0, 1, 3), (8, 16, 1, 3, 3), (2, 8, 1, 0, 0),
+                (2, 8, 1, 2, 0), (16, 32, 1, 2, 0),
                 (8, 16, 1, 1, 1), (8, 16, 1, 1, 5), (2, 16, 1, 0, 0), (1, 32, 1, 1, 2),
                 (8, 32, 1, 1, 4)]:
         fn = lambda gam, geo, a, out: cpi.refocus_tiled(gam, geo, a, out, bad)  # noqa: E731
