@@ -166,6 +166,23 @@ cpi_status cpi_refocus_workspace_size(const cpi_geometry* g, int32_t n_alpha,
 cpi_status cpi_refocus(const float* gamma, const cpi_geometry* g,
                        const double* alphas, int32_t n_alpha, float* out,
                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* cpi_refocus without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture into a HIP graph, serving loops,
+ * harnesses that forbid allocation).  The workspace is a 128 MiB array in the
+ * library's device memory, one per device, held until the process ends; the
+ * call allocates nothing.  It uses the configuration cpi_refocus would,
+ * except that the row-lane kernel is replaced by the column-sum kernel and
+ * view-row splits are halved until the tables and partial sums fit the
+ * array: the result is that of cpi_refocus_tiled with that configuration.
+ * Every call on one device shares its array, so calls that overlap on one
+ * device (other streams, other threads) race; serialise them.  Nothing in
+ * the array needs clearing between calls.
+ * Errors: those of cpi_refocus; CPI_ERR_WORKSPACE before any launch when the
+ * tables alone exceed 128 MiB (about n_alpha * hb * out_h * 16 bytes). */
+cpi_status cpi_refocus_noalloc(const float* gamma, const cpi_geometry* g,
+                               const double* alphas, int32_t n_alpha, float* out,
+                               void* stream);
 cpi_status cpi_refocus_plain(const float* gamma, const cpi_geometry* g,
                              const double* alphas, int32_t n_alpha, float* out,
                              void* workspace, size_t workspace_bytes, void* stream);

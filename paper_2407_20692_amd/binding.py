@@ -109,6 +109,8 @@ _SIGS = {
                             c_void_p, c_size_t, c_void_p]),
     "cpi_refocus_plain": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
+    "cpi_refocus_noalloc": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
+                                    c_void_p, c_void_p]),
     "cpi_autotune_refocus": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
                                      c_void_p, c_void_p, c_size_t, c_void_p]),
     "cpi_refocus_config": (c_int, [POINTER(Geometry), c_int32, POINTER(c_int32), POINTER(c_int32),
@@ -382,6 +384,20 @@ def _refocus_call(fn, gamma, g: Geometry, alphas, out, workspace, stream):
 def refocus(gamma, g: Geometry, alphas, out, workspace=None, stream=None):
     """Batched refocus of view-major FP32 Gamma into out (n_alpha, out_h, out_w)."""
     return _refocus_call(lib.cpi_refocus, gamma, g, alphas, out, workspace, stream)
+
+
+def refocus_noalloc(gamma, g: Geometry, alphas, out, stream=None):
+    """Batched refocus whose workspace is the library's fixed per-device array
+    (no allocation by the library or here); calls on one device must not
+    overlap."""
+    torch = _torch()
+    a, ap, na = _alphas(alphas)
+    pa = g.wa * g.ha
+    pb = g.wb * g.hb
+    _check(lib.cpi_refocus_noalloc(
+        _dev_ptr(gamma, "gamma", torch.float32, numel=pa * pb), ctypes.byref(g), ap, na,
+        _dev_ptr(out, "out", torch.float32, numel=na * g.out_w * g.out_h), _stream(stream)))
+    del a
 
 
 def refocus_plain(gamma, g: Geometry, alphas, out, workspace=None, stream=None):

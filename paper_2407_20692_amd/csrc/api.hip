@@ -329,7 +329,84 @@ cpi_status refocus_enqueue(const float* gamma, const cpi_geometry* g, const doub
   return CPI_OK;
 }
 
+// Enqueue with an explicit batched configuration against a workspace of
+// `ws_bytes`, which must hold the tables and that configuration's partial
+// sums (not the whole cpi_refocus_workspace_size).  Column-sum and per-row
+// kernels only.
+cpi_status refocus_enqueue_config(const float* gamma, const cpi_geometry* g, const double* alphas,
+                                  int32_t n_alpha, float* out, void* workspace, size_t ws_bytes,
+                                  hipStream_t st, const RefocusConfig& c) {
+  RefocusPlan pl;
+  std::string why;
+  cpi_status s = plan_refocus(g, n_alpha, &pl, &why);
+  if (s != CPI_OK) return set_error(s, why);
+  s = validate_alphas(g, alphas, n_alpha, &why);
+  if (s != CPI_OK) return set_error(s, why);
+  if (!gamma || !out || !workspace) return set_error(CPI_ERR_INVALID_ARG, "null device pointer");
+  if (!aligned16(gamma) || !aligned16(out) || !aligned16(workspace))
+    return set_error(CPI_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
+  if (c.mode == 2 || !refocus_config_supported(c))
+    return set_error(CPI_ERR_UNSUPPORTED, "refocus configuration is not built");
+  const int sp = std::min<int>(c.splits, g->hb);
+  const size_t need =
+      pl.off_partial +
+      (sp > 1 ? size_t(sp) * size_t(n_alpha) * size_t(g->out_w) * size_t(g->out_h) * 4 : 0);
+  if (ws_bytes < need)
+    return set_error(CPI_ERR_WORKSPACE, "refocus workspace too small: need " +
+                                            std::to_string(need) + " bytes");
+  uint8_t* ws = static_cast<uint8_t*>(workspace);
+  s = enqueue_tables(g, alphas, n_alpha, pl, ws, st);
+  if (s != CPI_OK) return s;
+  const RefGeom rg = ref_geom(g);
+  const int32_t* itab = reinterpret_cast<const int32_t*>(ws + pl.off_itab);
+  const float* ftab = reinterpret_cast<const float*>(ws + pl.off_ftab);
+  if (g->wa < 2 || g->ha < 2) {
+    ProfScope ps("refocus_plain", st);
+    for (int k = 0; k < n_alpha; ++k)
+      CPI_HIP(refocus_plain(gamma, rg, itab, ftab, pl.table_stride, k, out, st), "refocus");
+    return CPI_OK;
+  }
+  ProfScope ps("refocus_batched", st);
+  CPI_HIP(refocus_batched(gamma, rg, itab, ftab, ws + pl.off_ytab, ws + pl.off_bounds,
+                          pl.table_stride, n_alpha, c,
+                          reinterpret_cast<float*>(ws + pl.off_partial), out, st),
+          "refocus");
+  return CPI_OK;
+}
+
 }  // namespace cpi
+
+namespace {
+
+// Workspace of cpi_refocus_noalloc: one array per device, kept for the life
+// of the process, found once per device through its symbol address (the
+// array's name in host code is not its device address).
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+cpi_status noalloc_scratch(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(CPI_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(CPI_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(CPI_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                           hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return CPI_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -591,6 +668,38 @@ cpi_status cpi_refocus(const float* gamma, const cpi_geometry* g, const double* 
   return guarded([&]() -> cpi_status {
     return cpi::refocus_enqueue(gamma, g, alphas, n_alpha, out, workspace, workspace_bytes,
                                 static_cast<hipStream_t>(stream), nullptr, false);
+  });
+}
+
+cpi_status cpi_refocus_noalloc(const float* gamma, const cpi_geometry* g, const double* alphas,
+                               int32_t n_alpha, float* out, void* stream) {
+  return guarded([&]() -> cpi_status {
+    cpi::RefocusPlan pl;
+    std::string why;
+    cpi_status s = cpi::plan_refocus(g, n_alpha, &pl, &why);
+    if (s != CPI_OK) return set_error(s, why);
+    // The configuration cpi_refocus would take, restricted to the kernels
+    // whose workspace is the tables plus split partial sums, with view-row
+    // splits halved until that fits the scratch array.
+    cpi::RefocusConfig c = cpi::refocus_config_for(g, n_alpha);
+    if (c.mode == 2) c = cpi::default_sep_config(g, n_alpha);
+    auto need = [&](const cpi::RefocusConfig& k) {
+      const int sp = std::min<int>(k.splits, g->hb);
+      return pl.off_partial + (sp > 1 ? size_t(sp) * size_t(n_alpha) * size_t(g->out_w) *
+                                            size_t(g->out_h) * 4
+                                      : 0);
+    };
+    while (c.splits > 1 && need(c) > kNoAllocScratchBytes) c.splits /= 2;
+    if (need(c) > kNoAllocScratchBytes)
+      return set_error(CPI_ERR_WORKSPACE,
+                       "refocus needs " + std::to_string(need(c)) +
+                           " bytes of workspace; the allocation-free entry point has " +
+                           std::to_string(kNoAllocScratchBytes));
+    void* ws = nullptr;
+    s = noalloc_scratch(&ws);
+    if (s != CPI_OK) return s;
+    return cpi::refocus_enqueue_config(gamma, g, alphas, n_alpha, out, ws, need(c),
+                                       static_cast<hipStream_t>(stream), c);
   });
 }
 

@@ -26,6 +26,12 @@ cpi_status autotune_refocus(const float* gamma, const cpi_geometry* g, const dou
 
 // Enqueue a refocus (defined with the C ABI): `forced` overrides the
 // configuration; `plain` selects the one-plane-per-launch kernel.
+// Enqueue with an explicit column-sum or per-row configuration against a
+// workspace that holds the tables and that configuration's partial sums only.
+cpi_status refocus_enqueue_config(const float* gamma, const cpi_geometry* g, const double* alphas,
+                                  int32_t n_alpha, float* out, void* workspace, size_t ws_bytes,
+                                  hipStream_t st, const RefocusConfig& c);
+
 cpi_status refocus_enqueue(const float* gamma, const cpi_geometry* g, const double* alphas,
                            int32_t n_alpha, float* out, void* workspace, size_t ws_bytes,
                            hipStream_t st, const RefocusConfig* forced, bool plain);
