@@ -305,7 +305,6 @@ cpi_status refocus_enqueue(const float* gamma, const cpi_geometry* g, const doub
   if (c.mode == 2) {
     if (rows_supported(rg, alphas, n_alpha, c.kp, c.rw, pl.rows_chunk)) {
       RowsWorkspace w;
-      w.head = ws + pl.off_rows_head;
       w.xe = reinterpret_cast<int32_t*>(ws + pl.off_rows_xe);
       w.yr = reinterpret_cast<int2*>(ws + pl.off_rows_yr);
       w.t = partial;

@@ -177,11 +177,10 @@ hipError_t refocus_batched(const float* gamma, const RefGeom& g, const int32_t* 
                            hipStream_t s);
 
 // Row-lane batched refocus (x pass over view rows, then the fold over y_b),
-// planes in chunks of `chunk` (a multiple of 16).  Workspace pieces: window
-// heads and pair entries of one chunk, touched-row ranges, and T of one chunk
-// (chunk * hb * ha * wout_cap floats).
+// planes in chunks of `chunk` (a multiple of 16).  Workspace pieces: the
+// per-view tables of one chunk (header and pair entries), touched-row ranges,
+// and T of one chunk (chunk * hb * ha * wout_cap floats).
 struct RowsWorkspace {
-  void* head = nullptr;
   int32_t* xe = nullptr;
   int2* yr = nullptr;
   float* t = nullptr;

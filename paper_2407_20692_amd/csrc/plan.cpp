@@ -200,14 +200,12 @@ cpi_status plan_refocus(const cpi_geometry* g, int32_t n_alpha, RefocusPlan* p,
   q.rows_chunk = chunk;
   q.partial_bytes = std::max(q.partial_bytes, size_t(chunk) * t_plane);
   off = align256(off + q.partial_bytes);
-  // pair entries (3 words per (plane, output column, view column)) and window
-  // heads (at most one per 32 pairs) of one chunk; touched-row ranges (at
+  // per-view tables of one chunk: 3 words per (plane, output column, view
+  // column) and a 4-word header per 64 or more pairs; touched-row ranges (at
   // most one per plane and lens-plane row)
   const size_t pairs = size_t(chunk) * size_t(q.rows_wout_cap) * size_t(g->wb);
   q.off_rows_xe = off;
-  off = align256(off + pairs * 12);
-  q.off_rows_head = off;
-  off = align256(off + pairs / 32 * 8 + 8);
+  off = align256(off + pairs * 12 + pairs / 4 + 16);
   q.off_rows_yr = off;
   off = align256(off + size_t(chunk) * size_t(g->hb) * 8 + 8);
   q.total = off;

@@ -73,7 +73,7 @@ struct RefocusPlan {
   // row-lane kernel: planes per chunk (0: T of 16 planes would exceed 4 GiB),
   // output columns its T rows hold, and its table regions
   int64_t rows_chunk = 0, rows_wout_cap = 0;
-  size_t off_rows_head = 0, off_rows_xe = 0, off_rows_yr = 0;
+  size_t off_rows_xe = 0, off_rows_yr = 0;
   size_t total = 0;
 };
 
