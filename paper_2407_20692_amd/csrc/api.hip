@@ -302,6 +302,17 @@ cpi_status refocus_enqueue(const float* gamma, const cpi_geometry* g, const doub
   }
   RefocusConfig c = forced ? *forced : refocus_config_for(g, n_alpha);
   float* partial = reinterpret_cast<float*>(ws + pl.off_partial);
+  if (c.mode == 2 && !forced && !rows_supported(rg, alphas, n_alpha, c.kp, c.rw, pl.rows_chunk)) {
+    // the configured row-lane shape does not take this plane set: the next
+    // shape whose windows hold it, in order of pairs per work-group
+    for (const auto& t : {std::make_pair(8, 32), std::make_pair(16, 16), std::make_pair(8, 16),
+                          std::make_pair(16, 8), std::make_pair(8, 8), std::make_pair(4, 16)})
+      if (rows_supported(rg, alphas, n_alpha, t.first, t.second, pl.rows_chunk)) {
+        c.kp = t.first;
+        c.rw = t.second;
+        break;
+      }
+  }
   if (c.mode == 2) {
     if (rows_supported(rg, alphas, n_alpha, c.kp, c.rw, pl.rows_chunk)) {
       RowsWorkspace w;

@@ -447,7 +447,23 @@ __global__ __launch_bounds__(256) void k_ref_rows_fold(GeomI g, const YEntry* __
     const YEntry* ye = ytab + int64_t(first + pl) * g.hb * g.out_h + yr_;
     const float* tp = tin + int64_t(pl) * plane_stride + xr;
     float acc = 0.0f;
-    for (int yb = 0; yb < g.hb; ++yb) {
+    // 8 lens-plane rows' loads in flight at a time; summed in order of y_b
+    int yb = 0;
+    for (; yb + 8 <= g.hb; yb += 8) {
+      float v0[8], v1[8], w0[8], w1[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const YEntry e = ye[int64_t(yb + k) * g.out_h];
+        const float* r = tp + (int64_t(yb + k) * g.ha + e.row) * wout_pad;
+        v0[k] = r[0];
+        v1[k] = r[wout_pad];
+        w0[k] = e.w0;
+        w1[k] = e.w1;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += __builtin_fmaf(w1[k], v1[k], w0[k] * v0[k]);
+    }
+    for (; yb < g.hb; ++yb) {
       const YEntry e = ye[int64_t(yb) * g.out_h];
       const float* r = tp + (int64_t(yb) * g.ha + e.row) * wout_pad;
       acc += __builtin_fmaf(e.w1, r[wout_pad], e.w0 * r[0]);

@@ -48,15 +48,19 @@ def _both(cpi, g, gam32, al, tiles=None):
 
 def test_two_calls_second_smaller(cpi):
     """Two calls in a row on one device, the second with a smaller geometry
-    and fewer planes: each equals cpi_refocus bit for bit and meets the
-    tolerance against the oracle."""
+    and fewer planes: each meets the refocus tolerance against cpi_refocus
+    (which may take the row-lane kernel, summing in another order) and
+    against the oracle; where cpi_refocus takes the column-sum kernel, the
+    two are equal bit for bit."""
     for seed, g, n_alpha in [
             (11, oracle.Geometry(64, 64, 16, 16, 4.0, 4.0, 31.5, 31.5, 7.5, 7.5, 64, 64), 13),
             (12, oracle.Geometry(32, 24, 8, 6, 4.0, 4.0, 15.5, 11.5, 3.5, 2.5, 30, 20), 5)]:
         log(f"case noalloc seed {seed} {g.wa}x{g.ha} views {g.wb}x{g.hb} planes {n_alpha}")
         gam32, al = _case(seed, g, n_alpha)
         got, ref = _both(cpi, g, gam32, al)
-        assert np.array_equal(got, ref)
+        assert plane_rel_err(got, ref).max() <= TOL
+        if cpi.refocus_tiles(cpi.make_geometry(**g.__dict__), n_alpha)[3] != 2:
+            assert np.array_equal(got, ref)
         want = oracle.refocus(gam32.astype(np.float64), g, al)
         err = plane_rel_err(got, want)
         log(f"noalloc seed {seed}: worst plane relative error {err.max():.3g}")
@@ -64,17 +68,19 @@ def test_two_calls_second_smaller(cpi):
 
 
 def test_splits_reduced_to_fit(cpi):
-    """200 planes at Da 128x128, Db 64x64: the column-sum default's 16
-    view-row splits need more than the 128 MiB array; the call takes 8
-    splits and equals cpi_refocus_tiled with that configuration, sampled
+    """200 planes at Da 128x128, Db 64x64: cpi_refocus's default is the
+    row-lane kernel, which the allocation-free call replaces by the
+    column-sum default (4 planes x 16 rows, 16 view-row splits, 2 staged
+    windows); its partial sums need more than the 128 MiB array, so it takes
+    8 splits: equal to cpi_refocus_tiled with that configuration, sampled
     pixels within the tolerance of the oracle."""
     g = oracle.default_geometry(128, 128, 64, 64)
     gam32, al = _case(13, g, 200)
-    kp, rw, sp, kernel, stages = cpi.refocus_tiles(cpi.make_geometry(**g.__dict__), 200)
-    if kernel != 1 or sp != 16:
-        pytest.skip(f"cpi_refocus takes {(kp, rw, sp, kernel, stages)} here (tuned cache)")
+    tiles = cpi.refocus_tiles(cpi.make_geometry(**g.__dict__), 200)
+    if tiles[3] != 2:
+        pytest.skip(f"cpi_refocus takes {tiles} here (tuned cache)")
     log("case noalloc 200 planes, splits reduced")
-    got, ref = _both(cpi, g, gam32, al, tiles=(kp, rw, 8, kernel, stages))
+    got, ref = _both(cpi, g, gam32, al, tiles=(4, 16, 8, 1, 2))
     assert np.array_equal(got, ref)
     rng = np.random.default_rng(14)
     ys, xs = rng.integers(0, g.out_h, 48), rng.integers(0, g.out_w, 48)
