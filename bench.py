@@ -63,13 +63,17 @@ INT8_PEAK = 5.0e15          # dense int8 matrix-core ops/s, MI355X
 FP4_PEAK = 10.1e15          # dense FP4 (and FP6) matrix-core ops/s, MI355X
 FP32_VECTOR_PEAK = 157.3e12  # FP32 vector FLOP/s, MI355X (packed FP32 FMA)
 FP32_UNPACKED_PEAK = 78.6e12  # FP32 vector FLOP/s with one FMA per lane per cycle
-# LDS read bandwidth: 128 bytes per clock per CU, 256 CUs, 2.4 GHz
-LDS_PEAK = 128 * 256 * 2.4e9
+# LDS read bandwidth for 8- and 16-byte reads: 256 bytes per clock per CU,
+# 256 CUs, 2.4 GHz (a microbenchmark of conflict-free ds_read_b64 / b128 on
+# this part sustains 220-236 bytes per clock per CU; the paired and 4-byte
+# forms run at half that)
+LDS_PEAK = 256 * 256 * 2.4e9
 # workload keys of the committed counter summaries (contraction, refocus)
 PAPER_LIKE_KEY = ("da128_db64_n20000", "da128_db64_32planes")
 LARGE_KEY = ("da256_db128_n100000", "da256_db128_128planes")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_gemm.hip")
 REF_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_refocus.hip")
+ROWS_SOURCE = os.path.join(ROOT, "paper_2407_20692_amd", "csrc", "kernels_refocus_rows.hip")
 
 
 def log(msg):
@@ -705,11 +709,15 @@ def hot_path(args, cpi, torch, np, dev, w, n, fmt, da, db, alphas, tune=True, pl
     }
     fig["roofline_refocus"] = refocus_roofline(cpi, geo, alphas, groups["refocus_batched"],
                                                traffic_key)
-    # the other batched-refocus kernel with the same tiles (same inputs), where
-    # it is built for them (the column-sum kernel also takes shapes the
-    # per-row kernel does not)
+    # another batched-refocus kernel on the same inputs: for the row-lane
+    # kernel, the column-sum kernel's untuned default; otherwise the other of
+    # the per-row and column-sum kernels with the same tiles, where it is built
+    # for them
     tiles = cpi.refocus_tiles(geo, na)
-    other = (tiles[0], tiles[1], tiles[2], 1 - tiles[3], 2)
+    if tiles[3] == 2:
+        other = (4, 16 if geo.out_h >= 16 else 8, 16, 1, 2)
+    else:
+        other = (tiles[0], tiles[1], tiles[2], 1 - tiles[3], 2)
     try:
         cpi.refocus_tiled(g32, geo, alphas, out, other, workspace=ws_r)
     except cpi.CpiError:
@@ -722,7 +730,7 @@ def hot_path(args, cpi, torch, np, dev, w, n, fmt, da, db, alphas, tune=True, pl
         torch.cuda.synchronize()
         cpi.profile_end()
         cnt, tot = cpi.profile_query("refocus_batched")
-        fig["roofline_refocus"]["other_kernel_same_tiles"] = {
+        fig["roofline_refocus"]["other_kernel"] = {
             "tiles_kp_rw_splits_kernel_stages": list(other), "launch_ms": tot / max(cnt, 1)}
     state = {"gamma": gamma, "g32": g32, "geo": geo, "out": out, "ws_r": ws_r, "ws_c": ws_c}
     return fig, state
@@ -732,7 +740,8 @@ def pmc_summary(kind, key):
     """Committed counter summary of a kernel on a workload (None if no key)."""
     if key is None:
         return None
-    name = {"gemm": f"gemm_f4lds_{key[0]}_pmc.txt", "refocus": f"ref_sep_{key[1]}_pmc.txt"}[kind]
+    name = {"gemm": f"gemm_f4lds_{key[0]}_pmc.txt", "refocus": f"ref_sep_{key[1]}_pmc.txt",
+            "refocus_rows": f"ref_rows_{key[1]}_pmc.txt"}[kind]
     return os.path.join(ROOT, "profiles", name)
 
 
@@ -749,9 +758,15 @@ def refocus_roofline(cpi, geo, alphas, launch_ms, traffic_key):
     achieved = flops / (launch_ms * 1e-3) / 1e12
     tiles = cpi.refocus_tiles(geo, na)
     foot = refocus_algorithmic_bytes(geo, alphas)
-    traffic = measured_traffic(pmc_summary("refocus", traffic_key), REF_SOURCE, tiles)
+    rows = tiles[3] == 2
+    summary = pmc_summary("refocus_rows" if rows else "refocus", traffic_key)
+    source = ROWS_SOURCE if rows else REF_SOURCE
+    traffic = measured_traffic(summary, source, tiles)
     r = {
-        "kernel": ("k_ref_sep (planes batched per work-group, LDS-staged view windows, column "
+        "kernel": ("k_ref_rows + k_ref_rows_fold (row-lane x pass: lanes are view rows, window "
+                   "staged column by column in LDS, column cells and weights from a per-view "
+                   "table; then the fold over y_b)" if rows else
+                   "k_ref_sep (planes batched per work-group, LDS-staged view windows, column "
                    "interpolants summed over x_b before the row weights)" if tiles[3] == 1 else
                    "k_ref_batched (planes batched per work-group, LDS-staged view windows)"),
         "tiles_kp_rw_splits_kernel_stages": list(tiles),
@@ -771,11 +786,14 @@ def refocus_roofline(cpi, geo, alphas, launch_ms, traffic_key):
     if traffic:
         bw = traffic / (launch_ms * 1e-3) / 1e9
         r["hbm"] = {"GBps": bw, "peak": 8000.0, "frac": bw / 8000.0}
-    lds = measured_lds(pmc_summary("refocus", traffic_key), REF_SOURCE, tiles)
+    lds = measured_lds(summary, source, tiles)
     if lds:
         bw = lds / (launch_ms * 1e-3) / 1e12
         r["lds"] = {"bytes_per_launch": lds, "TBps": bw, "peak": LDS_PEAK / 1e12,
-                    "frac": bw * 1e12 / LDS_PEAK}
+                    "frac": bw * 1e12 / LDS_PEAK,
+                    "note": "LDS bytes read per launch from rocprofv3 counters (committed "
+                            "summary taken on this kernel source and tiles) over the whole "
+                            "refocus call's time"}
     return r
 
 

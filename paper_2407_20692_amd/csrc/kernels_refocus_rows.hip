@@ -14,16 +14,19 @@
 // 128 view rows, a group of NA planes and XR consecutive output columns:
 // P = NA * XR (plane, column) pairs, 64 per wave.  Each lane holds two view
 // rows, so for a given view and pair the column cell is the same for every
-// lane: cells and weights come from a table (k_rows_xtab) through scalar
-// loads, and the weights are scalar operands of the multiply-adds.  For
-// every view x_b the work-group stages a window of the band's rows and WW
-// columns (the union of its pairs' cells) in LDS, two stages deep, stored
-// column by column: one ds_read2_b64 then gives a lane both taps of both its
-// rows.  The window is loaded with coalesced 16-byte reads (16 rows x 64
-// bytes per instruction) into registers while the previous view is
-// interpolated, and stored transposed; a column stride of 132 floats keeps
-// those stores free of bank conflicts.  Work-groups are mapped so that all
-// those of one y_b run on one XCD and share its L2.
+// lane.  Cells and weights come from a per-view table (k_rows_xtab) staged
+// in LDS beside the window: three 16-byte reads per lane and view put 16
+// pairs' values in each register, one pair per lane of a row of 16, and a
+// DPP row broadcast hands a pair's value to every lane as an operand of the
+// address add and of the multiply-adds, so the table costs no LDS traffic
+// per tap.  For every view x_b the work-group stages a window of the band's
+// rows and WW columns (the union of its pairs' cells) in LDS, two stages
+// deep, stored column by column: two single 8-byte reads give a lane both
+// taps of both its rows.  The window is loaded with coalesced 16-byte reads
+// (16 rows x 64 bytes per instruction) into registers while the previous
+// view is interpolated, and stored transposed; a column stride of 132 floats
+// keeps those stores free of bank conflicts.  Work-groups are mapped so that
+// all those of one y_b run on one XCD and share its L2.
 //
 // Fold pass (k_ref_rows_fold): one thread per output pixel of a plane sums
 // the two T rows of each y_b with the row weights.
@@ -50,6 +53,11 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kRowsBand = 128;       // view rows per work-group (two per lane)
 constexpr int kBufferWord3 = 0x00020000;   // buffer descriptor word 3 for gfx9 (32-bit data)
 constexpr int kRowsColStride = 132;  // LDS floats per window column (even; 132 = 4 mod 64)
+
+// (plane, column) pairs per wave: 64 for work-groups of 256 pairs, else 32,
+// so that a work-group of 128 pairs has four waves and two such work-groups
+// (their LDS fits a CU twice) keep two waves on every SIMD.
+constexpr int rows_pairs_per_wave(int pairs) { return pairs >= 256 ? 64 : 32; }
 
 // Column cells of every (plane, output column) pair of work-group (group gq,
 // tile t) against lens-plane column x_b: a 4-word header (window start, and
@@ -109,10 +117,15 @@ __global__ __launch_bounds__(NA * XR) void k_rows_xtab(GeomI g, const int32_t* _
   // LDS reads inside it regardless.
   int rel = live ? c - wx0 : 0;
   rel = rel < 0 ? 0 : (rel > ww - 2 ? ww - 2 : rel);
+  // per wave slice of PW pairs: offsets, w0, w1, each PW words with pair
+  // 16 k + i of the slice at word NK i + k (NK = PW / 16: one read of NK
+  // words per lane gives lane i of every row of 16 the pairs it broadcasts)
+  constexpr int PW = rows_pairs_per_wave(P), NK = PW / 16;
   int32_t* e = xe + idx * (4 + 3 * P);
-  e[4 + p] = rel * kRowsColStride * 4;
-  e[4 + P + p] = __builtin_bit_cast(int32_t, live ? w0 : 0.0f);
-  e[4 + 2 * P + p] = __builtin_bit_cast(int32_t, live ? w1 : 0.0f);
+  const int q = p % PW, slot = 4 + 3 * PW * (p / PW) + NK * (q % 16) + q / 16;
+  e[slot] = rel * kRowsColStride * 4;
+  e[slot + PW] = __builtin_bit_cast(int32_t, live ? w0 : 0.0f);
+  e[slot + 2 * PW] = __builtin_bit_cast(int32_t, live ? w1 : 0.0f);
   if (p == 0) {
     e[0] = wx0;
     e[1] = int32_t(slive);
@@ -158,151 +171,213 @@ __global__ __launch_bounds__(256) void k_rows_yrange(GeomI g, const YEntry* __re
 template <int NA, int XR, int WW>
 struct RowsShape {
   static constexpr int P = NA * XR;               // (plane, column) pairs
-  static constexpr int NPS = P / 64;              // waves (64 pairs each)
+  static constexpr int PW = rows_pairs_per_wave(P);   // pairs per wave
+  static constexpr int NK = PW / 16;              // table values per lane and kind
+  static constexpr int NSTEP = PW / 4;            // steps (4 pairs each) per view
+  static constexpr int NPS = P / PW;              // waves
   static constexpr int TAB = 4 + 3 * P;           // table words per view (header, offsets, w0, w1)
   static constexpr int WIN = WW * kRowsColStride;    // window floats per stage
   static constexpr int STAGE = WIN + TAB;         // floats per stage
   static constexpr int NCP = 2 * (WW / 4);        // 16-row x 64-byte copies per view
   static constexpr int CPW = NCP / NPS;           // copies per wave per view
+  static constexpr int PH = CPW > 8 ? CPW / 8 : 1;  // copy phases per view (8 copies each)
+  static constexpr int CPH = CPW / PH;            // copies per phase
+  static constexpr int NM = 8 / NPS;              // row blocks a wave copies
   static_assert(P % 64 == 0 && P <= 256 && (XR % 64 == 0 || 64 % XR == 0) && XR % 4 == 0,
                 "pair layout");
   static_assert(WW == 16 || WW == 32 || WW == 64, "window width");
-  static_assert(NCP % NPS == 0, "copies per wave");
+  static_assert(NPS <= 8 && NCP % NPS == 0 && CPW % PH == 0 && NSTEP % PH == 0,
+                "copies per wave");
   static_assert(TAB / 4 <= NPS * 64, "table copy");
   static_assert(2 * STAGE * 4 <= 160 * 1024, "LDS");
 };
 
 typedef int i4 __attribute__((ext_vector_type(4)));
+template <int N>
+using ivec = int __attribute__((ext_vector_type(N)));
+template <int N>
+using fvec = float __attribute__((ext_vector_type(N)));
 
-// A wave's pass over its 64 pairs for one view, 4 pairs (chunk C) per step.
-// Each step is one inline-asm block that issues the LDS reads of chunk C + 1
-// (the 8 tap reads: both rows of a lane at the cell's column and at the next,
-// single 8-byte reads, which run at twice the rate of the paired form the
-// compiler would merge them into; the weights of chunk C + 1 and the cell
-// offsets of chunk C + 2, broadcast reads of the staged table at `tb`:
-// offsets, then P w0, then P w1), then the 16 multiply-adds of chunk C on
-// values read by the previous step, then waits for its reads: the LDS
-// latency of one chunk overlaps the arithmetic of the previous one.
-struct RowsChunk {
-  f2 lo[4], hi[4];   // taps: rows 2 lane, 2 lane + 1 at the cell's column / the next
-  f4 w0, w1;         // weights of the 4 pairs
+// The per-view table of a wave's PW pairs, as read by each lane: component k
+// of lane 16 r + i belongs to pair 16 k + i (every row of 16 lanes holds the
+// same values).  A DPP row broadcast (lane i of each row to the whole row)
+// then makes a pair's value an operand of every lane's instruction: the
+// column offset of its cell for the tap address, its weights for the
+// multiply-adds.
+template <int NK>
+struct RowsTab {
+  ivec<NK> off;     // byte offset of the cell's column in the window
+  fvec<NK> w0, w1;  // weights of the cell's two columns
+};
+struct RowsTaps {
+  f2 lo[4], hi[4];   // rows 2 lane, 2 lane + 1 at the cell's column / the next
 };
 
-template <int C, int P>
-__device__ __forceinline__ void rows_step(uint32_t tb, uint32_t lbase, RowsChunk& cur,
-                                          i4& off_next, float (&acc0)[64], float (&acc1)[64]) {
-  static_assert(kRowsColStride * 4 == 528, "column offset below");
+#define CPI_ROWS_READS                           \
+  "ds_read_b64 %[t0], %[a0]\n"                   \
+  "ds_read_b64 %[u0], %[a0] offset:528\n"        \
+  "ds_read_b64 %[t1], %[a1]\n"                   \
+  "ds_read_b64 %[u1], %[a1] offset:528\n"        \
+  "ds_read_b64 %[t2], %[a2]\n"                   \
+  "ds_read_b64 %[u2], %[a2] offset:528\n"        \
+  "ds_read_b64 %[t3], %[a3]\n"                   \
+  "ds_read_b64 %[u3], %[a3] offset:528\n"
+#define CPI_ROWS_ADDRS                                                            \
+  "v_add_u32_dpp %[b0], %[of], %[lb] row_newbcast:%[m0] row_mask:0xf bank_mask:0xf\n" \
+  "v_add_u32_dpp %[b1], %[of], %[lb] row_newbcast:%[m1] row_mask:0xf bank_mask:0xf\n" \
+  "v_add_u32_dpp %[b2], %[of], %[lb] row_newbcast:%[m2] row_mask:0xf bank_mask:0xf\n" \
+  "v_add_u32_dpp %[b3], %[of], %[lb] row_newbcast:%[m3] row_mask:0xf bank_mask:0xf\n"
+#define CPI_ROWS_FMA(c, w, v, n) \
+  "v_fmac_f32_dpp %[" c "], %[" w "], %[" v "] row_newbcast:%[" n "] row_mask:0xf bank_mask:0xf\n"
+#define CPI_ROWS_FMAS                                                            \
+  CPI_ROWS_FMA("c00", "x", "l0x", "n0") CPI_ROWS_FMA("c10", "x", "l0y", "n0")   \
+  CPI_ROWS_FMA("c00", "y", "h0x", "n0") CPI_ROWS_FMA("c10", "y", "h0y", "n0")   \
+  CPI_ROWS_FMA("c01", "x", "l1x", "n1") CPI_ROWS_FMA("c11", "x", "l1y", "n1")   \
+  CPI_ROWS_FMA("c01", "y", "h1x", "n1") CPI_ROWS_FMA("c11", "y", "h1y", "n1")   \
+  CPI_ROWS_FMA("c02", "x", "l2x", "n2") CPI_ROWS_FMA("c12", "x", "l2y", "n2")   \
+  CPI_ROWS_FMA("c02", "y", "h2x", "n2") CPI_ROWS_FMA("c12", "y", "h2y", "n2")   \
+  CPI_ROWS_FMA("c03", "x", "l3x", "n3") CPI_ROWS_FMA("c13", "x", "l3y", "n3")   \
+  CPI_ROWS_FMA("c03", "y", "h3x", "n3") CPI_ROWS_FMA("c13", "y", "h3y", "n3")
+#define CPI_ROWS_ACC_OUT                                                                   \
+  [c00] "+v"(acc0[p]), [c01] "+v"(acc0[p + 1]), [c02] "+v"(acc0[p + 2]),                   \
+      [c03] "+v"(acc0[p + 3]), [c10] "+v"(acc1[p]), [c11] "+v"(acc1[p + 1]),               \
+      [c12] "+v"(acc1[p + 2]), [c13] "+v"(acc1[p + 3])
+#define CPI_ROWS_FMA_IN                                                                    \
+  [x] "v"(tb.w0[K]), [y] "v"(tb.w1[K]), [n0] "i"(I), [n1] "i"(I + 1), [n2] "i"(I + 2),     \
+      [n3] "i"(I + 3), [l0x] "v"(cur.lo[0].x), [l0y] "v"(cur.lo[0].y),                     \
+      [l1x] "v"(cur.lo[1].x), [l1y] "v"(cur.lo[1].y), [l2x] "v"(cur.lo[2].x),              \
+      [l2y] "v"(cur.lo[2].y), [l3x] "v"(cur.lo[3].x), [l3y] "v"(cur.lo[3].y),              \
+      [h0x] "v"(cur.hi[0].x), [h0y] "v"(cur.hi[0].y), [h1x] "v"(cur.hi[1].x),              \
+      [h1y] "v"(cur.hi[1].y), [h2x] "v"(cur.hi[2].x), [h2y] "v"(cur.hi[2].y),              \
+      [h3x] "v"(cur.hi[3].x), [h3y] "v"(cur.hi[3].y)
+#define CPI_ROWS_READ_OUT                                                                  \
+  [t0] "=&v"(nx.lo[0]), [t1] "=&v"(nx.lo[1]), [t2] "=&v"(nx.lo[2]), [t3] "=&v"(nx.lo[3]), \
+      [u0] "=&v"(nx.hi[0]), [u1] "=&v"(nx.hi[1]), [u2] "=&v"(nx.hi[2]), [u3] "=&v"(nx.hi[3])
+
+// A wave's pass over its PW pairs for one view, 4 pairs (chunk C) per step.
+// Each step is one inline-asm block that issues the 8 tap reads of chunk
+// C + 1 (both rows of a lane at the cell's column and at the next: single
+// 8-byte reads, which run at twice the rate of the paired form the compiler
+// would merge them into), forms the tap addresses of chunk C + 2, does the 16
+// multiply-adds of chunk C on values read by the previous step, then waits
+// for its reads: the LDS latency of one chunk overlaps the arithmetic of the
+// previous one.  (DPP operands here are only ever written by LDS reads, or
+// by VALU instructions at least two instructions earlier.)
+template <int C, int NSTEP, int NK, int PW>
+__device__ __forceinline__ void rows_step(uint32_t lbase, const RowsTab<NK>& tb, RowsTaps& cur,
+                                          uint32_t (&addr)[4], float (&acc0)[PW],
+                                          float (&acc1)[PW]) {
   constexpr int p = 4 * C;
-  if constexpr (C == 15) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float w0 = cur.w0[i], w1 = cur.w1[i];
-      acc0[p + i] = __builtin_fmaf(w0, cur.lo[i].x, acc0[p + i]);
-      acc1[p + i] = __builtin_fmaf(w0, cur.lo[i].y, acc1[p + i]);
-      acc0[p + i] = __builtin_fmaf(w1, cur.hi[i].x, acc0[p + i]);
-      acc1[p + i] = __builtin_fmaf(w1, cur.hi[i].y, acc1[p + i]);
-    }
-  } else {
-    constexpr int kW0 = P * 4 + 16 * (C + 1), kW1 = 2 * P * 4 + 16 * (C + 1);
-    constexpr int kOn = 16 * (C + 2 < 16 ? C + 2 : 15);
-    const uint32_t a0 = lbase + uint32_t(off_next.x), a1 = lbase + uint32_t(off_next.y);
-    const uint32_t a2 = lbase + uint32_t(off_next.z), a3 = lbase + uint32_t(off_next.w);
-    RowsChunk nx;
-    i4 on;
-    asm volatile(
-        "ds_read_b64 %[t0], %[a0]\n"
-        "ds_read_b64 %[u0], %[a0] offset:528\n"
-        "ds_read_b64 %[t1], %[a1]\n"
-        "ds_read_b64 %[u1], %[a1] offset:528\n"
-        "ds_read_b64 %[t2], %[a2]\n"
-        "ds_read_b64 %[u2], %[a2] offset:528\n"
-        "ds_read_b64 %[t3], %[a3]\n"
-        "ds_read_b64 %[u3], %[a3] offset:528\n"
-        "ds_read_b128 %[w0], %[tb] offset:%[kw0]\n"
-        "ds_read_b128 %[w1], %[tb] offset:%[kw1]\n"
-        "ds_read_b128 %[on], %[tb] offset:%[kon]\n"
-        "v_fmac_f32 %[c00], %[x0], %[l0x]\n"
-        "v_fmac_f32 %[c10], %[x0], %[l0y]\n"
-        "v_fmac_f32 %[c00], %[y0], %[h0x]\n"
-        "v_fmac_f32 %[c10], %[y0], %[h0y]\n"
-        "v_fmac_f32 %[c01], %[x1], %[l1x]\n"
-        "v_fmac_f32 %[c11], %[x1], %[l1y]\n"
-        "v_fmac_f32 %[c01], %[y1], %[h1x]\n"
-        "v_fmac_f32 %[c11], %[y1], %[h1y]\n"
-        "v_fmac_f32 %[c02], %[x2], %[l2x]\n"
-        "v_fmac_f32 %[c12], %[x2], %[l2y]\n"
-        "v_fmac_f32 %[c02], %[y2], %[h2x]\n"
-        "v_fmac_f32 %[c12], %[y2], %[h2y]\n"
-        "v_fmac_f32 %[c03], %[x3], %[l3x]\n"
-        "v_fmac_f32 %[c13], %[x3], %[l3y]\n"
-        "v_fmac_f32 %[c03], %[y3], %[h3x]\n"
-        "v_fmac_f32 %[c13], %[y3], %[h3y]\n"
-        "s_waitcnt lgkmcnt(0)"
-        : [t0] "=&v"(nx.lo[0]), [t1] "=&v"(nx.lo[1]), [t2] "=&v"(nx.lo[2]), [t3] "=&v"(nx.lo[3]),
-          [u0] "=&v"(nx.hi[0]), [u1] "=&v"(nx.hi[1]), [u2] "=&v"(nx.hi[2]), [u3] "=&v"(nx.hi[3]),
-          [w0] "=&v"(nx.w0), [w1] "=&v"(nx.w1), [on] "=&v"(on),
-          [c00] "+v"(acc0[p]), [c01] "+v"(acc0[p + 1]), [c02] "+v"(acc0[p + 2]),
-          [c03] "+v"(acc0[p + 3]), [c10] "+v"(acc1[p]), [c11] "+v"(acc1[p + 1]),
-          [c12] "+v"(acc1[p + 2]), [c13] "+v"(acc1[p + 3])
-        : [a0] "v"(a0), [a1] "v"(a1), [a2] "v"(a2), [a3] "v"(a3), [tb] "v"(tb),
-          [kw0] "i"(kW0), [kw1] "i"(kW1), [kon] "i"(kOn),
-          [x0] "v"(cur.w0.x), [x1] "v"(cur.w0.y), [x2] "v"(cur.w0.z), [x3] "v"(cur.w0.w),
-          [y0] "v"(cur.w1.x), [y1] "v"(cur.w1.y), [y2] "v"(cur.w1.z), [y3] "v"(cur.w1.w),
-          [l0x] "v"(cur.lo[0].x), [l0y] "v"(cur.lo[0].y), [l1x] "v"(cur.lo[1].x),
-          [l1y] "v"(cur.lo[1].y), [l2x] "v"(cur.lo[2].x), [l2y] "v"(cur.lo[2].y),
-          [l3x] "v"(cur.lo[3].x), [l3y] "v"(cur.lo[3].y), [h0x] "v"(cur.hi[0].x),
-          [h0y] "v"(cur.hi[0].y), [h1x] "v"(cur.hi[1].x), [h1y] "v"(cur.hi[1].y),
-          [h2x] "v"(cur.hi[2].x), [h2y] "v"(cur.hi[2].y), [h3x] "v"(cur.hi[3].x),
-          [h3y] "v"(cur.hi[3].y));
+  constexpr int K = C / 4, I = 4 * (C % 4);             // chunk C's pairs: component, lanes
+  constexpr int K2 = (C + 2) / 4, I2 = 4 * ((C + 2) % 4); // chunk C + 2's
+  if constexpr (C == NSTEP - 1) {
+    asm volatile("s_nop 1\n" CPI_ROWS_FMAS : CPI_ROWS_ACC_OUT : CPI_ROWS_FMA_IN);
+  } else if constexpr (C == NSTEP - 2) {
+    RowsTaps nx;
+    asm volatile(CPI_ROWS_READS CPI_ROWS_FMAS "s_waitcnt lgkmcnt(0)"
+                 : CPI_ROWS_READ_OUT, CPI_ROWS_ACC_OUT
+                 : [a0] "v"(addr[0]), [a1] "v"(addr[1]), [a2] "v"(addr[2]), [a3] "v"(addr[3]),
+                   CPI_ROWS_FMA_IN);
     cur = nx;
-    off_next = on;
+  } else {
+    RowsTaps nx;
+    uint32_t na[4];
+    asm volatile(CPI_ROWS_READS CPI_ROWS_ADDRS CPI_ROWS_FMAS "s_waitcnt lgkmcnt(0)"
+                 : CPI_ROWS_READ_OUT, [b0] "=&v"(na[0]), [b1] "=&v"(na[1]), [b2] "=&v"(na[2]),
+                   [b3] "=&v"(na[3]), CPI_ROWS_ACC_OUT
+                 : [a0] "v"(addr[0]), [a1] "v"(addr[1]), [a2] "v"(addr[2]), [a3] "v"(addr[3]),
+                   [of] "v"(tb.off[K2]), [lb] "v"(lbase), [m0] "i"(I2), [m1] "i"(I2 + 1),
+                   [m2] "i"(I2 + 2), [m3] "i"(I2 + 3), CPI_ROWS_FMA_IN);
+    cur = nx;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) addr[j] = na[j];
   }
 }
 
-template <int P, int... C>
-__device__ __forceinline__ void rows_view(uint32_t tb, uint32_t lbase, float (&acc0)[64],
-                                          float (&acc1)[64], std::integer_sequence<int, C...>) {
-  // chunk 0's cells, then its taps and weights and chunk 1's cells
-  i4 off0, off1;
-  RowsChunk cur;
-  asm volatile("ds_read_b128 %0, %1\n"
-               "s_waitcnt lgkmcnt(0)"
-               : "=&v"(off0)
-               : "v"(tb));
-  {
-    const uint32_t a0 = lbase + uint32_t(off0.x), a1 = lbase + uint32_t(off0.y);
-    const uint32_t a2 = lbase + uint32_t(off0.z), a3 = lbase + uint32_t(off0.w);
-    asm volatile(
-        "ds_read_b64 %[t0], %[a0]\n"
-        "ds_read_b64 %[u0], %[a0] offset:528\n"
-        "ds_read_b64 %[t1], %[a1]\n"
-        "ds_read_b64 %[u1], %[a1] offset:528\n"
-        "ds_read_b64 %[t2], %[a2]\n"
-        "ds_read_b64 %[u2], %[a2] offset:528\n"
-        "ds_read_b64 %[t3], %[a3]\n"
-        "ds_read_b64 %[u3], %[a3] offset:528\n"
-        "ds_read_b128 %[w0], %[tb] offset:%[kw0]\n"
-        "ds_read_b128 %[w1], %[tb] offset:%[kw1]\n"
-        "ds_read_b128 %[on], %[tb] offset:16\n"
-        "s_waitcnt lgkmcnt(0)"
-        : [t0] "=&v"(cur.lo[0]), [t1] "=&v"(cur.lo[1]), [t2] "=&v"(cur.lo[2]),
-          [t3] "=&v"(cur.lo[3]), [u0] "=&v"(cur.hi[0]), [u1] "=&v"(cur.hi[1]),
-          [u2] "=&v"(cur.hi[2]), [u3] "=&v"(cur.hi[3]), [w0] "=&v"(cur.w0),
-          [w1] "=&v"(cur.w1), [on] "=&v"(off1)
-        : [a0] "v"(a0), [a1] "v"(a1), [a2] "v"(a2), [a3] "v"(a3), [tb] "v"(tb),
-          [kw0] "i"(P * 4), [kw1] "i"(2 * P * 4));
+// tbl: this lane's slot (NK words) of the wave's table slice; lbase: this
+// lane's two rows in the window's first column.  after(integral_constant<C>)
+// runs after step C (the next view's copies are spread over the pass).
+template <int NK, int PW, typename After, int... C>
+__device__ __forceinline__ void rows_view(uint32_t tbl, uint32_t lbase, float (&acc0)[PW],
+                                          float (&acc1)[PW], After&& after,
+                                          std::integer_sequence<int, C...>) {
+  constexpr int NSTEP = sizeof...(C);
+  static_assert(NSTEP == PW / 4 && NK == PW / 16, "pass shape");
+  RowsTab<NK> tb;
+  if constexpr (NK == 4) {
+    asm volatile("ds_read_b128 %0, %3\n"
+                 "ds_read_b128 %1, %3 offset:256\n"
+                 "ds_read_b128 %2, %3 offset:512\n"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(tb.off), "=&v"(tb.w0), "=&v"(tb.w1)
+                 : "v"(tbl));
+  } else {
+    asm volatile("ds_read_b64 %0, %3\n"
+                 "ds_read_b64 %1, %3 offset:128\n"
+                 "ds_read_b64 %2, %3 offset:256\n"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(tb.off), "=&v"(tb.w0), "=&v"(tb.w1)
+                 : "v"(tbl));
   }
-  (rows_step<C, P>(tb, lbase, cur, off1, acc0, acc1), ...);
+  // tap addresses of chunks 0 and 1, then chunk 0's taps
+  uint32_t a[4], addr[4];
+  asm volatile(
+      "s_nop 1\n"
+      "v_add_u32_dpp %[a0], %[of], %[lb] row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+      "v_add_u32_dpp %[a1], %[of], %[lb] row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+      "v_add_u32_dpp %[a2], %[of], %[lb] row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+      "v_add_u32_dpp %[a3], %[of], %[lb] row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+      "v_add_u32_dpp %[b0], %[of], %[lb] row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+      "v_add_u32_dpp %[b1], %[of], %[lb] row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+      "v_add_u32_dpp %[b2], %[of], %[lb] row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+      "v_add_u32_dpp %[b3], %[of], %[lb] row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+      : [a0] "=&v"(a[0]), [a1] "=&v"(a[1]), [a2] "=&v"(a[2]), [a3] "=&v"(a[3]),
+        [b0] "=&v"(addr[0]), [b1] "=&v"(addr[1]), [b2] "=&v"(addr[2]), [b3] "=&v"(addr[3])
+      : [of] "v"(tb.off[0]), [lb] "v"(lbase));
+  RowsTaps cur;
+  asm volatile(
+      "s_nop 1\n"
+      "ds_read_b64 %[t0], %[a0]\n"
+      "ds_read_b64 %[u0], %[a0] offset:528\n"
+      "ds_read_b64 %[t1], %[a1]\n"
+      "ds_read_b64 %[u1], %[a1] offset:528\n"
+      "ds_read_b64 %[t2], %[a2]\n"
+      "ds_read_b64 %[u2], %[a2] offset:528\n"
+      "ds_read_b64 %[t3], %[a3]\n"
+      "ds_read_b64 %[u3], %[a3] offset:528\n"
+      "s_waitcnt lgkmcnt(0)"
+      : [t0] "=&v"(cur.lo[0]), [t1] "=&v"(cur.lo[1]), [t2] "=&v"(cur.lo[2]),
+        [t3] "=&v"(cur.lo[3]), [u0] "=&v"(cur.hi[0]), [u1] "=&v"(cur.hi[1]),
+        [u2] "=&v"(cur.hi[2]), [u3] "=&v"(cur.hi[3])
+      : [a0] "v"(a[0]), [a1] "v"(a[1]), [a2] "v"(a[2]), [a3] "v"(a[3]));
+  ((rows_step<C, NSTEP, NK, PW>(lbase, tb, cur, addr, acc0, acc1),
+    after(std::integral_constant<int, C>{})),
+   ...);
+}
+
+#undef CPI_ROWS_READS
+#undef CPI_ROWS_ADDRS
+#undef CPI_ROWS_FMA
+#undef CPI_ROWS_FMAS
+#undef CPI_ROWS_ACC_OUT
+#undef CPI_ROWS_FMA_IN
+#undef CPI_ROWS_READ_OUT
+
+// Copies of the first view's window in all phases (before the loop).
+template <typename Load, typename Store, int... H>
+__device__ __forceinline__ void rows_copy_all(Load&& load, Store&& store,
+                                              std::integer_sequence<int, H...>) {
+  ((load(std::integral_constant<int, H>{}), store(std::integral_constant<int, H>{})), ...);
 }
 
 template <int NA, int XR, int WW>
 // (at least two waves per SIMD: the LDS of two work-groups fits a CU)
-__global__ __launch_bounds__(NA * XR, 2) void k_ref_rows(
+__global__ __launch_bounds__(NA * XR * 64 / rows_pairs_per_wave(NA * XR), 2) void k_ref_rows(
     const float* __restrict__ gamma, GeomI g, const int32_t* __restrict__ xe,
     const int2* __restrict__ yr, int groups, int tiles, int bands, int count,
     float* __restrict__ tout, int wout_pad) {
   typedef RowsShape<NA, XR, WW> Sh;
-  constexpr int P = Sh::P;
+  constexpr int PW = Sh::PW;
   // two stages, each the window (WW columns of kRowsColStride floats) and
   // the view's table
   __shared__ __attribute__((aligned(16))) float ring[2 * Sh::STAGE];
@@ -332,79 +407,102 @@ __global__ __launch_bounds__(NA * XR, 2) void k_ref_rows(
   const float* vrow = gamma + int64_t(yb) * g.wb * pa;
   const int32_t* tab0 = xe + int64_t(gq * tiles + t) * g.wb * Sh::TAB;
 
-  float acc0[64], acc1[64];
+  float acc0[PW], acc1[PW];
 #pragma unroll
-  for (int i = 0; i < 64; ++i) {
+  for (int i = 0; i < PW; ++i) {
     acc0[i] = 0.0f;
     acc1[i] = 0.0f;
   }
 
   if (band_live) {
-    // Copies: instruction k of wave ps covers window rows 16 m .. 16 m + 15
-    // and columns 16 q .. 16 q + 15 (m = c % 8, q = c / 8, c = ps + k NPS);
-    // lane: row 16 m + lane / 4, columns 16 q + 4 (lane % 4) ... + 3.  The
-    // window start of a view comes through a scalar load one view ahead.
+    // Copies: copy k of wave ps covers window rows 16 m .. 16 m + 15 and
+    // columns 16 q .. 16 q + 15 (c = ps + k NPS, m = c % 8 = ps + NPS (k %
+    // NM), q = c / 8 = k / NM); lane: row 16 m + lane / 4, columns
+    // 16 q + 4 (lane % 4) ... + 3.  A view's copies run in PH phases of CPH
+    // loads, spread over the pass of the previous view so that at most 8 are
+    // held in registers.  Rows past the view repeat its last row.  (Element
+    // offsets within a view: pa is below 2^31.)
     const int cr = lane >> 2, cc = 4 * (lane & 3);
-    // Every block of the band is copied (straight-line loads, so that they
-    // are all in flight together); rows past the view repeat its last row.
-    // (element offsets within a view: pa is below 2^31)
-    uint32_t roff[Sh::CPW];
+    uint32_t roff[Sh::NM];
 #pragma unroll
-    for (int k = 0; k < Sh::CPW; ++k) {
-      const int c = ps + k * Sh::NPS;
-      const int r = r0 + 16 * (c & 7) + cr;
-      roff[k] = uint32_t((r < g.ha ? r : g.ha - 1) * g.wa + 16 * (c >> 3) + cc);
+    for (int j = 0; j < Sh::NM; ++j) {
+      const int r = r0 + 16 * (ps + Sh::NPS * j) + cr;
+      roff[j] = uint32_t(((r < g.ha ? r : g.ha - 1) * g.wa + cc) * 4);
     }
     // Buffer loads (32-bit offsets from a per-view descriptor; a read past
     // the described range returns zero rather than touching memory).
-    f4 win[Sh::CPW];
+    f4 win[Sh::CPH];
     f4 tab = f4{0.f, 0.f, 0.f, 0.f};
     int wx0_next = tab0[0];
     const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<int32_t*>(tab0), short(0), int(g.wb * Sh::TAB * 4), kBufferWord3);
-    auto load = [&](int xb, int wx0) {
+    auto load = [&](int xb, int wx0, auto phase) {
+      constexpr int h = decltype(phase)::value;
       const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<float*>(vrow + int64_t(xb) * pa + wx0), short(0), int((pa - wx0) * 4),
           kBufferWord3);
 #pragma unroll
-      for (int k = 0; k < Sh::CPW; ++k)
-        win[k] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(vrs, roff[k] * 4, 0, 0));
-      if (tid < Sh::TAB / 4)
+      for (int i = 0; i < Sh::CPH; ++i) {
+        const int k = h * Sh::CPH + i;
+        win[i] = __builtin_bit_cast(
+            f4, __builtin_amdgcn_raw_buffer_load_b128(vrs, roff[k % Sh::NM] + 64 * (k / Sh::NM),
+                                                      0, 0));
+      }
+      if (h == Sh::PH - 1 && tid < Sh::TAB / 4)
         tab = __builtin_bit_cast(
             f4, __builtin_amdgcn_raw_buffer_load_b128(trs, (xb * Sh::TAB + 4 * tid) * 4, 0, 0));
     };
-    auto store = [&](int stage) {
+    auto store = [&](int stage, auto phase) {
+      constexpr int h = decltype(phase)::value;
       float* st = ring + stage * Sh::STAGE;
 #pragma unroll
-      for (int k = 0; k < Sh::CPW; ++k) {
-        const int c = ps + k * Sh::NPS;
-        float* d = st + (16 * (c >> 3) + cc) * kRowsColStride + 16 * (c & 7) + cr;
-        d[0] = win[k].x;
-        d[kRowsColStride] = win[k].y;
-        d[2 * kRowsColStride] = win[k].z;
-        d[3 * kRowsColStride] = win[k].w;
+      for (int i = 0; i < Sh::CPH; ++i) {
+        const int k = h * Sh::CPH + i;
+        const int m = ps + Sh::NPS * (k % Sh::NM), q = k / Sh::NM;
+        float* d = st + (16 * q + cc) * kRowsColStride + 16 * m + cr;
+        d[0] = win[i].x;
+        d[kRowsColStride] = win[i].y;
+        d[2 * kRowsColStride] = win[i].z;
+        d[3 * kRowsColStride] = win[i].w;
       }
-      if (tid < Sh::TAB / 4)
+      if (h == Sh::PH - 1 && tid < Sh::TAB / 4)
         *reinterpret_cast<f4*>(st + Sh::WIN + 4 * tid) = tab;
     };
 
-    load(0, wx0_next);
+    rows_copy_all([&](auto ph) { load(0, wx0_next, ph); }, [&](auto ph) { store(0, ph); },
+                  std::make_integer_sequence<int, Sh::PH>{});
     if (g.wb > 1) wx0_next = tab0[Sh::TAB];
-    store(0);
     const uint32_t ring_base = uint32_t(reinterpret_cast<uintptr_t>(ring));
+    // this lane's slot of the wave's table slice (offsets; w0 and w1 follow
+    // at PW and 2 PW words)
+    const uint32_t tab_lane = uint32_t((Sh::WIN + 4 + ps * 3 * PW + Sh::NK * (lane & 15)) * 4);
     for (int v = 0; v < g.wb; ++v) {
       // stage v & 1 holds view v; every wave is done with view v - 1's stage
       __syncthreads();
-      if (v + 1 < g.wb) {
-        load(v + 1, wx0_next);
+      const bool more = v + 1 < g.wb;
+      const int wx1 = wx0_next;   // window start of view v + 1
+      if (more) {
+        load(v + 1, wx1, std::integral_constant<int, 0>{});
         if (v + 2 < g.wb) wx0_next = tab0[int64_t(v + 2) * Sh::TAB];
       }
-      // the wave's 64 pairs against view v: table at tb (offsets, w0, w1 of
-      // its pairs), window columns at lbase (this lane's two rows)
+      // the wave's pairs against view v; phase h of the next view's copies
+      // is stored, and phase h + 1 loaded, after step NSTEP (h + 1) / PH - 1
       const uint32_t stage_base = ring_base + uint32_t((v & 1) * Sh::STAGE * 4);
-      rows_view<P>(stage_base + uint32_t((Sh::WIN + 4 + ps * 64) * 4), stage_base + 8 * lane,
-                   acc0, acc1, std::make_integer_sequence<int, 16>{});
-      if (v + 1 < g.wb) store((v + 1) & 1);
+      rows_view<Sh::NK, PW>(
+          stage_base + tab_lane, stage_base + 8 * lane, acc0, acc1,
+          [&](auto step) {
+            constexpr int C = decltype(step)::value;
+            constexpr int span = Sh::NSTEP / Sh::PH;
+            if constexpr (Sh::PH > 1 && C < Sh::NSTEP - 1 && (C + 1) % span == 0) {
+              constexpr int h = (C + 1) / span - 1;
+              if (more) {
+                store((v + 1) & 1, std::integral_constant<int, h>{});
+                load(v + 1, wx1, std::integral_constant<int, h + 1>{});
+              }
+            }
+          },
+          std::make_integer_sequence<int, Sh::NSTEP>{});
+      if (more) store((v + 1) & 1, std::integral_constant<int, Sh::PH - 1>{});
     }
   }
 
@@ -415,8 +513,8 @@ __global__ __launch_bounds__(NA * XR, 2) void k_ref_rows(
     if (r >= g.ha) continue;
     const bool keep = band_live && r >= yrg.x && r <= yrg.y;
 #pragma unroll
-    for (int i = 0; i < 64; i += 4) {
-      const int p = ps * 64 + i;
+    for (int i = 0; i < PW; i += 4) {
+      const int p = ps * PW + i;
       const int k = p / XR, j = p % XR;
       const int pl = gq * NA + k;
       if (pl < count) {
@@ -538,7 +636,8 @@ hipError_t launch_rows_ww(const float* gamma, const GeomI& gi, const int32_t* it
     if (e != hipSuccess) return e;
     const int64_t nwg = int64_t(8) * ((gi.hb + 7) / 8) * bands * tiles * groups;
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ref_rows<NA, XR, WW>), dim3(unsigned(nwg)), dim3(NA * XR), 0, s, gamma,
+    hipLaunchKernelGGL((k_ref_rows<NA, XR, WW>), dim3(unsigned(nwg)),
+                       dim3(RowsShape<NA, XR, WW>::NPS * 64), 0, s, gamma,
                        gi, w.xe, w.yr, groups, tiles, bands, count, w.t, wout_pad);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
