@@ -52,62 +52,6 @@ __global__ void k_add_i64(int64_t* __restrict__ dst, const int64_t* __restrict__
     dst[i] += src[i];
 }
 
-// Lane-indexed insert of a wave-uniform value: lane L of `old` becomes v
-// (v_writelane_b32 through its LLVM intrinsic, so that the compiler knows the
-// operation).  Callers keep it out of divergent control flow: every lane of
-// the wave is active wherever it is used.
-extern "C" __device__ uint32_t cpi_llvm_writelane(uint32_t v, uint32_t lane, uint32_t old) __asm(
-    "llvm.amdgcn.writelane.i32");
-
-template <int L>
-__device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t v) {
-  return cpi_llvm_writelane(v, uint32_t(L), old);
-}
-
-// Bit of pixel J (0..127) in this lane's 16 packed bytes of one frame.
-template <int J>
-__device__ __forceinline__ uint32_t pixel_bit(const uint32_t (&d)[4]) {
-  return (d[J >> 5] >> (J & 31)) & 1u;
-}
-
-// One ballot per pixel J: bit l of the result is pixel J in frame f0 + l.
-// Pixel J's 64 frame bits go to lane J % 64, words 2*SUB, 2*SUB+1 of half J/64.
-template <int SUB, int J, int ND>
-__device__ __forceinline__ void ballot_pixel(const uint32_t (&d)[ND], uint32_t (&w0)[16],
-                                             uint32_t (&w1)[16]) {
-  const unsigned long long m = __ballot(pixel_bit<J>(d));
-  const uint32_t lo = uint32_t(m), hi = uint32_t(m >> 32);
-  if constexpr (J < 64) {
-    w0[2 * SUB] = write_lane<J>(w0[2 * SUB], lo);
-    w0[2 * SUB + 1] = write_lane<J>(w0[2 * SUB + 1], hi);
-  } else {
-    w1[2 * SUB] = write_lane<J - 64>(w1[2 * SUB], lo);
-    w1[2 * SUB + 1] = write_lane<J - 64>(w1[2 * SUB + 1], hi);
-  }
-}
-
-template <int SUB, int ND, int... J>
-__device__ __forceinline__ void ballot_all(const uint32_t (&d)[ND], uint32_t (&w0)[16],
-                                           uint32_t (&w1)[16], std::integer_sequence<int, J...>) {
-  (ballot_pixel<SUB, J, ND>(d, w0, w1), ...);
-}
-
-// Loads the lane's frame data for sub-block SUB and transposes it.
-template <int SUB, int ND, typename Load>
-__device__ __forceinline__ void transpose_sub(Load&& load, uint32_t (&w0)[16],
-                                              uint32_t (&w1)[16]) {
-  uint32_t d[ND];
-  load(SUB, d);
-  ballot_all<SUB, ND>(d, w0, w1, std::make_integer_sequence<int, 128>{});
-}
-
-template <int ND, typename Load, int... S>
-__device__ __forceinline__ void transpose_block(Load&& load, uint32_t (&w0)[16],
-                                                uint32_t (&w1)[16],
-                                                std::integer_sequence<int, S...>) {
-  (transpose_sub<S, ND>(load, w0, w1), ...);
-}
-
 // Exchange bits 0 and 2 of every 4-bit group.
 __device__ __forceinline__ uint32_t swap_bits02(uint32_t x) {
   return (x & 0xAAAAAAAAu) | ((x & 0x11111111u) << 2) | ((x >> 2) & 0x11111111u);
@@ -120,84 +64,182 @@ unsigned grid_for(int64_t count, int threads) {
   return unsigned(g);
 }
 
-// Packed-bit frames -> bit rows.  One wave owns 128 pixels and a slice of
-// 512-frame blocks.  Lane l reads the 16 bytes (128 pixels) of frame
-// f0 + l; one wave ballot per pixel then yields that pixel's 64 frame bits,
-// which a lane select drops into the register of the lane that owns the pixel
-// (pixel j -> lane j % 64, half j / 64).
-__global__ __launch_bounds__(64) void k_ingest_bits(IngestJob j0, IngestJob j1, int64_t groups0,
-                                                   int64_t n, int64_t kw, int64_t nblocks,
-                                                   int64_t blocks_per_slice) {
-  // work-groups [0, groups0) take detector job j0, the rest job j1
-  const bool second = int64_t(blockIdx.x) >= groups0;
-  const uint8_t* __restrict__ frames = second ? j1.frames : j0.frames;
-  const int64_t fbytes = ((second ? j1.npix : j0.npix) + 7) / 8;
-  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(second ? j1.out : j0.out);
-  unsigned long long* __restrict__ sums =
-      reinterpret_cast<unsigned long long*>(second ? j1.sums : j0.sums);
-  const int swap02 = second ? j1.swap02 : j0.swap02;
-  const int lane = threadIdx.x;
-  const int64_t p0 = (int64_t(blockIdx.x) - (second ? groups0 : 0)) * 128;
-  const int64_t byte0 = p0 >> 3;
-  const int64_t kb0 = int64_t(blockIdx.y) * blocks_per_slice;
-  int64_t kb1 = kb0 + blocks_per_slice;
-  if (kb1 > nblocks) kb1 = nblocks;
-  const bool vec = ((fbytes & 15) == 0) && (byte0 + 16 <= fbytes);
-  unsigned long long s0 = 0, s1 = 0;
-  for (int64_t kb = kb0; kb < kb1; ++kb) {
-    uint32_t w0[16], w1[16];
+// In-place transpose of a 32 x 32 bit block: on entry bit j of d[k] is
+// element (k, j), on return bit k of d[j] is that element.  Five rounds of
+// block exchanges (Hacker's Delight, section 7-3, in least-significant-bit-
+// first order): round s swaps the upper s bits of each 2s-bit group of row k
+// with the lower s bits of the same group of row k + s, for every k with bit
+// s clear.
+__host__ __device__ __forceinline__ void transpose32(uint32_t (&d)[32]) {
+  constexpr uint32_t mask[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      w0[i] = 0;
-      w1[i] = 0;
-    }
-    // Branch-free: frames beyond n and bytes beyond the frame read valid
-    // addresses and are masked to zero, so the wave stays fully active.
-    auto load = [&](int sub, uint32_t(&d)[4]) {
-      const int64_t f = kb * 512 + sub * 64 + lane;
-      const bool fin = f < n;
-      const uint8_t* src = frames + (fin ? f : 0) * fbytes;
-      const uint32_t m = fin ? 0xffffffffu : 0u;
-      if (vec) {
-        const uint4 v = *reinterpret_cast<const uint4*>(src + byte0);
-        d[0] = v.x & m;
-        d[1] = v.y & m;
-        d[2] = v.z & m;
-        d[3] = v.w & m;
-      } else {
-        d[0] = d[1] = d[2] = d[3] = 0u;
+  for (int r = 0; r < 5; ++r) {
+    const int s = 16 >> r;
+    const uint32_t m = mask[r];
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-          const bool ok = byte0 + b < fbytes;
-          const uint32_t x = src[ok ? byte0 + b : 0];
-          d[b >> 2] |= (ok ? x : 0u) << (8 * (b & 3));
-        }
-        d[0] &= m;
-        d[1] &= m;
-        d[2] &= m;
-        d[3] &= m;
-      }
-    };
-    transpose_block<4>(load, w0, w1, std::make_integer_sequence<int, 8>{});
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      s0 += __popc(w0[i]);
-      s1 += __popc(w1[i]);
-      if (swap02) {
-        w0[i] = swap_bits02(w0[i]);
-        w1[i] = swap_bits02(w1[i]);
-      }
-    }
-    uint4* o0 = reinterpret_cast<uint4*>(out + (p0 + lane) * kw + kb * 16);
-    uint4* o1 = reinterpret_cast<uint4*>(out + (p0 + 64 + lane) * kw + kb * 16);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      o0[q] = make_uint4(w0[4 * q], w0[4 * q + 1], w0[4 * q + 2], w0[4 * q + 3]);
-      o1[q] = make_uint4(w1[4 * q], w1[4 * q + 1], w1[4 * q + 2], w1[4 * q + 3]);
+    for (int k = 0; k < 32; ++k) {
+      if (k & s) continue;
+      const uint32_t t = ((d[k] >> s) ^ d[k + s]) & m;
+      d[k] ^= t << s;
+      d[k + s] ^= t;
     }
   }
-  atomicAdd(&sums[p0 + lane], s0);
-  atomicAdd(&sums[p0 + 64 + lane], s1);
+}
+
+constexpr int kBitsTilePix = 1024;   // pixels per work-group tile (32 words of a frame row)
+constexpr int kBitsTileFr = 512;     // frames per tile (16 words of a bit row)
+// The tile is staged frame word by frame word: word fw of pixel 32 q + i at
+// stage[fw * kBitsLdsCol + 32 i + q].  The column stride (1060 = 36 mod 64)
+// keeps the two half-waves' writes (adjacent frame words) and the row-segment
+// reads (four frame words 4 apart) on distinct banks, and every offset of a
+// lane's accesses is an instruction immediate.
+constexpr int kBitsLdsCol = 1060;
+
+// Packed-bit frames -> bit rows, for the 512-frame tiles that lie wholly
+// below n, when frame rows are a multiple of 4 bytes long (k_ingest_bits_tail
+// writes the rest).  A work-group (4 waves) owns 1024 pixels and a slice of
+// those tiles.  For each tile, each half-wave takes 32
+// frames: lane q of the half reads word q of the tile's row segment in each
+// of the 32 frames (a half reads 128 contiguous bytes per frame) and
+// transposes the 32 x 32 bit block in registers, which leaves it the 32
+// frame bits of pixels 32 q .. 32 q + 31.  The words go to LDS and are
+// written out as 64-byte row segments (four lanes per row, 16 bytes each).  Per-pixel popcounts are kept in registers,
+// combined in LDS, and added to sums once per work-group.
+__global__ __launch_bounds__(256, 2) void k_ingest_bits(IngestJob j0, IngestJob j1, int64_t groups0,
+                                                    int64_t n, int64_t kw, int64_t ntiles,
+                                                    int64_t tiles_per_slice) {
+  __shared__ uint32_t stage[16 * kBitsLdsCol];
+  __shared__ uint32_t psum[kBitsTilePix];
+  // work-groups [0, groups0) take detector job j0, the rest job j1
+  const bool second = int64_t(blockIdx.x) >= groups0;
+  const IngestJob& job = second ? j1 : j0;
+  const uint8_t* __restrict__ frames = job.frames;
+  const int64_t fbytes = (job.npix + 7) / 8;
+  const int64_t npix_pad = job.npix_pad;
+  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(job.out);
+  const int swap02 = job.swap02;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int q = lane & 31, half = lane >> 5;
+  const int64_t p0 = (int64_t(blockIdx.x) - (second ? groups0 : 0)) * kBitsTilePix;
+  const int64_t byte = p0 / 8 + 4 * q;   // this lane's word in every frame row
+  const int64_t kt0 = int64_t(blockIdx.y) * tiles_per_slice;
+  int64_t kt1 = kt0 + tiles_per_slice;
+  if (kt1 > ntiles) kt1 = ntiles;
+
+  for (int i = tid; i < kBitsTilePix; i += 256) psum[i] = 0u;
+  uint32_t cnt[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) cnt[i] = 0u;
+
+  // The two 32-frame blocks of this lane in tile kt: frame words 2 wave +
+  // half and 8 + 2 wave + half of the tile (every frame of the tile is below
+  // n).  Buffer loads whose descriptor starts at the tile's first frame: the
+  // lane's row offset (block and byte) is the vector offset and the frame's
+  // row offset within the block the scalar one, so that no per-load address
+  // registers are needed.  Words past a frame row reread the row's first
+  // word and are masked to zero.  (Offsets stay below 2^31: rows are under
+  // 2^22 bytes.)
+  const bool word_in = byte + 4 <= fbytes;
+  const uint32_t word_mask = word_in ? 0xffffffffu : 0u;
+  int voff[2];
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass)
+    voff[pass] = int((8 * pass + 2 * wave + half) * 32 * fbytes + (word_in ? byte : 0));
+  auto load_tile = [&](int64_t kt, uint32_t(&d)[2][32]) {
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(frames + kt * kBitsTileFr * fbytes), short(0), 0x7fffffff,
+        0x00020000);
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        d[pass][k] =
+            uint32_t(__builtin_amdgcn_raw_buffer_load_b32(rb, voff[pass], int(k * fbytes), 0)) &
+            word_mask;
+  };
+  // row-segment writes: lane 4 r + e writes words 4 e .. 4 e + 3 of row
+  // 32 q2 + 2 j + wave / 2 (q2 = r + 16 (wave & 1)) for j = 0 .. 15
+  const int q2 = (lane >> 2) + 16 * (wave & 1), c2 = 4 * (lane & 3);
+  const int64_t row2 = p0 + 32 * q2 + (wave >> 1);
+  const int vo2 = int(((32 * q2 + (wave >> 1)) * kw + c2) * 4);
+  const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
+      out + p0 * kw, short(0), 0x7fffffff, 0x00020000);
+  uint32_t cur[2][32], nxt[2][32];
+  if (kt0 < kt1) load_tile(kt0, cur);
+  for (int64_t kt = kt0; kt < kt1; ++kt) {
+    // the next tile's loads are in flight while this one is transposed and
+    // written (straight-line: the last tile loads itself again)
+    load_tile(kt + 1 < kt1 ? kt + 1 : kt, nxt);
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int fw = 8 * pass + 2 * wave + half;
+      transpose32(cur[pass]);
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        cnt[i] += __popc(cur[pass][i]);
+        const uint32_t w = swap02 ? swap_bits02(cur[pass][i]) : cur[pass][i];
+        stage[fw * kBitsLdsCol + 32 * i + q] = w;
+      }
+    }
+    __syncthreads();
+    // 1024 rows x 16 words, 16 bytes per lane: consecutive lanes cover one
+    // 64-byte segment of a row.
+    // (buffer stores: the lane's row and word are the vector offset, the
+    // pass's row step and the tile's column the scalar one)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int i = 2 * j + (wave >> 1);
+      const uint32_t* src = stage + c2 * kBitsLdsCol + 32 * i + q2;
+      typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+      const u4v v = {src[0], src[kBitsLdsCol], src[2 * kBitsLdsCol], src[3 * kBitsLdsCol]};
+      if (row2 + 2 * j < npix_pad)
+        __builtin_amdgcn_raw_buffer_store_b128(v, ors, vo2, int((2 * j * kw + kt * 16) * 4), 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+      for (int k = 0; k < 32; ++k) cur[pass][k] = nxt[pass][k];
+  }
+#pragma unroll
+  for (int i = 0; i < 32; ++i) atomicAdd(&psum[32 * q + i], cnt[i]);
+  __syncthreads();
+  unsigned long long* __restrict__ sums = reinterpret_cast<unsigned long long*>(job.sums);
+  for (int i = tid; i < kBitsTilePix; i += 256)
+    if (p0 + i < npix_pad) atomicAdd(&sums[p0 + i], (unsigned long long)psum[i]);
+}
+
+// Packed-bit frames -> bit rows for row words [w0, kw) (frames 32 w0 ..):
+// one thread per pixel row p < npix_pad of either detector, 32 byte loads
+// per word (consecutive threads read the same or adjacent bytes of a frame),
+// popcounts added to sums.  Bits of pixels at or past 8 * row bytes, and of
+// frames at or past n, are zero.
+__global__ __launch_bounds__(256) void k_ingest_bits_tail(IngestJob j0, IngestJob j1, int64_t n,
+                                                         int64_t kw, int64_t w0) {
+  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const bool second = t >= j0.npix_pad;
+  const IngestJob& job = second ? j1 : j0;
+  const int64_t p = second ? t - j0.npix_pad : t;
+  if (p >= job.npix_pad) return;
+  const int64_t fbytes = (job.npix + 7) / 8;
+  const bool pin = p / 8 < fbytes;
+  const int64_t pb = pin ? p / 8 : 0;
+  const int sh = int(p & 7);
+  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(job.out) + p * kw;
+  unsigned long long cnt = 0;
+  for (int64_t w = w0; w < kw; ++w) {
+    uint32_t v = 0u;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const int64_t f = 32 * w + j;
+      const bool ok = pin && f < n;
+      const uint32_t x = job.frames[(ok ? f : 0) * fbytes + pb];
+      v |= (ok ? (x >> sh) & 1u : 0u) << j;
+    }
+    cnt += __popc(v);
+    out[w] = job.swap02 ? swap_bits02(v) : v;
+  }
+  atomicAdd(reinterpret_cast<unsigned long long*>(job.sums) + p, cnt);
 }
 
 // Byte frames -> bit rows.  Each wave owns 256 consecutive pixels (lane l:
@@ -513,19 +555,38 @@ hipError_t add_i64(int64_t* dst, const int64_t* src, int64_t count, hipStream_t 
 
 hipError_t ingest_bits(const IngestJob& a, const IngestJob& b, int64_t n, int64_t kpad_bits,
                        hipStream_t s) {
-  // a work-group covers 128 rows: the padded row counts must be multiples of it
+  // a work-group of the tile kernel covers 1024 rows (the last one of a
+  // detector may reach past npix_pad and writes only the rows below it) and
+  // 512-frame tiles below n; the tail kernel writes the remaining words
   for (const IngestJob* j : {&a, &b})
-    if (j->npix_pad % 128 != 0 || j->npix_pad < j->npix) return hipErrorInvalidValue;
-  const int64_t groups0 = a.npix_pad / 128;
-  const int64_t groups = groups0 + b.npix_pad / 128;
-  const int64_t nblocks = kpad_bits / 512;
-  const int64_t slices = slices_for(groups, nblocks, 8192);
-  const int64_t bps = (nblocks + slices - 1) / slices;
-  const int64_t used = (nblocks + bps - 1) / bps;
+    if (j->npix_pad % 128 != 0 || j->npix_pad < j->npix ||
+        (j->npix + 7) / 8 >= (int64_t(1) << 22))
+      return hipErrorInvalidValue;
+  // (row offsets within a 1024-row tile stay below 2^31 bytes)
+  if (kpad_bits % kBitsTileFr != 0 || n > kpad_bits || kpad_bits / 32 >= (int64_t(1) << 19))
+    return hipErrorInvalidValue;
+  const bool aligned = (((a.npix + 7) / 8) & 3) == 0 && (((b.npix + 7) / 8) & 3) == 0;
+  const int64_t full = aligned ? n / kBitsTileFr : 0;   // tiles for the tile kernel
+  const int64_t groups0 = (a.npix_pad + kBitsTilePix - 1) / kBitsTilePix;
+  const int64_t groups = groups0 + (b.npix_pad + kBitsTilePix - 1) / kBitsTilePix;
   if (groups > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_ingest_bits, dim3(unsigned(groups), unsigned(used)), dim3(64), 0, s, a, b,
-                     groups0, n, kpad_bits / 32, nblocks, bps);
-  return hipGetLastError();
+  if (full > 0 && groups > 0) {
+    const int64_t slices = slices_for(groups, full, 2048);
+    const int64_t tps = (full + slices - 1) / slices;
+    const int64_t used = (full + tps - 1) / tps;
+    hipLaunchKernelGGL(k_ingest_bits, dim3(unsigned(groups), unsigned(used)), dim3(256), 0, s, a,
+                       b, groups0, n, kpad_bits / 32, full, tps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int64_t kw = kpad_bits / 32, w0 = full * (kBitsTileFr / 32);
+  const int64_t rows = a.npix_pad + b.npix_pad;
+  if (w0 < kw && rows > 0) {
+    hipLaunchKernelGGL(k_ingest_bits_tail, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, s, a,
+                       b, n, kw, w0);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 hipError_t u8_sums(const IngestJob& a, const IngestJob& b, int64_t n, const uint32_t* stats,
