@@ -800,9 +800,12 @@ def refocus_roofline(cpi, geo, alphas, launch_ms, traffic_key):
 def streaming_bench(args, cpi, torch, np, dev):
     """The streamed workload: 1000-frame 1-bit chunks (Da 128x128, Db 64x64),
     all distinct (made on the device, staged in pinned host memory), each
-    pushed from the host and followed by a 32-plane refocus.  Latency per
-    chunk from the push to the stack's completion; sustained frames/s over
-    the whole run."""
+    pushed from the host and followed by a 32-plane refocus.  Overlapped: the
+    handle keeps two FP32 Gamma buffers and the refocus of chunk k runs on a
+    second stream while chunk k + 1 is copied and folded; serial: both on one
+    stream.  All chunks are enqueued without host waits; latency per chunk is
+    the device time from the start of its copy to the end of its refocus
+    (events), sustained frames/s the whole run's wall time."""
     from synth import WORKLOADS, alphas_for
     from synth.gpu_speckle import generate_binary_frames_gpu
 
@@ -813,49 +816,73 @@ def streaming_bench(args, cpi, torch, np, dev):
     ca = fa.cpu().pin_memory()
     cb = fb.cpu().pin_memory()
     del fa, fb
-    fa_b, fb_b = ca.shape[1], cb.shape[1]
-    st = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev)
     sgeo = cpi.geometry_default(ws.wa, ws.ha, ws.wb, ws.hb)
     sal = alphas_for(ws)
     sout = torch.empty(len(sal) * ws.pa, dtype=torch.float32, device=dev)
     sws = cpi.alloc_workspace(cpi.refocus_workspace_size(sgeo, len(sal)), dev)
-    # one warm-up chunk on a separate stream object (kernels loaded, tables cached)
-    warm = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev)
-    warm.push_host(ca[:ws.chunk].reshape(-1), cb[:ws.chunk].reshape(-1), ws.chunk)
-    warm.refocus(sgeo, sal, sout, workspace=sws)
-    torch.cuda.synchronize()
-    warm.close()
-    lat, dev_lat = [], []
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t_start = time.perf_counter()
-    for k in range(chunks):
-        cha = ca[k * ws.chunk:(k + 1) * ws.chunk].reshape(-1)
-        chb = cb[k * ws.chunk:(k + 1) * ws.chunk].reshape(-1)
-        t0 = time.perf_counter()
-        ev0.record()
-        st.push_host(cha, chb, ws.chunk)
-        st.refocus(sgeo, sal, sout, workspace=sws)
-        ev1.record()
-        ev1.synchronize()
-        lat.append((time.perf_counter() - t0) * 1e3)
-        dev_lat.append(ev0.elapsed_time(ev1))
-    t_total = time.perf_counter() - t_start
+
+    def run(overlap):
+        su = torch.cuda.Stream()
+        sr = torch.cuda.Stream() if overlap else su
+        nbuf = 2 if overlap else 1
+
+        def chunk(st, k):
+            st.push_host(ca[k * ws.chunk:(k + 1) * ws.chunk].reshape(-1),
+                         cb[k * ws.chunk:(k + 1) * ws.chunk].reshape(-1), ws.chunk)
+            if overlap:
+                st.refocus_async(sgeo, sal, sout, sws, sr)
+            else:
+                st.refocus(sgeo, sal, sout, workspace=sws)
+
+        # one warm-up chunk on a separate stream object (kernels loaded,
+        # tables cached)
+        warm = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev,
+                          stream=su, gamma_buffers=nbuf)
+        chunk(warm, 0)
+        torch.cuda.synchronize()
+        warm.close()
+        st = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev,
+                        stream=su, gamma_buffers=nbuf)
+        ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(chunks)]
+        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(chunks)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(chunks):
+            ev0[k].record(su)
+            chunk(st, k)
+            ev1[k].record(sr)
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
+        lat = [ev0[k].elapsed_time(ev1[k]) for k in range(chunks)]
+        res = {
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "frames_per_s": chunks * ws.chunk / t_total,
+            "device_frames_per_s": chunks * ws.chunk / (ev0[0].elapsed_time(ev1[-1]) * 1e-3),
+            "final_frames": st.frames,
+        }
+        st.close()
+        return res
+
+    log("bench: streaming, update and refocus on one stream")
+    one = run(False)
+    log("bench: streaming, refocus on a second stream")
+    two = run(True)
     res = {
         "workload": ws.name,
         "chunks": chunks,
         "chunk_frames": ws.chunk,
         "frames": f"{chunks} distinct seeded chunks ({chunks * ws.chunk} frames, made on the "
                   f"device, pushed from pinned host memory)",
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "device_p50_ms": float(np.percentile(dev_lat, 50)),
-        "device_p99_ms": float(np.percentile(dev_lat, 99)),
-        "frames_per_s": chunks * ws.chunk / t_total,
+        "mode": "update and refocus of each chunk on one stream; the host copy of chunk k + 1 "
+                "runs on the handle's copy stream during the work on chunk k; latency = device "
+                "time from a chunk's copy to the end of its refocus",
         "n_alpha": len(sal),
-        "final_frames": st.frames,
     }
-    st.close()
+    res.update(one)
+    two["mode"] = ("refocus of chunk k on a second stream while chunk k + 1 is folded (two FP32 "
+                   "Gamma buffers): the two streams' kernels share the CUs and slow each other")
+    res["two_stream_refocus"] = two
     return res
 
 

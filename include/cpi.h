@@ -323,7 +323,10 @@ cpi_status cpi_refocus_resampled(const float* gamma, const cpi_geometry* g,
  * cpi_stream_push: folds k <= max_chunk frame pairs (device pointers, format
  *   fmt) into S_ab, S_a, S_b and refreshes the handle's FP32 Gamma.
  * cpi_stream_push_host: the same for host chunks (pinned memory gives an
- *   asynchronous copy; pageable memory is copied synchronously).
+ *   asynchronous copy; pageable memory is copied synchronously).  The copy
+ *   runs on a stream of the handle's own, into one of two device staging
+ *   buffers, so that it overlaps the work on the previous chunk; the handle's
+ *   stream waits for it.
  * cpi_stream_frames: frames folded so far (host pointer).
  * cpi_stream_gamma: writes Gamma for all frames so far (each output nullable).
  * cpi_stream_gamma_f32_ptr: device address of the handle's FP32 view-major
@@ -333,6 +336,20 @@ cpi_status cpi_refocus_resampled(const float* gamma, const cpi_geometry* g,
  *   host buffer; both synchronise the stream.  A checkpoint loads only into a
  *   stream of the same pa, pb and fmt.
  * cpi_stream_destroy: frees the handle (not the workspace).
+ *
+ * Overlapping a refocus with the next update: cpi_stream_workspace_size_ex /
+ * cpi_stream_create_ex take gamma_buffers (1 or 2); with 2 the handle holds
+ * two FP32 Gamma buffers and push k writes buffer k % 2 (one more pa * pb * 4
+ * bytes of workspace).  cpi_stream_refocus_async enqueues the refocus of the
+ * latest push's Gamma on refocus_stream (a second stream of the same device):
+ * that stream first waits for the push; the next push that writes the same
+ * buffer waits on the handle's stream for the refocus.  Every other call
+ * keeps its meaning (cpi_stream_gamma_f32_ptr names the latest push's
+ * buffer).  With 2 buffers, update k + 1 runs on the handle's stream while
+ * refocus k runs on refocus_stream; results are those of the serial calls.
+ * The out and workspace buffers of an asynchronous refocus are in use until
+ * refocus_stream has reached it.  The handle and its events belong to one
+ * host thread at a time.
  * Errors: CPI_ERR_INVALID_ARG, CPI_ERR_OVERFLOW (N would break the bounds of
  *   cpi_correlate), CPI_ERR_NOT_READY (gamma requested before any frame),
  *   CPI_ERR_WORKSPACE, CPI_ERR_DEVICE.
@@ -344,6 +361,12 @@ cpi_status cpi_stream_workspace_size(int64_t pa, int64_t pb, cpi_frame_format fm
 cpi_status cpi_stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt,
                              int64_t max_chunk, void* workspace, size_t bytes,
                              void* stream, cpi_stream_t* out);
+cpi_status cpi_stream_workspace_size_ex(int64_t pa, int64_t pb, cpi_frame_format fmt,
+                                        int64_t max_chunk, int32_t gamma_buffers,
+                                        size_t* bytes);
+cpi_status cpi_stream_create_ex(int64_t pa, int64_t pb, cpi_frame_format fmt,
+                                int64_t max_chunk, int32_t gamma_buffers, void* workspace,
+                                size_t bytes, void* stream, cpi_stream_t* out);
 cpi_status cpi_stream_push(cpi_stream_t s, const void* chunk_a, const void* chunk_b,
                            int64_t k);
 cpi_status cpi_stream_push_host(cpi_stream_t s, const void* chunk_a,
@@ -356,6 +379,10 @@ cpi_status cpi_stream_gamma_f32_ptr(cpi_stream_t s, const float** gamma_f32);
 cpi_status cpi_stream_refocus(cpi_stream_t s, const cpi_geometry* g,
                               const double* alphas, int32_t n_alpha, float* out,
                               void* workspace, size_t workspace_bytes);
+cpi_status cpi_stream_refocus_async(cpi_stream_t s, const cpi_geometry* g,
+                                    const double* alphas, int32_t n_alpha, float* out,
+                                    void* workspace, size_t workspace_bytes,
+                                    void* refocus_stream);
 cpi_status cpi_stream_state_size(cpi_stream_t s, size_t* bytes);
 cpi_status cpi_stream_save(cpi_stream_t s, void* host_buf, size_t bytes);
 cpi_status cpi_stream_load(cpi_stream_t s, const void* host_buf, size_t bytes);

@@ -120,6 +120,10 @@ _SIGS = {
                                   c_void_p, POINTER(RefocusTiles), c_void_p, c_size_t,
                                   c_void_p]),
     "cpi_stream_workspace_size": (c_int, [c_int64, c_int64, c_int, c_int64, POINTER(c_size_t)]),
+    "cpi_stream_workspace_size_ex": (c_int, [c_int64, c_int64, c_int, c_int64, c_int32,
+                                             POINTER(c_size_t)]),
+    "cpi_stream_create_ex": (c_int, [c_int64, c_int64, c_int, c_int64, c_int32, c_void_p,
+                                     c_size_t, c_void_p, POINTER(c_void_p)]),
     "cpi_stream_create": (c_int, [c_int64, c_int64, c_int, c_int64, c_void_p, c_size_t, c_void_p,
                                   POINTER(c_void_p)]),
     "cpi_stream_push": (c_int, [c_void_p, c_void_p, c_void_p, c_int64]),
@@ -130,6 +134,8 @@ _SIGS = {
     "cpi_stream_gamma_f32_ptr": (c_int, [c_void_p, POINTER(c_void_p)]),
     "cpi_stream_refocus": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
                                    c_void_p, c_void_p, c_size_t]),
+    "cpi_stream_refocus_async": (c_int, [c_void_p, POINTER(Geometry), POINTER(c_double), c_int32,
+                                         c_void_p, c_void_p, c_size_t, c_void_p]),
     "cpi_stream_state_size": (c_int, [c_void_p, POINTER(c_size_t)]),
     "cpi_stream_save": (c_int, [c_void_p, c_void_p, c_size_t]),
     "cpi_stream_load": (c_int, [c_void_p, c_void_p, c_size_t]),
@@ -571,25 +577,31 @@ def profile_query(group: str):
 # streaming
 # ---------------------------------------------------------------------------
 
-def stream_workspace_size(pa: int, pb: int, fmt: int, max_chunk: int) -> int:
+def stream_workspace_size(pa: int, pb: int, fmt: int, max_chunk: int,
+                          gamma_buffers: int = 1) -> int:
     out = c_size_t(0)
-    _check(lib.cpi_stream_workspace_size(pa, pb, fmt, max_chunk, ctypes.byref(out)))
+    _check(lib.cpi_stream_workspace_size_ex(pa, pb, fmt, max_chunk, gamma_buffers,
+                                            ctypes.byref(out)))
     return out.value
 
 
 class Stream:
-    """Device-resident running sums of Eq. (1), updated chunk by chunk."""
+    """Device-resident running sums of Eq. (1), updated chunk by chunk.
+    gamma_buffers=2 keeps two FP32 Gamma buffers so that refocus_async of
+    chunk k (on another stream) overlaps the update of chunk k + 1."""
 
-    def __init__(self, pa: int, pb: int, fmt: int, max_chunk: int, device=None, stream=None):
+    def __init__(self, pa: int, pb: int, fmt: int, max_chunk: int, device=None, stream=None,
+                 gamma_buffers: int = 1):
         torch = _torch()
         self.pa, self.pb, self.fmt, self.max_chunk = pa, pb, fmt, max_chunk
-        need = stream_workspace_size(pa, pb, fmt, max_chunk)
+        need = stream_workspace_size(pa, pb, fmt, max_chunk, gamma_buffers)
         self.workspace = alloc_workspace(need, device)
         self._stream = stream
         h = c_void_p()
-        _check(lib.cpi_stream_create(pa, pb, fmt, max_chunk,
-                                     _dev_ptr(self.workspace, "workspace", torch.uint8, nbytes=need),
-                                     need, _stream(stream), ctypes.byref(h)))
+        _check(lib.cpi_stream_create_ex(pa, pb, fmt, max_chunk, gamma_buffers,
+                                        _dev_ptr(self.workspace, "workspace", torch.uint8,
+                                                 nbytes=need),
+                                        need, _stream(stream), ctypes.byref(h)))
         self.handle = h
 
     def close(self):
@@ -687,6 +699,18 @@ class Stream:
             _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need))
         del a
         return workspace
+
+    def refocus_async(self, g: Geometry, alphas, out, workspace, stream):
+        """Refocus of the latest push's Gamma enqueued on `stream` (after that
+        push); out and workspace stay in use until `stream` reaches it."""
+        torch = _torch()
+        a, ap, na = _alphas(alphas)
+        need = refocus_workspace_size(g, na)
+        _check(lib.cpi_stream_refocus_async(
+            self.handle, ctypes.byref(g), ap, na,
+            _dev_ptr(out, "out", torch.float32, numel=na * g.out_w * g.out_h),
+            _dev_ptr(workspace, "workspace", torch.uint8, nbytes=need), need, _stream(stream)))
+        del a
 
     def state_size(self) -> int:
         out = c_size_t(0)

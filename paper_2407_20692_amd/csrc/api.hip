@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -959,6 +960,33 @@ struct cpi_stream_s {
   uint8_t* ws = nullptr;
   hipStream_t st = nullptr;
   int64_t n_total = 0;
+  // FP32 Gamma buffers: push k writes buffer k % gamma_buffers; `cur` is the
+  // one the latest push (or checkpoint load) wrote.  written[b] is recorded
+  // on st after a write of buffer b; read[b] on the refocus stream after an
+  // asynchronous refocus of it, and the next write of b waits for it.
+  int64_t writes = 0;
+  int cur = 0;
+  hipEvent_t written[2] = {nullptr, nullptr};
+  hipEvent_t read[2] = {nullptr, nullptr};
+  bool read_pending[2] = {false, false};
+  float* gamma32(int b) const {
+    return reinterpret_cast<float*>(ws + (b == 0 ? plan.off_gamma32 : plan.off_gamma32b));
+  }
+  // Host chunks are copied on a stream of the handle's own (made at the first
+  // host push) into one of two staging pairs, so that the copy of chunk k + 1
+  // overlaps the work on chunk k: copied[b] is recorded after the copy into
+  // pair b, staged_free[b] on st after the push that read it.
+  hipStream_t cst = nullptr;
+  int stage_next = 0;
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  hipEvent_t staged_free[2] = {nullptr, nullptr};
+  bool stage_used[2] = {false, false};
+  ~cpi_stream_s() {
+    for (hipEvent_t e : {written[0], written[1], read[0], read[1], copied[0], copied[1],
+                         staged_free[0], staged_free[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (cst) (void)hipStreamDestroy(cst);
+  }
 };
 
 namespace {
@@ -973,6 +1001,24 @@ struct StateHeader {
 size_t state_bytes(const cpi_stream_s* s) {
   return sizeof(StateHeader) + size_t(s->pa) * 8 + size_t(s->pb) * 8 +
          size_t(s->pa) * size_t(s->pb) * (s->plan.state64 ? 8 : 4);
+}
+
+// The buffer the next Gamma32 write goes to; the stream waits until an
+// asynchronous refocus of it has finished.
+hipError_t gamma32_write_begin(cpi_stream_s* h, int* b) {
+  *b = int(h->writes % h->plan.gamma_buffers);
+  if (h->read_pending[*b]) {
+    hipError_t e = hipStreamWaitEvent(h->st, h->read[*b], 0);
+    if (e != hipSuccess) return e;
+    h->read_pending[*b] = false;
+  }
+  return hipSuccess;
+}
+
+hipError_t gamma32_write_end(cpi_stream_s* h, int b) {
+  h->cur = b;
+  ++h->writes;
+  return hipEventRecord(h->written[b], h->st);
 }
 
 cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t* fb, int64_t k) {
@@ -1027,7 +1073,6 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
   g.csum_a = csum_a;
   g.csum_b = csum_b;
   g.stats = stats;
-  g.gamma_f32 = reinterpret_cast<float*>(h->ws + h->plan.off_gamma32);
 
   const bool fp4 = cpi::bits_use_fp4(cp.kpad_bits / cpi::kBitBlock);
   g.fp4 = fp4 ? 1 : 0;
@@ -1040,12 +1085,18 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
       CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
       CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
     }
-    ProfScope ps("gemm", st);
-    g.row_bytes = cp.row_bytes_bits;
-    g.kblocks = cp.kpad_bits / cpi::kBitBlock;
-    g.mode = cpi::EPI_STREAM32;
-    g.acc32 = reinterpret_cast<int32_t*>(h->ws + h->plan.off_sab);
-    CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
+    int b = 0;
+    CPI_HIP(gamma32_write_begin(h, &b), "gamma buffer");
+    g.gamma_f32 = h->gamma32(b);
+    {
+      ProfScope ps("gemm", st);
+      g.row_bytes = cp.row_bytes_bits;
+      g.kblocks = cp.kpad_bits / cpi::kBitBlock;
+      g.mode = cpi::EPI_STREAM32;
+      g.acc32 = reinterpret_cast<int32_t*>(h->ws + h->plan.off_sab);
+      CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
+    }
+    CPI_HIP(gamma32_write_end(h, b), "gamma buffer");
   } else {
     int64_t* csum2_a = reinterpret_cast<int64_t*>(cws + mp.off_sum2_a);
     int64_t* csum2_b = reinterpret_cast<int64_t*>(cws + mp.off_sum2_b);
@@ -1059,6 +1110,9 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
       CPI_HIP(cpi::add_select_i64(tot_b, csum_b, csum2_b, cp.pb_pad, stats, st), "sums");
       CPI_HIP(cpi::u8_to_bytes(ja, jb, k, cp.kpad_bytes, stats, st), "ingest");
     }
+    int b = 0;
+    CPI_HIP(gamma32_write_begin(h, &b), "gamma buffer");
+    g.gamma_f32 = h->gamma32(b);
     ProfScope ps("gemm", st);
     g.mode = cpi::EPI_STREAM64;
     g.acc64 = reinterpret_cast<int64_t*>(h->ws + h->plan.off_sab);
@@ -1075,8 +1129,46 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
     gy.csum_a = csum2_a;
     gy.csum_b = csum2_b;
     CPI_HIP(cpi::gemm_correlate(gy, false, st), "gemm");
+    CPI_HIP(gamma32_write_end(h, b), "gamma buffer");
   }
   h->n_total = n_new;
+  return CPI_OK;
+}
+
+cpi_status stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t max_chunk,
+                         int gamma_buffers, void* workspace, size_t bytes, void* stream,
+                         cpi_stream_t* out) {
+  if (!out) return set_error(CPI_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  cpi::StreamPlan pl;
+  std::string why;
+  cpi_status s = cpi::plan_stream(pa, pb, int(fmt), max_chunk, &pl, &why, gamma_buffers);
+  if (s != CPI_OK) return set_error(s, why);
+  if (!workspace || !aligned16(workspace))
+    return set_error(CPI_ERR_INVALID_ARG, "workspace must be a 16-byte aligned device pointer");
+  if (bytes < pl.total)
+    return set_error(CPI_ERR_WORKSPACE,
+                     "stream workspace too small: need " + std::to_string(pl.total) + " bytes");
+  std::unique_ptr<cpi_stream_s> h(new cpi_stream_s());
+  h->plan = pl;
+  h->pa = pa;
+  h->pb = pb;
+  h->fmt = int(fmt);
+  h->ws = static_cast<uint8_t*>(workspace);
+  h->st = static_cast<hipStream_t>(stream);
+  for (int b = 0; b < 2; ++b)
+    for (hipEvent_t* e : {&h->written[b], &h->read[b], &h->copied[b], &h->staged_free[b]})
+      CPI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming), "stream init");
+  const int64_t sab_words = pa * pb * (pl.state64 ? 2 : 1);
+  CPI_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(h->ws + pl.off_sab), sab_words, 0, h->st),
+          "stream init");
+  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(h->ws + pl.off_sum_a), pl.chunk.pa_pad, 0,
+                        h->st),
+          "stream init");
+  CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(h->ws + pl.off_sum_b), pl.chunk.pb_pad, 0,
+                        h->st),
+          "stream init");
+  *out = h.release();
   return CPI_OK;
 }
 
@@ -1084,52 +1176,37 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
 
 extern "C" {
 
-cpi_status cpi_stream_workspace_size(int64_t pa, int64_t pb, cpi_frame_format fmt,
-                                     int64_t max_chunk, size_t* bytes) {
+cpi_status cpi_stream_workspace_size_ex(int64_t pa, int64_t pb, cpi_frame_format fmt,
+                                        int64_t max_chunk, int32_t gamma_buffers,
+                                        size_t* bytes) {
   return guarded([&]() -> cpi_status {
     if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");
     cpi::StreamPlan pl;
     std::string why;
-    cpi_status s = cpi::plan_stream(pa, pb, int(fmt), max_chunk, &pl, &why);
+    cpi_status s = cpi::plan_stream(pa, pb, int(fmt), max_chunk, &pl, &why, gamma_buffers);
     if (s != CPI_OK) return set_error(s, why);
     *bytes = pl.total;
     return CPI_OK;
   });
 }
 
+cpi_status cpi_stream_workspace_size(int64_t pa, int64_t pb, cpi_frame_format fmt,
+                                     int64_t max_chunk, size_t* bytes) {
+  return cpi_stream_workspace_size_ex(pa, pb, fmt, max_chunk, 1, bytes);
+}
+
+cpi_status cpi_stream_create_ex(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t max_chunk,
+                                int32_t gamma_buffers, void* workspace, size_t bytes,
+                                void* stream, cpi_stream_t* out) {
+  return guarded([&]() -> cpi_status {
+    return stream_create(pa, pb, fmt, max_chunk, gamma_buffers, workspace, bytes, stream, out);
+  });
+}
+
 cpi_status cpi_stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t max_chunk,
                              void* workspace, size_t bytes, void* stream, cpi_stream_t* out) {
   return guarded([&]() -> cpi_status {
-    if (!out) return set_error(CPI_ERR_INVALID_ARG, "out is null");
-    *out = nullptr;
-    cpi::StreamPlan pl;
-    std::string why;
-    cpi_status s = cpi::plan_stream(pa, pb, int(fmt), max_chunk, &pl, &why);
-    if (s != CPI_OK) return set_error(s, why);
-    if (!workspace || !aligned16(workspace))
-      return set_error(CPI_ERR_INVALID_ARG, "workspace must be a 16-byte aligned device pointer");
-    if (bytes < pl.total)
-      return set_error(CPI_ERR_WORKSPACE,
-                       "stream workspace too small: need " + std::to_string(pl.total) + " bytes");
-    cpi_stream_s* h = new cpi_stream_s();
-    h->plan = pl;
-    h->pa = pa;
-    h->pb = pb;
-    h->fmt = int(fmt);
-    h->ws = static_cast<uint8_t*>(workspace);
-    h->st = static_cast<hipStream_t>(stream);
-    const int64_t sab_words = pa * pb * (pl.state64 ? 2 : 1);
-    hipError_t e = cpi::fill_u32(reinterpret_cast<uint32_t*>(h->ws + pl.off_sab), sab_words, 0, h->st);
-    if (e == hipSuccess)
-      e = cpi::fill_u64(reinterpret_cast<uint64_t*>(h->ws + pl.off_sum_a), pl.chunk.pa_pad, 0, h->st);
-    if (e == hipSuccess)
-      e = cpi::fill_u64(reinterpret_cast<uint64_t*>(h->ws + pl.off_sum_b), pl.chunk.pb_pad, 0, h->st);
-    if (e != hipSuccess) {
-      delete h;
-      return device_error(e, "stream init");
-    }
-    *out = h;
-    return CPI_OK;
+    return stream_create(pa, pb, fmt, max_chunk, 1, workspace, bytes, stream, out);
   });
 }
 
@@ -1150,13 +1227,32 @@ cpi_status cpi_stream_push_host(cpi_stream_t s, const void* chunk_a, const void*
     if (!chunk_a || !chunk_b) return set_error(CPI_ERR_INVALID_ARG, "chunk pointers must not be null");
     if (k <= 0 || k > s->plan.max_chunk)
       return set_error(CPI_ERR_INVALID_ARG, "chunk size must be in [1, max_chunk]");
-    uint8_t* da = s->ws + s->plan.off_stage_a;
-    uint8_t* db = s->ws + s->plan.off_stage_b;
+    if (!s->cst) {
+      // the copy stream lives on the workspace's device
+      hipPointerAttribute_t at;
+      CPI_HIP(hipPointerGetAttributes(&at, s->ws), "copy stream");
+      int cur_dev = 0;
+      CPI_HIP(hipGetDevice(&cur_dev), "copy stream");
+      CPI_HIP(hipSetDevice(at.device), "copy stream");
+      hipError_t e = hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking);
+      (void)hipSetDevice(cur_dev);
+      CPI_HIP(e, "copy stream");
+    }
+    const int sb = s->stage_next;
+    uint8_t* da = s->ws + (sb == 0 ? s->plan.off_stage_a : s->plan.off_stage_a2);
+    uint8_t* db = s->ws + (sb == 0 ? s->plan.off_stage_b : s->plan.off_stage_b2);
     const size_t ba = size_t(k) * size_t(cpi::frame_bytes(s->pa, s->fmt));
     const size_t bb = size_t(k) * size_t(cpi::frame_bytes(s->pb, s->fmt));
-    CPI_HIP(hipMemcpyAsync(da, chunk_a, ba, hipMemcpyHostToDevice, s->st), "copy chunk");
-    CPI_HIP(hipMemcpyAsync(db, chunk_b, bb, hipMemcpyHostToDevice, s->st), "copy chunk");
-    return stream_push_device(s, da, db, k);
+    if (s->stage_used[sb]) CPI_HIP(hipStreamWaitEvent(s->cst, s->staged_free[sb], 0), "copy chunk");
+    CPI_HIP(hipMemcpyAsync(da, chunk_a, ba, hipMemcpyHostToDevice, s->cst), "copy chunk");
+    CPI_HIP(hipMemcpyAsync(db, chunk_b, bb, hipMemcpyHostToDevice, s->cst), "copy chunk");
+    CPI_HIP(hipEventRecord(s->copied[sb], s->cst), "copy chunk");
+    CPI_HIP(hipStreamWaitEvent(s->st, s->copied[sb], 0), "copy chunk");
+    s->stage_next ^= 1;
+    const cpi_status c = stream_push_device(s, da, db, k);
+    CPI_HIP(hipEventRecord(s->staged_free[sb], s->st), "copy chunk");
+    s->stage_used[sb] = true;
+    return c;
   });
 }
 
@@ -1196,7 +1292,7 @@ cpi_status cpi_stream_gamma(cpi_stream_t s, cpi_gamma_layout layout, double* gam
 cpi_status cpi_stream_gamma_f32_ptr(cpi_stream_t s, const float** gamma_f32) {
   return guarded([&]() -> cpi_status {
     if (!s || !gamma_f32) return set_error(CPI_ERR_INVALID_ARG, "null argument");
-    *gamma_f32 = reinterpret_cast<const float*>(s->ws + s->plan.off_gamma32);
+    *gamma_f32 = s->gamma32(s->cur);
     return CPI_OK;
   });
 }
@@ -1209,9 +1305,28 @@ cpi_status cpi_stream_refocus(cpi_stream_t s, const cpi_geometry* g, const doubl
     if (s->n_total == 0) return set_error(CPI_ERR_NOT_READY, "no frames pushed yet");
     if (g && (int64_t(g->wa) * g->ha != s->pa || int64_t(g->wb) * g->hb != s->pb))
       return set_error(CPI_ERR_INVALID_ARG, "geometry does not match the stream's detectors");
-    return cpi::refocus_enqueue(reinterpret_cast<const float*>(s->ws + s->plan.off_gamma32), g,
-                                alphas, n_alpha, out, workspace, workspace_bytes, s->st, nullptr,
-                                false);
+    return cpi::refocus_enqueue(s->gamma32(s->cur), g, alphas, n_alpha, out, workspace,
+                                workspace_bytes, s->st, nullptr, false);
+  });
+}
+
+cpi_status cpi_stream_refocus_async(cpi_stream_t s, const cpi_geometry* g, const double* alphas,
+                                    int32_t n_alpha, float* out, void* workspace,
+                                    size_t workspace_bytes, void* refocus_stream) {
+  return guarded([&]() -> cpi_status {
+    if (!s) return set_error(CPI_ERR_INVALID_ARG, "stream handle is null");
+    if (s->n_total == 0) return set_error(CPI_ERR_NOT_READY, "no frames pushed yet");
+    if (g && (int64_t(g->wa) * g->ha != s->pa || int64_t(g->wb) * g->hb != s->pb))
+      return set_error(CPI_ERR_INVALID_ARG, "geometry does not match the stream's detectors");
+    hipStream_t rs = static_cast<hipStream_t>(refocus_stream);
+    const int b = s->cur;
+    CPI_HIP(hipStreamWaitEvent(rs, s->written[b], 0), "refocus wait");
+    cpi_status st = cpi::refocus_enqueue(s->gamma32(b), g, alphas, n_alpha, out, workspace,
+                                         workspace_bytes, rs, nullptr, false);
+    if (st != CPI_OK) return st;
+    CPI_HIP(hipEventRecord(s->read[b], rs), "refocus record");
+    s->read_pending[b] = true;
+    return CPI_OK;
   });
 }
 
@@ -1269,10 +1384,13 @@ cpi_status cpi_stream_load(cpi_stream_t s, const void* host_buf, size_t bytes) {
     if (s->n_total > 0) {
       const int64_t* ta = reinterpret_cast<const int64_t*>(s->ws + s->plan.off_sum_a);
       const int64_t* tb = reinterpret_cast<const int64_t*>(s->ws + s->plan.off_sum_b);
+      int b = 0;
+      CPI_HIP(gamma32_write_begin(s, &b), "load");
       CPI_HIP(cpi::state_gamma(s->ws + s->plan.off_sab, s->plan.state64, ta, tb, s->n_total, s->pa,
-                               s->pb, CPI_GAMMA_VIEW_MAJOR, nullptr,
-                               reinterpret_cast<float*>(s->ws + s->plan.off_gamma32), nullptr, s->st),
+                               s->pb, CPI_GAMMA_VIEW_MAJOR, nullptr, s->gamma32(b), nullptr,
+                               s->st),
               "load");
+      CPI_HIP(gamma32_write_end(s, b), "load");
     }
     CPI_HIP(hipStreamSynchronize(s->st), "load");
     return CPI_OK;

@@ -210,36 +210,62 @@ __global__ __launch_bounds__(256, 2) void k_ingest_bits(IngestJob j0, IngestJob 
 }
 
 // Packed-bit frames -> bit rows for row words [w0, kw) (frames 32 w0 ..):
-// one thread per pixel row p < npix_pad of either detector, 32 byte loads
-// per word (consecutive threads read the same or adjacent bytes of a frame),
-// popcounts added to sums.  Bits of pixels at or past 8 * row bytes, and of
-// frames at or past n, are zero.
+// one thread per (pixel word q, row word w) of either detector (w fastest),
+// which reads word q of frames 32 w .. 32 w + 31 (guarded byte loads: bits
+// of pixels at or past 8 * row bytes, and of frames at or past n, are zero)
+// and transposes the 32 x 32 block into row word w of pixels 32 q .. 32 q + 31.
+// Popcounts are combined per work-group in LDS, then added to sums.
 __global__ __launch_bounds__(256) void k_ingest_bits_tail(IngestJob j0, IngestJob j1, int64_t n,
                                                          int64_t kw, int64_t w0) {
-  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  const bool second = t >= j0.npix_pad;
+  constexpr int kRows = (256 + 2) * 32;   // rows a work-group can touch
+  __shared__ uint32_t psum[kRows];
+  const int64_t wt = kw - w0;   // row words per pixel word
+  const int64_t q0a = j0.npix_pad / 32;
+  const int64_t t0 = int64_t(blockIdx.x) * 256;
+  const int64_t qlo = t0 / wt;   // first pixel word (over both detectors) of the block
+  for (int i = threadIdx.x; i < kRows; i += 256) psum[i] = 0u;
+  __syncthreads();
+  const int64_t t = t0 + threadIdx.x;
+  const int64_t qg = t / wt, w = w0 + t % wt;
+  const bool second = qg >= q0a;
   const IngestJob& job = second ? j1 : j0;
-  const int64_t p = second ? t - j0.npix_pad : t;
-  if (p >= job.npix_pad) return;
-  const int64_t fbytes = (job.npix + 7) / 8;
-  const bool pin = p / 8 < fbytes;
-  const int64_t pb = pin ? p / 8 : 0;
-  const int sh = int(p & 7);
-  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(job.out) + p * kw;
-  unsigned long long cnt = 0;
-  for (int64_t w = w0; w < kw; ++w) {
-    uint32_t v = 0u;
+  const int64_t q = second ? qg - q0a : qg;
+  if (q < job.npix_pad / 32) {
+    const int64_t fbytes = (job.npix + 7) / 8;
+    uint32_t d[32];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      const int64_t f = 32 * w + j;
-      const bool ok = pin && f < n;
-      const uint32_t x = job.frames[(ok ? f : 0) * fbytes + pb];
-      v |= (ok ? (x >> sh) & 1u : 0u) << j;
+    for (int k = 0; k < 32; ++k) {
+      const int64_t f = 32 * w + k;
+      const uint8_t* row = job.frames + (f < n ? f : 0) * fbytes;
+      uint32_t v = 0u;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t by = 4 * q + b;
+        const bool ok = f < n && by < fbytes;
+        v |= (ok ? uint32_t(row[ok ? by : 0]) : 0u) << (8 * b);
+      }
+      d[k] = v;
     }
-    cnt += __popc(v);
-    out[w] = job.swap02 ? swap_bits02(v) : v;
+    transpose32(d);
+    uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(job.out) + 32 * q * kw + w;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      out[i * kw] = job.swap02 ? swap_bits02(d[i]) : d[i];
+      if (d[i]) atomicAdd(&psum[(qg - qlo) * 32 + i], uint32_t(__popc(d[i])));
+    }
   }
-  atomicAdd(reinterpret_cast<unsigned long long*>(job.sums) + p, cnt);
+  __syncthreads();
+  const int64_t qhi = (t0 + 255) / wt;
+  for (int64_t r = threadIdx.x; r < (qhi - qlo + 1) * 32; r += 256) {
+    const uint32_t c = psum[r];
+    if (!c) continue;
+    const int64_t qq = qlo + r / 32;
+    const bool sec = qq >= q0a;
+    const IngestJob& jb = sec ? j1 : j0;
+    const int64_t p = (sec ? qq - q0a : qq) * 32 + r % 32;
+    if (p < jb.npix_pad)
+      atomicAdd(reinterpret_cast<unsigned long long*>(jb.sums) + p, (unsigned long long)c);
+  }
 }
 
 // Byte frames -> bit rows.  Each wave owns 256 consecutive pixels (lane l:
@@ -580,10 +606,11 @@ hipError_t ingest_bits(const IngestJob& a, const IngestJob& b, int64_t n, int64_
     if (e != hipSuccess) return e;
   }
   const int64_t kw = kpad_bits / 32, w0 = full * (kBitsTileFr / 32);
-  const int64_t rows = a.npix_pad + b.npix_pad;
-  if (w0 < kw && rows > 0) {
-    hipLaunchKernelGGL(k_ingest_bits_tail, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, s, a,
-                       b, n, kw, w0);
+  const int64_t threads = (a.npix_pad + b.npix_pad) / 32 * (kw - w0);
+  if (threads > 0) {
+    if ((threads + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ingest_bits_tail, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s,
+                       a, b, n, kw, w0);
     return hipGetLastError();
   }
   return hipSuccess;

@@ -214,9 +214,11 @@ cpi_status plan_refocus(const cpi_geometry* g, int32_t n_alpha, RefocusPlan* p,
 }
 
 cpi_status plan_stream(int64_t pa, int64_t pb, int fmt, int64_t max_chunk, StreamPlan* p,
-                       std::string* why) {
+                       std::string* why, int gamma_buffers) {
   if (!p) return fail(why, CPI_ERR_INVALID_ARG, "plan output is null");
   if (max_chunk <= 0) return fail(why, CPI_ERR_INVALID_ARG, "max_chunk must be positive");
+  if (gamma_buffers != 1 && gamma_buffers != 2)
+    return fail(why, CPI_ERR_INVALID_ARG, "gamma_buffers must be 1 or 2");
   if (fmt == CPI_FRAMES_U8 && max_chunk > kByteChunk)
     return fail(why, CPI_ERR_INVALID_ARG, "U8 chunks are limited to 131008 frames");
   StreamPlan q;
@@ -239,6 +241,16 @@ cpi_status plan_stream(int64_t pa, int64_t pb, int fmt, int64_t max_chunk, Strea
   off = align256(off + size_t(max_chunk) * size_t(frame_bytes(pa, fmt)));
   q.off_stage_b = off;
   off = align256(off + size_t(max_chunk) * size_t(frame_bytes(pb, fmt)));
+  q.off_stage_a2 = off;
+  off = align256(off + size_t(max_chunk) * size_t(frame_bytes(pa, fmt)));
+  q.off_stage_b2 = off;
+  off = align256(off + size_t(max_chunk) * size_t(frame_bytes(pb, fmt)));
+  q.gamma_buffers = gamma_buffers;
+  q.off_gamma32b = q.off_gamma32;
+  if (gamma_buffers == 2) {
+    q.off_gamma32b = off;
+    off = align256(off + size_t(pa) * size_t(pb) * 4);
+  }
   q.total = off;
   *p = q;
   return CPI_OK;

@@ -92,10 +92,13 @@ struct StreamPlan {
   size_t off_chunk_ws = 0;          // chunk workspace (operands, chunk sums, stats)
   size_t off_sab = 0, off_sum_a = 0, off_sum_b = 0, off_gamma32 = 0;
   size_t off_stage_a = 0, off_stage_b = 0;   // device copies of host chunks
+  size_t off_stage_a2 = 0, off_stage_b2 = 0; // the second pair (copies alternate)
+  int gamma_buffers = 1;            // FP32 Gamma buffers (2: pushes alternate)
+  size_t off_gamma32b = 0;          // second buffer (== off_gamma32 when one)
   size_t total = 0;
 };
 
 cpi_status plan_stream(int64_t pa, int64_t pb, int fmt, int64_t max_chunk,
-                       StreamPlan* p, std::string* why);
+                       StreamPlan* p, std::string* why, int gamma_buffers = 1);
 
 }  // namespace cpi

@@ -134,6 +134,17 @@ int main() {
   CHECK(plan_stream(64, 16, 0, 200000, &sp, &why) == CPI_ERR_INVALID_ARG);
   CHECK(plan_stream(64, 16, 0, 1000, &sp, &why) == CPI_OK && sp.state64);
   CHECK(plan_stream(64, 16, 1, 0, &sp, &why) == CPI_ERR_INVALID_ARG);
+  // two FP32 Gamma buffers: the second one past the staging copies
+  StreamPlan sp1, sp2;
+  CHECK(plan_stream(16384, 4096, 1, 1000, &sp1, &why) == CPI_OK);
+  CHECK(sp1.gamma_buffers == 1 && sp1.off_gamma32b == sp1.off_gamma32);
+  CHECK(plan_stream(16384, 4096, 1, 1000, &sp2, &why, 2) == CPI_OK);
+  CHECK(sp2.gamma_buffers == 2 && sp2.off_gamma32 == sp1.off_gamma32);
+  CHECK(sp2.off_gamma32b >= sp2.off_stage_b + size_t(1000) * 512);
+  CHECK(sp2.total - sp2.off_gamma32b >= size_t(16384) * 4096 * 4);
+  CHECK(sp2.total - sp1.total >= size_t(16384) * 4096 * 4);
+  CHECK(plan_stream(64, 16, 1, 100, &sp, &why, 3) == CPI_ERR_INVALID_ARG);
+  CHECK(plan_stream(64, 16, 1, 100, &sp, &why, 0) == CPI_ERR_INVALID_ARG);
 
   if (failures) {
     std::fprintf(stderr, "%d failures\n", failures);

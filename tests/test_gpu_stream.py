@@ -258,3 +258,114 @@ def test_streaming_workload_200_distinct_chunks(cpi):
     assert torch.equal(numf.sum(dim=0), n * a_tb - sa_f * sb_f.sum())
     assert torch.equal(numf.sum(dim=1), n * b_ta - sb_f * sa_f.sum())
     assert torch.equal(numf @ v, n * bt_av - sb_f * (sa_f @ v))
+
+
+@pytest.mark.parametrize("buffers", [2, 1])
+def test_overlapped_refocus_matches_serial(cpi, buffers):
+    """The streamed workload (Da 128x128, Db 64x64, 200 distinct chunks of 1000
+    1-bit frames) with the refocus of chunk k enqueued on a second stream while
+    chunk k + 1 is folded on the handle's stream (two FP32 Gamma buffers; one
+    buffer serialises the two and must give the same results).  Every chunk's
+    refocused stack equals the serial stream's bit for bit, and the final state
+    equals single-shot correlation of all 200000 frames over every entry."""
+    import torch
+    from synth.gpu_speckle import generate_binary_frames_gpu
+
+    w = WORKLOADS["da128_db64_stream200x1000_bit1"]
+    n, pa, pb, k = w.n_frames, w.pa, w.pb, w.chunk
+    nch = n // k if buffers == 2 else 20
+    d = dev()
+    log(f"case {w.name}: {nch} chunks, {buffers} Gamma buffers")
+    fa, fb = generate_binary_frames_gpu(w, count=nch * k, device=d)
+    geo = cpi.geometry_default(w.wa, w.ha, w.wb, w.hb)
+    al = alphas_for(w)
+    na = len(al)
+    need = cpi.refocus_workspace_size(geo, na)
+    ser = cpi.Stream(pa, pb, cpi.FRAMES_BIT1, max_chunk=k)
+    out_s = torch.empty((nch, na * pa), dtype=torch.float32, device=d)
+    ws_s = cpi.alloc_workspace(need, d)
+    for c in range(nch):
+        ser.push(fa[c * k:(c + 1) * k].reshape(-1), fb[c * k:(c + 1) * k].reshape(-1), k)
+        ser.refocus(geo, al, out_s[c], workspace=ws_s)
+    torch.cuda.synchronize()
+    su, sr = torch.cuda.Stream(), torch.cuda.Stream()
+    ovl = cpi.Stream(pa, pb, cpi.FRAMES_BIT1, max_chunk=k, stream=su, gamma_buffers=buffers)
+    out_o = torch.full((nch, na * pa), float("nan"), dtype=torch.float32, device=d)
+    ws_o = cpi.alloc_workspace(need, d)
+    torch.cuda.synchronize()
+    for c in range(nch):
+        ovl.push(fa[c * k:(c + 1) * k].reshape(-1), fb[c * k:(c + 1) * k].reshape(-1), k)
+        ovl.refocus_async(geo, al, out_o[c], ws_o, sr)
+    torch.cuda.synchronize()
+    assert ovl.frames == nch * k
+    bad = [c for c in range(nch) if not torch.equal(out_o[c], out_s[c])]
+    assert not bad, f"chunks whose stacks differ: {bad[:10]}"
+    keys = ("gamma", "gamma_f32", "numer", "sum_a", "sum_b")
+    sizes = {"gamma": (pa * pb, torch.float64), "gamma_f32": (pa * pb, torch.float32),
+             "numer": (pa * pb, torch.int64), "sum_a": (pa, torch.int64), "sum_b": (pb, torch.int64)}
+    got = {key: torch.empty(sizes[key][0], dtype=sizes[key][1], device=d) for key in keys}
+    ovl.gamma(cpi.GAMMA_VIEW_MAJOR, **got)
+    torch.cuda.synchronize()
+    one = {key: torch.empty_like(v) for key, v in got.items()}
+    cpi.correlate(fa.reshape(-1), fb.reshape(-1), nch * k, pa, pb, cpi.FRAMES_BIT1,
+                  cpi.GAMMA_VIEW_MAJOR, **one)
+    torch.cuda.synchronize()
+    for key in keys:
+        assert torch.equal(got[key], one[key]), key
+    ser.close()
+    ovl.close()
+
+
+def test_overlapped_stream_errors(cpi):
+    import torch
+
+    with pytest.raises(cpi.CpiError) as e:
+        cpi.Stream(64, 16, cpi.FRAMES_BIT1, max_chunk=100, gamma_buffers=3)
+    assert e.value.status == 1
+    s = cpi.Stream(64, 16, cpi.FRAMES_BIT1, max_chunk=100, gamma_buffers=2)
+    geo = cpi.geometry_default(8, 8, 4, 4)
+    out = torch.empty(64, dtype=torch.float32, device=dev())
+    ws = cpi.alloc_workspace(cpi.refocus_workspace_size(geo, 1), dev())
+    with pytest.raises(cpi.CpiError) as e:
+        s.refocus_async(geo, [1.0], out, ws, torch.cuda.Stream())
+    assert e.value.status == 6   # not ready
+    s.close()
+
+
+def test_host_pushes_from_pinned_memory(cpi):
+    """Host chunks from pinned memory (copies on the handle's copy stream,
+    alternating staging buffers, no host waits between pushes), u8 and 1-bit,
+    with ragged chunk sizes: the final state equals pushes of the same chunks
+    from device memory bit for bit, and the FP32 Gamma after each push equals
+    the device-push stream's."""
+    import torch
+
+    rng = np.random.default_rng(31)
+    for fmt_name in ("bit1", "u8"):
+        n, pa, pb = 6000, 256, 64
+        a = (rng.random((n, pa)) < 0.25).astype(np.uint8)
+        b = (rng.random((n, pb)) < 0.25).astype(np.uint8)
+        fmt = cpi.FRAMES_BIT1 if fmt_name == "bit1" else cpi.FRAMES_U8
+        fa = pack_bits_lsb(a) if fmt_name == "bit1" else a
+        fb = pack_bits_lsb(b) if fmt_name == "bit1" else b
+        ha = torch.from_numpy(np.ascontiguousarray(fa)).pin_memory()
+        hb = torch.from_numpy(np.ascontiguousarray(fb)).pin_memory()
+        sh = cpi.Stream(pa, pb, fmt, max_chunk=1100)
+        sd = cpi.Stream(pa, pb, fmt, max_chunk=1100)
+        g_h, g_d = [], []
+        for lo, hi in _chunks(n, [1000, 7, 1100, 513, 999, 1100, 64, 1100, 117]):
+            log(f"case host push {fmt_name} frames {lo}..{hi}")
+            sh.push_host(ha[lo:hi].reshape(-1), hb[lo:hi].reshape(-1), hi - lo)
+            sd.push(to_dev(fa[lo:hi]), to_dev(fb[lo:hi]), hi - lo)
+            x = torch.empty(pa * pb, dtype=torch.float32, device=dev())
+            y = torch.empty_like(x)
+            sh.gamma(cpi.GAMMA_VIEW_MAJOR, gamma_f32=x)
+            sd.gamma(cpi.GAMMA_VIEW_MAJOR, gamma_f32=y)
+            g_h.append(x)
+            g_d.append(y)
+        torch.cuda.synchronize()
+        for x, y in zip(g_h, g_d):
+            assert torch.equal(x, y)
+        assert_bit_exact(_gamma(cpi, sh), _gamma(cpi, sd))
+        sh.close()
+        sd.close()
