@@ -560,7 +560,11 @@ def hot_path(args, cpi, torch, np, dev, w, n, fmt, da, db, alphas, tune=True, pl
     pa, pb = w.pa, w.pb
     gamma = torch.empty(pa * pb, dtype=torch.float64, device=dev)
     g32 = torch.empty(pa * pb, dtype=torch.float32, device=dev)
-    ws_c = cpi.alloc_workspace(cpi.correlate_workspace_size(n, pa, pb, fmt), dev)
+    # the one-shot workspace, or what memory allows (the library then folds
+    # the frames in blocks)
+    ws_need = cpi.correlate_workspace_size(n, pa, pb, fmt)
+    ws_bytes = min(ws_need, torch.cuda.mem_get_info(dev)[0] - (16 << 30))
+    ws_c = cpi.alloc_workspace(ws_bytes, dev)
     geo = cpi.geometry_default(w.wa, w.ha, w.wb, w.hb)
     na = len(alphas)
     out = torch.empty(na * w.pa, dtype=torch.float32, device=dev)
@@ -631,6 +635,8 @@ def hot_path(args, cpi, torch, np, dev, w, n, fmt, da, db, alphas, tune=True, pl
     fig = {
         "workload": w.name,
         "n_frames": n,
+        "correlate_workspace": {"bytes": ws_bytes, "one_shot_bytes": ws_need,
+                                "blocked": ws_bytes < ws_need},
         "ms_per_step": ms_step,
         "pixel_pair_frames_per_s": pairs / (ms_step * 1e-3),
         "correlate": {"ms": ms_corr, "ingest_ms": groups["ingest"], "gemm_ms": groups["gemm"],
@@ -916,8 +922,10 @@ def next_rows(cpi, torch, np, dev, g32, geo, w, alphas):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 3 for the paper workload)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default 3; 1 for the paper workload)")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--stream-chunks", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -943,9 +951,13 @@ def main():
     ap.add_argument("--runs", type=int, default=625,
                     help="denoise workload: streams of 50000 frames (32 pairs each)")
     ap.add_argument("--epochs", type=int, default=4, help="denoise workload: training epochs")
-    ap.add_argument("--files", type=int, default=11,
+    ap.add_argument("--files", type=int, default=7808,
                     help="paper workload: files of 512 frames (the paper uses 11, 100, 500, 7808)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 3 if args.workload == "paper" else 20
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "paper" else 3
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

@@ -114,10 +114,13 @@ cpi_status cpi_geometry_default(int32_t wa, int32_t ha, int32_t wb, int32_t hb,
  *   by the memory available): when workspace_bytes, capped by
  *   CPI_WORKSPACE_LIMIT if set, is below the one-shot size, the frames are
  *   folded in blocks of F frames through the running sums of the streaming
- *   calls (F the largest multiple of 512 whose state, see
- *   cpi_stream_workspace_size, fits); the results are identical and the call
- *   stays asynchronous (one push per block is enqueued).  A workspace below
- *   the state for F = 512 gives CPI_ERR_WORKSPACE.
+ *   calls (F the largest multiple of 512 whose state fits: the int32 or int64
+ *   S_ab, the sums and one block's operands, without the streaming calls'
+ *   FP32 Gamma buffer); the results are identical and the call stays
+ *   asynchronous (one push per block is enqueued).  Blocks only pay when the
+ *   frames' operands outweigh S_ab (n above about 32 * pa * pb / (pa + pb)
+ *   frames for 1-bit data: 1.05e6 at 65536 x 65536 pixels).  A workspace
+ *   below the state for F = 512 gives CPI_ERR_WORKSPACE.
  *   Errors: CPI_ERR_INVALID_ARG (null frames/workspace, n, pa or pb <= 0,
  *   bad enum, misalignment, all outputs null), CPI_ERR_OVERFLOW (n*n*255*255
  *   >= 2^63 for U8, n*n >= 2^53 for either format), CPI_ERR_WORKSPACE,

@@ -478,6 +478,12 @@ size_t usable_workspace(size_t given) {
 
 constexpr int64_t kBlockUnit = 512;   // frames; keeps every block 16-byte aligned
 
+// Defined with the streaming calls below; gamma_buffers 0 makes a handle
+// whose pushes fold the sums only (the blocks of cpi_correlate).
+cpi_status stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t max_chunk,
+                         int gamma_buffers, void* workspace, size_t bytes, void* stream,
+                         cpi_stream_t* out);
+
 // Memory-adaptive blocking: the largest multiple of kBlockUnit frames (at most
 // n rounded up) whose running-sum state fits in `bytes`, and that state's
 // size; 0 when not even kBlockUnit frames fit.
@@ -486,7 +492,8 @@ int64_t block_frames(int64_t n, int64_t pa, int64_t pb, cpi_frame_format fmt, si
   auto size_for = [&](int64_t units, size_t* b) {
     cpi::StreamPlan sp;
     std::string why;
-    if (cpi::plan_stream(pa, pb, int(fmt), units * kBlockUnit, &sp, &why) != CPI_OK) return false;
+    if (cpi::plan_stream(pa, pb, int(fmt), units * kBlockUnit, &sp, &why, 0) != CPI_OK)
+      return false;
     *b = sp.total;
     return true;
   };
@@ -564,7 +571,7 @@ cpi_status cpi_correlate(const void* frames_a, const void* frames_b, int64_t n, 
                                                 " bytes, or at least " + std::to_string(need) +
                                                 " to work in blocks of 512 frames");
       cpi_stream_t h = nullptr;
-      s = cpi_stream_create(pa, pb, fmt, f, workspace, usable, stream, &h);
+      s = stream_create(pa, pb, fmt, f, 0, workspace, usable, stream, &h);
       if (s != CPI_OK) return s;
       const int64_t fa = cpi::frame_bytes(pa, int(fmt)), fb = cpi::frame_bytes(pb, int(fmt));
       const uint8_t* a8 = static_cast<const uint8_t*>(frames_a);
@@ -966,6 +973,9 @@ struct cpi_stream_s {
   // asynchronous refocus of it, and the next write of b waits for it.
   int64_t writes = 0;
   int cur = 0;
+  // false for the internal streams of blocked correlation: pushes then only
+  // fold the sums (the outputs are made once, from the final state)
+  bool refresh_gamma32 = true;
   hipEvent_t written[2] = {nullptr, nullptr};
   hipEvent_t read[2] = {nullptr, nullptr};
   bool read_pending[2] = {false, false};
@@ -1086,8 +1096,10 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
       CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
     }
     int b = 0;
-    CPI_HIP(gamma32_write_begin(h, &b), "gamma buffer");
-    g.gamma_f32 = h->gamma32(b);
+    if (h->refresh_gamma32) {
+      CPI_HIP(gamma32_write_begin(h, &b), "gamma buffer");
+      g.gamma_f32 = h->gamma32(b);
+    }
     {
       ProfScope ps("gemm", st);
       g.row_bytes = cp.row_bytes_bits;
@@ -1096,7 +1108,7 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
       g.acc32 = reinterpret_cast<int32_t*>(h->ws + h->plan.off_sab);
       CPI_HIP(cpi::gemm_correlate(g, true, st), "gemm");
     }
-    CPI_HIP(gamma32_write_end(h, b), "gamma buffer");
+    if (h->refresh_gamma32) CPI_HIP(gamma32_write_end(h, b), "gamma buffer");
   } else {
     int64_t* csum2_a = reinterpret_cast<int64_t*>(cws + mp.off_sum2_a);
     int64_t* csum2_b = reinterpret_cast<int64_t*>(cws + mp.off_sum2_b);
@@ -1111,8 +1123,10 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
       CPI_HIP(cpi::u8_to_bytes(ja, jb, k, cp.kpad_bytes, stats, st), "ingest");
     }
     int b = 0;
-    CPI_HIP(gamma32_write_begin(h, &b), "gamma buffer");
-    g.gamma_f32 = h->gamma32(b);
+    if (h->refresh_gamma32) {
+      CPI_HIP(gamma32_write_begin(h, &b), "gamma buffer");
+      g.gamma_f32 = h->gamma32(b);
+    }
     ProfScope ps("gemm", st);
     g.mode = cpi::EPI_STREAM64;
     g.acc64 = reinterpret_cast<int64_t*>(h->ws + h->plan.off_sab);
@@ -1129,7 +1143,7 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
     gy.csum_a = csum2_a;
     gy.csum_b = csum2_b;
     CPI_HIP(cpi::gemm_correlate(gy, false, st), "gemm");
-    CPI_HIP(gamma32_write_end(h, b), "gamma buffer");
+    if (h->refresh_gamma32) CPI_HIP(gamma32_write_end(h, b), "gamma buffer");
   }
   h->n_total = n_new;
   return CPI_OK;
@@ -1156,6 +1170,7 @@ cpi_status stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t m
   h->fmt = int(fmt);
   h->ws = static_cast<uint8_t*>(workspace);
   h->st = static_cast<hipStream_t>(stream);
+  h->refresh_gamma32 = gamma_buffers > 0;
   for (int b = 0; b < 2; ++b)
     for (hipEvent_t* e : {&h->written[b], &h->read[b], &h->copied[b], &h->staged_free[b]})
       CPI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming), "stream init");
@@ -1181,6 +1196,8 @@ cpi_status cpi_stream_workspace_size_ex(int64_t pa, int64_t pb, cpi_frame_format
                                         size_t* bytes) {
   return guarded([&]() -> cpi_status {
     if (!bytes) return set_error(CPI_ERR_INVALID_ARG, "bytes is null");
+    if (gamma_buffers != 1 && gamma_buffers != 2)
+      return set_error(CPI_ERR_INVALID_ARG, "gamma_buffers must be 1 or 2");
     cpi::StreamPlan pl;
     std::string why;
     cpi_status s = cpi::plan_stream(pa, pb, int(fmt), max_chunk, &pl, &why, gamma_buffers);
@@ -1199,6 +1216,8 @@ cpi_status cpi_stream_create_ex(int64_t pa, int64_t pb, cpi_frame_format fmt, in
                                 int32_t gamma_buffers, void* workspace, size_t bytes,
                                 void* stream, cpi_stream_t* out) {
   return guarded([&]() -> cpi_status {
+    if (gamma_buffers != 1 && gamma_buffers != 2)
+      return set_error(CPI_ERR_INVALID_ARG, "gamma_buffers must be 1 or 2");
     return stream_create(pa, pb, fmt, max_chunk, gamma_buffers, workspace, bytes, stream, out);
   });
 }

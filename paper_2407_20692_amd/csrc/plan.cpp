@@ -217,7 +217,7 @@ cpi_status plan_stream(int64_t pa, int64_t pb, int fmt, int64_t max_chunk, Strea
                        std::string* why, int gamma_buffers) {
   if (!p) return fail(why, CPI_ERR_INVALID_ARG, "plan output is null");
   if (max_chunk <= 0) return fail(why, CPI_ERR_INVALID_ARG, "max_chunk must be positive");
-  if (gamma_buffers != 1 && gamma_buffers != 2)
+  if (gamma_buffers < 0 || gamma_buffers > 2)
     return fail(why, CPI_ERR_INVALID_ARG, "gamma_buffers must be 1 or 2");
   if (fmt == CPI_FRAMES_U8 && max_chunk > kByteChunk)
     return fail(why, CPI_ERR_INVALID_ARG, "U8 chunks are limited to 131008 frames");
@@ -235,8 +235,8 @@ cpi_status plan_stream(int64_t pa, int64_t pb, int fmt, int64_t max_chunk, Strea
   off = align256(off + size_t(q.chunk.pa_pad) * 8);
   q.off_sum_b = off;
   off = align256(off + size_t(q.chunk.pb_pad) * 8);
-  q.off_gamma32 = off;
-  off = align256(off + size_t(pa) * size_t(pb) * 4);
+  q.off_gamma32 = off;   // (no buffer when gamma_buffers is 0: sums only)
+  off = align256(off + (gamma_buffers > 0 ? size_t(pa) * size_t(pb) * 4 : 0));
   q.off_stage_a = off;
   off = align256(off + size_t(max_chunk) * size_t(frame_bytes(pa, fmt)));
   q.off_stage_b = off;

@@ -93,7 +93,8 @@ struct StreamPlan {
   size_t off_sab = 0, off_sum_a = 0, off_sum_b = 0, off_gamma32 = 0;
   size_t off_stage_a = 0, off_stage_b = 0;   // device copies of host chunks
   size_t off_stage_a2 = 0, off_stage_b2 = 0; // the second pair (copies alternate)
-  int gamma_buffers = 1;            // FP32 Gamma buffers (2: pushes alternate)
+  int gamma_buffers = 1;            // FP32 Gamma buffers (2: pushes alternate; 0: none,
+                                    // the pushes fold the sums only)
   size_t off_gamma32b = 0;          // second buffer (== off_gamma32 when one)
   size_t total = 0;
 };

@@ -144,7 +144,13 @@ int main() {
   CHECK(sp2.total - sp2.off_gamma32b >= size_t(16384) * 4096 * 4);
   CHECK(sp2.total - sp1.total >= size_t(16384) * 4096 * 4);
   CHECK(plan_stream(64, 16, 1, 100, &sp, &why, 3) == CPI_ERR_INVALID_ARG);
-  CHECK(plan_stream(64, 16, 1, 100, &sp, &why, 0) == CPI_ERR_INVALID_ARG);
+  CHECK(plan_stream(64, 16, 1, 100, &sp, &why, -1) == CPI_ERR_INVALID_ARG);
+  // no FP32 Gamma buffer (blocked correlation): the state is S_ab, the sums
+  // and one block's operands
+  StreamPlan sp0;
+  CHECK(plan_stream(16384, 4096, 1, 1000, &sp0, &why, 0) == CPI_OK);
+  CHECK(sp0.gamma_buffers == 0 && sp1.total - sp0.total >= size_t(16384) * 4096 * 4);
+  CHECK(sp0.total - sp0.off_sab >= size_t(16384) * 4096 * 4);
 
   if (failures) {
     std::fprintf(stderr, "%d failures\n", failures);
