@@ -303,25 +303,26 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
 // ---- convolution, backward-weight -------------------------------------------
 // dW[n][k] += sum over pixels m of dY[m][n] * X(m, k), X the implicit im2col of
 // the input.  A work-group owns an NT x KT tile of dW (NT = 32 or 64 output
-// channels, KT = 64, 128 or 256 K values) and a range of pixels, taken 64 at
-// a time: dY and X blocks are loaded with 16-byte loads and stored transposed
-// in LDS ([channel][pixel]) so that each lane's 8 consecutive pixels are one
-// 16-byte LDS read.  NT = 64: wave w owns channels 32 (w & 1) + [0, 32) and K
-// values (KT / 2) (w >> 1) + [0, KT / 2); NT = 32: all 32 channels and K
-// values (KT / 4) w + [0, KT / 4).  The work-group's partial tile is added to
-// dW with FP32 atomics.  Work-groups of the first K tile also sum their dY
-// block over pixels into db (if given).  KT = 64 is used: wider K tiles re-read
-// fewer dY blocks but measured slower (their transposing LDS writes and
-// registers grow with KT).
+// channels, KT = 64 K values) and a range of pixels, taken 64 at a time: dY
+// and X blocks are loaded with 16-byte loads and stored as they are in LDS
+// ([pixel][channel]), and the matrix-core operands, whose K index is the
+// pixel, are read with the transposing LDS loads of this part
+// (ds_read_b64_tr_b16: within each 16 lanes, lane j receives element j % 4 of
+// the 8-byte rows that lanes 4 k + j / 4 address, k = 0 .. 3; so when lane
+// 4 k + q addresses pixel k, channels 4 q .. 4 q + 3, lane j gets channel j at
+// four consecutive pixels).  NT = 64: wave w owns channels 32 (w & 1) +
+// [0, 32) and K values (KT / 2) (w >> 1) + [0, KT / 2); NT = 32: all 32
+// channels and K values (KT / 4) w + [0, KT / 4).  The work-group's partial
+// tile is added to dW with FP32 atomics.  Work-groups of the first K tile also
+// sum their dY block over pixels into db (if given).
 template <int KS, int NT, int KT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
   constexpr int HALF = KS / 2;
   constexpr int PB = 64;                 // pixels per block
-  constexpr int LP = PB + 8;             // LDS row pitch (elements)
   constexpr int KW = NT == 64 ? KT / 2 : KT / 4;  // K values per wave
   constexpr int NKB = KW / 16;                    // 16-wide K blocks per wave
-  __shared__ __attribute__((aligned(16))) uint16_t ty[NT][LP];
-  __shared__ __attribute__((aligned(16))) uint16_t tx[KT][LP];
+  __shared__ __attribute__((aligned(16))) uint16_t ty[PB][NT + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t tx[PB][KT + 8];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int r = lane & 15, g = lane >> 4;
@@ -344,9 +345,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
   float bsum = 0.0f;
   // A block's loads all go out before any of its LDS writes, and the next
   // block's loads are issued before the current block's matrix-core ops.
-  // Piece c covers pixel c % PB and channel group c / PB: the 64 lanes of a
-  // wave hold 64 consecutive pixels of one group, so their transposed 2-byte
-  // LDS writes fall on consecutive addresses (no bank conflicts).
+  // Piece c covers pixel c % PB and channel group c / PB (16 bytes, stored
+  // as loaded).
   constexpr int YQ = PB * (NT / 8) / 256;   // dY pieces per thread
   constexpr int XQ = PB * (KT / 8) / 256;   // X pieces per thread
   static_assert(YQ >= 1 && XQ >= 1, "tile too small for 256 threads");
@@ -382,19 +382,26 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
 #pragma unroll
     for (int u = 0; u < YQ; ++u) {
       const int c = t + 256 * u;
-      const int p = c % PB, q = c / PB;
-      const uint16_t* hv = reinterpret_cast<const uint16_t*>(&yv[u]);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) ty[8 * q + e][p] = hv[e];
+      *reinterpret_cast<uint4*>(&ty[c % PB][8 * (c / PB)]) = yv[u];
     }
 #pragma unroll
     for (int u = 0; u < XQ; ++u) {
       const int c = t + 256 * u;
-      const int p = c % PB, q = c / PB;
-      const uint16_t* hv = reinterpret_cast<const uint16_t*>(&xv[u]);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) tx[8 * q + e][p] = hv[e];
+      *reinterpret_cast<uint4*>(&tx[c % PB][8 * (c / PB)]) = xv[u];
     }
+  };
+  typedef short v4s __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) v4s lds_v4s;
+  // 8 K values (pixels 8 g .. 8 g + 7 of a 32-pixel step) of channel col0 +
+  // r: two transposing reads, lane 4 k + q addressing pixel k (+ 4 in the
+  // second), channels col0 + 4 q .. + 3
+  auto frag = [&](const uint16_t* tile, int pitch, int p0, int col0) {
+    const uint16_t* base = tile + (p0 + 8 * g + (r >> 2)) * pitch + col0 + 4 * (r & 3);
+    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(base));
+    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(base + 4 * pitch));
+    typedef short v8s __attribute__((ext_vector_type(8)));
+    const v8s v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(v8bf, v);
   };
   if (mlo < mhi) load(mlo);
   for (int64_t mb = mlo; mb < mhi; mb += PB) {
@@ -402,21 +409,18 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
     __syncthreads();
     if (mb + PB < mhi) load(mb + PB);
     if (bias && t < NT)
-      for (int p = 0; p < PB; ++p) bsum += bf2f(ty[t][p]);
+      for (int p = 0; p < PB; ++p) bsum += bf2f(ty[p][t]);
 #pragma unroll
     for (int s = 0; s < PB / 32; ++s) {
-      uint4 av[2];
+      v8bf av[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        av[i] = *reinterpret_cast<const uint4*>(&ty[nb0 + 16 * i + r][32 * s + 8 * g]);
+      for (int i = 0; i < 2; ++i) av[i] = frag(&ty[0][0], NT + 8, 32 * s, nb0 + 16 * i);
 #pragma unroll
       for (int j = 0; j < NKB; ++j) {
-        const uint4 bv = *reinterpret_cast<const uint4*>(&tx[kb0 + 16 * j + r][32 * s + 8 * g]);
+        const v8bf bv = frag(&tx[0][0], KT + 8, 32 * s, kb0 + 16 * j);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av[i]),
-                                                              __builtin_bit_cast(v8bf, bv),
-                                                              acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv, acc[i][j], 0, 0, 0);
       }
     }
     __syncthreads();
