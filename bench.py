@@ -43,6 +43,7 @@ Printed as ONE JSON line:
   measured_peaks the device's sustained matrix-core and copy rates (microbenchmarks)
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -821,15 +822,23 @@ def streaming_bench(args, cpi, torch, np, dev):
     fa, fb = generate_binary_frames_gpu(ws, count=chunks * ws.chunk, device=dev)
     ca = fa.cpu().pin_memory()
     cb = fb.cpu().pin_memory()
+    # one device copy of every pinned chunk before timing: the first DMA over
+    # a pinned page pays a one-time mapping cost (measured: up to 17 ms of
+    # host stall in the first timed pass otherwise)
+    fa.copy_(ca)
+    fb.copy_(cb)
+    torch.cuda.synchronize()
     del fa, fb
     sgeo = cpi.geometry_default(ws.wa, ws.ha, ws.wb, ws.hb)
     sal = alphas_for(ws)
     sout = torch.empty(len(sal) * ws.pa, dtype=torch.float32, device=dev)
     sws = cpi.alloc_workspace(cpi.refocus_workspace_size(sgeo, len(sal)), dev)
 
+    su_, sr_ = torch.cuda.Stream(), torch.cuda.Stream()   # the same two for both runs
+
     def run(overlap):
-        su = torch.cuda.Stream()
-        sr = torch.cuda.Stream() if overlap else su
+        su = su_
+        sr = sr_ if overlap else su
         nbuf = 2 if overlap else 1
 
         def chunk(st, k):
@@ -840,25 +849,36 @@ def streaming_bench(args, cpi, torch, np, dev):
             else:
                 st.refocus(sgeo, sal, sout, workspace=sws)
 
-        # one warm-up chunk on a separate stream object (kernels loaded,
-        # tables cached)
+        # warm-up on a separate stream object: one untimed pass over all the
+        # chunks (kernels loaded, tables cached; the host copies of a
+        # process's first fraction of a second of streaming stalled the host
+        # for up to 20 ms at times)
         warm = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev,
                           stream=su, gamma_buffers=nbuf)
-        chunk(warm, 0)
+        for k in range(chunks):
+            chunk(warm, k)
         torch.cuda.synchronize()
         warm.close()
         st = cpi.Stream(ws.pa, ws.pb, cpi.FRAMES_BIT1, max_chunk=ws.chunk, device=dev,
                         stream=su, gamma_buffers=nbuf)
         ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(chunks)]
         ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(chunks)]
+        # (torch makes a HIP event at its first record: done here, outside the
+        # timed loop, where 400 fresh events stalled the first timed pass)
+        for e in ev0 + ev1:
+            e.record(su)
         torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for k in range(chunks):
-            ev0[k].record(su)
-            chunk(st, k)
-            ev1[k].record(sr)
-        torch.cuda.synchronize()
-        t_total = time.perf_counter() - t_start
+        gc.disable()   # no collector pauses between the enqueues
+        try:
+            t_start = time.perf_counter()
+            for k in range(chunks):
+                ev0[k].record(su)
+                chunk(st, k)
+                ev1[k].record(sr)
+            torch.cuda.synchronize()
+            t_total = time.perf_counter() - t_start
+        finally:
+            gc.enable()
         lat = [ev0[k].elapsed_time(ev1[k]) for k in range(chunks)]
         res = {
             "p50_ms": float(np.percentile(lat, 50)),
@@ -881,13 +901,15 @@ def streaming_bench(args, cpi, torch, np, dev):
         "frames": f"{chunks} distinct seeded chunks ({chunks * ws.chunk} frames, made on the "
                   f"device, pushed from pinned host memory)",
         "mode": "update and refocus of each chunk on one stream; the host copy of chunk k + 1 "
-                "runs on the handle's copy stream during the work on chunk k; latency = device "
+                "runs on the library's copy stream during the work on chunk k; latency = device "
                 "time from a chunk's copy to the end of its refocus",
         "n_alpha": len(sal),
     }
     res.update(one)
     two["mode"] = ("refocus of chunk k on a second stream while chunk k + 1 is folded (two FP32 "
-                   "Gamma buffers): the two streams' kernels share the CUs and slow each other")
+                   "Gamma buffers); the two streams' kernels share the CUs, and the gain depends "
+                   "on how the runtime places the streams on its hardware queues (1.1-1.33e6 "
+                   "frames/s measured over runs)")
     res["two_stream_refocus"] = two
     return res
 

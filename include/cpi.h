@@ -327,9 +327,10 @@ cpi_status cpi_refocus_resampled(const float* gamma, const cpi_geometry* g,
  *   fmt) into S_ab, S_a, S_b and refreshes the handle's FP32 Gamma.
  * cpi_stream_push_host: the same for host chunks (pinned memory gives an
  *   asynchronous copy; pageable memory is copied synchronously).  The copy
- *   runs on a stream of the handle's own, into one of two device staging
- *   buffers, so that it overlaps the work on the previous chunk; the handle's
- *   stream waits for it.
+ *   runs on a copy stream the library keeps per device (made at the first
+ *   handle), into one of two device staging buffers of the handle, so that it
+ *   overlaps the work on the previous chunk; the handle's stream waits for
+ *   it.
  * cpi_stream_frames: frames folded so far (host pointer).
  * cpi_stream_gamma: writes Gamma for all frames so far (each output nullable).
  * cpi_stream_gamma_f32_ptr: device address of the handle's FP32 view-major

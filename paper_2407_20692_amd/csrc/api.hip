@@ -982,10 +982,11 @@ struct cpi_stream_s {
   float* gamma32(int b) const {
     return reinterpret_cast<float*>(ws + (b == 0 ? plan.off_gamma32 : plan.off_gamma32b));
   }
-  // Host chunks are copied on a stream of the handle's own (made at the first
-  // host push) into one of two staging pairs, so that the copy of chunk k + 1
-  // overlaps the work on chunk k: copied[b] is recorded after the copy into
-  // pair b, staged_free[b] on st after the push that read it.
+  // Host chunks are copied on the device's copy stream (shared by the
+  // handles, see make_copy_stream) into one of two staging pairs, so that the
+  // copy of chunk k + 1 overlaps the work on chunk k: copied[b] is recorded
+  // after the copy into pair b, staged_free[b] on st after the push that
+  // read it.
   hipStream_t cst = nullptr;
   int stage_next = 0;
   hipEvent_t copied[2] = {nullptr, nullptr};
@@ -995,7 +996,6 @@ struct cpi_stream_s {
     for (hipEvent_t e : {written[0], written[1], read[0], read[1], copied[0], copied[1],
                          staged_free[0], staged_free[1]})
       if (e) (void)hipEventDestroy(e);
-    if (cst) (void)hipStreamDestroy(cst);
   }
 };
 
@@ -1089,11 +1089,10 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
   if (h->fmt == CPI_FRAMES_BIT1) {
     {
       ProfScope ps("ingest", st);
-      const cpi::IngestJob ja{fa, h->pa, cp.pa_pad, op_a, csum_a, nullptr, 0};
-      const cpi::IngestJob jb{fb, h->pb, cp.pb_pad, op_b, csum_b, nullptr, fp4 ? 1 : 0};
+      // the chunk's popcounts are added straight into the running sums
+      const cpi::IngestJob ja{fa, h->pa, cp.pa_pad, op_a, tot_a, nullptr, 0};
+      const cpi::IngestJob jb{fb, h->pb, cp.pb_pad, op_b, tot_b, nullptr, fp4 ? 1 : 0};
       CPI_HIP(cpi::ingest_bits(ja, jb, k, cp.kpad_bits, st), "ingest");
-      CPI_HIP(cpi::add_i64(tot_a, csum_a, cp.pa_pad, st), "sums");
-      CPI_HIP(cpi::add_i64(tot_b, csum_b, cp.pb_pad, st), "sums");
     }
     int b = 0;
     if (h->refresh_gamma32) {
@@ -1149,6 +1148,36 @@ cpi_status stream_push_device(cpi_stream_s* h, const uint8_t* fa, const uint8_t*
   return CPI_OK;
 }
 
+// The copy stream of the workspace's device: one per device for the
+// process, made at first use and kept (each handle orders its copies with
+// its own events).  Making a stream per handle would add hardware-queue
+// users: with the runtime's default of four queues, streams then share them,
+// and a refocus stream sharing a queue with the update stream loses its
+// overlap.
+std::mutex g_copy_mu;
+hipStream_t g_copy_stream[64] = {};
+
+hipError_t make_copy_stream(cpi_stream_s* h) {
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, h->ws);
+  if (e != hipSuccess) return e;
+  if (at.device < 0 || at.device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_copy_mu);
+  if (!g_copy_stream[at.device]) {
+    int cur_dev = 0;
+    e = hipGetDevice(&cur_dev);
+    if (e != hipSuccess) return e;
+    e = hipSetDevice(at.device);
+    if (e != hipSuccess) return e;
+    e = hipStreamCreateWithFlags(&g_copy_stream[at.device], hipStreamNonBlocking);
+    const hipError_t e2 = hipSetDevice(cur_dev);
+    if (e != hipSuccess) return e;
+    if (e2 != hipSuccess) return e2;
+  }
+  h->cst = g_copy_stream[at.device];
+  return hipSuccess;
+}
+
 cpi_status stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t max_chunk,
                          int gamma_buffers, void* workspace, size_t bytes, void* stream,
                          cpi_stream_t* out) {
@@ -1183,6 +1212,9 @@ cpi_status stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t m
   CPI_HIP(cpi::fill_u64(reinterpret_cast<uint64_t*>(h->ws + pl.off_sum_b), pl.chunk.pb_pad, 0,
                         h->st),
           "stream init");
+  // made now rather than at the first host push, which would pay for it
+  // (the internal handles of blocked correlation push device frames only)
+  if (gamma_buffers > 0) CPI_HIP(make_copy_stream(h.get()), "stream init");
   *out = h.release();
   return CPI_OK;
 }
@@ -1246,17 +1278,7 @@ cpi_status cpi_stream_push_host(cpi_stream_t s, const void* chunk_a, const void*
     if (!chunk_a || !chunk_b) return set_error(CPI_ERR_INVALID_ARG, "chunk pointers must not be null");
     if (k <= 0 || k > s->plan.max_chunk)
       return set_error(CPI_ERR_INVALID_ARG, "chunk size must be in [1, max_chunk]");
-    if (!s->cst) {
-      // the copy stream lives on the workspace's device
-      hipPointerAttribute_t at;
-      CPI_HIP(hipPointerGetAttributes(&at, s->ws), "copy stream");
-      int cur_dev = 0;
-      CPI_HIP(hipGetDevice(&cur_dev), "copy stream");
-      CPI_HIP(hipSetDevice(at.device), "copy stream");
-      hipError_t e = hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking);
-      (void)hipSetDevice(cur_dev);
-      CPI_HIP(e, "copy stream");
-    }
+    if (!s->cst) CPI_HIP(make_copy_stream(s), "copy stream");
     const int sb = s->stage_next;
     uint8_t* da = s->ws + (sb == 0 ? s->plan.off_stage_a : s->plan.off_stage_a2);
     uint8_t* db = s->ws + (sb == 0 ? s->plan.off_stage_b : s->plan.off_stage_b2);

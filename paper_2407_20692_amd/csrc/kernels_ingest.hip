@@ -211,8 +211,9 @@ __global__ __launch_bounds__(256, 2) void k_ingest_bits(IngestJob j0, IngestJob 
 
 // Packed-bit frames -> bit rows for row words [w0, kw) (frames 32 w0 ..):
 // one thread per (pixel word q, row word w) of either detector (w fastest),
-// which reads word q of frames 32 w .. 32 w + 31 (guarded byte loads: bits
-// of pixels at or past 8 * row bytes, and of frames at or past n, are zero)
+// which reads word q of frames 32 w .. 32 w + 31 (guarded word loads, or byte
+// loads when rows are not whole words: bits of pixels at or past 8 * row
+// bytes, and of frames at or past n, are zero)
 // and transposes the 32 x 32 block into row word w of pixels 32 q .. 32 q + 31.
 // Popcounts are combined per work-group in LDS, then added to sums.
 __global__ __launch_bounds__(256) void k_ingest_bits_tail(IngestJob j0, IngestJob j1, int64_t n,
@@ -233,18 +234,31 @@ __global__ __launch_bounds__(256) void k_ingest_bits_tail(IngestJob j0, IngestJo
   if (q < job.npix_pad / 32) {
     const int64_t fbytes = (job.npix + 7) / 8;
     uint32_t d[32];
+    if ((fbytes & 3) == 0) {
+      // whole-word rows: one 4-byte load per frame
+      const bool win = 4 * q + 4 <= fbytes;
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int64_t f = 32 * w + k;
-      const uint8_t* row = job.frames + (f < n ? f : 0) * fbytes;
-      uint32_t v = 0u;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int64_t by = 4 * q + b;
-        const bool ok = f < n && by < fbytes;
-        v |= (ok ? uint32_t(row[ok ? by : 0]) : 0u) << (8 * b);
+      for (int k = 0; k < 32; ++k) {
+        const int64_t f = 32 * w + k;
+        const bool ok = f < n && win;
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(
+            job.frames + (ok ? f * fbytes + 4 * q : 0));
+        d[k] = ok ? v : 0u;
       }
-      d[k] = v;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 32; ++k) {
+        const int64_t f = 32 * w + k;
+        const uint8_t* row = job.frames + (f < n ? f : 0) * fbytes;
+        uint32_t v = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t by = 4 * q + b;
+          const bool ok = f < n && by < fbytes;
+          v |= (ok ? uint32_t(row[ok ? by : 0]) : 0u) << (8 * b);
+        }
+        d[k] = v;
+      }
     }
     transpose32(d);
     uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(job.out) + 32 * q * kw + w;
