@@ -569,7 +569,14 @@ cpi_status cpi_image_quality(const float* pred, const float* target, int32_t bat
  *   kpad := kpad_t) it is the gradient with respect to the input.
  * cpi_nn_conv2d_wgrad: dw[co][tap][ci] += sum over pixels p of
  *   dy[p][co] * x[p + tap offset][ci] (FP32, accumulated into dw), and, if db
- *   is not null, db[co] += sum over pixels of dy[p][co].
+ *   is not null, db[co] += sum over pixels of dy[p][co].  The pixels are
+ *   split over work-groups.  With a workspace (device memory, 16-byte
+ *   aligned, at least cpi_nn_conv2d_wgrad_workspace_size bytes, owned by the
+ *   caller and free again when the stream has run the call) each split
+ *   stores its partial sums there and one more kernel adds them to dw and db
+ *   in split order, so the result is reproducible bit for bit; with a null
+ *   workspace the splits add with FP32 atomics (order not fixed).  A
+ *   workspace smaller than the size query gives CPI_ERR_WORKSPACE.
  * cpi_nn_bias_grad: db[c] += sum over pixels of dy[p][c].
  * cpi_nn_maxpool2 / _grad: 2x2 maximum (h, w even); the gradient goes to the
  *   first maximal position in the order (0,0), (0,1), (1,0), (1,1).
@@ -592,9 +599,12 @@ cpi_status cpi_nn_conv2d(const uint16_t* x, const uint16_t* w_packed, const floa
                          const uint16_t* mask, int32_t relu, int32_t b, int32_t h, int32_t w,
                          int32_t cin, int32_t cout, int32_t ks, int32_t kpad, uint16_t* out,
                          float* out_f32, void* stream);
+cpi_status cpi_nn_conv2d_wgrad_workspace_size(int32_t b, int32_t h, int32_t w, int32_t cin,
+                                              int32_t cout, int32_t ks, size_t* bytes);
 cpi_status cpi_nn_conv2d_wgrad(const uint16_t* x, const uint16_t* dy, int32_t b, int32_t h,
                                int32_t w, int32_t cin, int32_t cout, int32_t ks, float* dw,
-                               float* db, void* stream);
+                               float* db, void* workspace, size_t workspace_bytes,
+                               void* stream);
 cpi_status cpi_nn_bias_grad(const uint16_t* dy, int64_t pixels, int32_t c, float* db,
                             void* stream);
 cpi_status cpi_nn_maxpool2(const uint16_t* x, int32_t b, int32_t h, int32_t w, int32_t c,

@@ -181,8 +181,11 @@ _SIGS = {
     "cpi_nn_conv2d": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
                               c_int32, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                               c_void_p]),
+    "cpi_nn_conv2d_wgrad_workspace_size": (c_int, [c_int32, c_int32, c_int32, c_int32, c_int32,
+                                                   c_int32, POINTER(c_size_t)]),
     "cpi_nn_conv2d_wgrad": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
-                                    c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+                                    c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
+                                    c_void_p]),
     "cpi_nn_upsample2_concat": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
                                         c_int32, c_void_p, c_void_p]),
     "cpi_nn_upsample2_concat_grad": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32,

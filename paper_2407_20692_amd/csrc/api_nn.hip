@@ -15,6 +15,7 @@
 #include <cstdint>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <string>
 #include <utility>
 
@@ -105,17 +106,19 @@ struct Net {
   uint16_t* act[kNumLayers - 1];  // outputs of the ReLU layers
   uint16_t* pool[3];
   uint16_t* cat[3];
-  float* outf;
+  float* outf;       // the network's output channel [P0], FP32
+  float* opart;      // partial sums of the output layer's gradients
   float* xf;
   float* tn;
   float* stats;
   double* norm_scratch;
   float* loss_scratch;
-  uint16_t* g0;
-  uint16_t* g1;
+  uint16_t* g[3];  // gradient buffers, taken in turn by the backward pass
   uint16_t* skip[3];
   uint16_t* wpack;
   float* grads;
+  float* wpart;      // partial sums of the weight gradients' pixel splits
+  int64_t wpart_cap; // floats at wpart
   size_t bytes;
 };
 
@@ -139,18 +142,34 @@ Net plan_net(uint8_t* base, int B, int H, int W, bool train) {
     n.pool[l] = static_cast<uint16_t*>(take(size_t(P(l + 1)) * wid[l] * 2));
     n.cat[l] = static_cast<uint16_t*>(take(size_t(P(l)) * (wid[l + 1] + wid[l]) * 2));
   }
-  n.outf = static_cast<float*>(take(size_t(P0) * 32 * 4));
+  n.outf = static_cast<float*>(take(size_t(P0) * 4));
   n.xf = static_cast<float*>(take(size_t(P0) * 4));
   n.stats = static_cast<float*>(take(size_t(B) * 2 * 4));
   n.norm_scratch = static_cast<double*>(take(cpi::nn_normalize_scratch_bytes(B)));
   n.wpack = static_cast<uint16_t*>(take(size_t(pl.packed_total) * 2));
   if (train) {
     n.tn = static_cast<float*>(take(size_t(P0) * 4));
+    n.opart = static_cast<float*>(take(size_t(cpi::nn_out1_bwd_groups(P0)) * 36 * 4));
     n.loss_scratch = static_cast<float*>(take(64));
-    n.g0 = static_cast<uint16_t*>(take(size_t(P0) * 96 * 2));
-    n.g1 = static_cast<uint16_t*>(take(size_t(P0) * 96 * 2));
+    for (int k = 0; k < 3; ++k) n.g[k] = static_cast<uint16_t*>(take(size_t(P0) * 96 * 2));
     for (int l = 0; l < 3; ++l) n.skip[l] = static_cast<uint16_t*>(take(size_t(P(l)) * wid[l] * 2));
     n.grads = static_cast<float*>(take(size_t(pl.total) * 4));
+    int64_t cap = 0;
+    for (int i = 0; i < kNumLayers; ++i) {
+      const Layer& L = kLayers[i];
+      cpi::NnWgradArgs w;
+      w.B = B;
+      w.H = H >> L.level;
+      w.W = W >> L.level;
+      w.Cin = L.cin;
+      w.Cout = L.cout;
+      w.ks = L.ks;
+      w.Kpad = pl.kpad[i];
+      const int64_t f = cpi::nn_conv_wgrad_part_floats(w);
+      if (f > cap) cap = f;
+    }
+    n.wpart_cap = cap;
+    n.wpart = static_cast<float*>(take(size_t(cap) * 4));
   }
   n.bytes = off;
   return n;
@@ -164,6 +183,43 @@ cpi_status check_net_shape(int B, int H, int W) {
   return CPI_OK;
 }
 
+// ---- weight-gradient stream ------------------------------------------------------
+// The backward pass runs each layer's weight gradient on a second stream of
+// the device (one per device, made at first use, default priority), so that
+// it overlaps the chain of input gradients on the caller's stream.  Events
+// order the two: each host thread keeps its own events per device.
+constexpr int kSideEvents = 40;
+std::mutex g_side_mu;
+hipStream_t g_side_stream[64] = {};
+thread_local hipEvent_t t_side_ev[64][kSideEvents] = {};
+
+hipError_t side_resources(const void* ws, hipStream_t* side, hipEvent_t** ev) {
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, ws);
+  if (e != hipSuccess) return e;
+  const int dev = at.device;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (!g_side_stream[dev] || !t_side_ev[dev][kSideEvents - 1]) {
+    int cur = 0;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    e = hipSetDevice(dev);
+    if (e != hipSuccess) return e;
+    {
+      std::lock_guard<std::mutex> lk(g_side_mu);
+      if (!g_side_stream[dev]) e = hipStreamCreateWithFlags(&g_side_stream[dev], hipStreamNonBlocking);
+    }
+    for (int k = 0; k < kSideEvents && e == hipSuccess; ++k)
+      if (!t_side_ev[dev][k]) e = hipEventCreateWithFlags(&t_side_ev[dev][k], hipEventDisableTiming);
+    const hipError_t e2 = hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (e2 != hipSuccess) return e2;
+  }
+  *side = g_side_stream[dev];
+  *ev = t_side_ev[dev];
+  return hipSuccess;
+}
+
 // ---- network passes --------------------------------------------------------------
 struct Pass {
   const Params& pl;
@@ -171,6 +227,10 @@ struct Pass {
   const float* params;
   int B, H, W;
   hipStream_t s;
+  hipStream_t side = nullptr;  // weight-gradient stream, or null: all on s
+  hipEvent_t* ev = nullptr;    // kSideEvents events for ordering s and side
+  int* nev = nullptr;          // events used so far
+  float* loss = nullptr;       // the loss is added here by backward()
 
   int hl(int level) const { return H >> level; }
   int wl(int level) const { return W >> level; }
@@ -195,11 +255,21 @@ struct Pass {
     return cpi::nn_conv(a, s);
   }
 
-  // weight and bias gradients of layer i; input gradient into gin (masked by
-  // `mask` if given) unless gin is null
+  // weight and bias gradients of layer i (on the weight-gradient stream when
+  // there is one: it waits for the caller's stream up to here, and *done is
+  // recorded after it); input gradient into gin (masked by `mask` if given)
+  // unless gin is null, on the caller's stream
   hipError_t back(int i, const uint16_t* in, const uint16_t* g, uint16_t* gin,
-                  const uint16_t* mask) const {
+                  const uint16_t* mask, hipEvent_t* done = nullptr) const {
     const Layer& L = kLayers[i];
+    hipStream_t ws = s;
+    hipError_t e;
+    if (side) {
+      const hipEvent_t ready = ev[(*nev)++];
+      if ((e = hipEventRecord(ready, s)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(side, ready, 0)) != hipSuccess) return e;
+      ws = side;
+    }
     cpi::NnWgradArgs w;
     w.in = in;
     w.dy = g;
@@ -212,8 +282,14 @@ struct Pass {
     w.ks = L.ks;
     w.Kpad = pl.kpad[i];
     w.db = n.grads + pl.b_off[i];
-    hipError_t e = cpi::nn_conv_wgrad(w, s);
-    if (e != hipSuccess || !gin) return e;
+    w.part = n.wpart;
+    w.part_cap = n.wpart_cap;
+    if ((e = cpi::nn_conv_wgrad(w, ws)) != hipSuccess) return e;
+    if (side && done) {
+      *done = ev[(*nev)++];
+      if ((e = hipEventRecord(*done, side)) != hipSuccess) return e;
+    }
+    if (!gin) return hipSuccess;
     cpi::NnConvArgs a;
     a.in = g;
     a.wk = n.wpack + pl.wt_off[i];
@@ -276,39 +352,76 @@ struct Pass {
       NN_STEP(conv(da + 1, n.act[da], n.act[da + 1], nullptr, true));
       h = n.act[da + 1];
     }
-    NN_STEP(conv(OUT, h, nullptr, n.outf, false));
+    NN_STEP(cpi::nn_out1_fwd(h, n.wpack + pl.wf_off[OUT], params + pl.b_off[OUT], P(0), n.outf, s));
     return hipSuccess;
   }
 
-  // gradients of the loss whose output gradient (channel 0 of a 32-channel
-  // tensor) is in g0
+  // the loss of the output in n.outf against the targets in n.tn (added to
+  // *loss) and its gradients.  Each step writes its result into the next of
+  // the three gradient buffers; a buffer is taken again three steps later,
+  // after the caller's stream has waited for the weight gradient that read it.
   hipError_t backward() const {
     hipError_t e;
     const int wid[4] = {32, 64, 128, 256};
-    uint16_t* g0 = n.g0;
-    uint16_t* g1 = n.g1;
-    NN_STEP(back(OUT, n.act[DEC1B], g0, g1, n.act[DEC1B]));
-    // decoder, level 0 up to 2: g1 holds the gradient of the level's second
+    hipEvent_t busy[3] = {nullptr, nullptr, nullptr};
+    int cur = 0, nxt = 0;
+    auto take = [&](int* b) -> hipError_t {
+      *b = nxt;
+      nxt = (nxt + 1) % 3;
+      if (busy[*b]) {
+        const hipError_t r = hipStreamWaitEvent(s, busy[*b], 0);
+        busy[*b] = nullptr;
+        return r;
+      }
+      return hipSuccess;
+    };
+    // layer i's gradients from the gradient in buffer cur; its input
+    // gradient (unless last) into a new buffer, which becomes cur
+    auto layer = [&](int i, const uint16_t* in, const uint16_t* mask, bool input_grad) {
+      int b = -1;
+      hipError_t r = input_grad ? take(&b) : hipSuccess;
+      if (r != hipSuccess) return r;
+      r = back(i, in, n.g[cur], input_grad ? n.g[b] : nullptr, mask, &busy[cur]);
+      if (input_grad) cur = b;
+      return r;
+    };
+    {
+      int b;
+      NN_STEP(take(&b));
+      NN_STEP(cpi::nn_out1_bwd(n.outf, n.xf, n.tn, P(0), n.act[DEC1B], n.wpack + pl.wf_off[OUT],
+                               n.g[b], loss, n.opart, n.grads + pl.w_off[OUT],
+                               n.grads + pl.b_off[OUT], s));
+      cur = b;
+    }
+    // decoder, level 0 up to 2: cur holds the gradient of the level's second
     // convolution's pre-activation
     const uint16_t* below[3] = {n.act[DEC2B], n.act[DEC3B], n.act[MIDB]};
     for (int l = 0; l < 3; ++l) {
       const int da = DEC1A - 2 * l;
-      NN_STEP(back(da + 1, n.act[da], g1, g0, n.act[da]));
-      NN_STEP(back(da, n.cat[l], g0, g1, nullptr));
-      NN_STEP(cpi::nn_upcat_grad(g1, B, hl(l + 1), wl(l + 1), wid[l + 1], wid[l], below[l], g0,
-                                 n.skip[l], s));
-      std::swap(g0, g1);
+      NN_STEP(layer(da + 1, n.act[da], n.act[da], true));
+      NN_STEP(layer(da, n.cat[l], nullptr, true));
+      int b;
+      NN_STEP(take(&b));
+      NN_STEP(cpi::nn_upcat_grad(n.g[cur], B, hl(l + 1), wl(l + 1), wid[l + 1], wid[l], below[l],
+                                 n.g[b], n.skip[l], s));
+      cur = b;
     }
-    NN_STEP(back(MIDB, n.act[MIDA], g1, g0, n.act[MIDA]));
-    NN_STEP(back(MIDA, n.pool[2], g0, g1, nullptr));
-    // encoder, level 2 down to 0: g1 holds the gradient of the pooled output
+    NN_STEP(layer(MIDB, n.act[MIDA], n.act[MIDA], true));
+    NN_STEP(layer(MIDA, n.pool[2], nullptr, true));
+    // encoder, level 2 down to 0: cur holds the gradient of the pooled output
     for (int l = 2; l >= 0; --l) {
       uint16_t* yb = n.act[2 * l + 1];
-      NN_STEP(cpi::nn_maxpool_bwd(yb, B, hl(l), wl(l), wid[l], g1, g0, s));
-      NN_STEP(cpi::nn_add_mask(g0, n.skip[l], yb, P(l) * wid[l], s));
-      NN_STEP(back(2 * l + 1, n.act[2 * l], g0, g1, n.act[2 * l]));
-      NN_STEP(back(2 * l, l == 0 ? n.x8 : n.pool[l - 1], g1, l == 0 ? nullptr : g0, nullptr));
-      std::swap(g0, g1);
+      int b;
+      NN_STEP(take(&b));
+      NN_STEP(cpi::nn_pool_bwd_add(yb, B, hl(l), wl(l), wid[l], n.g[cur], n.skip[l], n.g[b], s));
+      cur = b;
+      NN_STEP(layer(2 * l + 1, n.act[2 * l], n.act[2 * l], true));
+      NN_STEP(layer(2 * l, l == 0 ? n.x8 : n.pool[l - 1], nullptr, l != 0));
+    }
+    if (side) {
+      const hipEvent_t joined = ev[(*nev)++];
+      NN_STEP(hipEventRecord(joined, side));
+      NN_STEP(hipStreamWaitEvent(s, joined, 0));
     }
     return hipSuccess;
 #undef NN_STEP
@@ -381,7 +494,7 @@ cpi_status cpi_denoiser_forward(const float* params, int32_t batch, int32_t h, i
            "denoiser normalise");
     NN_HIP(ps.pack(false), "denoiser weights");
     NN_HIP(ps.forward(), "denoiser forward");
-    NN_HIP(cpi::nn_denormalize(n.outf, 32, n.xf, n.stats, hw, batch, out, s), "denoiser output");
+    NN_HIP(cpi::nn_denormalize(n.outf, 1, n.xf, n.stats, hw, batch, out, s), "denoiser output");
     return CPI_OK;
   });
 }
@@ -406,7 +519,11 @@ cpi_status cpi_denoiser_train_step(float* params, float* adam_m, float* adam_v, 
                                                  std::to_string(n.bytes) + " bytes");
     const Params pl = param_layout();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Pass ps{pl, n, params, batch, h, w, s};
+    hipStream_t side = nullptr;
+    hipEvent_t* ev = nullptr;
+    int nev = 0;
+    NN_HIP(side_resources(workspace, &side, &ev), "denoiser weight-gradient stream");
+    const Pass ps{pl, n, params, batch, h, w, s, side, ev, &nev, loss};
     const int64_t hw = int64_t(h) * w, P0 = int64_t(batch) * hw;
     NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, targets, n.tn, n.stats,
                              n.norm_scratch, s),
@@ -415,7 +532,6 @@ cpi_status cpi_denoiser_train_step(float* params, float* adam_m, float* adam_v, 
     NN_HIP(ps.forward(), "denoiser forward");
     NN_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(n.grads), pl.total, 0u, s), "denoiser grads");
     NN_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(loss), 1, 0u, s), "denoiser loss");
-    NN_HIP(cpi::nn_mse(n.outf, 32, n.xf, n.tn, P0, loss, n.g0, s), "denoiser loss");
     NN_HIP(ps.backward(), "denoiser backward");
     const double b1 = 0.9, b2 = 0.999;
     const float c1 = float(1.0 - std::pow(b1, double(step)));
@@ -445,7 +561,11 @@ cpi_status cpi_denoiser_gradients(const float* params, int32_t batch, int32_t h,
     n.grads = grads;
     const Params pl = param_layout();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Pass ps{pl, n, params, batch, h, w, s};
+    hipStream_t side = nullptr;
+    hipEvent_t* ev = nullptr;
+    int nev = 0;
+    NN_HIP(side_resources(workspace, &side, &ev), "denoiser weight-gradient stream");
+    const Pass ps{pl, n, params, batch, h, w, s, side, ev, &nev, loss};
     const int64_t hw = int64_t(h) * w, P0 = int64_t(batch) * hw;
     NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, targets, n.tn, n.stats,
                              n.norm_scratch, s),
@@ -454,7 +574,6 @@ cpi_status cpi_denoiser_gradients(const float* params, int32_t batch, int32_t h,
     NN_HIP(ps.forward(), "denoiser forward");
     NN_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(grads), pl.total, 0u, s), "denoiser grads");
     NN_HIP(cpi::fill_u32(reinterpret_cast<uint32_t*>(loss), 1, 0u, s), "denoiser loss");
-    NN_HIP(cpi::nn_mse(n.outf, 32, n.xf, n.tn, P0, loss, n.g0, s), "denoiser loss");
     NN_HIP(ps.backward(), "denoiser backward");
     return CPI_OK;
   });
@@ -514,26 +633,55 @@ cpi_status cpi_nn_conv2d(const uint16_t* x, const uint16_t* w_packed, const floa
   });
 }
 
+namespace {
+cpi::NnWgradArgs wgrad_args(int32_t b, int32_t h, int32_t w, int32_t cin, int32_t cout,
+                            int32_t ks) {
+  cpi::NnWgradArgs a;
+  a.B = b;
+  a.H = h;
+  a.W = w;
+  a.Cin = cin;
+  a.Cout = cout;
+  a.ks = ks;
+  a.Kpad = int(round_up(int64_t(ks) * ks * cin, 32));
+  return a;
+}
+}  // namespace
+
+cpi_status cpi_nn_conv2d_wgrad_workspace_size(int32_t b, int32_t h, int32_t w, int32_t cin,
+                                              int32_t cout, int32_t ks, size_t* bytes) {
+  return guarded([&]() -> cpi_status {
+    if (!bytes) return bad("bytes is null");
+    cpi_status st = check_conv(b, h, w, cin, cout, ks);
+    if (st != CPI_OK) return st;
+    *bytes = size_t(cpi::nn_conv_wgrad_part_floats(wgrad_args(b, h, w, cin, cout, ks))) * 4;
+    return CPI_OK;
+  });
+}
+
 cpi_status cpi_nn_conv2d_wgrad(const uint16_t* x, const uint16_t* dy, int32_t b, int32_t h,
                                int32_t w, int32_t cin, int32_t cout, int32_t ks, float* dw,
-                               float* db, void* stream) {
+                               float* db, void* workspace, size_t workspace_bytes,
+                               void* stream) {
   return guarded([&]() -> cpi_status {
     cpi_status st = check_conv(b, h, w, cin, cout, ks);
     if (st != CPI_OK) return st;
     if (!x || !dy || !dw) return bad("null device pointer");
     if (!al16(x) || !al16(dy)) return bad("x and dy must be 16-byte aligned");
-    cpi::NnWgradArgs a;
+    cpi::NnWgradArgs a = wgrad_args(b, h, w, cin, cout, ks);
+    if (workspace) {
+      const int64_t need = cpi::nn_conv_wgrad_part_floats(a);
+      if (workspace_bytes < size_t(need) * 4)
+        return report_error(CPI_ERR_WORKSPACE, "conv2d wgrad workspace too small: need " +
+                                                   std::to_string(need * 4) + " bytes");
+      if (!al16(workspace)) return bad("workspace must be 16-byte aligned");
+      a.part = static_cast<float*>(workspace);
+      a.part_cap = need;
+    }
     a.in = x;
     a.dy = dy;
     a.dw = dw;
     a.db = db;
-    a.B = b;
-    a.H = h;
-    a.W = w;
-    a.Cin = cin;
-    a.Cout = cout;
-    a.ks = ks;
-    a.Kpad = int(round_up(int64_t(ks) * ks * cin, 32));
     NN_HIP(cpi::nn_conv_wgrad(a, static_cast<hipStream_t>(stream)), "conv2d wgrad");
     return CPI_OK;
   });

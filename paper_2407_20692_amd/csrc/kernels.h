@@ -229,11 +229,19 @@ hipError_t nn_conv(const NnConvArgs& a, hipStream_t s);
 struct NnWgradArgs {
   const uint16_t* in = nullptr;    // [B][H][W][Cin] layer input
   const uint16_t* dy = nullptr;    // [B][H][W][Cout] output gradient
-  float* dw = nullptr;             // [Cout][ks*ks*Cin], accumulated into (FP32 atomics)
+  float* dw = nullptr;             // [Cout][ks*ks*Cin], accumulated into
   float* db = nullptr;             // [Cout] bias gradient accumulated into, or null
+  // Partial sums of the pixel splits ([split][Cout*ks*ks*Cin + Cout] floats),
+  // or null: with it the splits store their tiles and one more kernel adds
+  // them to dw and db in split order (deterministic); without it they add
+  // with FP32 atomics.
+  float* part = nullptr;
+  int64_t part_cap = 0;            // floats available at part
   int B = 0, H = 0, W = 0, Cin = 0, Cout = 0, ks = 0, Kpad = 0;
 };
 hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s);
+// floats of partial sums nn_conv_wgrad uses for this shape (the part buffer)
+int64_t nn_conv_wgrad_part_floats(const NnWgradArgs& a);
 // db[n] += sum over the M pixels of dy[m][n]
 hipError_t nn_bias_grad(const uint16_t* dy, int64_t M, int C, float* db, hipStream_t s);
 // FP32 weights [Cout][ks*ks][Cin] -> bfloat16 [Cout][kpad] and, if wt is not
@@ -261,6 +269,20 @@ hipError_t nn_upcat(const uint16_t* low, const uint16_t* skip, int B, int H, int
                     uint16_t* out, hipStream_t s);
 hipError_t nn_upcat_grad(const uint16_t* d, int B, int H, int W, int C1, int C2,
                          const uint16_t* mask, uint16_t* dlow, uint16_t* dskip, hipStream_t s);
+// din = (dout routed to each 2x2 window's first maximal position) + skip,
+// zeroed where in <= 0; C % 8 == 0
+hipError_t nn_pool_bwd_add(const uint16_t* in, int B, int H, int W, int C, const uint16_t* dout,
+                           const uint16_t* skip, uint16_t* din, hipStream_t s);
+// the output layer (1x1 to one channel of 32): y[p] = bias[0] + sum_c w[c] h[p][c]
+hipError_t nn_out1_fwd(const uint16_t* h, const uint16_t* w, const float* bias, int64_t P, float* y,
+                       hipStream_t s);
+// work-groups (rows of 36 partial-sum floats) nn_out1_bwd uses for P pixels
+int nn_out1_bwd_groups(int64_t P);
+// loss (added to *loss), output-layer input gradient gin [P][32] and its
+// weight (dw[0 .. 31]) and bias (db[0]) gradients added in, via part
+hipError_t nn_out1_bwd(const float* y, const float* res, const float* t, int64_t P,
+                       const uint16_t* h, const uint16_t* w, uint16_t* gin, float* loss,
+                       float* part, float* dw, float* db, hipStream_t s);
 hipError_t nn_add_mask(uint16_t* x, const uint16_t* add, const uint16_t* mask, int64_t n,
                        hipStream_t s);
 hipError_t nn_mse(const float* y, int C, const float* res, const float* t, int64_t P, float* loss,

@@ -312,9 +312,10 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
 // 4 k + q addresses pixel k, channels 4 q .. 4 q + 3, lane j gets channel j at
 // four consecutive pixels).  NT = 64: wave w owns channels 32 (w & 1) +
 // [0, 32) and K values (KT / 2) (w >> 1) + [0, KT / 2); NT = 32: all 32
-// channels and K values (KT / 4) w + [0, KT / 4).  The work-group's partial
-// tile is added to dW with FP32 atomics.  Work-groups of the first K tile also
-// sum their dY block over pixels into db (if given).
+// channels and K values (KT / 4) w + [0, KT / 4).  The work-group's tile goes
+// to its pixel split's slot of the partial buffer (added to dW with FP32
+// atomics when there is none).  Work-groups of the first K tile also sum
+// their dY block over pixels into db (if given).
 template <int KS, int NT, int KT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
   constexpr int HALF = KS / 2;
@@ -426,6 +427,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
     __syncthreads();
   }
   // element (n = nb0 + 16 i + 4g + e, k = kb0 + 16 j + r)
+  float* pz = a.part ? a.part + int64_t(blockIdx.z) * (int64_t(a.Cout) * K + a.Cout) : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -434,9 +436,293 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(NnWgradArgs a) {
       for (int e = 0; e < 4; ++e) {
         const int n = n0 + nb0 + 16 * i + 4 * g + e;
         const int k = kc + kb0 + 16 * j + r;
-        if (n < a.Cout && k < K) atomicAdd(&a.dw[int64_t(n) * K + k], acc[i][j][e]);
+        if (n < a.Cout && k < K) {
+          if (pz)
+            __builtin_nontemporal_store(acc[i][j][e], &pz[int64_t(n) * K + k]);
+          else
+            atomicAdd(&a.dw[int64_t(n) * K + k], acc[i][j][e]);
+        }
       }
-  if (bias && t < NT && n0 + t < a.Cout) atomicAdd(&a.db[n0 + t], bsum);
+  if (bias && t < NT && n0 + t < a.Cout) {
+    if (pz)
+      __builtin_nontemporal_store(bsum, &pz[int64_t(a.Cout) * K + n0 + t]);
+    else
+      atomicAdd(&a.db[n0 + t], bsum);
+  }
+}
+
+// ---- 3x3 convolution, backward-weight, all taps per work-group --------------
+// dW[n][tap * Cin + ci] = sum over pixels (y, x) of dY[y][x][n] *
+// X[y + ky - 1][x + kx - 1][ci], tap = 3 ky + kx.  A work-group owns NT
+// output channels x one slice of 32 input channels x all nine taps, and walks
+// a range of pixel blocks of R rows x TW columns.  Per block, the dY block
+// ([pixel][channel]) and its input halo ((R + 2) x (TW + 2) pixels of the 32
+// channels, zero outside the image) are staged in LDS once, and all nine taps
+// read the one halo at shifted offsets, so each input pixel is fetched about
+// once per slice instead of once per tap.  The matrix-core K index is the
+// pixel: both operands come from the transposing LDS reads
+// (ds_read_b64_tr_b16; lane 4 k + q addresses pixel p + k, channels
+// c + 4 q .. + 3, and lane j receives channel c + j at pixels p .. p + 3).
+// K slots 8 g .. 8 g + 7 of a 32-pixel step hold pixels 4 g .. 4 g + 3 and
+// 16 + 4 g .. + 3, so the eight pixels that half a wave reads in one go are
+// consecutive; with row pitches of an odd multiple of 32 bytes they cover all
+// 64 LDS banks once.  Wave w takes input channels 16 (w & 1) + [0, 16); for
+// NT = 64 it takes output channels 32 (w >> 1) + [0, 32) and every step, for
+// NT = 32 all 32 channels and the steps of parity w >> 1.  A wave's 18 tiles
+// (2 channel tiles x 9 taps) go to the pixel split's slot of the partial
+// buffer (added to dW with FP32 atomics when there is none); the bias
+// gradient is summed from the dY operands of the waves on input channels
+// 0 .. 15 of the first slice.
+template <int NT, int TW, int R>
+__global__ __launch_bounds__(256) void k_conv3_wgrad(NnWgradArgs a) {
+  constexpr int PXB = TW * R;             // pixels per block
+  constexpr int STEPS = PXB / 32;         // 32-pixel matrix-core steps per block
+  constexpr int PY = NT + 16;             // dY row pitch (elements): 96 or 160 bytes
+  constexpr int PX = 48;                  // halo row pitch (elements): 96 bytes
+  constexpr int HW = TW + 2, HP = (R + 2) * HW;
+  static_assert(PXB % 64 == 0 && TW % 16 == 0, "block shape");
+  static_assert(NT == 32 || NT == 64, "channel tile");
+  // the dY block, then the halo; reused at the end (NT = 32) to combine the
+  // two step parities: [9][32][RP] floats of dW, then 32 floats of db
+  constexpr int TY = PXB * PY, TX = HP * PX, RP = 36;
+  static_assert(NT == 64 || (9 * 32 * RP + 32) * 4 <= (TY + TX) * 2, "reduction space");
+  __shared__ __attribute__((aligned(16))) uint16_t lds[TY + TX];
+  uint16_t* const ty = lds;
+  uint16_t* const tx = lds + TY;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int ct = wave & 1;
+  const int nt0 = NT == 64 ? 2 * (wave >> 1) : 0;
+  const int par = NT == 64 ? 0 : wave >> 1;
+  const int n0 = blockIdx.x * NT, c0 = blockIdx.y * 32;
+  const int Cin = a.Cin, K = 9 * Cin;
+  const int bx = (a.W + TW - 1) / TW, by = (a.H + R - 1) / R;
+  const int64_t nb = int64_t(a.B) * bx * by;
+  const int64_t per = (nb + gridDim.z - 1) / gridDim.z;
+  const int64_t blo = int64_t(blockIdx.z) * per;
+  const int64_t bhi = blo + per < nb ? blo + per : nb;
+  const bool bias = a.db && blockIdx.y == 0 && ct == 0;
+
+  v4f acc[9][2];
+#pragma unroll
+  for (int u = 0; u < 9; ++u) acc[u][0] = acc[u][1] = v4f{0, 0, 0, 0};
+  float bsum[2] = {0.0f, 0.0f};
+
+  // staging: dY piece c = (pixel c / (NT / 8), channels 8 (c % (NT / 8)));
+  // halo piece c = (halo pixel c / 4, channels 8 (c % 4))
+  constexpr int YQ = PXB * NT / 8 / 256;
+  constexpr int XQ = (HP * 4 + 255) / 256;
+  static_assert(YQ * 256 == PXB * NT / 8, "dY pieces");
+  uint4 yv[YQ], xv[XQ];
+  auto load = [&](int64_t blk) {
+    const int ix = int(blk % bx);
+    const int64_t rest = blk / bx;
+    const int iy = int(rest % by);
+    const int64_t b = rest / by;
+    const int x0 = ix * TW, y0 = iy * R;
+#pragma unroll
+    for (int u = 0; u < YQ; ++u) {
+      const int c = t + 256 * u;
+      const int px = c / (NT / 8), part = c % (NT / 8);
+      const int y = y0 + px / TW, x = x0 + px % TW;
+      yv[u] = make_uint4(0, 0, 0, 0);
+      if (y < a.H && x < a.W)
+        yv[u] = *reinterpret_cast<const uint4*>(a.dy + ((b * a.H + y) * a.W + x) * a.Cout + n0 +
+                                                8 * part);
+    }
+#pragma unroll
+    for (int u = 0; u < XQ; ++u) {
+      const int c = t + 256 * u;
+      const int hp = c >> 2, part = c & 3;
+      const int y = y0 + hp / HW - 1, x = x0 + hp % HW - 1;
+      xv[u] = make_uint4(0, 0, 0, 0);
+      if (c < HP * 4 && y >= 0 && y < a.H && x >= 0 && x < a.W)
+        xv[u] = *reinterpret_cast<const uint4*>(a.in + ((b * a.H + y) * a.W + x) * Cin + c0 +
+                                                8 * part);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < YQ; ++u) {
+      const int c = t + 256 * u;
+      *reinterpret_cast<uint4*>(&ty[(c / (NT / 8)) * PY + 8 * (c % (NT / 8))]) = yv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < XQ; ++u) {
+      const int c = t + 256 * u;
+      if (c < HP * 4) *reinterpret_cast<uint4*>(&tx[(c >> 2) * PX + 8 * (c & 3)]) = xv[u];
+    }
+  };
+  typedef short v4s __attribute__((ext_vector_type(4)));
+  typedef short v8s __attribute__((ext_vector_type(8)));
+  typedef __attribute__((address_space(3))) v4s lds_v4s;
+  // lane parts of the addresses: pixel 4 g + (r >> 2), channels 4 (r & 3)
+  const uint16_t* ybase = ty + (4 * g + (r >> 2)) * PY + 16 * nt0 + 4 * (r & 3);
+  const uint16_t* xbase = tx + (4 * g + (r >> 2)) * PX + 16 * ct + 4 * (r & 3);
+  auto pair = [](const uint16_t* lo, const uint16_t* hi) {
+    const v4s u = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)lo);
+    const v4s v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)hi);
+    const v8s w = {u[0], u[1], u[2], u[3], v[0], v[1], v[2], v[3]};
+    return __builtin_bit_cast(v8bf, w);
+  };
+
+  if (blo < bhi) load(blo);
+#pragma unroll 1
+  for (int64_t blk = blo; blk < bhi; ++blk) {
+    store();
+    __syncthreads();
+    if (blk + 1 < bhi) load(blk + 1);
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+      if (NT == 32 && (s & 1) != par) continue;
+      // block pixel 32 s + 16 h + lane part: row (32 s + 16 h) / TW, column
+      // (32 s + 16 h) % TW + lane part (a 16-pixel run never crosses a row)
+      const int p0 = 32 * s, p1 = 32 * s + 16;
+      v8bf av[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = pair(ybase + p0 * PY + 16 * i, ybase + p1 * PY + 16 * i);
+        if (bias) {
+          const v8s e = __builtin_bit_cast(v8s, av[i]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) bsum[i] += bf2f(uint16_t(e[j]));
+        }
+      }
+      const int h0 = (p0 / TW) * HW + p0 % TW, h1 = (p1 / TW) * HW + p1 % TW;
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+          const int o = ky * HW + kx;
+          const v8bf bv = pair(xbase + (h0 + o) * PX, xbase + (h1 + o) * PX);
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            acc[3 * ky + kx][i] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv, acc[3 * ky + kx][i], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  // element (n = n0 + 16 (nt0 + i) + 4 g + e, ci = c0 + 16 ct + r) of tap u
+  float* pz = a.part ? a.part + int64_t(blockIdx.z) * (int64_t(a.Cout) * K + a.Cout) : nullptr;
+  float bv[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    bv[i] = bsum[i];
+    bv[i] += __shfl_xor(bv[i], 16);
+    bv[i] += __shfl_xor(bv[i], 32);
+  }
+  if (NT == 64) {
+#pragma unroll
+    for (int u = 0; u < 9; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int n = n0 + 16 * (nt0 + i) + 4 * g + e;
+          const int64_t o = int64_t(n) * K + u * Cin + c0 + 16 * ct + r;
+          if (pz)
+            __builtin_nontemporal_store(acc[u][i][e], &pz[o]);
+          else
+            atomicAdd(&a.dw[o], acc[u][i][e]);
+        }
+  } else {
+    // the waves of parity 1 add their tiles to those of parity 0 in LDS (the
+    // loop's last barrier has freed it), then the work-group stores the
+    // 32 x 9 x 32 tile with coalesced writes
+    float* red = reinterpret_cast<float*>(lds);
+    float* rb = red + 9 * 32 * RP;
+    if (par == 0) {
+#pragma unroll
+      for (int u = 0; u < 9; ++u)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            red[(u * 32 + 16 * i + 4 * g + e) * RP + 16 * ct + r] = acc[u][i][e];
+      if (bias && g == 0) rb[r] = bv[0], rb[16 + r] = bv[1];
+    }
+    __syncthreads();
+    if (par == 1) {
+#pragma unroll
+      for (int u = 0; u < 9; ++u)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            red[(u * 32 + 16 * i + 4 * g + e) * RP + 16 * ct + r] += acc[u][i][e];
+      if (bias && g == 0) rb[r] += bv[0], rb[16 + r] += bv[1];
+    }
+    __syncthreads();
+    for (int q = t; q < 9 * 32 * 32; q += 256) {
+      const int u = q >> 10, n = (q >> 5) & 31, ci = q & 31;
+      const float v = red[(u * 32 + n) * RP + ci];
+      const int64_t o = int64_t(n0 + n) * K + u * Cin + c0 + ci;
+      if (pz)
+        __builtin_nontemporal_store(v, &pz[o]);
+      else
+        atomicAdd(&a.dw[o], v);
+    }
+    if (bias && par == 0 && g == 0) bv[0] = rb[r], bv[1] = rb[16 + r];
+  }
+  if (bias && par == 0 && g == 0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int n = n0 + 16 * (nt0 + i) + r;
+      if (pz)
+        __builtin_nontemporal_store(bv[i], &pz[int64_t(a.Cout) * K + n]);
+      else
+        atomicAdd(&a.db[n], bv[i]);
+    }
+  }
+}
+
+// dw[i] += sum over splits z of part[z][i] (i < nw), db[i - nw] += the same
+// for the bias slots (db non-null).  Rows are nw + cout floats, a multiple
+// of 4, and part is 16-byte aligned.  A work-group takes 64 consecutive
+// elements as 16 float4 columns; thread (slot, l) sums splits slot,
+// slot + 16, ... of column l in that order, and thread e < 64 then adds the
+// 16 slot sums of element e in slot order: a fixed order, whatever the
+// scheduling.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int splits,
+                                                      int64_t nw, int cout,
+                                                      float* __restrict__ dw,
+                                                      float* __restrict__ db) {
+  __shared__ v4f red[256];
+  const int t = threadIdx.x, l = t & 15, slot = t >> 4;
+  const int64_t stride = nw + cout, n = db ? stride : nw, st4 = stride / 4;
+  for (int64_t i0 = int64_t(blockIdx.x) * 64; i0 < n; i0 += int64_t(gridDim.x) * 64) {
+    const int64_t i = i0 + 4 * l;
+    v4f s = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (i < n) {
+      const v4f* q = reinterpret_cast<const v4f*>(part + i);
+      int z = slot;
+      for (; z + 48 < splits; z += 64) {
+        const v4f v0 = __builtin_nontemporal_load(q + z * st4);
+        const v4f v1 = __builtin_nontemporal_load(q + (z + 16) * st4);
+        const v4f v2 = __builtin_nontemporal_load(q + (z + 32) * st4);
+        const v4f v3 = __builtin_nontemporal_load(q + (z + 48) * st4);
+        s += v0;
+        s += v1;
+        s += v2;
+        s += v3;
+      }
+      for (; z < splits; z += 16) s += __builtin_nontemporal_load(q + z * st4);
+    }
+    red[t] = s;
+    __syncthreads();
+    if (t < 64 && i0 + t < n) {
+      const float* rf = reinterpret_cast<const float*>(red);
+      float tot = 0.0f;
+      for (int k = 0; k < 16; ++k) tot += rf[4 * (16 * k + (t >> 2)) + (t & 3)];
+      if (i0 + t < nw)
+        dw[i0 + t] += tot;
+      else
+        db[i0 + t - nw] += tot;
+    }
+    __syncthreads();
+  }
 }
 
 // db[n] += sum over pixels of dY[m][n]
@@ -702,6 +988,140 @@ __global__ __launch_bounds__(256) void k_add_mask(uint16_t* __restrict__ x,
 // Mean squared error of the prediction z = y[p][0] + res[p] (y with C
 // channels per pixel, res nullable) against t over P pixels:
 // loss += sum (z - t)^2 / P; dy = 2 (z - t) / P in channel 0, 0 elsewhere.
+// Max-pooling backward fused with the skip addition and the ReLU mask:
+// din[q] = (dout of q's window if q is the window's first maximal position,
+// else 0) + skip[q], zeroed where in[q] <= 0 (bfloat16 out).  A thread takes
+// one pooled pixel and 8 channels (16-byte loads and stores).
+__global__ __launch_bounds__(256) void k_pool_bwd_add(const uint16_t* __restrict__ in, int B,
+                                                      int H, int W, int C,
+                                                      const uint16_t* __restrict__ dout,
+                                                      const uint16_t* __restrict__ skip,
+                                                      uint16_t* __restrict__ din) {
+  const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+  const int64_t n = int64_t(B) * Ho * Wo * C8;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int c8 = int(i % C8);
+    const int64_t p = i / C8;
+    const int x = int(p % Wo), y = int((p / Wo) % Ho), b = int(p / (int64_t(Wo) * Ho));
+    const int64_t base = ((int64_t(b) * H + 2 * y) * W + 2 * x) * C + 8 * c8;
+    const int64_t off[4] = {0, C, int64_t(W) * C, int64_t(W) * C + C};
+    uint4 v[4], sk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = *reinterpret_cast<const uint4*>(in + base + off[q]);
+      sk[q] = *reinterpret_cast<const uint4*>(skip + base + off[q]);
+    }
+    const uint4 dv = *reinterpret_cast<const uint4*>(dout + p * C + 8 * c8);
+    const uint16_t* vh[4] = {reinterpret_cast<const uint16_t*>(&v[0]),
+                             reinterpret_cast<const uint16_t*>(&v[1]),
+                             reinterpret_cast<const uint16_t*>(&v[2]),
+                             reinterpret_cast<const uint16_t*>(&v[3])};
+    const uint16_t* dh = reinterpret_cast<const uint16_t*>(&dv);
+    uint4 o[4];
+    uint16_t* oh[4] = {reinterpret_cast<uint16_t*>(&o[0]), reinterpret_cast<uint16_t*>(&o[1]),
+                       reinterpret_cast<uint16_t*>(&o[2]), reinterpret_cast<uint16_t*>(&o[3])};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int best = 0;
+      float m = bf2f(vh[0][e]);
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        const float w = bf2f(vh[q][e]);
+        if (w > m) {
+          m = w;
+          best = q;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float r = (q == best ? bf2f(dh[e]) : 0.0f) +
+                  bf2f(reinterpret_cast<const uint16_t*>(&sk[q])[e]);
+        if (!(bf2f(vh[q][e]) > 0.0f)) r = 0.0f;
+        oh[q][e] = f2bf(r);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<uint4*>(din + base + off[q]) = o[q];
+  }
+}
+
+// The output layer (1x1 convolution to one channel of a 32-channel input):
+// y[p] = b + sum over c of w[c] * h[p][c], the products of bfloat16 values
+// summed in FP32 in order of c.
+__global__ __launch_bounds__(256) void k_out1_fwd(const uint16_t* __restrict__ h,
+                                                  const uint16_t* __restrict__ w,
+                                                  const float* __restrict__ bias, int64_t P,
+                                                  float* __restrict__ y) {
+  for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < P; p += int64_t(gridDim.x) * 256) {
+    float s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 v = *reinterpret_cast<const uint4*>(h + p * 32 + 8 * q);
+      const uint16_t* vh = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s = __builtin_fmaf(bf2f(w[8 * q + e]), bf2f(vh[e]), s);
+    }
+    y[p] = s + bias[0];
+  }
+}
+
+// Squared-error loss and the output layer's backward pass in one sweep over
+// the pixels: z = y[p] + res[p] (res nullable), d = z - t[p]; loss += sum of
+// d^2 / P; the output gradient g = bf16(2 d / P); the input gradient
+// gin[p][c] = bf16(g * w[c]) where h[p][c] > 0 (h: the layer input, a ReLU
+// output), else 0; and the work-group's partial sums of g * h[p][c] (weight
+// gradient, c < 32) and of g (bias gradient) into part[blockIdx.x][0 .. 35]
+// (slots 33 .. 35 zero), summed over the work-group in a fixed order.
+__global__ __launch_bounds__(256) void k_out1_bwd(const float* __restrict__ y,
+                                                  const float* __restrict__ res,
+                                                  const float* __restrict__ t, int64_t P,
+                                                  const uint16_t* __restrict__ h,
+                                                  const uint16_t* __restrict__ w,
+                                                  uint16_t* __restrict__ gin,
+                                                  float* __restrict__ loss,
+                                                  float* __restrict__ part) {
+  __shared__ float red[34][256];
+  const float inv = 1.0f / float(P);
+  float acc[33], ls = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 33; ++c) acc[c] = 0.0f;
+  float wf[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) wf[c] = bf2f(w[c]);
+  for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < P; p += int64_t(gridDim.x) * 256) {
+    const float d = (res ? y[p] + res[p] : y[p]) - t[p];
+    ls += d * d;
+    const float g = bf2f(f2bf(2.0f * d * inv));
+    acc[32] += g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 v = *reinterpret_cast<const uint4*>(h + p * 32 + 8 * q);
+      const uint16_t* vh = reinterpret_cast<const uint16_t*>(&v);
+      uint4 o;
+      uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float hv = bf2f(vh[e]);
+        acc[8 * q + e] = __builtin_fmaf(g, hv, acc[8 * q + e]);
+        oh[e] = hv > 0.0f ? f2bf(g * wf[8 * q + e]) : uint16_t(0);
+      }
+      *reinterpret_cast<uint4*>(gin + p * 32 + 8 * q) = o;
+    }
+  }
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 33; ++c) red[c][tid] = acc[c];
+  red[33][tid] = ls;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o)
+      for (int c = 0; c < 34; ++c) red[c][tid] += red[c][tid + o];
+    __syncthreads();
+  }
+  if (tid < 36) part[int64_t(blockIdx.x) * 36 + tid] = tid < 33 ? red[tid][0] : 0.0f;
+  if (tid == 0 && loss) atomicAdd(loss, red[33][0] * inv);
+}
+
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, int C,
                                              const float* __restrict__ res,
                                              const float* __restrict__ t, int64_t P,
@@ -988,27 +1408,72 @@ hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int KS, int NT, int KT>
-void launch_wgrad(const NnWgradArgs& a, hipStream_t s) {
-  const int64_t M = int64_t(a.B) * a.H * a.W;
-  const unsigned gx = unsigned((a.Cout + NT - 1) / NT), gy = unsigned((a.Kpad + KT - 1) / KT);
-  // split the pixels so that the grid holds up to ~2048 work-groups, each of
-  // at least 512 pixels (every split adds one FP32 atomic per dW element)
-  int64_t z = 2048 / (int64_t(gx) * gy);
-  if (z > M / 512) z = M / 512;
+// Launch shape of a weight gradient: the kernel (3x3 all-taps kernel with
+// NT = 64 or 32 and block width TW = 64, 32 or 16; else the general kernel
+// for ks = 3 or 1 with NT = 64 or 32) and the grid, whose z dimension splits
+// the pixels.
+struct WgradPlan {
+  int kind;  // 0..5: k_conv3_wgrad (NT 64: TW 64, 32, 16; NT 32: TW 64, 32, 16); 6..9: k_conv_wgrad
+  unsigned gx, gy, gz;
+};
+
+WgradPlan wgrad_plan(const NnWgradArgs& a) {
+  WgradPlan p{};
+  const bool wide = a.Cout % 64 == 0;
+  const int NT = wide ? 64 : 32;
+  p.gx = unsigned(a.Cout / NT);
+  int64_t z;
+  if (a.ks == 3 && a.Cin % 32 == 0) {
+    const int tw = a.W >= 64 ? 64 : a.W >= 32 ? 32 : 16;
+    const int rows = (wide ? 128 : 256) / tw;
+    p.kind = (wide ? 0 : 3) + (tw == 64 ? 0 : tw == 32 ? 1 : 2);
+    p.gy = unsigned(a.Cin / 32);
+    const int64_t nb = int64_t(a.B) * ((a.H + rows - 1) / rows) * ((a.W + tw - 1) / tw);
+    // up to ~256 work-groups (one per compute unit), each of >= 2 blocks
+    z = 256 / (int64_t(p.gx) * p.gy);
+    if (z > nb / 2) z = nb / 2;
+  } else {
+    p.kind = 6 + (a.ks == 1 ? 2 : 0) + (wide ? 0 : 1);
+    p.gy = unsigned((a.Kpad + 63) / 64);
+    const int64_t M = int64_t(a.B) * a.H * a.W;
+    // up to ~2048 work-groups, each of >= 512 pixels
+    z = 2048 / (int64_t(p.gx) * p.gy);
+    if (z > M / 512) z = M / 512;
+  }
   if (z < 1) z = 1;
   if (z > 65535) z = 65535;
-  hipLaunchKernelGGL((k_conv_wgrad<KS, NT, KT>), dim3(gx, gy, unsigned(z)), dim3(256), 0, s, a);
+  p.gz = unsigned(z);
+  return p;
+}
+
+int64_t nn_conv_wgrad_part_floats(const NnWgradArgs& a) {
+  const WgradPlan p = wgrad_plan(a);
+  return int64_t(p.gz) * (int64_t(a.Cout) * a.ks * a.ks * a.Cin + a.Cout);
 }
 
 hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
-  const bool wide = a.Cout % 64 == 0;
-  if (a.ks == 3) {
-    if (wide) launch_wgrad<3, 64, 64>(a, s); else launch_wgrad<3, 32, 64>(a, s);
-  } else if (a.ks == 1) {
-    if (wide) launch_wgrad<1, 64, 64>(a, s); else launch_wgrad<1, 32, 64>(a, s);
-  } else {
-    return hipErrorInvalidValue;
+  if (a.ks != 3 && a.ks != 1) return hipErrorInvalidValue;
+  const WgradPlan p = wgrad_plan(a);
+  if (a.part && a.part_cap < nn_conv_wgrad_part_floats(a)) return hipErrorInvalidValue;
+  const dim3 grid(p.gx, p.gy, p.gz), block(256);
+  switch (p.kind) {
+    case 0: hipLaunchKernelGGL((k_conv3_wgrad<64, 64, 2>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_conv3_wgrad<64, 32, 4>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_conv3_wgrad<64, 16, 8>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_conv3_wgrad<32, 64, 4>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_conv3_wgrad<32, 32, 8>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_conv3_wgrad<32, 16, 16>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_conv_wgrad<3, 64, 64>), grid, block, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_conv_wgrad<3, 32, 64>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_conv_wgrad<1, 64, 64>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_conv_wgrad<1, 32, 64>), grid, block, 0, s, a); break;
+  }
+  if (a.part) {
+    const int64_t nw = int64_t(a.Cout) * a.ks * a.ks * a.Cin;
+    int64_t blocks = (nw + a.Cout + 63) / 64;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(unsigned(blocks)), dim3(256), 0, s, a.part,
+                       int(p.gz), nw, a.Cout, a.dw, a.db);
   }
   return hipGetLastError();
 }
@@ -1127,6 +1592,37 @@ hipError_t nn_denormalize(const float* x, int C, const float* res, const float* 
                           int B, float* y, hipStream_t s) {
   hipLaunchKernelGGL(k_denormalize, dim3(grid1(int64_t(B) * hw)), dim3(256), 0, s, x, C, res, stats,
                      hw, B, y);
+  return hipGetLastError();
+}
+
+hipError_t nn_pool_bwd_add(const uint16_t* in, int B, int H, int W, int C, const uint16_t* dout,
+                           const uint16_t* skip, uint16_t* din, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid1(int64_t(B) * (H / 2) * (W / 2) * (C / 8))),
+                     dim3(256), 0, s, in, B, H, W, C, dout, skip, din);
+  return hipGetLastError();
+}
+
+hipError_t nn_out1_fwd(const uint16_t* h, const uint16_t* w, const float* bias, int64_t P, float* y,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_out1_fwd, dim3(grid1(P)), dim3(256), 0, s, h, w, bias, P, y);
+  return hipGetLastError();
+}
+
+int nn_out1_bwd_groups(int64_t P) {
+  int64_t g = (P + 1023) / 1024;  // about four pixels per thread
+  if (g < 1) g = 1;
+  if (g > 1024) g = 1024;
+  return int(g);
+}
+
+hipError_t nn_out1_bwd(const float* y, const float* res, const float* t, int64_t P,
+                       const uint16_t* h, const uint16_t* w, uint16_t* gin, float* loss,
+                       float* part, float* dw, float* db, hipStream_t s) {
+  const int g = nn_out1_bwd_groups(P);
+  hipLaunchKernelGGL(k_out1_bwd, dim3(unsigned(g)), dim3(256), 0, s, y, res, t, P, h, w, gin, loss,
+                     part);
+  // rows of 36: 32 weight slots, then db[0 .. 3] (slots 1 .. 3 add zero)
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(1), dim3(256), 0, s, part, g, int64_t(32), 4, dw, db);
   return hipGetLastError();
 }
 

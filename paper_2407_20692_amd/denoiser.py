@@ -208,9 +208,18 @@ def conv2d(x, w_packed, ks: int, cout: int, bias=None, mask=None, relu=False, ou
     return out if out is not None else out_f32
 
 
-def conv2d_wgrad(x, dy, ks: int, dw, db=None, stream=None):
+def conv2d_wgrad_workspace_size(b: int, h: int, w: int, cin: int, cout: int, ks: int) -> int:
+    """Bytes of the partial-sum workspace conv2d_wgrad uses for this shape."""
+    out = c_size_t(0)
+    _check(lib.cpi_nn_conv2d_wgrad_workspace_size(b, h, w, cin, cout, ks, ctypes.byref(out)))
+    return out.value
+
+
+def conv2d_wgrad(x, dy, ks: int, dw, db=None, workspace=None, stream=None):
     """dw [cout, ks, ks, cin] FP32 += weight gradient (and db [cout] += bias
-    gradient if given)."""
+    gradient if given).  With a workspace (a uint8 device tensor of at least
+    conv2d_wgrad_workspace_size bytes) the pixel splits are summed in a fixed
+    order; without one they add with FP32 atomics."""
     torch = _torch()
     b, h, w, cin = x.shape
     cout = dy.shape[3]
@@ -219,7 +228,12 @@ def conv2d_wgrad(x, dy, ks: int, dw, db=None, stream=None):
                                    _dev_ptr(dw, "dw", dtype=torch.float32,
                                             numel=cout * ks * ks * cin),
                                    _dev_ptr(db, "db", dtype=torch.float32, numel=cout)
-                                   if db is not None else None, _stream(stream)))
+                                   if db is not None else None,
+                                   _dev_ptr(workspace, "workspace") if workspace is not None
+                                   else None,
+                                   workspace.numel() * workspace.element_size()
+                                   if workspace is not None else 0,
+                                   _stream(stream)))
     return dw
 
 

@@ -71,6 +71,10 @@ CONV_CASES = [
     (16, 64, 64, 32, 32, 3),
     (8, 64, 60, 96, 32, 3),
     (16, 32, 32, 32, 32, 3),
+    # all-taps 3x3 weight gradient: 64-column blocks with ragged rows and
+    # columns, for 32 and 64 output channels
+    (2, 21, 70, 32, 32, 3),
+    (3, 9, 67, 64, 64, 3),
 ]
 
 
@@ -126,16 +130,50 @@ def test_conv_weight_and_bias_grad(nn, case):
     dw = torch.from_numpy(dw0.copy()).to(dev())
     db0 = rng.standard_normal(cout).astype(np.float32)
     dbf = torch.from_numpy(db0.copy()).to(dev())
-    nn.conv2d_wgrad(bf16_tensor(x), bf16_tensor(dy), ks, dw, db=dbf)
     ref = dw0 + dn.conv2d_grad_weight(x, dy, ks)
     S = np.abs(dw0) + dn.conv2d_grad_weight(np.abs(x), np.abs(dy), ks)
     M = b * h * w
-    assert np.all(np.abs(host(dw) - ref) <= (M + 2) * 2.0 ** -23 * S)
     Sb = np.abs(dy).sum(axis=(0, 1, 2))
+    xt, dyt = bf16_tensor(x), bf16_tensor(dy)
+    # pixel splits added with FP32 atomics (no workspace)
+    nn.conv2d_wgrad(xt, dyt, ks, dw, db=dbf)
+    assert np.all(np.abs(host(dw) - ref) <= (M + 2) * 2.0 ** -23 * S)
     assert np.all(np.abs(host(dbf) - db0 - dn.bias_grad(dy)) <= (M + 2) * 2.0 ** -23 * (Sb + np.abs(db0)))
+    # partial sums in a workspace, added in split order: same bound, and two
+    # calls agree bit for bit
+    ws = torch.empty(nn.conv2d_wgrad_workspace_size(b, h, w, cin, cout, ks), dtype=torch.uint8,
+                     device=dev())
+    runs = []
+    for _ in range(2):
+        dw2 = torch.from_numpy(dw0.copy()).to(dev())
+        db2 = torch.from_numpy(db0.copy()).to(dev())
+        nn.conv2d_wgrad(xt, dyt, ks, dw2, db=db2, workspace=ws)
+        runs.append((host(dw2), host(db2)))
+    assert np.all(np.abs(runs[0][0] - ref) <= (M + 2) * 2.0 ** -23 * S)
+    assert np.all(np.abs(runs[0][1] - db0 - dn.bias_grad(dy)) <= (M + 2) * 2.0 ** -23 * (Sb + np.abs(db0)))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    # without a bias gradient the bias slots are neither written nor read
+    dw3 = torch.from_numpy(dw0.copy()).to(dev())
+    nn.conv2d_wgrad(xt, dyt, ks, dw3, workspace=ws)
+    assert np.array_equal(host(dw3), runs[0][0])
     db = torch.zeros(cout, dtype=torch.float32, device=dev())
     nn.bias_grad(bf16_tensor(dy), db)
     assert np.all(np.abs(host(db) - dn.bias_grad(dy)) <= (M + 2) * 2.0 ** -23 * Sb)
+
+
+def test_wgrad_workspace_too_small(nn):
+    import torch
+    from paper_2407_20692_amd.binding import CpiError
+    b, h, w, cin, cout = 2, 16, 16, 32, 64
+    need = nn.conv2d_wgrad_workspace_size(b, h, w, cin, cout, 3)
+    assert need > 0
+    x = torch.zeros(b, h, w, cin, dtype=torch.bfloat16, device=dev())
+    dy = torch.zeros(b, h, w, cout, dtype=torch.bfloat16, device=dev())
+    dw = torch.zeros(cout, 3, 3, cin, dtype=torch.float32, device=dev())
+    ws = torch.empty(need - 4, dtype=torch.uint8, device=dev())
+    with pytest.raises(CpiError) as e:
+        nn.conv2d_wgrad(x, dy, 3, dw, workspace=ws)
+    assert "workspace" in str(e.value)
 
 
 def test_routing_kernels_bit_exact(nn):
