@@ -165,7 +165,9 @@ Net plan_net(uint8_t* base, int B, int H, int W, bool train) {
       w.Cout = L.cout;
       w.ks = L.ks;
       w.Kpad = pl.kpad[i];
-      const int64_t f = cpi::nn_conv_wgrad_part_floats(w);
+      const int64_t f = i == ENC1A ? int64_t(cpi::nn_in1_wgrad_groups(P0)) *
+                                         (int64_t(32) * 9 * L.cin + 32)
+                                   : cpi::nn_conv_wgrad_part_floats(w);
       if (f > cap) cap = f;
     }
     n.wpart_cap = cap;
@@ -238,6 +240,9 @@ struct Pass {
 
   hipError_t conv(int i, const uint16_t* in, uint16_t* out, float* out_f32, bool relu) const {
     const Layer& L = kLayers[i];
+    if (i == ENC1A && relu && out && !out_f32)
+      return cpi::nn_in1_fwd(in, B, hl(L.level), wl(L.level), L.cin, n.wpack + pl.wf_off[i],
+                             pl.kpad[i], params + pl.b_off[i], out, s);
     cpi::NnConvArgs a;
     a.in = in;
     a.wk = n.wpack + pl.wf_off[i];
@@ -284,7 +289,11 @@ struct Pass {
     w.db = n.grads + pl.b_off[i];
     w.part = n.wpart;
     w.part_cap = n.wpart_cap;
-    if ((e = cpi::nn_conv_wgrad(w, ws)) != hipSuccess) return e;
+    if (i == ENC1A && !gin)
+      e = cpi::nn_in1_wgrad(in, B, w.H, w.W, L.cin, g, n.wpart, w.dw, w.db, ws);
+    else
+      e = cpi::nn_conv_wgrad(w, ws);
+    if (e != hipSuccess) return e;
     if (side && done) {
       *done = ev[(*nev)++];
       if ((e = hipEventRecord(*done, side)) != hipSuccess) return e;

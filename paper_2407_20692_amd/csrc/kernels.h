@@ -269,6 +269,14 @@ hipError_t nn_upcat(const uint16_t* low, const uint16_t* skip, int B, int H, int
                     uint16_t* out, hipStream_t s);
 hipError_t nn_upcat_grad(const uint16_t* d, int B, int H, int W, int C1, int C2,
                          const uint16_t* mask, uint16_t* dlow, uint16_t* dskip, hipStream_t s);
+// the first 3x3 layer: one input channel used (stride cx), 32 outputs, ReLU
+hipError_t nn_in1_fwd(const uint16_t* x, int B, int H, int W, int cx, const uint16_t* wk, int kpad,
+                      const float* bias, uint16_t* out, hipStream_t s);
+// work-groups (partial rows of 32 * 9 * cx + 32 floats) nn_in1_wgrad uses
+int nn_in1_wgrad_groups(int64_t P);
+// its weight (dw [32][9 * cx]) and bias (db [32]) gradients added in, via part
+hipError_t nn_in1_wgrad(const uint16_t* x, int B, int H, int W, int cx, const uint16_t* dy,
+                        float* part, float* dw, float* db, hipStream_t s);
 // din = (dout routed to each 2x2 window's first maximal position) + skip,
 // zeroed where in <= 0; C % 8 == 0
 hipError_t nn_pool_bwd_add(const uint16_t* in, int B, int H, int W, int C, const uint16_t* dout,

@@ -262,12 +262,13 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
       for (int j = 0; j < TN; ++j)
         bv[j] = *reinterpret_cast<const uint4*>(
             &slab[(kx * NT + wn * 16 * TN + 16 * j + r) * PITCH + 8 * g]);
+      // weights as the A operand (rows: channels), pixels as B (columns)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(v8bf, av[i]), __builtin_bit_cast(v8bf, bv[j]), acc[i][j], 0, 0,
+              __builtin_bit_cast(v8bf, bv[j]), __builtin_bit_cast(v8bf, av[i]), acc[i][j], 0, 0,
               0);
     }
     if (next) {
@@ -277,26 +278,36 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
       __syncthreads();
     }
   }
-  // element (column 4g + e of row wm*TM + i, channel r of tile j)
+  // elements (column r of row wm*TM + i, channels 4g .. 4g + 3 of tile j):
+  // four consecutive channels of one pixel per lane, stored together
+  const int xx = x0 + r;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int yy = y0 + wm * TM + i;
-    if (yy >= a.H) continue;
+    if (yy >= a.H || xx >= a.W) continue;
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+    for (int j = 0; j < TN; ++j) {
+      const int n = n0 + wn * 16 * TN + 16 * j + 4 * g;
+      const int64_t o = ((int64_t(b) * a.H + yy) * a.W + xx) * a.Cout + n;
+      float v[4];
+      uint2 mk = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+      if (a.mask) mk = *reinterpret_cast<const uint2*>(a.mask + o);
+      const uint16_t* mh = reinterpret_cast<const uint16_t*>(&mk);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int xx = x0 + 4 * g + e;
-        if (xx >= a.W) continue;
-        const int n = n0 + wn * 16 * TN + 16 * j + r;
-        float v = acc[i][j][e];
-        if (a.bias) v += a.bias[n];
-        if (a.relu && v < 0.0f) v = 0.0f;
-        const int64_t o = ((int64_t(b) * a.H + yy) * a.W + xx) * a.Cout + n;
-        if (a.mask && !(bf2f(a.mask[o]) > 0.0f)) v = 0.0f;
-        if (a.out) a.out[o] = f2bf(v);
-        if (a.out_f32) a.out_f32[o] = v;
+        v[e] = acc[i][j][e];
+        if (a.bias) v[e] += a.bias[n + e];
+        if (a.relu && v[e] < 0.0f) v[e] = 0.0f;
+        if (a.mask && !(bf2f(mh[e]) > 0.0f)) v[e] = 0.0f;
       }
+      if (a.out) {
+        uint2 ov;
+        ov.x = uint32_t(f2bf(v[0])) | (uint32_t(f2bf(v[1])) << 16);
+        ov.y = uint32_t(f2bf(v[2])) | (uint32_t(f2bf(v[3])) << 16);
+        *reinterpret_cast<uint2*>(a.out + o) = ov;
+      }
+      if (a.out_f32) *reinterpret_cast<float4*>(a.out_f32 + o) = make_float4(v[0], v[1], v[2], v[3]);
+    }
   }
 }
 
@@ -772,26 +783,23 @@ __global__ __launch_bounds__(256) void k_pack_weights(const float* __restrict__ 
 // the concatenated packed arrays belongs to the last layer whose begin <= i.
 __global__ __launch_bounds__(256) void k_pack_all(const float* __restrict__ params,
                                                   uint16_t* __restrict__ packed, NnPackTable tab) {
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < tab.total;
-       i += int64_t(gridDim.x) * 256) {
-    int l = 0;
-    while (l + 1 < tab.n && tab.layer[l + 1].begin <= i) ++l;
-    const NnPackLayer& L = tab.layer[l];
-    const int taps = L.ks * L.ks;
-    const float* w = params + L.w_off;
-    const int64_t j = i - L.begin;
-    const int64_t nf = int64_t(L.cout) * L.kpad;
+  // one grid row per layer; every per-layer index fits 32 bits
+  const NnPackLayer& L = tab.layer[blockIdx.y];
+  const int taps = L.ks * L.ks;
+  const float* w = params + L.w_off;
+  const int nf = L.cout * L.kpad;
+  const int n = nf + (L.transposed ? L.cin * L.kpad_t : 0);
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
     if (j < nf) {
-      const int co = int(j / L.kpad), k = int(j % L.kpad);
-      packed[L.wf_off + j] =
-          k < taps * L.cin ? f2bf(w[int64_t(co) * taps * L.cin + k]) : uint16_t(0);
+      const int co = j / L.kpad, k = j - co * L.kpad;
+      packed[L.wf_off + j] = k < taps * L.cin ? f2bf(w[co * taps * L.cin + k]) : uint16_t(0);
     } else {
-      const int64_t jt = j - nf;
-      const int ci = int(jt / L.kpad_t), k = int(jt % L.kpad_t);
+      const int jt = j - nf;
+      const int ci = jt / L.kpad_t, k = jt - ci * L.kpad_t;
       uint16_t v = 0;
       if (k < taps * L.cout) {
-        const int tp = k / L.cout, co = k % L.cout;
-        v = f2bf(w[(int64_t(co) * taps + (taps - 1 - tp)) * L.cin + ci]);
+        const int tp = k / L.cout, co = k - tp * L.cout;
+        v = f2bf(w[(co * taps + (taps - 1 - tp)) * L.cin + ci]);
       }
       packed[L.wt_off + jt] = v;
     }
@@ -988,6 +996,150 @@ __global__ __launch_bounds__(256) void k_add_mask(uint16_t* __restrict__ x,
 // Mean squared error of the prediction z = y[p][0] + res[p] (y with C
 // channels per pixel, res nullable) against t over P pixels:
 // loss += sum (z - t)^2 / P; dy = 2 (z - t) / P in channel 0, 0 elsewhere.
+// The first 3x3 layer, whose input has one channel used of cx stored (the
+// others zero): out[p][n] = relu(b[n] + sum over taps of w[n][tap] x[p + tap]
+// (channel 0, zero padding)) for 32 output channels, w the packed weights
+// (w[n][tap] at wk[n * kpad + tap * cx]); products of bfloat16 values summed
+// in FP32 in tap order.
+__global__ __launch_bounds__(256) void k_in1_fwd(const uint16_t* __restrict__ x, int B, int H,
+                                                 int W, int cx, const uint16_t* __restrict__ wk,
+                                                 int kpad, const float* __restrict__ bias,
+                                                 uint16_t* __restrict__ out) {
+  // weights as [tap][channel] (four channels per 16-byte read), bias after
+  __shared__ __attribute__((aligned(16))) float ws[10 * 32];
+  const int t = threadIdx.x;
+  for (int q = t; q < 32 * 9; q += 256) ws[(q % 9) * 32 + q / 9] = bf2f(wk[(q / 9) * kpad + (q % 9) * cx]);
+  if (t < 32) ws[9 * 32 + t] = bias ? bias[t] : 0.0f;
+  __syncthreads();
+  const v4f* w4 = reinterpret_cast<const v4f*>(ws);
+  const int64_t P = int64_t(B) * H * W;
+  // two pixels per thread: p and p + half of the grid's stride
+  const int64_t stride = int64_t(gridDim.x) * 512;
+  for (int64_t p0 = int64_t(blockIdx.x) * 512 + t; p0 < P; p0 += stride) {
+    int64_t pp[2] = {p0, p0 + 256};
+    float v[2][9];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t p = pp[u] < P ? pp[u] : p0;
+      const int xx = int(p % W), yy = int((p / W) % H);
+      const int64_t img = p - (int64_t(yy) * W + xx);
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int y = yy + tap / 3 - 1, xc = xx + tap % 3 - 1;
+        v[u][tap] = (y >= 0 && y < H && xc >= 0 && xc < W)
+                        ? bf2f(x[(img + int64_t(y) * W + xc) * cx])
+                        : 0.0f;
+      }
+    }
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      v4f acc[2][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) acc[u][0] = acc[u][1] = v4f{0, 0, 0, 0};
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const v4f wa = w4[tap * 8 + 2 * q], wb = w4[tap * 8 + 2 * q + 1];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[u][0][e] = __builtin_fmaf(wa[e], v[u][tap], acc[u][0][e]);
+            acc[u][1][e] = __builtin_fmaf(wb[e], v[u][tap], acc[u][1][e]);
+          }
+      }
+      const v4f ba = w4[72 + 2 * q], bb = w4[72 + 2 * q + 1];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (pp[u] >= P) continue;
+        uint4 o;
+        uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float ra = acc[u][0][e] + ba[e], rb = acc[u][1][e] + bb[e];
+          oh[e] = f2bf(ra < 0.0f ? 0.0f : ra);
+          oh[4 + e] = f2bf(rb < 0.0f ? 0.0f : rb);
+        }
+        *reinterpret_cast<uint4*>(out + pp[u] * 32 + 8 * q) = o;
+      }
+    }
+  }
+}
+
+// Weight and bias gradients of that layer: dW[n][tap * cx] = sum over pixels
+// of dy[p][n] x[p + tap] (channel 0) and db[n] = sum of dy[p][n], as one row
+// of partial sums per work-group (row layout of the weight-gradient partial
+// buffer: 32 * 9 * cx weight slots, zero for input channels > 0, then 32
+// bias slots).  Thread t takes channels 8 (t & 3) .. + 7 of every 64th pixel
+// of the work-group's range; lanes of one channel group are summed with
+// shuffles, then the four waves in order.
+__global__ __launch_bounds__(256) void k_in1_wgrad(const uint16_t* __restrict__ x, int B, int H,
+                                                   int W, int cx, const uint16_t* __restrict__ dy,
+                                                   float* __restrict__ part) {
+  __shared__ float red[4][4][80];
+  __shared__ float fin[4 * 80];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int q = t & 3;
+  const int64_t P = int64_t(B) * H * W;
+  const int64_t per = (P + gridDim.x - 1) / gridDim.x;
+  const int64_t plo = int64_t(blockIdx.x) * per;
+  const int64_t phi = plo + per < P ? plo + per : P;
+  float acc[80];
+#pragma unroll
+  for (int k = 0; k < 80; ++k) acc[k] = 0.0f;
+#pragma unroll 4
+  for (int64_t p = plo + (t >> 2); p < phi; p += 64) {
+    const int xx = int(p % W), yy = int((p / W) % H);
+    const int64_t img = p - (int64_t(yy) * W + xx);
+    float v[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int y = yy + tap / 3 - 1, xc = xx + tap % 3 - 1;
+      v[tap] = (y >= 0 && y < H && xc >= 0 && xc < W) ? bf2f(x[(img + int64_t(y) * W + xc) * cx])
+                                                      : 0.0f;
+    }
+    const uint4 d4 = *reinterpret_cast<const uint4*>(dy + p * 32 + 8 * q);
+    const uint16_t* dh = reinterpret_cast<const uint16_t*>(&d4);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float d = bf2f(dh[e]);
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) acc[e * 9 + tap] = __builtin_fmaf(d, v[tap], acc[e * 9 + tap]);
+      acc[72 + e] += d;
+    }
+  }
+  // lanes 4 k + q, k = 0 .. 15, share channel group q
+#pragma unroll
+  for (int k = 0; k < 80; ++k) {
+    float a = acc[k];
+    a += __shfl_xor(a, 4);
+    a += __shfl_xor(a, 8);
+    a += __shfl_xor(a, 16);
+    a += __shfl_xor(a, 32);
+    acc[k] = a;
+  }
+  if (lane < 4)
+#pragma unroll
+    for (int k = 0; k < 80; ++k) red[wave][lane][k] = acc[k];
+  __syncthreads();
+  for (int k = t; k < 320; k += 256)
+    fin[k] = ((red[0][k / 80][k % 80] + red[1][k / 80][k % 80]) + red[2][k / 80][k % 80]) +
+             red[3][k / 80][k % 80];
+  __syncthreads();
+  const int K = 9 * cx, nw = 32 * K;
+  float* row = part + int64_t(blockIdx.x) * (nw + 32);
+  for (int j = t; j < nw + 32; j += 256) {
+    float val = 0.0f;
+    if (j >= nw) {
+      const int n = j - nw;
+      val = fin[(n >> 3) * 80 + 72 + (n & 7)];
+    } else {
+      const int n = j / K, k = j - n * K;
+      if (k % cx == 0) val = fin[(n >> 3) * 80 + (n & 7) * 9 + k / cx];
+    }
+    __builtin_nontemporal_store(val, &row[j]);
+  }
+}
+
 // Max-pooling backward fused with the skip addition and the ReLU mask:
 // din[q] = (dout of q's window if q is the window's first maximal position,
 // else 0) + skip[q], zeroed where in[q] <= 0 (bfloat16 out).  A thread takes
@@ -1584,7 +1736,17 @@ hipError_t nn_normalize(const float* planes, int B, int64_t hw, int C, uint16_t*
 
 hipError_t nn_pack_all(const float* params, uint16_t* packed, const NnPackTable& tab,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_all, dim3(grid1(tab.total)), dim3(256), 0, s, params, packed, tab);
+  int64_t most = 0;
+  for (int l = 0; l < tab.n; ++l) {
+    const NnPackLayer& L = tab.layer[l];
+    const int64_t n = int64_t(L.cout) * L.kpad + (L.transposed ? int64_t(L.cin) * L.kpad_t : 0);
+    if (n > most) most = n;
+  }
+  if (most >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  int64_t gx = (most + 4 * 256 - 1) / (4 * 256);  // about four elements per thread
+  if (gx < 1) gx = 1;
+  hipLaunchKernelGGL(k_pack_all, dim3(unsigned(gx), unsigned(tab.n)), dim3(256), 0, s, params,
+                     packed, tab);
   return hipGetLastError();
 }
 
@@ -1592,6 +1754,30 @@ hipError_t nn_denormalize(const float* x, int C, const float* res, const float* 
                           int B, float* y, hipStream_t s) {
   hipLaunchKernelGGL(k_denormalize, dim3(grid1(int64_t(B) * hw)), dim3(256), 0, s, x, C, res, stats,
                      hw, B, y);
+  return hipGetLastError();
+}
+
+hipError_t nn_in1_fwd(const uint16_t* x, int B, int H, int W, int cx, const uint16_t* wk, int kpad,
+                      const float* bias, uint16_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_in1_fwd, dim3(grid1((int64_t(B) * H * W + 1) / 2)), dim3(256), 0, s, x, B,
+                     H, W, cx, wk, kpad, bias, out);
+  return hipGetLastError();
+}
+
+int nn_in1_wgrad_groups(int64_t P) {
+  int64_t g = (P + 511) / 512;  // about eight pixels per thread
+  if (g < 1) g = 1;
+  if (g > 512) g = 512;
+  return int(g);
+}
+
+hipError_t nn_in1_wgrad(const uint16_t* x, int B, int H, int W, int cx, const uint16_t* dy,
+                        float* part, float* dw, float* db, hipStream_t s) {
+  const int g = nn_in1_wgrad_groups(int64_t(B) * H * W);
+  hipLaunchKernelGGL(k_in1_wgrad, dim3(unsigned(g)), dim3(256), 0, s, x, B, H, W, cx, dy, part);
+  const int64_t nw = int64_t(32) * 9 * cx;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(unsigned((nw + 32 + 63) / 64)), dim3(256), 0, s, part, g,
+                     nw, 32, dw, db);
   return hipGetLastError();
 }
 
