@@ -59,6 +59,10 @@ struct Layer {
 };
 
 constexpr int kNumLayers = 15;
+// gradient buffers of the backward pass, taken in turn: the chain of input
+// gradients may run this many steps ahead of the weight gradients that read
+// its results
+constexpr int kGradBufs = 6;
 const Layer kLayers[kNumLayers] = {
     {"enc1a", 8, 32, 3, 1, 32, 0},     {"enc1b", 32, 32, 3, 32, 32, 0},
     {"enc2a", 32, 64, 3, 32, 64, 1},   {"enc2b", 64, 64, 3, 64, 64, 1},
@@ -113,7 +117,7 @@ struct Net {
   float* stats;
   double* norm_scratch;
   float* loss_scratch;
-  uint16_t* g[3];  // gradient buffers, taken in turn by the backward pass
+  uint16_t* g[kGradBufs];  // gradient buffers, taken in turn by the backward pass
   uint16_t* skip[3];
   uint16_t* wpack;
   float* grads;
@@ -151,7 +155,7 @@ Net plan_net(uint8_t* base, int B, int H, int W, bool train) {
     n.tn = static_cast<float*>(take(size_t(P0) * 4));
     n.opart = static_cast<float*>(take(size_t(cpi::nn_out1_bwd_groups(P0)) * 36 * 4));
     n.loss_scratch = static_cast<float*>(take(64));
-    for (int k = 0; k < 3; ++k) n.g[k] = static_cast<uint16_t*>(take(size_t(P0) * 96 * 2));
+    for (int k = 0; k < kGradBufs; ++k) n.g[k] = static_cast<uint16_t*>(take(size_t(P0) * 96 * 2));
     for (int l = 0; l < 3; ++l) n.skip[l] = static_cast<uint16_t*>(take(size_t(P(l)) * wid[l] * 2));
     n.grads = static_cast<float*>(take(size_t(pl.total) * 4));
     int64_t cap = 0;
@@ -367,16 +371,16 @@ struct Pass {
 
   // the loss of the output in n.outf against the targets in n.tn (added to
   // *loss) and its gradients.  Each step writes its result into the next of
-  // the three gradient buffers; a buffer is taken again three steps later,
+  // the kGradBufs gradient buffers; a buffer is taken again kGradBufs steps later,
   // after the caller's stream has waited for the weight gradient that read it.
   hipError_t backward() const {
     hipError_t e;
     const int wid[4] = {32, 64, 128, 256};
-    hipEvent_t busy[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t busy[kGradBufs] = {};
     int cur = 0, nxt = 0;
     auto take = [&](int* b) -> hipError_t {
       *b = nxt;
-      nxt = (nxt + 1) % 3;
+      nxt = (nxt + 1) % kGradBufs;
       if (busy[*b]) {
         const hipError_t r = hipStreamWaitEvent(s, busy[*b], 0);
         busy[*b] = nullptr;

@@ -151,17 +151,18 @@ __global__ __launch_bounds__(256) void k_conv(NnConvArgs a) {
 // (WM x WN); wave (wm, wn) owns rows [wm*TM, (wm+1)*TM) (one 16-pixel
 // fragment per row) and channels [wn*16*TN, (wn+1)*16*TN).  Per chunk of 32
 // input channels the block's input pixels with their one-pixel halo
-// ((TH + 2) x 18 pixels) are staged in LDS once; per kernel row ky the
-// weights of its three taps for the NT channels are staged beside them, and
-// the three taps run from LDS.  Pixel and weight rows are padded to 40
-// elements (80 bytes) to spread LDS banks.
-template <int TM, int TN, int WM, int WN>
+// ((TH + 2) x 18 pixels) are staged in LDS once; per phase of KY kernel rows
+// (KY = 1 or 3) the weights of their taps for the NT channels are staged
+// beside them, and those taps run from LDS.  Pixel and weight rows are padded
+// to 40 elements (80 bytes) to spread LDS banks.
+template <int TM, int TN, int WM, int WN, int KY>
 __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
   constexpr int TH = WM * TM, TW = 16, NT = WN * TN * 16;
   constexpr int HW = TW + 2, HH = TH + 2;
   constexpr int PITCH = 40;  // elements per staged pixel / weight row
+  static_assert(KY == 1 || KY == 3, "kernel rows per phase");
   __shared__ __attribute__((aligned(16))) uint16_t halo[HH * HW * PITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t slab[3 * NT * PITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t slab[3 * KY * NT * PITCH];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int r = lane & 15, g = lane >> 4;
@@ -183,11 +184,13 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0, 0, 0, 0};
 
-  // Phases p = 3 * chunk + ky.  The global loads of phase p + 1 (the halo
-  // when a new chunk starts, and the weight slab) are issued into registers
-  // before the matrix-core ops of phase p and written to LDS after them.
-  constexpr int HQ = (HH * HW * 4 + 255) / 256;   // halo pieces per thread
-  constexpr int SQ = (3 * NT * 4 + 255) / 256;    // slab pieces per thread
+  // Phases p = (3 / KY) * chunk + kernel-row group.  The global loads of
+  // phase p + 1 (the halo when a new chunk starts, and the weight slab) are
+  // issued into registers before the matrix-core ops of phase p and written
+  // to LDS after them.
+  constexpr int PPC = 3 / KY;                          // phases per chunk
+  constexpr int HQ = (HH * HW * 4 + 255) / 256;        // halo pieces per thread
+  constexpr int SQ = (3 * KY * NT * 4 + 255) / 256;    // slab pieces per thread
   uint4 hreg[HQ], sreg[SQ];
   auto load_halo = [&](int c0) {
 #pragma unroll
@@ -213,15 +216,15 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
         *reinterpret_cast<uint4*>(&halo[(q >> 2) * PITCH + 8 * (q & 3)]) = hreg[u];
     }
   };
-  auto load_slab = [&](int c0, int ky) {
+  auto load_slab = [&](int c0, int ky0) {
 #pragma unroll
     for (int u = 0; u < SQ; ++u) {
       const int q = t + 256 * u;
       uint4 v = make_uint4(0, 0, 0, 0);
-      if (q < 3 * NT * 4) {
-        const int part = q & 3, row = q >> 2;  // row = kx * NT + n
-        const int kx = row / NT, n = row % NT;
-        const int k = (ky * 3 + kx) * Cin + c0 + 8 * part;
+      if (q < 3 * KY * NT * 4) {
+        const int part = q & 3, row = q >> 2;  // row = (3 * kyi + kx) * NT + n
+        const int tl = row / NT, n = row % NT;
+        const int k = (ky0 * 3 + tl) * Cin + c0 + 8 * part;
         v = *reinterpret_cast<const uint4*>(a.wk + int64_t(n0 + n) * a.Kpad + k);
       }
       sreg[u] = v;
@@ -231,12 +234,12 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
 #pragma unroll
     for (int u = 0; u < SQ; ++u) {
       const int q = t + 256 * u;
-      if (q < 3 * NT * 4)
+      if (q < 3 * KY * NT * 4)
         *reinterpret_cast<uint4*>(&slab[(q >> 2) * PITCH + 8 * (q & 3)]) = sreg[u];
     }
   };
 
-  const int phases = (Cin / 32) * 3;
+  const int phases = (Cin / 32) * PPC;
   load_halo(0);
   load_slab(0, 0);
   store_halo();
@@ -244,15 +247,16 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
   __syncthreads();
 #pragma unroll 1
   for (int p = 0; p < phases; ++p) {
-    const int ky = p % 3;
+    const int ky0 = KY * (p % PPC);
     const bool next = p + 1 < phases;
-    const int pn = p + 1, cn = 32 * (pn / 3), kyn = pn % 3;
+    const int pn = p + 1, cn = 32 * (pn / PPC), kyn = KY * (pn % PPC);
     if (next) {
       if (kyn == 0) load_halo(cn);
       load_slab(cn, kyn);
     }
 #pragma unroll
-    for (int kx = 0; kx < 3; ++kx) {
+    for (int tl = 0; tl < 3 * KY; ++tl) {
+      const int ky = ky0 + tl / 3, kx = tl % 3;
       uint4 av[TM], bv[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
 #pragma unroll
       for (int j = 0; j < TN; ++j)
         bv[j] = *reinterpret_cast<const uint4*>(
-            &slab[(kx * NT + wn * 16 * TN + 16 * j + r) * PITCH + 8 * g]);
+            &slab[(tl * NT + wn * 16 * TN + 16 * j + r) * PITCH + 8 * g]);
       // weights as the A operand (rows: channels), pixels as B (columns)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -1519,12 +1523,17 @@ void conv_ks(const NnConvArgs& a, hipStream_t s) {
     launch_conv<KS, 1, 2>(a, s);
 }
 
+// Kernel rows per phase: all three (one phase per chunk of 32 input
+// channels) for 64-channel tiles; one for 128-channel tiles, whose nine
+// taps' weights would not leave room for a second work-group, and for
+// 32-channel tiles, whose level-0 grids gain more from occupancy.
 template <int TM, int TN, int WM, int WN>
 void launch_conv3_lds(const NnConvArgs& a, hipStream_t s) {
   constexpr int TH = WM * TM, NT = WN * TN * 16;
+  constexpr int KY = NT == 64 ? 3 : 1;
   const int64_t blocks = int64_t((a.W + 15) / 16) * ((a.H + TH - 1) / TH) * a.B;
-  hipLaunchKernelGGL((k_conv3_lds<TM, TN, WM, WN>), dim3(unsigned(blocks), unsigned(a.Cout / NT)),
-                     dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_conv3_lds<TM, TN, WM, WN, KY>),
+                     dim3(unsigned(blocks), unsigned(a.Cout / NT)), dim3(256), 0, s, a);
 }
 
 // Work-groups of the LDS-staged 3x3 kernel for a tile of TH rows and NT channels.
@@ -1534,8 +1543,8 @@ int64_t lds_groups(const NnConvArgs& a, int th, int nt) {
 
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
   if (a.ks == 3 && a.Cin % 32 == 0) {
-    // the first tile shape (rows x channels) whose grid holds >= 256 work-groups
-    constexpr int64_t kMin = 256;
+    // the first tile shape (rows x channels) whose grid holds >= 512 work-groups
+    constexpr int64_t kMin = 512;
     if (a.Cout % 128 == 0 && lds_groups(a, 8, 128) >= kMin)
       launch_conv3_lds<4, 4, 2, 2>(a, s);
     else if (a.Cout % 64 == 0 && lds_groups(a, 8, 64) >= kMin)

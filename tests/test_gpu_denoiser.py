@@ -63,14 +63,17 @@ CONV_CASES = [
     (2, 9, 13, 128, 64, 1),
     (1, 12, 10, 160, 32, 1),
     # LDS-staged 3x3 kernel: the first tile shape (rows x channels) whose
-    # grid holds >= 256 work-groups; one case per shape (8 x 128, 8 x 64,
+    # grid holds >= 512 work-groups; every shape covered (8 x 128, 8 x 64,
     # 4 x 64, 16 x 32, 8 x 32, 4 x 32), ragged edges
-    (8, 64, 64, 32, 128, 3),
-    (8, 60, 62, 64, 64, 3),
-    (16, 16, 16, 128, 256, 3),
-    (16, 64, 64, 32, 32, 3),
-    (8, 64, 60, 96, 32, 3),
-    (16, 32, 32, 32, 32, 3),
+    (16, 64, 64, 32, 128, 3),   # 8 x 128
+    (8, 64, 64, 32, 128, 3),    # 8 x 64
+    (9, 60, 62, 64, 64, 3),     # 4 x 64
+    (16, 128, 64, 32, 32, 3),   # 16 x 32
+    (8, 60, 62, 64, 64, 3),     # 8 x 32
+    (16, 64, 64, 32, 32, 3),    # 8 x 32
+    (16, 16, 16, 128, 256, 3),  # 4 x 32
+    (8, 64, 60, 96, 32, 3),     # 4 x 32
+    (16, 32, 32, 32, 32, 3),    # register-fed (grid too small)
     # all-taps 3x3 weight gradient: 64-column blocks with ragged rows and
     # columns, for 32 and 64 output channels
     (2, 21, 70, 32, 32, 3),
