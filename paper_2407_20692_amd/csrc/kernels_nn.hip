@@ -1543,22 +1543,28 @@ int64_t lds_groups(const NnConvArgs& a, int th, int nt) {
 
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
   if (a.ks == 3 && a.Cin % 32 == 0) {
-    // the first tile shape (rows x channels) whose grid holds >= 512 work-groups
-    constexpr int64_t kMin = 512;
-    if (a.Cout % 128 == 0 && lds_groups(a, 8, 128) >= kMin)
-      launch_conv3_lds<4, 4, 2, 2>(a, s);
-    else if (a.Cout % 64 == 0 && lds_groups(a, 8, 64) >= kMin)
-      launch_conv3_lds<4, 2, 2, 2>(a, s);
-    else if (a.Cout % 64 == 0 && lds_groups(a, 4, 64) >= kMin)
-      launch_conv3_lds<2, 2, 2, 2>(a, s);
-    else if (lds_groups(a, 16, 32) >= kMin)
-      launch_conv3_lds<4, 2, 4, 1>(a, s);
-    else if (lds_groups(a, 8, 32) >= kMin)
-      launch_conv3_lds<2, 2, 4, 1>(a, s);
-    else if (lds_groups(a, 4, 32) >= kMin)
-      launch_conv3_lds<1, 2, 4, 1>(a, s);
-    else
-      conv_ks<3>(a, s);
+    // the first tile shape (rows x channels) whose grid holds >= 512
+    // work-groups; failing that >= 256, then >= 128; else the register-fed
+    // kernel
+    bool done = false;
+    for (int64_t kMin = 512; kMin >= 128 && !done; kMin /= 2) {
+      done = true;
+      if (a.Cout % 128 == 0 && lds_groups(a, 8, 128) >= kMin)
+        launch_conv3_lds<4, 4, 2, 2>(a, s);
+      else if (a.Cout % 64 == 0 && lds_groups(a, 8, 64) >= kMin)
+        launch_conv3_lds<4, 2, 2, 2>(a, s);
+      else if (a.Cout % 64 == 0 && lds_groups(a, 4, 64) >= kMin)
+        launch_conv3_lds<2, 2, 2, 2>(a, s);
+      else if (lds_groups(a, 16, 32) >= kMin)
+        launch_conv3_lds<4, 2, 4, 1>(a, s);
+      else if (lds_groups(a, 8, 32) >= kMin)
+        launch_conv3_lds<2, 2, 4, 1>(a, s);
+      else if (lds_groups(a, 4, 32) >= kMin)
+        launch_conv3_lds<1, 2, 4, 1>(a, s);
+      else
+        done = false;
+    }
+    if (!done) conv_ks<3>(a, s);
   } else if (a.ks == 3) {
     conv_ks<3>(a, s);
   } else if (a.ks == 1) {

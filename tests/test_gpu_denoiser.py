@@ -63,7 +63,7 @@ CONV_CASES = [
     (2, 9, 13, 128, 64, 1),
     (1, 12, 10, 160, 32, 1),
     # LDS-staged 3x3 kernel: the first tile shape (rows x channels) whose
-    # grid holds >= 512 work-groups; every shape covered (8 x 128, 8 x 64,
+    # grid holds >= 512 work-groups (then 256, 128); every shape covered (8 x 128, 8 x 64,
     # 4 x 64, 16 x 32, 8 x 32, 4 x 32), ragged edges
     (16, 64, 64, 32, 128, 3),   # 8 x 128
     (8, 64, 64, 32, 128, 3),    # 8 x 64
@@ -73,7 +73,7 @@ CONV_CASES = [
     (16, 64, 64, 32, 32, 3),    # 8 x 32
     (16, 16, 16, 128, 256, 3),  # 4 x 32
     (8, 64, 60, 96, 32, 3),     # 4 x 32
-    (16, 32, 32, 32, 32, 3),    # register-fed (grid too small)
+    (16, 32, 32, 32, 32, 3),    # 4 x 32 at the 256-group threshold
     # all-taps 3x3 weight gradient: 64-column blocks with ragged rows and
     # columns, for 32 and 64 output channels
     (2, 21, 70, 32, 32, 3),
