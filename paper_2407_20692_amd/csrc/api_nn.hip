@@ -242,17 +242,9 @@ struct Pass {
   int wl(int level) const { return W >> level; }
   int64_t P(int level) const { return int64_t(B) * hl(level) * wl(level); }
 
-  hipError_t conv(int i, const uint16_t* in, uint16_t* out, float* out_f32, bool relu) const {
+  cpi::NnConvArgs conv_args(int i) const {
     const Layer& L = kLayers[i];
-    if (i == ENC1A && relu && out && !out_f32)
-      return cpi::nn_in1_fwd(in, B, hl(L.level), wl(L.level), L.cin, n.wpack + pl.wf_off[i],
-                             pl.kpad[i], params + pl.b_off[i], out, s);
     cpi::NnConvArgs a;
-    a.in = in;
-    a.wk = n.wpack + pl.wf_off[i];
-    a.bias = params + pl.b_off[i];
-    a.out = out;
-    a.out_f32 = out_f32;
     a.B = B;
     a.H = hl(L.level);
     a.W = wl(L.level);
@@ -260,7 +252,33 @@ struct Pass {
     a.Cout = L.cout;
     a.ks = L.ks;
     a.Kpad = pl.kpad[i];
+    return a;
+  }
+
+  // whether layer i's convolution reads its input as [upsampled low (c_low
+  // channels), in] without the concatenation being written out
+  bool reads_concat(int i, int c_low) const {
+    cpi::NnConvArgs a = conv_args(i);
+    a.c_low = c_low;
+    return cpi::nn_conv_takes_low(a);
+  }
+
+  // input: in, or [upsample2(low) (c_low channels), in] when low is set
+  hipError_t conv(int i, const uint16_t* in, uint16_t* out, float* out_f32, bool relu,
+                  const uint16_t* low = nullptr, int c_low = 0) const {
+    const Layer& L = kLayers[i];
+    if (i == ENC1A && relu && out && !out_f32)
+      return cpi::nn_in1_fwd(in, B, hl(L.level), wl(L.level), L.cin, n.wpack + pl.wf_off[i],
+                             pl.kpad[i], params + pl.b_off[i], out, s);
+    cpi::NnConvArgs a = conv_args(i);
+    a.in = in;
+    a.wk = n.wpack + pl.wf_off[i];
+    a.bias = params + pl.b_off[i];
+    a.out = out;
+    a.out_f32 = out_f32;
     a.relu = relu ? 1 : 0;
+    a.low = low;
+    a.c_low = low ? c_low : 0;
     return cpi::nn_conv(a, s);
   }
 
@@ -269,7 +287,8 @@ struct Pass {
   // recorded after it); input gradient into gin (masked by `mask` if given)
   // unless gin is null, on the caller's stream
   hipError_t back(int i, const uint16_t* in, const uint16_t* g, uint16_t* gin,
-                  const uint16_t* mask, hipEvent_t* done = nullptr) const {
+                  const uint16_t* mask, hipEvent_t* done = nullptr, const uint16_t* low = nullptr,
+                  int c_low = 0) const {
     const Layer& L = kLayers[i];
     hipStream_t ws = s;
     hipError_t e;
@@ -293,6 +312,8 @@ struct Pass {
     w.db = n.grads + pl.b_off[i];
     w.part = n.wpart;
     w.part_cap = n.wpart_cap;
+    w.low = low;
+    w.c_low = low ? c_low : 0;
     if (i == ENC1A && !gin)
       e = cpi::nn_in1_wgrad(in, B, w.H, w.W, L.cin, g, n.wpart, w.dw, w.db, ws);
     else
@@ -359,9 +380,13 @@ struct Pass {
     h = n.act[MIDB];
     for (int l = 2; l >= 0; --l) {
       const int da = DEC3A + 2 * (2 - l);
-      NN_STEP(cpi::nn_upcat(h, n.act[2 * l + 1], B, hl(l + 1), wl(l + 1), wid[l + 1], wid[l],
-                            n.cat[l], s));
-      NN_STEP(conv(da, n.cat[l], n.act[da], nullptr, true));
+      if (reads_concat(da, wid[l + 1])) {
+        NN_STEP(conv(da, n.act[2 * l + 1], n.act[da], nullptr, true, h, wid[l + 1]));
+      } else {
+        NN_STEP(cpi::nn_upcat(h, n.act[2 * l + 1], B, hl(l + 1), wl(l + 1), wid[l + 1], wid[l],
+                              n.cat[l], s));
+        NN_STEP(conv(da, n.cat[l], n.act[da], nullptr, true));
+      }
       NN_STEP(conv(da + 1, n.act[da], n.act[da + 1], nullptr, true));
       h = n.act[da + 1];
     }
@@ -390,11 +415,12 @@ struct Pass {
     };
     // layer i's gradients from the gradient in buffer cur; its input
     // gradient (unless last) into a new buffer, which becomes cur
-    auto layer = [&](int i, const uint16_t* in, const uint16_t* mask, bool input_grad) {
+    auto layer = [&](int i, const uint16_t* in, const uint16_t* mask, bool input_grad,
+                     const uint16_t* low = nullptr, int c_low = 0) {
       int b = -1;
       hipError_t r = input_grad ? take(&b) : hipSuccess;
       if (r != hipSuccess) return r;
-      r = back(i, in, n.g[cur], input_grad ? n.g[b] : nullptr, mask, &busy[cur]);
+      r = back(i, in, n.g[cur], input_grad ? n.g[b] : nullptr, mask, &busy[cur], low, c_low);
       if (input_grad) cur = b;
       return r;
     };
@@ -412,7 +438,8 @@ struct Pass {
     for (int l = 0; l < 3; ++l) {
       const int da = DEC1A - 2 * l;
       NN_STEP(layer(da + 1, n.act[da], n.act[da], true));
-      NN_STEP(layer(da, n.cat[l], nullptr, true));
+      // the input [upsampled level l + 1 output, encoder output] read as such
+      NN_STEP(layer(da, n.act[2 * l + 1], nullptr, true, below[l], wid[l + 1]));
       int b;
       NN_STEP(take(&b));
       NN_STEP(cpi::nn_upcat_grad(n.g[cur], B, hl(l + 1), wl(l + 1), wid[l + 1], wid[l], below[l],

@@ -221,10 +221,18 @@ struct NnConvArgs {
   float* out_f32 = nullptr;        // [B][H][W][Cout] FP32, or null
   int B = 0, H = 0, W = 0, Cin = 0, Cout = 0, ks = 0, Kpad = 0;
   int relu = 0;
+  // Concatenated input: if low is set, input channels [0, c_low) are the
+  // nearest 2x upsampling of low ([B][H/2][W/2][c_low], H and W even) and
+  // channels [c_low, Cin) come from in ([B][H][W][Cin - c_low]); c_low % 32
+  // == 0.  Only the LDS-staged 3x3 kernels take it (nn_conv_takes_low).
+  const uint16_t* low = nullptr;
+  int c_low = 0;
 };
 // Forward convolution (zero padding, ks odd); the backward-data
 // convolution is the same call on dY with the flipped, transposed weights.
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s);
+// whether nn_conv runs this shape on a kernel that reads a concatenated input
+bool nn_conv_takes_low(const NnConvArgs& a);
 
 struct NnWgradArgs {
   const uint16_t* in = nullptr;    // [B][H][W][Cin] layer input
@@ -238,6 +246,9 @@ struct NnWgradArgs {
   float* part = nullptr;
   int64_t part_cap = 0;            // floats available at part
   int B = 0, H = 0, W = 0, Cin = 0, Cout = 0, ks = 0, Kpad = 0;
+  // concatenated input as in NnConvArgs (3x3 layers with Cin % 32 == 0 only)
+  const uint16_t* low = nullptr;
+  int c_low = 0;
 };
 hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s);
 // floats of partial sums nn_conv_wgrad uses for this shape (the part buffer)

@@ -176,7 +176,11 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
   const int x0 = bx * TW, y0 = by * TH;
   const int n0 = blockIdx.y * NT;
   const int Cin = a.Cin;
-  const uint16_t* img = a.in + int64_t(b) * a.H * a.W * Cin;
+  // input channels [0, c_low) from the upsampled low-resolution tensor, the
+  // rest from in (c_low = 0: all from in)
+  const int Cs = Cin - a.c_low, Wl = a.W / 2;
+  const uint16_t* img = a.in + int64_t(b) * a.H * a.W * Cs;
+  const uint16_t* limg = a.low ? a.low + int64_t(b) * (a.H / 2) * Wl * a.c_low : nullptr;
 
   v4f acc[TM][TN];
 #pragma unroll
@@ -202,8 +206,11 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
         const int hy = px / HW, hx = px % HW;
         const int yy = y0 + hy - 1, xx = x0 + hx - 1;
         if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-          v = *reinterpret_cast<const uint4*>(img + (int64_t(yy) * a.W + xx) * Cin + c0 +
-                                              8 * part);
+          v = c0 < a.c_low
+                  ? *reinterpret_cast<const uint4*>(
+                        limg + (int64_t(yy >> 1) * Wl + (xx >> 1)) * a.c_low + c0 + 8 * part)
+                  : *reinterpret_cast<const uint4*>(img + (int64_t(yy) * a.W + xx) * Cs + c0 -
+                                                    a.c_low + 8 * part);
       }
       hreg[u] = v;
     }
@@ -553,8 +560,13 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(NnWgradArgs a) {
       const int y = y0 + hp / HW - 1, x = x0 + hp % HW - 1;
       xv[u] = make_uint4(0, 0, 0, 0);
       if (c < HP * 4 && y >= 0 && y < a.H && x >= 0 && x < a.W)
-        xv[u] = *reinterpret_cast<const uint4*>(a.in + ((b * a.H + y) * a.W + x) * Cin + c0 +
-                                                8 * part);
+        xv[u] = c0 < a.c_low
+                    ? *reinterpret_cast<const uint4*>(
+                          a.low + ((b * (a.H / 2) + (y >> 1)) * (a.W / 2) + (x >> 1)) * a.c_low +
+                          c0 + 8 * part)
+                    : *reinterpret_cast<const uint4*>(
+                          a.in + ((b * a.H + y) * a.W + x) * (Cin - a.c_low) + c0 - a.c_low +
+                          8 * part);
     }
   };
   auto store = [&]() {
@@ -1541,30 +1553,39 @@ int64_t lds_groups(const NnConvArgs& a, int th, int nt) {
   return int64_t((a.W + 15) / 16) * ((a.H + th - 1) / th) * a.B * (a.Cout / nt);
 }
 
+// The LDS-staged tile for a 3x3 layer with Cin % 32 == 0: the first shape
+// (rows x channels: 8 x 128, 8 x 64, 4 x 64, 16 x 32, 8 x 32, 4 x 32) whose
+// grid holds >= 512 work-groups, failing that >= 256, then >= 128; -1: none
+// (the register-fed kernel).
+int conv3_tile(const NnConvArgs& a) {
+  if (a.ks != 3 || a.Cin % 32 != 0) return -1;
+  for (int64_t kMin = 512; kMin >= 128; kMin /= 2) {
+    if (a.Cout % 128 == 0 && lds_groups(a, 8, 128) >= kMin) return 0;
+    if (a.Cout % 64 == 0 && lds_groups(a, 8, 64) >= kMin) return 1;
+    if (a.Cout % 64 == 0 && lds_groups(a, 4, 64) >= kMin) return 2;
+    if (lds_groups(a, 16, 32) >= kMin) return 3;
+    if (lds_groups(a, 8, 32) >= kMin) return 4;
+    if (lds_groups(a, 4, 32) >= kMin) return 5;
+  }
+  return -1;
+}
+
+bool nn_conv_takes_low(const NnConvArgs& a) {
+  return conv3_tile(a) >= 0 && a.c_low % 32 == 0 && a.H % 2 == 0 && a.W % 2 == 0;
+}
+
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
-  if (a.ks == 3 && a.Cin % 32 == 0) {
-    // the first tile shape (rows x channels) whose grid holds >= 512
-    // work-groups; failing that >= 256, then >= 128; else the register-fed
-    // kernel
-    bool done = false;
-    for (int64_t kMin = 512; kMin >= 128 && !done; kMin /= 2) {
-      done = true;
-      if (a.Cout % 128 == 0 && lds_groups(a, 8, 128) >= kMin)
-        launch_conv3_lds<4, 4, 2, 2>(a, s);
-      else if (a.Cout % 64 == 0 && lds_groups(a, 8, 64) >= kMin)
-        launch_conv3_lds<4, 2, 2, 2>(a, s);
-      else if (a.Cout % 64 == 0 && lds_groups(a, 4, 64) >= kMin)
-        launch_conv3_lds<2, 2, 2, 2>(a, s);
-      else if (lds_groups(a, 16, 32) >= kMin)
-        launch_conv3_lds<4, 2, 4, 1>(a, s);
-      else if (lds_groups(a, 8, 32) >= kMin)
-        launch_conv3_lds<2, 2, 4, 1>(a, s);
-      else if (lds_groups(a, 4, 32) >= kMin)
-        launch_conv3_lds<1, 2, 4, 1>(a, s);
-      else
-        done = false;
+  if (a.low && !nn_conv_takes_low(a)) return hipErrorInvalidValue;
+  const int tile = conv3_tile(a);
+  if (tile >= 0) {
+    switch (tile) {
+      case 0: launch_conv3_lds<4, 4, 2, 2>(a, s); break;
+      case 1: launch_conv3_lds<4, 2, 2, 2>(a, s); break;
+      case 2: launch_conv3_lds<2, 2, 2, 2>(a, s); break;
+      case 3: launch_conv3_lds<4, 2, 4, 1>(a, s); break;
+      case 4: launch_conv3_lds<2, 2, 4, 1>(a, s); break;
+      default: launch_conv3_lds<1, 2, 4, 1>(a, s); break;
     }
-    if (!done) conv_ks<3>(a, s);
   } else if (a.ks == 3) {
     conv_ks<3>(a, s);
   } else if (a.ks == 1) {
@@ -1621,6 +1642,7 @@ int64_t nn_conv_wgrad_part_floats(const NnWgradArgs& a) {
 hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
   if (a.ks != 3 && a.ks != 1) return hipErrorInvalidValue;
   const WgradPlan p = wgrad_plan(a);
+  if (a.low && (p.kind > 5 || a.c_low % 32 || a.H % 2 || a.W % 2)) return hipErrorInvalidValue;
   if (a.part && a.part_cap < nn_conv_wgrad_part_floats(a)) return hipErrorInvalidValue;
   const dim3 grid(p.gx, p.gy, p.gz), block(256);
   switch (p.kind) {

@@ -296,7 +296,10 @@ def _synthetic_planes(rng, b, h, w):
     return (t + 0.4 * rng.standard_normal(t.shape)).astype(np.float32), t.astype(np.float32)
 
 
-@pytest.mark.parametrize("shape", [(2, 16, 16), (1, 24, 40)])
+# (8, 32, 32) and (4, 64, 64): the decoder's first convolutions read their
+# concatenated input directly at levels 0 and 1 (grids large enough for the
+# LDS-staged kernel) and through a written-out concatenation at level 2
+@pytest.mark.parametrize("shape", [(2, 16, 16), (1, 24, 40), (8, 32, 32), (4, 64, 64)])
 def test_network_forward_and_gradients(nn, shape):
     import torch
     b, h, w = shape
