@@ -350,7 +350,7 @@ def resampled_refocus_bench(cpi, torch, np, dev, g32, geo, w, alphas, reps=3):
     }
 
 
-def denoiser_timing(torch, np, dev, batch=16, planes=32, h=128, w=128, reps=20):
+def denoiser_timing(torch, np, dev, batch=16, planes=32, h=128, w=128, reps=100, warmup=10):
     """Training-step and inference time of the denoiser on synthetic planes,
     with the algorithmic BF16 FLOP rate of each against the matrix-core peak."""
     import paper_2407_20692_amd.denoiser as dn
@@ -362,7 +362,7 @@ def denoiser_timing(torch, np, dev, batch=16, planes=32, h=128, w=128, reps=20):
     net = dn.Denoiser(seed=11, device=dev)
     xb, tb = x[:batch].contiguous(), t[:batch].contiguous()
     out = torch.empty_like(x)
-    for _ in range(3):
+    for _ in range(warmup):
         net.train_step(xb, tb, 1e-4)
         net.forward(x, out=out)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]

@@ -263,9 +263,10 @@ struct Pass {
     return cpi::nn_conv_takes_low(a);
   }
 
-  // input: in, or [upsample2(low) (c_low channels), in] when low is set
+  // input: in, or [upsample2(low) (c_low channels), in] when low is set, or
+  // the 2x2 max-pooling of in when pool_in
   hipError_t conv(int i, const uint16_t* in, uint16_t* out, float* out_f32, bool relu,
-                  const uint16_t* low = nullptr, int c_low = 0) const {
+                  const uint16_t* low = nullptr, int c_low = 0, bool pool_in = false) const {
     const Layer& L = kLayers[i];
     if (i == ENC1A && relu && out && !out_f32)
       return cpi::nn_in1_fwd(in, B, hl(L.level), wl(L.level), L.cin, n.wpack + pl.wf_off[i],
@@ -279,7 +280,21 @@ struct Pass {
     a.relu = relu ? 1 : 0;
     a.low = low;
     a.c_low = low ? c_low : 0;
+    a.pool_in = pool_in ? 1 : 0;
     return cpi::nn_conv(a, s);
+  }
+
+  // layer i (ReLU output into out) on the 2x2 max-pooling of the encoder
+  // output n.act[2 * lv + 1] (level lv), read in place when the kernel can,
+  // else pooled into n.pool[lv] first
+  hipError_t conv_pooled(int i, int lv, uint16_t* out) const {
+    cpi::NnConvArgs a = conv_args(i);
+    a.pool_in = 1;
+    if (cpi::nn_conv_takes_low(a)) return conv(i, n.act[2 * lv + 1], out, nullptr, true, nullptr, 0, true);
+    const int wid[4] = {32, 64, 128, 256};
+    hipError_t e = cpi::nn_maxpool(n.act[2 * lv + 1], B, hl(lv), wl(lv), wid[lv], n.pool[lv], s);
+    if (e != hipSuccess) return e;
+    return conv(i, n.pool[lv], out, nullptr, true);
   }
 
   // weight and bias gradients of layer i (on the weight-gradient stream when
@@ -288,7 +303,7 @@ struct Pass {
   // unless gin is null, on the caller's stream
   hipError_t back(int i, const uint16_t* in, const uint16_t* g, uint16_t* gin,
                   const uint16_t* mask, hipEvent_t* done = nullptr, const uint16_t* low = nullptr,
-                  int c_low = 0) const {
+                  int c_low = 0, bool pool_in = false) const {
     const Layer& L = kLayers[i];
     hipStream_t ws = s;
     hipError_t e;
@@ -314,6 +329,7 @@ struct Pass {
     w.part_cap = n.wpart_cap;
     w.low = low;
     w.c_low = low ? c_low : 0;
+    w.pool_in = pool_in ? 1 : 0;
     if (i == ENC1A && !gin)
       e = cpi::nn_in1_wgrad(in, B, w.H, w.W, L.cin, g, n.wpart, w.dw, w.db, ws);
     else
@@ -364,20 +380,23 @@ struct Pass {
 
   hipError_t forward() const {
     hipError_t e;
-#define NN_STEP(x)          \
-  if ((e = (x)) != hipSuccess) \
-  return e
-    const uint16_t* h = n.x8;
+#define NN_STEP(x)                  \
+  do {                              \
+    if ((e = (x)) != hipSuccess) return e; \
+  } while (0)
     const int wid[4] = {32, 64, 128, 256};
+    // encoder: level l's first layer reads the pooled output of level l - 1
     for (int l = 0; l < 3; ++l) {
-      NN_STEP(conv(2 * l, h, n.act[2 * l], nullptr, true));
+      if (l == 0) {
+        NN_STEP(conv(0, n.x8, n.act[0], nullptr, true));
+      } else {
+        NN_STEP(conv_pooled(2 * l, l - 1, n.act[2 * l]));
+      }
       NN_STEP(conv(2 * l + 1, n.act[2 * l], n.act[2 * l + 1], nullptr, true));
-      NN_STEP(cpi::nn_maxpool(n.act[2 * l + 1], B, hl(l), wl(l), wid[l], n.pool[l], s));
-      h = n.pool[l];
     }
-    NN_STEP(conv(MIDA, h, n.act[MIDA], nullptr, true));
+    NN_STEP(conv_pooled(MIDA, 2, n.act[MIDA]));
     NN_STEP(conv(MIDB, n.act[MIDA], n.act[MIDB], nullptr, true));
-    h = n.act[MIDB];
+    const uint16_t* h = n.act[MIDB];
     for (int l = 2; l >= 0; --l) {
       const int da = DEC3A + 2 * (2 - l);
       if (reads_concat(da, wid[l + 1])) {
@@ -416,11 +435,12 @@ struct Pass {
     // layer i's gradients from the gradient in buffer cur; its input
     // gradient (unless last) into a new buffer, which becomes cur
     auto layer = [&](int i, const uint16_t* in, const uint16_t* mask, bool input_grad,
-                     const uint16_t* low = nullptr, int c_low = 0) {
+                     const uint16_t* low = nullptr, int c_low = 0, bool pool_in = false) {
       int b = -1;
       hipError_t r = input_grad ? take(&b) : hipSuccess;
       if (r != hipSuccess) return r;
-      r = back(i, in, n.g[cur], input_grad ? n.g[b] : nullptr, mask, &busy[cur], low, c_low);
+      r = back(i, in, n.g[cur], input_grad ? n.g[b] : nullptr, mask, &busy[cur], low, c_low,
+               pool_in);
       if (input_grad) cur = b;
       return r;
     };
@@ -447,7 +467,8 @@ struct Pass {
       cur = b;
     }
     NN_STEP(layer(MIDB, n.act[MIDA], n.act[MIDA], true));
-    NN_STEP(layer(MIDA, n.pool[2], nullptr, true));
+    // the first layer of levels 1 .. 3 reads the pooled encoder output in place
+    NN_STEP(layer(MIDA, n.act[ENC3B], nullptr, true, nullptr, 0, true));
     // encoder, level 2 down to 0: cur holds the gradient of the pooled output
     for (int l = 2; l >= 0; --l) {
       uint16_t* yb = n.act[2 * l + 1];
@@ -456,7 +477,11 @@ struct Pass {
       NN_STEP(cpi::nn_pool_bwd_add(yb, B, hl(l), wl(l), wid[l], n.g[cur], n.skip[l], n.g[b], s));
       cur = b;
       NN_STEP(layer(2 * l + 1, n.act[2 * l], n.act[2 * l], true));
-      NN_STEP(layer(2 * l, l == 0 ? n.x8 : n.pool[l - 1], nullptr, l != 0));
+      if (l == 0) {
+        NN_STEP(layer(0, n.x8, nullptr, false));
+      } else {
+        NN_STEP(layer(2 * l, n.act[2 * l - 1], nullptr, true, nullptr, 0, true));
+      }
     }
     if (side) {
       const hipEvent_t joined = ev[(*nev)++];

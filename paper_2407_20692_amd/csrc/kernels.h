@@ -227,11 +227,15 @@ struct NnConvArgs {
   // == 0.  Only the LDS-staged 3x3 kernels take it (nn_conv_takes_low).
   const uint16_t* low = nullptr;
   int c_low = 0;
+  // Pooled input: if set (low unset), in is [B][2H][2W][Cin] and the input
+  // is its 2x2 max-pooling.  Also LDS-staged 3x3 kernels only.
+  int pool_in = 0;
 };
 // Forward convolution (zero padding, ks odd); the backward-data
 // convolution is the same call on dY with the flipped, transposed weights.
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s);
-// whether nn_conv runs this shape on a kernel that reads a concatenated input
+// whether nn_conv runs this shape on a kernel that reads a concatenated or
+// pooled input in place
 bool nn_conv_takes_low(const NnConvArgs& a);
 
 struct NnWgradArgs {
@@ -246,9 +250,11 @@ struct NnWgradArgs {
   float* part = nullptr;
   int64_t part_cap = 0;            // floats available at part
   int B = 0, H = 0, W = 0, Cin = 0, Cout = 0, ks = 0, Kpad = 0;
-  // concatenated input as in NnConvArgs (3x3 layers with Cin % 32 == 0 only)
+  // concatenated or pooled input as in NnConvArgs (3x3 layers with
+  // Cin % 32 == 0 only)
   const uint16_t* low = nullptr;
   int c_low = 0;
+  int pool_in = 0;
 };
 hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s);
 // floats of partial sums nn_conv_wgrad uses for this shape (the part buffer)

@@ -32,6 +32,24 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
+// 2x2 max-pooling of 8 channels: elementwise maximum of the four 16-byte
+// pieces at p, p + dx, p + dy, p + dy + dx, in that order (as k_maxpool)
+__device__ __forceinline__ uint4 pool4(const uint16_t* p, int64_t dx, int64_t dy) {
+  const uint4 v[4] = {*reinterpret_cast<const uint4*>(p), *reinterpret_cast<const uint4*>(p + dx),
+                      *reinterpret_cast<const uint4*>(p + dy),
+                      *reinterpret_cast<const uint4*>(p + dy + dx)};
+  uint4 o;
+  uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    float m = bf2f(reinterpret_cast<const uint16_t*>(&v[0])[e]);
+#pragma unroll
+    for (int q = 1; q < 4; ++q) m = fmaxf(m, bf2f(reinterpret_cast<const uint16_t*>(&v[q])[e]));
+    oh[e] = f2bf(m);
+  }
+  return o;
+}
+
 unsigned grid1(int64_t n, int threads = 256) {
   int64_t g = (n + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -205,12 +223,18 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
         const int px = q >> 2, part = q & 3;
         const int hy = px / HW, hx = px % HW;
         const int yy = y0 + hy - 1, xx = x0 + hx - 1;
-        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-          v = c0 < a.c_low
-                  ? *reinterpret_cast<const uint4*>(
-                        limg + (int64_t(yy >> 1) * Wl + (xx >> 1)) * a.c_low + c0 + 8 * part)
-                  : *reinterpret_cast<const uint4*>(img + (int64_t(yy) * a.W + xx) * Cs + c0 -
-                                                    a.c_low + 8 * part);
+        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+          if (a.pool_in)
+            v = pool4(a.in + ((int64_t(b) * 2 * a.H + 2 * yy) * 2 * a.W + 2 * xx) * Cin + c0 +
+                          8 * part,
+                      Cin, int64_t(2) * a.W * Cin);
+          else
+            v = c0 < a.c_low
+                    ? *reinterpret_cast<const uint4*>(
+                          limg + (int64_t(yy >> 1) * Wl + (xx >> 1)) * a.c_low + c0 + 8 * part)
+                    : *reinterpret_cast<const uint4*>(img + (int64_t(yy) * a.W + xx) * Cs + c0 -
+                                                      a.c_low + 8 * part);
+        }
       }
       hreg[u] = v;
     }
@@ -559,7 +583,10 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(NnWgradArgs a) {
       const int hp = c >> 2, part = c & 3;
       const int y = y0 + hp / HW - 1, x = x0 + hp % HW - 1;
       xv[u] = make_uint4(0, 0, 0, 0);
-      if (c < HP * 4 && y >= 0 && y < a.H && x >= 0 && x < a.W)
+      if (c < HP * 4 && y >= 0 && y < a.H && x >= 0 && x < a.W && a.pool_in)
+        xv[u] = pool4(a.in + ((b * 2 * a.H + 2 * y) * 2 * a.W + 2 * x) * Cin + c0 + 8 * part, Cin,
+                      int64_t(2) * a.W * Cin);
+      else if (c < HP * 4 && y >= 0 && y < a.H && x >= 0 && x < a.W)
         xv[u] = c0 < a.c_low
                     ? *reinterpret_cast<const uint4*>(
                           a.low + ((b * (a.H / 2) + (y >> 1)) * (a.W / 2) + (x >> 1)) * a.c_low +
@@ -1571,11 +1598,13 @@ int conv3_tile(const NnConvArgs& a) {
 }
 
 bool nn_conv_takes_low(const NnConvArgs& a) {
-  return conv3_tile(a) >= 0 && a.c_low % 32 == 0 && a.H % 2 == 0 && a.W % 2 == 0;
+  if (a.low && a.pool_in) return false;
+  if (a.low && (a.c_low % 32 || a.H % 2 || a.W % 2)) return false;
+  return conv3_tile(a) >= 0;
 }
 
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
-  if (a.low && !nn_conv_takes_low(a)) return hipErrorInvalidValue;
+  if ((a.low || a.pool_in) && !nn_conv_takes_low(a)) return hipErrorInvalidValue;
   const int tile = conv3_tile(a);
   if (tile >= 0) {
     switch (tile) {
@@ -1642,7 +1671,9 @@ int64_t nn_conv_wgrad_part_floats(const NnWgradArgs& a) {
 hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
   if (a.ks != 3 && a.ks != 1) return hipErrorInvalidValue;
   const WgradPlan p = wgrad_plan(a);
-  if (a.low && (p.kind > 5 || a.c_low % 32 || a.H % 2 || a.W % 2)) return hipErrorInvalidValue;
+  if ((a.low || a.pool_in) &&
+      (p.kind > 5 || (a.low && a.pool_in) || (a.low && (a.c_low % 32 || a.H % 2 || a.W % 2))))
+    return hipErrorInvalidValue;
   if (a.part && a.part_cap < nn_conv_wgrad_part_floats(a)) return hipErrorInvalidValue;
   const dim3 grid(p.gx, p.gy, p.gz), block(256);
   switch (p.kind) {
