@@ -227,6 +227,16 @@ hipError_t side_resources(const void* ws, hipStream_t* side, hipEvent_t** ev) {
 }
 
 // ---- network passes --------------------------------------------------------------
+// The input gradient of a decoder level's first layer, split as its input
+// [upsample2(low) (c1 channels), skip]: dlow (summed over the four copies,
+// zeroed where mask <= 0) and dskip.
+struct GradSplit {
+  uint16_t* dlow;
+  uint16_t* dskip;
+  const uint16_t* mask;
+  int c1;
+};
+
 struct Pass {
   const Params& pl;
   const Net& n;
@@ -301,9 +311,11 @@ struct Pass {
   // there is one: it waits for the caller's stream up to here, and *done is
   // recorded after it); input gradient into gin (masked by `mask` if given)
   // unless gin is null, on the caller's stream
+  // With split, gin is scratch for the whole input gradient when the
+  // convolution cannot write it split itself.
   hipError_t back(int i, const uint16_t* in, const uint16_t* g, uint16_t* gin,
                   const uint16_t* mask, hipEvent_t* done = nullptr, const uint16_t* low = nullptr,
-                  int c_low = 0, bool pool_in = false) const {
+                  int c_low = 0, bool pool_in = false, const GradSplit* split = nullptr) const {
     const Layer& L = kLayers[i];
     hipStream_t ws = s;
     hipError_t e;
@@ -352,6 +364,19 @@ struct Pass {
     a.Cout = L.cin;
     a.ks = L.ks;
     a.Kpad = pl.kpad_t[i];
+    if (split) {
+      cpi::NnConvArgs sa = a;
+      sa.out = nullptr;
+      sa.mask = nullptr;
+      sa.dlow = split->dlow;
+      sa.dskip = split->dskip;
+      sa.low_mask = split->mask;
+      sa.c1 = split->c1;
+      if (cpi::nn_conv_takes_split(sa)) return cpi::nn_conv(sa, s);
+      if ((e = cpi::nn_conv(a, s)) != hipSuccess) return e;
+      return cpi::nn_upcat_grad(gin, B, a.H / 2, a.W / 2, split->c1, a.Cout - split->c1, split->mask,
+                                split->dlow, split->dskip, s);
+    }
     return cpi::nn_conv(a, s);
   }
 
@@ -458,13 +483,15 @@ struct Pass {
     for (int l = 0; l < 3; ++l) {
       const int da = DEC1A - 2 * l;
       NN_STEP(layer(da + 1, n.act[da], n.act[da], true));
-      // the input [upsampled level l + 1 output, encoder output] read as such
-      NN_STEP(layer(da, n.act[2 * l + 1], nullptr, true, below[l], wid[l + 1]));
-      int b;
-      NN_STEP(take(&b));
-      NN_STEP(cpi::nn_upcat_grad(n.g[cur], B, hl(l + 1), wl(l + 1), wid[l + 1], wid[l], below[l],
-                                 n.g[b], n.skip[l], s));
-      cur = b;
+      // the input [upsampled level l + 1 output, encoder output] read as
+      // such; its gradient written split into dlow (level l + 1) and skip[l]
+      int bs, bl;
+      NN_STEP(take(&bs));
+      NN_STEP(take(&bl));
+      const GradSplit sp{n.g[bl], n.skip[l], below[l], wid[l + 1]};
+      NN_STEP(back(da, n.act[2 * l + 1], n.g[cur], n.g[bs], nullptr, &busy[cur], below[l],
+                   wid[l + 1], false, &sp));
+      cur = bl;
     }
     NN_STEP(layer(MIDB, n.act[MIDA], n.act[MIDA], true));
     // the first layer of levels 1 .. 3 reads the pooled encoder output in place

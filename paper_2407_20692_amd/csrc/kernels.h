@@ -230,6 +230,16 @@ struct NnConvArgs {
   // Pooled input: if set (low unset), in is [B][2H][2W][Cin] and the input
   // is its 2x2 max-pooling.  Also LDS-staged 3x3 kernels only.
   int pool_in = 0;
+  // Split output (instead of out, out_f32, bias, ReLU and mask): output
+  // channels [0, c1) summed over each 2x2 pixel window (of the values
+  // rounded to bfloat16, as ((00 + 01) + (10 + 11))) into dlow
+  // [B][H/2][W/2][c1], zeroed where low_mask <= 0 (nullable); channels
+  // [c1, Cout) into dskip [B][H][W][Cout - c1].  The gradient of
+  // [upsample2(low), skip] in one pass (nn_conv_takes_split).
+  uint16_t* dlow = nullptr;
+  uint16_t* dskip = nullptr;
+  const uint16_t* low_mask = nullptr;
+  int c1 = 0;
 };
 // Forward convolution (zero padding, ks odd); the backward-data
 // convolution is the same call on dY with the flipped, transposed weights.
@@ -237,6 +247,8 @@ hipError_t nn_conv(const NnConvArgs& a, hipStream_t s);
 // whether nn_conv runs this shape on a kernel that reads a concatenated or
 // pooled input in place
 bool nn_conv_takes_low(const NnConvArgs& a);
+// whether nn_conv can write this shape's output split (dlow / dskip)
+bool nn_conv_takes_split(const NnConvArgs& a);
 
 struct NnWgradArgs {
   const uint16_t* in = nullptr;    // [B][H][W][Cin] layer input

@@ -173,8 +173,11 @@ __global__ __launch_bounds__(256) void k_conv(NnConvArgs a) {
 // (KY = 1 or 3) the weights of their taps for the NT channels are staged
 // beside them, and those taps run from LDS.  Pixel and weight rows are padded
 // to 40 elements (80 bytes) to spread LDS banks.
-template <int TM, int TN, int WM, int WN, int KY>
+// MODE: 0 input and output as stored; 1 input read through the 2x2
+// max-pool; 2 output split (dlow / dskip); 3 input concatenated (low).
+template <int TM, int TN, int WM, int WN, int KY, int MODE>
 __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
+  constexpr bool POOL = MODE == 1, SPLIT = MODE == 2, CAT = MODE == 3;
   constexpr int TH = WM * TM, TW = 16, NT = WN * TN * 16;
   constexpr int HW = TW + 2, HH = TH + 2;
   constexpr int PITCH = 40;  // elements per staged pixel / weight row
@@ -224,12 +227,12 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
         const int hy = px / HW, hx = px % HW;
         const int yy = y0 + hy - 1, xx = x0 + hx - 1;
         if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
-          if (a.pool_in)
+          if constexpr (POOL)
             v = pool4(a.in + ((int64_t(b) * 2 * a.H + 2 * yy) * 2 * a.W + 2 * xx) * Cin + c0 +
                           8 * part,
                       Cin, int64_t(2) * a.W * Cin);
           else
-            v = c0 < a.c_low
+            v = (CAT && c0 < a.c_low)
                     ? *reinterpret_cast<const uint4*>(
                           limg + (int64_t(yy >> 1) * Wl + (xx >> 1)) * a.c_low + c0 + 8 * part)
                     : *reinterpret_cast<const uint4*>(img + (int64_t(yy) * a.W + xx) * Cs + c0 -
@@ -316,6 +319,57 @@ __global__ __launch_bounds__(256) void k_conv3_lds(NnConvArgs a) {
   // elements (column r of row wm*TM + i, channels 4g .. 4g + 3 of tile j):
   // four consecutive channels of one pixel per lane, stored together
   const int xx = x0 + r;
+  if constexpr (SPLIT) {
+    // split output: the 2x2 window of rows (i, i + 1) (TM even) and columns
+    // (r, r ^ 1) (lanes r and r ^ 1)
+    static_assert(TM % 2 == 0, "split output needs an even number of rows per wave");
+    {
+      const bool to_low = n0 < a.c1;  // the whole tile is on one side (c1 % NT == 0)
+      const int C2 = a.Cout - a.c1;
+#pragma unroll
+      for (int i = 0; i < TM; i += 2) {
+        const int yy = y0 + wm * TM + i;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int n = n0 + wn * 16 * TN + 16 * j + 4 * g;
+          if (!to_low) {
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+              if (yy + di >= a.H || xx >= a.W) continue;
+              uint2 ov;
+              ov.x = uint32_t(f2bf(acc[i + di][j][0])) | (uint32_t(f2bf(acc[i + di][j][1])) << 16);
+              ov.y = uint32_t(f2bf(acc[i + di][j][2])) | (uint32_t(f2bf(acc[i + di][j][3])) << 16);
+              *reinterpret_cast<uint2*>(
+                  a.dskip + ((int64_t(b) * a.H + yy + di) * a.W + xx) * C2 + (n - a.c1)) = ov;
+            }
+          } else {
+            float sv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float v00 = bf2f(f2bf(acc[i][j][e])), v10 = bf2f(f2bf(acc[i + 1][j][e]));
+              const float v01 = __shfl_xor(v00, 1), v11 = __shfl_xor(v10, 1);
+              sv[e] = (v00 + v01) + (v10 + v11);
+            }
+            if ((r & 1) == 0 && yy < a.H && xx < a.W) {
+              const int64_t lo =
+                  ((int64_t(b) * (a.H / 2) + yy / 2) * (a.W / 2) + xx / 2) * a.c1 + n;
+              uint2 mk = make_uint2(0x3F803F80u, 0x3F803F80u);  // 1.0 in every element
+              if (a.low_mask) mk = *reinterpret_cast<const uint2*>(a.low_mask + lo);
+              const uint16_t* mh = reinterpret_cast<const uint16_t*>(&mk);
+              uint16_t o[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) o[e] = bf2f(mh[e]) > 0.0f ? f2bf(sv[e]) : uint16_t(0);
+              uint2 ov;
+              ov.x = uint32_t(o[0]) | (uint32_t(o[1]) << 16);
+              ov.y = uint32_t(o[2]) | (uint32_t(o[3]) << 16);
+              *reinterpret_cast<uint2*>(a.dlow + lo) = ov;
+            }
+          }
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int yy = y0 + wm * TM + i;
@@ -1571,8 +1625,19 @@ void launch_conv3_lds(const NnConvArgs& a, hipStream_t s) {
   constexpr int TH = WM * TM, NT = WN * TN * 16;
   constexpr int KY = NT == 64 ? 3 : 1;
   const int64_t blocks = int64_t((a.W + 15) / 16) * ((a.H + TH - 1) / TH) * a.B;
-  hipLaunchKernelGGL((k_conv3_lds<TM, TN, WM, WN, KY>),
-                     dim3(unsigned(blocks), unsigned(a.Cout / NT)), dim3(256), 0, s, a);
+  const dim3 grid(unsigned(blocks), unsigned(a.Cout / NT));
+  if constexpr (TM % 2 == 0) {
+    if (a.dlow) {
+      hipLaunchKernelGGL((k_conv3_lds<TM, TN, WM, WN, KY, 2>), grid, dim3(256), 0, s, a);
+      return;
+    }
+  }
+  if (a.pool_in)
+    hipLaunchKernelGGL((k_conv3_lds<TM, TN, WM, WN, KY, 1>), grid, dim3(256), 0, s, a);
+  else if (a.low)
+    hipLaunchKernelGGL((k_conv3_lds<TM, TN, WM, WN, KY, 3>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_conv3_lds<TM, TN, WM, WN, KY, 0>), grid, dim3(256), 0, s, a);
 }
 
 // Work-groups of the LDS-staged 3x3 kernel for a tile of TH rows and NT channels.
@@ -1597,6 +1662,16 @@ int conv3_tile(const NnConvArgs& a) {
   return -1;
 }
 
+bool nn_conv_takes_split(const NnConvArgs& a) {
+  if (a.low || a.pool_in || a.out || a.out_f32 || a.bias || a.relu || a.mask) return false;
+  if (a.H % 2 || a.W % 2 || a.c1 <= 0 || a.c1 >= a.Cout) return false;
+  // tiles 0 .. 4 have an even number of rows per wave; tile channel widths
+  // 128, 64, 64, 32, 32 must divide c1
+  const int tile = conv3_tile(a);
+  static const int nt[5] = {128, 64, 64, 32, 32};
+  return tile >= 0 && tile <= 4 && a.c1 % nt[tile] == 0 && (a.Cout - a.c1) % 8 == 0;
+}
+
 bool nn_conv_takes_low(const NnConvArgs& a) {
   if (a.low && a.pool_in) return false;
   if (a.low && (a.c_low % 32 || a.H % 2 || a.W % 2)) return false;
@@ -1605,6 +1680,7 @@ bool nn_conv_takes_low(const NnConvArgs& a) {
 
 hipError_t nn_conv(const NnConvArgs& a, hipStream_t s) {
   if ((a.low || a.pool_in) && !nn_conv_takes_low(a)) return hipErrorInvalidValue;
+  if ((a.dlow || a.dskip) && (!a.dlow || !a.dskip || !nn_conv_takes_split(a))) return hipErrorInvalidValue;
   const int tile = conv3_tile(a);
   if (tile >= 0) {
     switch (tile) {
