@@ -793,10 +793,12 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(NnWgradArgs a) {
 // slot + 16, ... of column l in that order, and thread e < 64 then adds the
 // 16 slot sums of element e in slot order: a fixed order, whatever the
 // scheduling.
+// scx > 0: the nw weight slots are dense (n, tap) pairs of a 3x3 layer with
+// one input channel used of scx, added to dw[n][tap * scx].
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int splits,
                                                       int64_t nw, int cout,
                                                       float* __restrict__ dw,
-                                                      float* __restrict__ db) {
+                                                      float* __restrict__ db, int scx = 0) {
   __shared__ v4f red[256];
   const int t = threadIdx.x, l = t & 15, slot = t >> 4;
   const int64_t stride = nw + cout, n = db ? stride : nw, st4 = stride / 4;
@@ -824,10 +826,13 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
       const float* rf = reinterpret_cast<const float*>(red);
       float tot = 0.0f;
       for (int k = 0; k < 16; ++k) tot += rf[4 * (16 * k + (t >> 2)) + (t & 3)];
-      if (i0 + t < nw)
-        dw[i0 + t] += tot;
+      const int64_t i = i0 + t;
+      if (i >= nw)
+        db[i - nw] += tot;
+      else if (scx > 0)
+        dw[(i / 9) * 9 * scx + (i % 9) * scx] += tot;
       else
-        db[i0 + t - nw] += tot;
+        dw[i] += tot;
     }
     __syncthreads();
   }
@@ -1109,22 +1114,22 @@ __global__ __launch_bounds__(256) void k_in1_fwd(const uint16_t* __restrict__ x,
   if (t < 32) ws[9 * 32 + t] = bias ? bias[t] : 0.0f;
   __syncthreads();
   const v4f* w4 = reinterpret_cast<const v4f*>(ws);
-  const int64_t P = int64_t(B) * H * W;
+  const int P = B * H * W;  // < 2^26 (the network's shape check)
   // two pixels per thread: p and p + half of the grid's stride
-  const int64_t stride = int64_t(gridDim.x) * 512;
-  for (int64_t p0 = int64_t(blockIdx.x) * 512 + t; p0 < P; p0 += stride) {
-    int64_t pp[2] = {p0, p0 + 256};
+  const int stride = gridDim.x * 512;
+  for (int p0 = blockIdx.x * 512 + t; p0 < P; p0 += stride) {
+    int pp[2] = {p0, p0 + 256};
     float v[2][9];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int64_t p = pp[u] < P ? pp[u] : p0;
-      const int xx = int(p % W), yy = int((p / W) % H);
-      const int64_t img = p - (int64_t(yy) * W + xx);
+      const int p = pp[u] < P ? pp[u] : p0;
+      const int row = p / W, xx = p - row * W, yy = row % H;
+      const int img = p - (yy * W + xx);
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const int y = yy + tap / 3 - 1, xc = xx + tap % 3 - 1;
         v[u][tap] = (y >= 0 && y < H && xc >= 0 && xc < W)
-                        ? bf2f(x[(img + int64_t(y) * W + xc) * cx])
+                        ? bf2f(x[int64_t(img + y * W + xc) * cx])
                         : 0.0f;
       }
     }
@@ -1156,7 +1161,7 @@ __global__ __launch_bounds__(256) void k_in1_fwd(const uint16_t* __restrict__ x,
           oh[e] = f2bf(ra < 0.0f ? 0.0f : ra);
           oh[4 + e] = f2bf(rb < 0.0f ? 0.0f : rb);
         }
-        *reinterpret_cast<uint4*>(out + pp[u] * 32 + 8 * q) = o;
+        *reinterpret_cast<uint4*>(out + int64_t(pp[u]) * 32 + 8 * q) = o;
       }
     }
   }
@@ -1164,37 +1169,36 @@ __global__ __launch_bounds__(256) void k_in1_fwd(const uint16_t* __restrict__ x,
 
 // Weight and bias gradients of that layer: dW[n][tap * cx] = sum over pixels
 // of dy[p][n] x[p + tap] (channel 0) and db[n] = sum of dy[p][n], as one row
-// of partial sums per work-group (row layout of the weight-gradient partial
-// buffer: 32 * 9 * cx weight slots, zero for input channels > 0, then 32
-// bias slots).  Thread t takes channels 8 (t & 3) .. + 7 of every 64th pixel
-// of the work-group's range; lanes of one channel group are summed with
-// shuffles, then the four waves in order.
+// of 320 partial sums per work-group (n * 9 + tap, then the 32 bias slots).
+// Thread t takes channels 8 (t & 3) .. + 7 of every 64th pixel of the
+// work-group's range; the 64 threads of one channel group are then summed
+// through LDS in thread order (two rounds of 40 of the 80 sums).
 __global__ __launch_bounds__(256) void k_in1_wgrad(const uint16_t* __restrict__ x, int B, int H,
                                                    int W, int cx, const uint16_t* __restrict__ dy,
                                                    float* __restrict__ part) {
-  __shared__ float red[4][4][80];
+  __shared__ float red[40][257];
   __shared__ float fin[4 * 80];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x;
   const int q = t & 3;
-  const int64_t P = int64_t(B) * H * W;
-  const int64_t per = (P + gridDim.x - 1) / gridDim.x;
-  const int64_t plo = int64_t(blockIdx.x) * per;
-  const int64_t phi = plo + per < P ? plo + per : P;
+  const int P = B * H * W;  // < 2^26 (the network's shape check)
+  const int per = (P + gridDim.x - 1) / gridDim.x;
+  const int plo = blockIdx.x * per;
+  const int phi = plo + per < P ? plo + per : P;
   float acc[80];
 #pragma unroll
   for (int k = 0; k < 80; ++k) acc[k] = 0.0f;
 #pragma unroll 4
-  for (int64_t p = plo + (t >> 2); p < phi; p += 64) {
-    const int xx = int(p % W), yy = int((p / W) % H);
-    const int64_t img = p - (int64_t(yy) * W + xx);
+  for (int p = plo + (t >> 2); p < phi; p += 64) {
+    const int row = p / W, xx = p - row * W, yy = row % H;
+    const int img = p - (yy * W + xx);
     float v[9];
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int y = yy + tap / 3 - 1, xc = xx + tap % 3 - 1;
-      v[tap] = (y >= 0 && y < H && xc >= 0 && xc < W) ? bf2f(x[(img + int64_t(y) * W + xc) * cx])
+      v[tap] = (y >= 0 && y < H && xc >= 0 && xc < W) ? bf2f(x[int64_t(img + y * W + xc) * cx])
                                                       : 0.0f;
     }
-    const uint4 d4 = *reinterpret_cast<const uint4*>(dy + p * 32 + 8 * q);
+    const uint4 d4 = *reinterpret_cast<const uint4*>(dy + int64_t(p) * 32 + 8 * q);
     const uint16_t* dh = reinterpret_cast<const uint16_t*>(&d4);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -1204,36 +1208,27 @@ __global__ __launch_bounds__(256) void k_in1_wgrad(const uint16_t* __restrict__ 
       acc[72 + e] += d;
     }
   }
-  // lanes 4 k + q, k = 0 .. 15, share channel group q
+  // threads t = 4 m + q (m = 0 .. 63) share channel group q: sum 40 of the
+  // 80 accumulators per round, over m in order
 #pragma unroll
-  for (int k = 0; k < 80; ++k) {
-    float a = acc[k];
-    a += __shfl_xor(a, 4);
-    a += __shfl_xor(a, 8);
-    a += __shfl_xor(a, 16);
-    a += __shfl_xor(a, 32);
-    acc[k] = a;
-  }
-  if (lane < 4)
+  for (int h = 0; h < 2; ++h) {
 #pragma unroll
-    for (int k = 0; k < 80; ++k) red[wave][lane][k] = acc[k];
-  __syncthreads();
-  for (int k = t; k < 320; k += 256)
-    fin[k] = ((red[0][k / 80][k % 80] + red[1][k / 80][k % 80]) + red[2][k / 80][k % 80]) +
-             red[3][k / 80][k % 80];
-  __syncthreads();
-  const int K = 9 * cx, nw = 32 * K;
-  float* row = part + int64_t(blockIdx.x) * (nw + 32);
-  for (int j = t; j < nw + 32; j += 256) {
-    float val = 0.0f;
-    if (j >= nw) {
-      const int n = j - nw;
-      val = fin[(n >> 3) * 80 + 72 + (n & 7)];
-    } else {
-      const int n = j / K, k = j - n * K;
-      if (k % cx == 0) val = fin[(n >> 3) * 80 + (n & 7) * 9 + k / cx];
+    for (int k = 0; k < 40; ++k) red[k][t] = acc[40 * h + k];
+    __syncthreads();
+    for (int o = t; o < 160; o += 256) {
+      const int k = o >> 2, qq = o & 3;
+      float sum = 0.0f;
+      for (int m = 0; m < 64; ++m) sum += red[k][4 * m + qq];
+      fin[qq * 80 + 40 * h + k] = sum;
     }
-    __builtin_nontemporal_store(val, &row[j]);
+    __syncthreads();
+  }
+  float* out = part + int64_t(blockIdx.x) * 320;
+  for (int j = t; j < 320; j += 256) {
+    const int n = j < 288 ? j / 9 : j - 288;
+    const float val = j < 288 ? fin[(n >> 3) * 80 + (n & 7) * 9 + (j - 9 * n)]
+                              : fin[(n >> 3) * 80 + 72 + (n & 7)];
+    __builtin_nontemporal_store(val, &out[j]);
   }
 }
 
@@ -1247,11 +1242,11 @@ __global__ __launch_bounds__(256) void k_pool_bwd_add(const uint16_t* __restrict
                                                       const uint16_t* __restrict__ skip,
                                                       uint16_t* __restrict__ din) {
   const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
-  const int64_t n = int64_t(B) * Ho * Wo * C8;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    const int c8 = int(i % C8);
-    const int64_t p = i / C8;
-    const int x = int(p % Wo), y = int((p / Wo) % Ho), b = int(p / (int64_t(Wo) * Ho));
+  // B * H * W <= 2^26 and C <= 256 (the network's shapes): 32-bit indices
+  const int n = B * Ho * Wo * C8;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int p = i / C8, c8 = i - p * C8;
+    const int q = p / Wo, x = p - q * Wo, b = q / Ho, y = q - b * Ho;
     const int64_t base = ((int64_t(b) * H + 2 * y) * W + 2 * x) * C + 8 * c8;
     const int64_t off[4] = {0, C, int64_t(W) * C, int64_t(W) * C + C};
     uint4 v[4], sk[4];
@@ -1260,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_pool_bwd_add(const uint16_t* __restrict
       v[q] = *reinterpret_cast<const uint4*>(in + base + off[q]);
       sk[q] = *reinterpret_cast<const uint4*>(skip + base + off[q]);
     }
-    const uint4 dv = *reinterpret_cast<const uint4*>(dout + p * C + 8 * c8);
+    const uint4 dv = *reinterpret_cast<const uint4*>(dout + int64_t(p) * C + 8 * c8);
     const uint16_t* vh[4] = {reinterpret_cast<const uint16_t*>(&v[0]),
                              reinterpret_cast<const uint16_t*>(&v[1]),
                              reinterpret_cast<const uint16_t*>(&v[2]),
@@ -1903,6 +1898,7 @@ hipError_t nn_denormalize(const float* x, int C, const float* res, const float* 
 
 hipError_t nn_in1_fwd(const uint16_t* x, int B, int H, int W, int cx, const uint16_t* wk, int kpad,
                       const float* bias, uint16_t* out, hipStream_t s) {
+  if (int64_t(B) * H * W >= (int64_t(1) << 30)) return hipErrorInvalidValue;  // 32-bit indices
   hipLaunchKernelGGL(k_in1_fwd, dim3(grid1((int64_t(B) * H * W + 1) / 2)), dim3(256), 0, s, x, B,
                      H, W, cx, wk, kpad, bias, out);
   return hipGetLastError();
@@ -1917,16 +1913,17 @@ int nn_in1_wgrad_groups(int64_t P) {
 
 hipError_t nn_in1_wgrad(const uint16_t* x, int B, int H, int W, int cx, const uint16_t* dy,
                         float* part, float* dw, float* db, hipStream_t s) {
+  if (int64_t(B) * H * W >= (int64_t(1) << 30)) return hipErrorInvalidValue;  // 32-bit indices
   const int g = nn_in1_wgrad_groups(int64_t(B) * H * W);
   hipLaunchKernelGGL(k_in1_wgrad, dim3(unsigned(g)), dim3(256), 0, s, x, B, H, W, cx, dy, part);
-  const int64_t nw = int64_t(32) * 9 * cx;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(unsigned((nw + 32 + 63) / 64)), dim3(256), 0, s, part, g,
-                     nw, 32, dw, db);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(5), dim3(256), 0, s, part, g, int64_t(288), 32, dw, db,
+                     cx);
   return hipGetLastError();
 }
 
 hipError_t nn_pool_bwd_add(const uint16_t* in, int B, int H, int W, int C, const uint16_t* dout,
                            const uint16_t* skip, uint16_t* din, hipStream_t s) {
+  if (int64_t(B) * H * W * C >= (int64_t(1) << 31)) return hipErrorInvalidValue;  // 32-bit indices
   hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid1(int64_t(B) * (H / 2) * (W / 2) * (C / 8))),
                      dim3(256), 0, s, in, B, H, W, C, dout, skip, din);
   return hipGetLastError();
