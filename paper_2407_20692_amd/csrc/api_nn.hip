@@ -121,8 +121,10 @@ struct Net {
   uint16_t* skip[3];
   uint16_t* wpack;
   float* grads;
-  float* wpart;      // partial sums of the weight gradients' pixel splits
-  int64_t wpart_cap; // floats at wpart
+  float* wpart[2];   // partial sums of the weight gradients' pixel splits (two,
+                     // used in turn, so one layer's reduction can overlap the
+                     // next layer's kernel)
+  int64_t wpart_cap; // floats at each wpart
   size_t bytes;
 };
 
@@ -175,7 +177,7 @@ Net plan_net(uint8_t* base, int B, int H, int W, bool train) {
       if (f > cap) cap = f;
     }
     n.wpart_cap = cap;
-    n.wpart = static_cast<float*>(take(size_t(cap) * 4));
+    for (int k = 0; k < 2; ++k) n.wpart[k] = static_cast<float*>(take(size_t(cap) * 4));
   }
   n.bytes = off;
   return n;
@@ -189,23 +191,25 @@ cpi_status check_net_shape(int B, int H, int W) {
   return CPI_OK;
 }
 
-// ---- weight-gradient stream ------------------------------------------------------
+// ---- weight-gradient streams -----------------------------------------------------
 // The backward pass runs each layer's weight gradient on a second stream of
-// the device (one per device, made at first use, default priority), so that
-// it overlaps the chain of input gradients on the caller's stream.  Events
-// order the two: each host thread keeps its own events per device.
-constexpr int kSideEvents = 40;
+// the device, and the reduction of its partial sums on a third (both one per
+// device, made at first use, default priority), so that they overlap the
+// chain of input gradients on the caller's stream and each other.  Events
+// order the streams: each host thread keeps its own events per device.
+constexpr int kSideEvents = 96;
 std::mutex g_side_mu;
 hipStream_t g_side_stream[64] = {};
+hipStream_t g_red_stream[64] = {};
 thread_local hipEvent_t t_side_ev[64][kSideEvents] = {};
 
-hipError_t side_resources(const void* ws, hipStream_t* side, hipEvent_t** ev) {
+hipError_t side_resources(const void* ws, hipStream_t* side, hipStream_t* red, hipEvent_t** ev) {
   hipPointerAttribute_t at;
   hipError_t e = hipPointerGetAttributes(&at, ws);
   if (e != hipSuccess) return e;
   const int dev = at.device;
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  if (!g_side_stream[dev] || !t_side_ev[dev][kSideEvents - 1]) {
+  if (!g_side_stream[dev] || !g_red_stream[dev] || !t_side_ev[dev][kSideEvents - 1]) {
     int cur = 0;
     e = hipGetDevice(&cur);
     if (e != hipSuccess) return e;
@@ -214,6 +218,8 @@ hipError_t side_resources(const void* ws, hipStream_t* side, hipEvent_t** ev) {
     {
       std::lock_guard<std::mutex> lk(g_side_mu);
       if (!g_side_stream[dev]) e = hipStreamCreateWithFlags(&g_side_stream[dev], hipStreamNonBlocking);
+      if (e == hipSuccess && !g_red_stream[dev])
+        e = hipStreamCreateWithFlags(&g_red_stream[dev], hipStreamNonBlocking);
     }
     for (int k = 0; k < kSideEvents && e == hipSuccess; ++k)
       if (!t_side_ev[dev][k]) e = hipEventCreateWithFlags(&t_side_ev[dev][k], hipEventDisableTiming);
@@ -222,6 +228,7 @@ hipError_t side_resources(const void* ws, hipStream_t* side, hipEvent_t** ev) {
     if (e2 != hipSuccess) return e2;
   }
   *side = g_side_stream[dev];
+  *red = g_red_stream[dev];
   *ev = t_side_ev[dev];
   return hipSuccess;
 }
@@ -244,8 +251,11 @@ struct Pass {
   int B, H, W;
   hipStream_t s;
   hipStream_t side = nullptr;  // weight-gradient stream, or null: all on s
-  hipEvent_t* ev = nullptr;    // kSideEvents events for ordering s and side
+  hipStream_t red = nullptr;   // their reductions' stream (set with side)
+  hipEvent_t* ev = nullptr;    // kSideEvents events for ordering the streams
   int* nev = nullptr;          // events used so far
+  hipEvent_t* pfree = nullptr; // [2]: the reduction that last read n.wpart[k], or null
+  int* pnext = nullptr;        // the partial buffer the next weight gradient takes
   float* loss = nullptr;       // the loss is added here by backward()
 
   int hl(int level) const { return H >> level; }
@@ -337,19 +347,35 @@ struct Pass {
     w.ks = L.ks;
     w.Kpad = pl.kpad[i];
     w.db = n.grads + pl.b_off[i];
-    w.part = n.wpart;
     w.part_cap = n.wpart_cap;
     w.low = low;
     w.c_low = low ? c_low : 0;
     w.pool_in = pool_in ? 1 : 0;
-    if (i == ENC1A && !gin)
-      e = cpi::nn_in1_wgrad(in, B, w.H, w.W, L.cin, g, n.wpart, w.dw, w.db, ws);
-    else
-      e = cpi::nn_conv_wgrad(w, ws);
-    if (e != hipSuccess) return e;
-    if (side && done) {
-      *done = ev[(*nev)++];
-      if ((e = hipEventRecord(*done, side)) != hipSuccess) return e;
+    const bool in1 = i == ENC1A && !gin;
+    auto run = [&](hipStream_t st, int phases) {
+      return in1 ? cpi::nn_in1_wgrad(in, B, w.H, w.W, L.cin, g, w.part, w.dw, w.db, st, phases)
+                 : cpi::nn_conv_wgrad(w, st, phases);
+    };
+    if (!side) {
+      w.part = n.wpart[0];
+      if ((e = run(s, 3)) != hipSuccess) return e;
+    } else {
+      // partial buffer k in turn, once the reduction that last read it is done
+      const int k = *pnext;
+      *pnext ^= 1;
+      if (pfree[k]) {
+        if ((e = hipStreamWaitEvent(side, pfree[k], 0)) != hipSuccess) return e;
+        pfree[k] = nullptr;
+      }
+      w.part = n.wpart[k];
+      if ((e = run(side, 1)) != hipSuccess) return e;
+      const hipEvent_t wdone = ev[(*nev)++];
+      if ((e = hipEventRecord(wdone, side)) != hipSuccess) return e;
+      if (done) *done = wdone;  // the kernel that read g
+      if ((e = hipStreamWaitEvent(red, wdone, 0)) != hipSuccess) return e;
+      if ((e = run(red, 2)) != hipSuccess) return e;
+      pfree[k] = ev[(*nev)++];
+      if ((e = hipEventRecord(pfree[k], red)) != hipSuccess) return e;
     }
     if (!gin) return hipSuccess;
     cpi::NnConvArgs a;
@@ -511,9 +537,11 @@ struct Pass {
       }
     }
     if (side) {
-      const hipEvent_t joined = ev[(*nev)++];
-      NN_STEP(hipEventRecord(joined, side));
-      NN_STEP(hipStreamWaitEvent(s, joined, 0));
+      for (hipStream_t st : {side, red}) {
+        const hipEvent_t joined = ev[(*nev)++];
+        NN_STEP(hipEventRecord(joined, st));
+        NN_STEP(hipStreamWaitEvent(s, joined, 0));
+      }
     }
     return hipSuccess;
 #undef NN_STEP
@@ -611,11 +639,12 @@ cpi_status cpi_denoiser_train_step(float* params, float* adam_m, float* adam_v, 
                                                  std::to_string(n.bytes) + " bytes");
     const Params pl = param_layout();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipStream_t side = nullptr;
+    hipStream_t side = nullptr, red = nullptr;
     hipEvent_t* ev = nullptr;
-    int nev = 0;
-    NN_HIP(side_resources(workspace, &side, &ev), "denoiser weight-gradient stream");
-    const Pass ps{pl, n, params, batch, h, w, s, side, ev, &nev, loss};
+    int nev = 0, pnext = 0;
+    hipEvent_t pfree[2] = {nullptr, nullptr};
+    NN_HIP(side_resources(workspace, &side, &red, &ev), "denoiser weight-gradient streams");
+    const Pass ps{pl, n, params, batch, h, w, s, side, red, ev, &nev, pfree, &pnext, loss};
     const int64_t hw = int64_t(h) * w, P0 = int64_t(batch) * hw;
     NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, targets, n.tn, n.stats,
                              n.norm_scratch, s),
@@ -653,11 +682,12 @@ cpi_status cpi_denoiser_gradients(const float* params, int32_t batch, int32_t h,
     n.grads = grads;
     const Params pl = param_layout();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipStream_t side = nullptr;
+    hipStream_t side = nullptr, red = nullptr;
     hipEvent_t* ev = nullptr;
-    int nev = 0;
-    NN_HIP(side_resources(workspace, &side, &ev), "denoiser weight-gradient stream");
-    const Pass ps{pl, n, params, batch, h, w, s, side, ev, &nev, loss};
+    int nev = 0, pnext = 0;
+    hipEvent_t pfree[2] = {nullptr, nullptr};
+    NN_HIP(side_resources(workspace, &side, &red, &ev), "denoiser weight-gradient streams");
+    const Pass ps{pl, n, params, batch, h, w, s, side, red, ev, &nev, pfree, &pnext, loss};
     const int64_t hw = int64_t(h) * w, P0 = int64_t(batch) * hw;
     NN_HIP(cpi::nn_normalize(planes, batch, hw, 8, n.x8, n.xf, targets, n.tn, n.stats,
                              n.norm_scratch, s),

@@ -268,7 +268,10 @@ struct NnWgradArgs {
   int c_low = 0;
   int pool_in = 0;
 };
-hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s);
+// phases: 1 the splits' kernel, 2 the reduction of the partial buffer into
+// dw / db (part set), 3 both (the reduction may go on another stream, after
+// the first phase and before the partial buffer is used again)
+hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s, int phases = 3);
 // floats of partial sums nn_conv_wgrad uses for this shape (the part buffer)
 int64_t nn_conv_wgrad_part_floats(const NnWgradArgs& a);
 // db[n] += sum over the M pixels of dy[m][n]
@@ -305,7 +308,7 @@ hipError_t nn_in1_fwd(const uint16_t* x, int B, int H, int W, int cx, const uint
 int nn_in1_wgrad_groups(int64_t P);
 // its weight (dw [32][9 * cx]) and bias (db [32]) gradients added in, via part
 hipError_t nn_in1_wgrad(const uint16_t* x, int B, int H, int W, int cx, const uint16_t* dy,
-                        float* part, float* dw, float* db, hipStream_t s);
+                        float* part, float* dw, float* db, hipStream_t s, int phases = 3);
 // din = (dout routed to each 2x2 window's first maximal position) + skip,
 // zeroed where in <= 0; C % 8 == 0
 hipError_t nn_pool_bwd_add(const uint16_t* in, int B, int H, int W, int C, const uint16_t* dout,

@@ -1739,15 +1739,16 @@ int64_t nn_conv_wgrad_part_floats(const NnWgradArgs& a) {
   return int64_t(p.gz) * (int64_t(a.Cout) * a.ks * a.ks * a.Cin + a.Cout);
 }
 
-hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
+hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s, int phases) {
   if (a.ks != 3 && a.ks != 1) return hipErrorInvalidValue;
+  if ((phases & 2) && !(phases & 1) && !a.part) return hipErrorInvalidValue;
   const WgradPlan p = wgrad_plan(a);
   if ((a.low || a.pool_in) &&
       (p.kind > 5 || (a.low && a.pool_in) || (a.low && (a.c_low % 32 || a.H % 2 || a.W % 2))))
     return hipErrorInvalidValue;
   if (a.part && a.part_cap < nn_conv_wgrad_part_floats(a)) return hipErrorInvalidValue;
   const dim3 grid(p.gx, p.gy, p.gz), block(256);
-  switch (p.kind) {
+  if (phases & 1) switch (p.kind) {
     case 0: hipLaunchKernelGGL((k_conv3_wgrad<64, 64, 2>), grid, block, 0, s, a); break;
     case 1: hipLaunchKernelGGL((k_conv3_wgrad<64, 32, 4>), grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_conv3_wgrad<64, 16, 8>), grid, block, 0, s, a); break;
@@ -1759,7 +1760,7 @@ hipError_t nn_conv_wgrad(const NnWgradArgs& a, hipStream_t s) {
     case 8: hipLaunchKernelGGL((k_conv_wgrad<1, 64, 64>), grid, block, 0, s, a); break;
     default: hipLaunchKernelGGL((k_conv_wgrad<1, 32, 64>), grid, block, 0, s, a); break;
   }
-  if (a.part) {
+  if (a.part && (phases & 2)) {
     const int64_t nw = int64_t(a.Cout) * a.ks * a.ks * a.Cin;
     int64_t blocks = (nw + a.Cout + 63) / 64;
     if (blocks > 65536) blocks = 65536;
@@ -1912,12 +1913,14 @@ int nn_in1_wgrad_groups(int64_t P) {
 }
 
 hipError_t nn_in1_wgrad(const uint16_t* x, int B, int H, int W, int cx, const uint16_t* dy,
-                        float* part, float* dw, float* db, hipStream_t s) {
+                        float* part, float* dw, float* db, hipStream_t s, int phases) {
   if (int64_t(B) * H * W >= (int64_t(1) << 30)) return hipErrorInvalidValue;  // 32-bit indices
   const int g = nn_in1_wgrad_groups(int64_t(B) * H * W);
-  hipLaunchKernelGGL(k_in1_wgrad, dim3(unsigned(g)), dim3(256), 0, s, x, B, H, W, cx, dy, part);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(5), dim3(256), 0, s, part, g, int64_t(288), 32, dw, db,
-                     cx);
+  if (phases & 1)
+    hipLaunchKernelGGL(k_in1_wgrad, dim3(unsigned(g)), dim3(256), 0, s, x, B, H, W, cx, dy, part);
+  if (phases & 2)
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(5), dim3(256), 0, s, part, g, int64_t(288), 32, dw, db,
+                       cx);
   return hipGetLastError();
 }
 
