@@ -1,14 +1,15 @@
 """Memory-adaptive blocking at the paper's pixel counts: 256 x 256 regions on
-both detectors (Gamma 65536 x 65536) and 2097152 distinct 1-bit frames (4096
-files of 512), made on the device (seeded).  The workspace given to
-cpi_correlate holds the running sums and about 480000 frames' operands, not
-the one-shot operands of all frames, so the frames are folded in five blocks.
+both detectors (Gamma 65536 x 65536) and the paper's full frame count,
+3997696 distinct 1-bit frames (7808 files of 512), made on the device
+(seeded).  The workspace given to cpi_correlate holds the running sums and
+about 480000 frames' operands, not the one-shot operands of all frames, so the
+frames are folded in several blocks.
 
 Gamma is checked against the oracle on sampled pixel pairs (from those
 pixels' frame columns only) and through integer identities over every entry:
 row sums, column sums and a Freivalds product of the exact numerator,
-recovered as rint(Gamma * N^2) (exact: N^2 is a power of two and |numer| <
-2^53), evaluated in int64, and the FP32 Gamma is the rounding of the FP64 one."""
+recovered as rint(Gamma * N^2) (exact: |numer| <= N^2 / 4 < 2^52, so the two
+roundings move Gamma * N^2 by at most |numer| * 2^-52 < 0.01), evaluated in int64, and the FP32 Gamma is the rounding of the FP64 one."""
 import numpy as np
 import pytest
 
@@ -20,7 +21,7 @@ from tests.gpu_util import dev, log
 pytestmark = pytest.mark.gpu
 
 W = WORKLOADS["da256_db256_files11_bit1"]
-N = 4096 * 512
+N = 7808 * 512
 
 
 @pytest.fixture(scope="module")
@@ -42,7 +43,7 @@ def _unpacked_chunks(torch, packed, npix, step=8192):
         yield lo, ((c.unsqueeze(2) >> bits) & 1).reshape(c.shape[0], -1)[:, :npix]
 
 
-def test_blocked_correlate_paper_pixels_2m_frames(cpi):
+def test_blocked_correlate_paper_pixels_paper_frames(cpi):
     import torch
 
     n, pa, pb = N, W.pa, W.pb
