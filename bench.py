@@ -1054,7 +1054,7 @@ def main():
                                                                 else None)))
     pairs = float(n) * pa * pb
     line = {
-        "metric": "Gamma pixel-pair*frames/s and refocused planes/s: int8-MFMA vs plain FP32, 1 GPU",
+        "metric": "\u0393 pixel-pair\u00b7frames/s and refocused planes/s: int8-MFMA vs plain FP32, 1 GPU",
         "value": pairs / (fig["ms_per_step"] * 1e-3),
         "unit": "pixel-pair*frames/s",
         "n_gpus": 1,
