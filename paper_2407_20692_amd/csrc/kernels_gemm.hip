@@ -351,7 +351,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-// ---- FP4 contraction fed through an LDS pipeline --------------------------
+// ---- Bit-row contraction fed through an LDS pipeline ----------------------
+// FP4 (k_gemm_f4lds) or int8 (k_gemm_i8lds) matrix-core ops on bit rows, with
+// the expansions of the register-fed kernel above.
 // A work-group computes a 128 x 128 tile (2 x 2 waves of 64 x 64).  Each
 // 512-frame block needs 256 operand rows x 64 bytes = 16 KB, which direct
 // global->LDS copies (no registers) bring into one of S stages, S - 1 blocks
@@ -400,14 +402,15 @@ __device__ __forceinline__ void wait_copies() {
 // registers (no spills), so that three work-groups share a CU (the LDS limit):
 // measured 12% faster than its unconstrained allocation (240 registers, two
 // work-groups) on Da 128 x 128, Db 64 x 64, 20000 frames.
-template <int MODE, int S>
-__global__ __launch_bounds__(256, 2) void k_gemm_f4lds(GemmArgs g) {
+constexpr int kLdsStage = 16384;   // bytes per stage
+
+template <int MODE, int S, bool I8>
+__device__ __forceinline__ void gemm_lds(const GemmArgs& g, uint8_t* stage) {
   if (g.cond) {
     const uint32_t mx = g.stats[0];
     if ((g.cond == 1) != (mx <= 1u)) return;
   }
-  constexpr int kStage = 16384;
-  __shared__ __attribute__((aligned(16))) uint8_t stage[S * kStage];
+  constexpr int kStage = kLdsStage;
   const int tiles_m = int(g.m_pad / 128);
   int tm, tn;
   tile_of(blockIdx.x, gridDim.x, tiles_m, &tm, &tn);
@@ -439,11 +442,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f4lds(GemmArgs g) {
   const int r = lane & 15, kg = lane >> 4;
   const uint32_t roff = uint32_t(r * 64 + 16 * (kg ^ ((r >> 2) & 3)));
 
-  v4f acc[4][4];
+  using Acc = std::conditional_t<I8, v4i, v4f>;
+  Acc acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
   const int64_t last = g.kblocks - 1;
 #pragma unroll
@@ -462,19 +466,47 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f4lds(GemmArgs g) {
     const uint32_t ba = base + wm * 4096, bb = base + 8192 + wn * 4096;
     v4i am[4], bn[4];
     lds_read8(ba, ba + 1024, ba + 2048, ba + 3072, bb, bb + 1024, bb + 2048, bb + 3072, am, bn);
+    if constexpr (I8) {
+      const int mask = 0x01010101;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      v8i ea[4], eb[4];
+      for (int w = 0; w < 4; ++w) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ea[i] = fp4_operand_m(uint32_t(am[i][w]));
+        for (int h = 0; h < 2; ++h) {
+          v4i ea[4], eb[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) eb[j] = fp4_operand_n(uint32_t(bn[j][w]));
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t x = uint32_t(am[i][w]);
+            ea[i] = v4i{int((x >> (4 * h + 0)) & mask), int((x >> (4 * h + 1)) & mask),
+                        int((x >> (4 * h + 2)) & mask), int((x >> (4 * h + 3)) & mask)};
+          }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t x = uint32_t(bn[j][w]);
+            eb[j] = v4i{int((x >> (4 * h + 0)) & mask), int((x >> (4 * h + 1)) & mask),
+                        int((x >> (4 * h + 2)) & mask), int((x >> (4 * h + 3)) & mask)};
+          }
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-              ea[i], eb[j], acc[i][j], kFmtE2M1, kFmtE2M1, 0, kNoScale, 0, kNoScale);
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ea[i], eb[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        v8i ea[4], eb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ea[i] = fp4_operand_m(uint32_t(am[i][w]));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) eb[j] = fp4_operand_n(uint32_t(bn[j][w]));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                ea[i], eb[j], acc[i][j], kFmtE2M1, kFmtE2M1, 0, kNoScale, 0, kNoScale);
+      }
     }
     st = st == S - 1 ? 0 : st + 1;
   }
@@ -520,6 +552,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f4lds(GemmArgs g) {
   }
 }
 
+template <int MODE, int S>
+__global__ __launch_bounds__(256, 2) void k_gemm_f4lds(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage[S * kLdsStage];
+  gemm_lds<MODE, S, false>(g, stage);
+}
+
+template <int MODE, int S>
+__global__ __launch_bounds__(256, 2) void k_gemm_i8lds(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage[S * kLdsStage];
+  gemm_lds<MODE, S, true>(g, stage);
+}
+
 // One thread per Gamma element of a streaming state.
 __global__ __launch_bounds__(256) void k_state_gamma(const void* __restrict__ sab, int sab64,
                                                      const int64_t* __restrict__ sum_a,
@@ -544,8 +588,9 @@ __global__ __launch_bounds__(256) void k_state_gamma(const void* __restrict__ sa
   }
 }
 
-// CPI_GEMM_FEED=regs selects the register-fed FP4 kernel (measurement runs);
-// the default feeds the matrix cores through the LDS pipeline.
+// CPI_GEMM_FEED=regs selects the register-fed kernels for bit rows
+// (measurement runs); the default feeds the matrix cores through the LDS
+// pipeline.
 bool fp4_from_registers() {
   static const bool on = [] {
     const char* v = std::getenv("CPI_GEMM_FEED");
@@ -575,14 +620,17 @@ bool fp4_enabled() { return g_mma_encoding.load(std::memory_order_relaxed) == CP
 
 constexpr int64_t kFp4MaxFrames = int64_t(1) << 24;
 
-template <int MODE, int S>
-hipError_t launch_f4lds(const GemmArgs& a, hipStream_t s) {
+template <int MODE, int S, bool I8>
+hipError_t launch_lds(const GemmArgs& a, hipStream_t s) {
   const int64_t tiles_m = a.m_pad / 128, tiles_n = a.n_pad / 128;
   if (tiles_m * 128 != a.m_pad || tiles_n * 128 != a.n_pad || a.kblocks < 1)
     return hipErrorInvalidValue;
   const int64_t nwg = tiles_m * tiles_n;
   if (nwg > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm_f4lds<MODE, S>), dim3(unsigned(nwg)), dim3(256), 0, s, a);
+  if constexpr (I8)
+    hipLaunchKernelGGL((k_gemm_i8lds<MODE, S>), dim3(unsigned(nwg)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_gemm_f4lds<MODE, S>), dim3(unsigned(nwg)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -591,9 +639,10 @@ hipError_t launch_bits(const GemmArgs& a, hipStream_t s) {
   if (a.fp4) {
     if (a.kblocks * 512 > kFp4MaxFrames) return hipErrorInvalidValue;
     if (fp4_from_registers()) return launch_gemm<4, 4, true, MODE, true>(a, s);
-    return launch_f4lds<MODE, 3>(a, s);
+    return launch_lds<MODE, 3, false>(a, s);
   }
-  return launch_gemm<4, 4, true, MODE>(a, s);
+  if (fp4_from_registers()) return launch_gemm<4, 4, true, MODE>(a, s);
+  return launch_lds<MODE, 3, true>(a, s);
 }
 
 }  // namespace

@@ -113,7 +113,8 @@ def test_binary_bytes_match_packed_bits(cpi):
 
 @pytest.mark.parametrize("enc", ["auto", "int8"])
 @pytest.mark.parametrize("n,pa,pb,kind", [(777, 1001, 77, "bits"), (1536, 512, 512, "bits"),
-                                          (4099, 300, 260, "u8_binary"), (1, 33, 18, "bits")])
+                                          (4099, 300, 260, "u8_binary"), (1, 33, 18, "bits"),
+                                          (5000, 2048, 640, "bits")])
 def test_binary_encodings(cpi, enc, n, pa, pb, kind):
     """Binary frames through either matrix-core encoding (FP4 with FP32 sums,
     int8 with int32 sums) give the oracle's results bit for bit; every frame

@@ -43,8 +43,20 @@ def _chunks(n, sizes):
         lo += k
 
 
+@pytest.mark.parametrize("enc", ["auto", "int8"])
 @pytest.mark.parametrize("fmt_name", ["bit1", "u8_binary", "u8_counts"])
-def test_chunked_equals_single_shot(cpi, fmt_name):
+def test_chunked_equals_single_shot(cpi, fmt_name, enc):
+    """Chunks of every format folded into the running sums equal the oracle's
+    single shot, under either matrix-core encoding of binary chunks."""
+    before = cpi.get_mma_encoding()
+    cpi.set_mma_encoding(cpi.MMA_INT8 if enc == "int8" else cpi.MMA_AUTO)
+    try:
+        _chunked_equals_single_shot(cpi, fmt_name, enc)
+    finally:
+        cpi.set_mma_encoding(before)
+
+
+def _chunked_equals_single_shot(cpi, fmt_name, enc):
     rng = np.random.default_rng(21)
     n, pa, pb = 5000, 300, 70
     if fmt_name == "u8_counts":
@@ -60,7 +72,7 @@ def test_chunked_equals_single_shot(cpi, fmt_name):
     for lo, hi in _chunks(n, [1000, 1, 1200, 999, 64, 1136, 600]):
         ca = pack_bits_lsb(a[lo:hi]) if fmt_name == "bit1" else a[lo:hi]
         cb = pack_bits_lsb(b[lo:hi]) if fmt_name == "bit1" else b[lo:hi]
-        log(f"case stream {fmt_name} chunk [{lo},{hi})")
+        log(f"case stream {fmt_name} encoding={enc} chunk [{lo},{hi})")
         s.push(to_dev(ca), to_dev(cb), hi - lo)
     assert s.frames == n
     ref = oracle.correlation(a, b, n, pa, pb, oracle.FRAMES_U8)
