@@ -706,7 +706,7 @@ def hot_path(args, cpi, torch, np, dev, w, n, fmt, da, db, alphas, tune=True, pl
     }
     achieved8 = gemm_ops / (ms_gemm_int8 * 1e-3) / 1e12
     fig["roofline_int8"] = {
-        "kernel": "k_gemm<bits> (int8 matrix-core contraction, exact epilogue)",
+        "kernel": "k_gemm_i8lds (int8 matrix-core contraction of bit rows, LDS pipeline, exact epilogue)",
         "bound": "mfma",
         "achieved": achieved8,
         "peak": INT8_PEAK / 1e12,
