@@ -61,9 +61,9 @@ constexpr int rows_pairs_per_wave(int pairs) { return pairs >= 256 ? 64 : 32; }
 
 // Column cells of every (plane, output column) pair of work-group (group gq,
 // tile t) against lens-plane column x_b: a 4-word header (window start, and
-// one bit per 8-pair chunk with a nonzero weight), then per pair the byte
-// offset of its cell's column in the window and its two weights (zero for
-// pairs past the planes or columns, or whose taps fall outside the view).  One
+// one bit per 8-pair chunk with a nonzero weight), then per pair the byte offset of its cell's column in the window
+// and its two weights (zero for pairs
+// past the planes or columns, or whose taps fall outside the view).  One
 // block per (gq, t, x_b), one thread per pair.  The arithmetic is that of the
 // other refocus kernels.
 template <int NA, int XR>
