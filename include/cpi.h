@@ -120,7 +120,10 @@ cpi_status cpi_geometry_default(int32_t wa, int32_t ha, int32_t wb, int32_t hb,
  *   asynchronous (one push per block is enqueued).  Blocks only pay when the
  *   frames' operands outweigh S_ab (n above about 32 * pa * pb / (pa + pb)
  *   frames for 1-bit data: 1.05e6 at 65536 x 65536 pixels).  A workspace
- *   below the state for F = 512 gives CPI_ERR_WORKSPACE.
+ *   below the state for F = 512 gives CPI_ERR_WORKSPACE.  Inputs longer than
+ *   one ingest pass (n above 2^24 - 512 = 16776704 frames) are always folded
+ *   this way, in blocks of at most that many frames; for them
+ *   cpi_correlate_workspace_size reports the state for such blocks.
  *   Errors: CPI_ERR_INVALID_ARG (null frames/workspace, n, pa or pb <= 0,
  *   bad enum, misalignment, all outputs null), CPI_ERR_OVERFLOW (n*n*255*255
  *   >= 2^63 for U8, n*n >= 2^53 for either format), CPI_ERR_WORKSPACE,

@@ -478,6 +478,11 @@ size_t usable_workspace(size_t given) {
 
 constexpr int64_t kBlockUnit = 512;   // frames; keeps every block 16-byte aligned
 
+// Frames one pass of the ingest kernels takes (the bit-row offsets within a
+// tile of 1024 rows stay below 2^31 bytes); longer inputs are folded in
+// blocks of at most this many frames through the running sums.
+constexpr int64_t kMaxPassFrames = (int64_t(1) << 24) - kBlockUnit;
+
 // Defined with the streaming calls below; gamma_buffers 0 makes a handle
 // whose pushes fold the sums only (the blocks of cpi_correlate).
 cpi_status stream_create(int64_t pa, int64_t pb, cpi_frame_format fmt, int64_t max_chunk,
@@ -528,11 +533,18 @@ cpi_status cpi_correlate_workspace_size(int64_t n, int64_t pa, int64_t pb, cpi_f
     cpi_status s = cpi::plan_correlate(n, pa, pb, int(fmt), &pl, &why);
     if (s != CPI_OK) return set_error(s, why);
     *bytes = pl.total;
-    const size_t limit = usable_workspace(pl.total);
-    if (limit < pl.total) {
+    if (n > kMaxPassFrames) {
+      // blocks of kMaxPassFrames frames
+      size_t need = 0;
+      block_frames(kMaxPassFrames, pa, pb, fmt, SIZE_MAX, &need);
+      if (need == 0) return set_error(CPI_ERR_INVALID_ARG, "pa * pb too large for blocked work");
+      *bytes = need;
+    }
+    const size_t limit = usable_workspace(*bytes);
+    if (limit < *bytes) {
       size_t need = 0;
       block_frames(n, pa, pb, fmt, limit, &need);
-      if (need > 0 && need < pl.total) *bytes = need;
+      if (need > 0 && need < *bytes) *bytes = need;
     }
     return CPI_OK;
   });
@@ -560,11 +572,13 @@ cpi_status cpi_correlate(const void* frames_a, const void* frames_b, int64_t n, 
     if (!workspace || !aligned16(workspace))
       return set_error(CPI_ERR_INVALID_ARG, "workspace must be a 16-byte aligned device pointer");
     const size_t usable = usable_workspace(workspace_bytes);
-    if (usable < pl.total) {
-      // memory-adaptive blocking: fold the frames in blocks through the
-      // running sums of the streaming path (exact, same result)
+    if (usable < pl.total || n > kMaxPassFrames) {
+      // memory-adaptive blocking (and inputs longer than one ingest pass):
+      // fold the frames in blocks through the running sums of the streaming
+      // path (exact, same result)
       size_t need = 0;
-      const int64_t f = block_frames(n, pa, pb, fmt, usable, &need);
+      int64_t f = block_frames(n, pa, pb, fmt, usable, &need);
+      if (f > kMaxPassFrames) f = kMaxPassFrames;
       if (f == 0)
         return set_error(CPI_ERR_WORKSPACE, "correlate workspace too small: need " +
                                                 std::to_string(pl.total) +

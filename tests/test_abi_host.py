@@ -44,6 +44,14 @@ def test_workspace_sizes(cpi):
     # U8 above 131008 frames needs the int64 accumulator of the flush passes
     big = cpi.correlate_workspace_size(140000, 64, 32, cpi.FRAMES_U8)
     assert big >= 64 * 32 * 8 + 96 * 140032
+    # past one ingest pass (2^24 - 512 frames; reachable for 1-bit frames, as
+    # byte frames overflow int64 first) the frames are folded in blocks of
+    # that many frames: the workspace no longer grows with n
+    one_pass = (1 << 24) - 512
+    last = cpi.correlate_workspace_size(one_pass, 40, 24, cpi.FRAMES_BIT1)
+    past = cpi.correlate_workspace_size(one_pass + 1, 40, 24, cpi.FRAMES_BIT1)
+    assert past == cpi.correlate_workspace_size(1 << 25, 40, 24, cpi.FRAMES_BIT1) > 0
+    assert past <= 2 * last
     assert cpi.correlate_f32_plain_workspace_size(20000, 16384, 4096, cpi.FRAMES_U8) >= \
         20000 * (16384 + 4096) * 4
     g = cpi.geometry_default(128, 128, 64, 64)

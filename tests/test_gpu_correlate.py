@@ -140,6 +140,29 @@ def test_binary_encodings(cpi, enc, n, pa, pb, kind):
     assert_bit_exact(got, oracle_in_layout(ref, cpi.GAMMA_VIEW_MAJOR))
 
 
+def test_frames_past_one_ingest_pass(cpi):
+    """2^24 + 4099 bit frames, more than one ingest pass takes: folded in
+    blocks through the running sums, under either matrix-core encoding;
+    every output bit-exact against the oracle."""
+    n = (1 << 24) + 4099
+    pa, pb = 40, 24
+    rng = np.random.default_rng(24)
+    fa = rng.integers(0, 256, size=(n, (pa + 7) // 8), dtype=np.uint8)
+    fb = rng.integers(0, 256, size=(n, (pb + 7) // 8), dtype=np.uint8)
+    fa = np.concatenate([fa.reshape(-1), np.zeros(16, np.uint8)])
+    fb = np.concatenate([fb.reshape(-1), np.zeros(16, np.uint8)])
+    ref = oracle.correlation(fa, fb, n, pa, pb, oracle.FRAMES_BIT1)
+    before = cpi.get_mma_encoding()
+    try:
+        for enc in (cpi.MMA_AUTO, cpi.MMA_INT8):
+            log(f"case frames past one ingest pass n={n} pa={pa} pb={pb} encoding={enc}")
+            cpi.set_mma_encoding(enc)
+            got = run_correlate(cpi, fa, fb, n, pa, pb, cpi.FRAMES_BIT1, cpi.GAMMA_VIEW_MAJOR)
+            assert_bit_exact(got, oracle_in_layout(ref, cpi.GAMMA_VIEW_MAJOR))
+    finally:
+        cpi.set_mma_encoding(before)
+
+
 @pytest.mark.parametrize("n", [131008, 131073, 270000])
 def test_int32_flush_passes(cpi, n):
     """Byte frames beyond 131008 frames fold int32 partial sums into int64."""
