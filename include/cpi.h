@@ -323,7 +323,9 @@ cpi_status cpi_refocus_resampled(const float* gamma, const cpi_geometry* g,
  * far is available after every chunk.
  *
  * cpi_stream_workspace_size: device bytes a stream needs for pa, pb, fmt and
- *   chunks of at most max_chunk frames.
+ *   chunks of at most max_chunk frames (max_chunk at most 131008 for
+ *   CPI_FRAMES_U8 and 16776704, one ingest pass, for CPI_FRAMES_BIT1; larger
+ *   values give CPI_ERR_INVALID_ARG).
  * cpi_stream_create: builds a handle over caller workspace (device) on `stream`;
  *   the handle owns host-side state only.  Sums start at zero.
  * cpi_stream_push: folds k <= max_chunk frame pairs (device pointers, format

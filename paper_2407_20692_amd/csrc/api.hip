@@ -478,10 +478,10 @@ size_t usable_workspace(size_t given) {
 
 constexpr int64_t kBlockUnit = 512;   // frames; keeps every block 16-byte aligned
 
-// Frames one pass of the ingest kernels takes (the bit-row offsets within a
-// tile of 1024 rows stay below 2^31 bytes); longer inputs are folded in
-// blocks of at most this many frames through the running sums.
-constexpr int64_t kMaxPassFrames = (int64_t(1) << 24) - kBlockUnit;
+// Longer inputs than one ingest pass takes are folded in blocks of at most
+// that many frames through the running sums.
+using cpi::kMaxPassFrames;
+static_assert(kMaxPassFrames % kBlockUnit == 0, "blocks of whole 512-frame units");
 
 // Defined with the streaming calls below; gamma_buffers 0 makes a handle
 // whose pushes fold the sums only (the blocks of cpi_correlate).

@@ -221,6 +221,8 @@ cpi_status plan_stream(int64_t pa, int64_t pb, int fmt, int64_t max_chunk, Strea
     return fail(why, CPI_ERR_INVALID_ARG, "gamma_buffers must be 1 or 2");
   if (fmt == CPI_FRAMES_U8 && max_chunk > kByteChunk)
     return fail(why, CPI_ERR_INVALID_ARG, "U8 chunks are limited to 131008 frames");
+  if (max_chunk > kMaxPassFrames)
+    return fail(why, CPI_ERR_INVALID_ARG, "chunks are limited to 16776704 frames");
   StreamPlan q;
   cpi_status s = plan_correlate(max_chunk, pa, pb, fmt, &q.chunk, why);
   if (s != CPI_OK) return s;

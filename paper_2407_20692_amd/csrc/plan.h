@@ -18,6 +18,9 @@ constexpr int64_t kBitBlock = 512;      // frames per 64-byte row segment, 1 bit
 constexpr int64_t kByteBlock = 64;      // frames per 64-byte row segment, 1 byte/frame
 // Frames per int32 pass for byte operands: 131008 * 128 * 128 < 2^31 - 1.
 constexpr int64_t kByteChunk = 131008;
+// Frames one pass of the bit-row ingest takes (row offsets within a tile of
+// 1024 rows stay below 2^31 bytes).
+constexpr int64_t kMaxPassFrames = (int64_t(1) << 24) - kBitBlock;
 constexpr int kMaxAlpha = 4096;
 constexpr int kAlphaPerLaunch = 64;     // plane parameters passed by value per table launch
 

@@ -57,6 +57,13 @@ def test_workspace_sizes(cpi):
     g = cpi.geometry_default(128, 128, 64, 64)
     assert cpi.refocus_workspace_size(g, 32) >= 32 * (128 + 128 + 64 + 64) * 8
     assert cpi.stream_workspace_size(16384, 4096, cpi.FRAMES_BIT1, 1000) >= 16384 * 4096 * 8
+    # chunks are limited to one ingest pass (1-bit) and one int32 pass (bytes)
+    assert cpi.stream_workspace_size(64, 32, cpi.FRAMES_BIT1, (1 << 24) - 512) > 0
+    assert cpi.stream_workspace_size(64, 32, cpi.FRAMES_U8, 131008) > 0
+    for fmt, chunk in ((cpi.FRAMES_BIT1, (1 << 24) - 511), (cpi.FRAMES_U8, 131009)):
+        with pytest.raises(cpi.CpiError) as e:
+            cpi.stream_workspace_size(64, 32, fmt, chunk)
+        assert e.value.status == 1
 
 
 @pytest.mark.parametrize("args,status", [
